@@ -1,0 +1,305 @@
+"""Benchmark of the splatting hot path on one MI355X.
+
+Headline: forward frames/s of the plain path (preprocess -> bin/sort -> composite) on a
+1M-Gaussian SH-3 scene (mixture of 32 anisotropic clusters, random storage order) at
+1256x828, cycling over 8 orbit views. Also reported: per-stage kernel times and their
+algorithmic rates, fwd+bwd views/s (200k Gaussians, one 1256x828 view; and 1M Gaussians,
+8 views of uneven size, batched vs one view at a time), importance views/s, the FP64
+oracle timed on the host cores on a bounded sample, and the roofline of the dominant
+kernel (compositing), measured with HIP events on the stream the kernels run on.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s fwd (1M Gaussians, 1256x828) + fwd+bwd views/s vs plain; % HBM roofline"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s (FP32 or
+# FP64, one FMA = one lane-op; the 157.3 TFLOP/s FP32 figure counts FMA = 2 and packed = 2)
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+# algorithmic lane-ops of one composited (pixel, Gaussian) evaluation: FP64 support test
+# (2 sub, 3 mul, 2 fma, 1 cmp = 8) + opacity and blend in FP32 (cvt, scale, exp = 4 slots,
+# mul, min, weight, 3 fma colour, 1 - alpha, transmittance, stop test = 15)
+OPS_PER_COMPOSITE = 23
+SPLAT = 64
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every gs_* call is enqueued on)."""
+
+    def __init__(self, torch):
+        self.t = torch
+        self.s = torch.cuda.Event(enable_timing=True)
+        self.e = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.s.record()
+        return self
+
+    def __exit__(self, *a):
+        self.e.record()
+
+    def ms(self):
+        self.e.synchronize()
+        return self.s.elapsed_time(self.e)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards over views "
+              "with one all-reduce per pass and is not run across GPUs here", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2403_13806_amd as gs
+    import scenes
+
+    dev = torch.device("cuda:0")
+    P = scenes.Params()
+    K, W = args.steps, args.warmup
+
+    log("scene: 1M Gaussians, mixture-32, SH degree 3")
+    sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+    cams = scenes.orbit_views(8)
+    g = gs.Gaussians.from_scene(sc, dev)
+    rs = [gs.Renderer(g, gs.ViewBatch([c], (16, 16), dev), P) for c in cams]
+    torch.cuda.synchronize()
+
+    # ---------------- headline: plain forward frames/s ----------------
+    for i in range(W):
+        rs[i % 8].forward()
+    torch.cuda.synchronize()
+    log(f"timing {K} forward frames")
+    t0 = time.perf_counter()
+    with Timer(torch) as tm:
+        for i in range(K):
+            rs[i % 8].forward()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = tm.ms()
+    for r in rs:
+        ovf, _ = r.check()
+        assert not ovf, "pair capacity overflowed during the timed frames"
+    fps = K / wall
+    log(f"forward: {fps:.1f} frames/s (wall), {K / ev_ms * 1e3:.1f} frames/s (events)")
+
+    # ---------------- per-stage kernel times (events around each call) ----------------
+    import ctypes
+    from paper_2403_13806_amd import _lib as L
+    from paper_2403_13806_amd.splat import _ptr, _stream
+    lib = L.load()
+    stages = {"preprocess": [], "bin_sort": [], "render_fwd": []}
+    pairs, composites, tested, visible = [], [], [], []
+    ncontrib = torch.empty(rs[0].views.n_pixels, dtype=torch.int32, device=dev)
+    reps = max(3, K // 8)
+    for r in rs:
+        s = _stream(dev)
+        for _ in range(reps):
+            with Timer(torch) as a:
+                L.check(lib.gs_preprocess(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r.p), None, r.g.n, 1,
+                                          ctypes.byref(r._sp), s))
+            with Timer(torch) as b:
+                L.check(lib.gs_bin_sort(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb), _ptr(r.ws),
+                                        r.ws.numel(), s))
+            with Timer(torch) as c:
+                r.render_only(s, ncontrib)
+            stages["preprocess"].append(a.ms())
+            stages["bin_sort"].append(b.ms())
+            stages["render_fwd"].append(c.ms())
+        # work counts of this view
+        npairs = int(r.bins.n_pairs.item())
+        pairs.append(npairs)
+        composites.append(int(ncontrib.sum().item()))
+        visible.append(int((r.proj.count > 0).sum().item()))
+        cam = r.views.cams[0]
+        tx = (cam.width + 15) // 16
+        py, px = torch.meshgrid(torch.arange(cam.height, device=dev), torch.arange(cam.width, device=dev),
+                                indexing="ij")
+        tile = ((py // 16) * tx + px // 16).reshape(-1)
+        rg = r.bins.ranges.view(-1, 2).long()
+        st, en = rg[tile, 0], rg[tile, 1]
+        stopped = r.t_final < P.t_min
+        tested.append(int(torch.where(stopped, r.n_last.long() - st, en - st).sum().item()))
+    avg = {k: float(np.mean(v)) for k, v in stages.items()}
+    npx = rs[0].views.n_pixels
+    n = g.n
+    mp, mc, mt, mv = (float(np.mean(x)) for x in (pairs, composites, tested, visible))
+    passes = (32 + int(np.ceil(np.log2(rs[0].views.n_tiles))) + 7) // 8
+    bytes_pre = 4 * n * (3 + 3 + 4 + 1 + 48) + 4 * n + mv * (SPLAT + 4 + 8)
+    bytes_sort = 3 * 4 * n + mp * (12 + passes * (8 + 24)) + rs[0].views.n_tiles * 8
+    bytes_render = mp * (4 + SPLAT) + npx * (12 + 4 + 4) + rs[0].views.n_tiles * 8
+    ops_render = OPS_PER_COMPOSITE * mc
+    stage_rows = {
+        "preprocess": {"ms": avg["preprocess"], "alg_GBps": bytes_pre / avg["preprocess"] / 1e6,
+                       "hbm_frac": bytes_pre / avg["preprocess"] / 1e-3 / PEAK_HBM},
+        "bin_sort": {"ms": avg["bin_sort"], "alg_GBps": bytes_sort / avg["bin_sort"] / 1e6,
+                     "hbm_frac": bytes_sort / avg["bin_sort"] / 1e-3 / PEAK_HBM, "radix_passes": passes},
+        "render_fwd": {"ms": avg["render_fwd"], "alg_Tops": ops_render / avg["render_fwd"] / 1e9,
+                       "alu_frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS,
+                       "alg_GBps": bytes_render / avg["render_fwd"] / 1e6,
+                       "hbm_frac": bytes_render / avg["render_fwd"] / 1e-3 / PEAK_HBM},
+    }
+    work = {"visible_per_view": mv, "pairs_per_view": mp, "composited_per_view": mc,
+            "tested_per_view": mt, "composited_per_pixel": mc / npx, "tested_per_composited": mt / max(mc, 1)}
+    log(f"stages (ms): {json.dumps({k: round(v, 4) for k, v in avg.items()})}; work {json.dumps(work)}")
+    roofline = {"bound": "alu", "kernel": "k_render<16,16,fwd>", "achieved": ops_render / avg["render_fwd"] / 1e9,
+                "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-ops/s",
+                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": None,
+                "per_unit": f"{OPS_PER_COMPOSITE} lane-ops per composited (pixel, Gaussian)",
+                "units_per_launch": mc, "avg_launch_ms": avg["render_fwd"]}
+
+    extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3}
+
+    if not args.quick:
+        extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
+        extra["importance"] = importance_rate(torch, gs, rs, n, dev, K)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc, cams[0], P)
+
+    line = {
+        "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "1M Gaussians (mixture of 32 clusters, SH degree 3), 1256x828, 8 orbit views, "
+                               "plain forward per frame", "gaussians": n, "width": 1256, "height": 828,
+                   "views": 8, "tile": "16x16", "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):
+    out = {}
+    # --- 200k Gaussians, one 1256x828 view, forward + L1 + backward ---
+    log("fwd+bwd: 200k Gaussians, 1256x828")
+    sc = scenes.mixture_scene(200_000, seed=0, sh_degree=3, log_scale_mu=-4.0)
+    cam = scenes.orbit_camera(0.0, np.deg2rad(15.0), 4.0, 1256, 828)
+    g = gs.Gaussians.from_scene(sc, dev)
+    r = gs.Renderer(g, gs.ViewBatch([cam], (16, 16), dev), P)
+    tgt = torch.as_tensor(scenes.target_images([cam])[0].reshape(-1), device=dev)
+    grad = gs.Gaussians(torch.zeros_like(g.mean), torch.zeros_like(g.scale), torch.zeros_like(g.quat),
+                        torch.zeros_like(g.opacity), torch.zeros_like(g.sh), 3)
+    dl = torch.empty_like(tgt)
+    loss = torch.zeros(1, device=dev)
+
+    def step():
+        rgb = r.forward()
+        gs.l1_loss_grad(rgb[:tgt.numel()], tgt, dl, loss)
+        r.backward(dl, grad)
+
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    out["fwd_bwd_200k_1view_views_per_s"] = K / (time.perf_counter() - t0)
+    log(f"  {out['fwd_bwd_200k_1view_views_per_s']:.1f} views/s")
+
+    # --- 1M Gaussians, 8 uneven views: batched (one call chain) vs one view at a time ---
+    log("fwd+bwd: 1M Gaussians, 8 uneven views, batched vs per view")
+    cams = scenes.uneven_views()
+    tg = scenes.target_images(cams)
+    vb = gs.ViewBatch(cams, (16, 16), dev)
+    rb = gs.Renderer(g1m, vb, P)
+    tb = vb.pack_images(tg)
+    gradb = gs.Gaussians(torch.zeros_like(g1m.mean), torch.zeros_like(g1m.scale), torch.zeros_like(g1m.quat),
+                         torch.zeros_like(g1m.opacity), torch.zeros_like(g1m.sh), 3)
+    dlb = torch.empty_like(tb)
+    lb = torch.zeros(1, device=dev)
+    singles = []
+    for v, c in enumerate(cams):
+        rv = gs.Renderer(g1m, gs.ViewBatch([c], (16, 16), dev), P)
+        tv = torch.as_tensor(tg[v].reshape(-1), device=dev)
+        singles.append((rv, tv, torch.empty_like(tv)))
+
+    def batched():
+        rgb = rb.forward()
+        gs.l1_loss_grad(rgb[:tb.numel()], tb, dlb, lb)
+        rb.backward(dlb, gradb)
+
+    def plain():
+        for rv, tv, dv in singles:
+            rgb = rv.forward()
+            gs.l1_loss_grad(rgb[:tv.numel()], tv, dv, lb)
+            rv.backward(dv, gradb)
+
+    kk = max(3, K // 8)
+    for fn, name in ((batched, "batched"), (plain, "plain")):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(kk):
+            fn()
+        torch.cuda.synchronize()
+        out[f"fwd_bwd_1M_8uneven_{name}_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
+        log(f"  {name}: {out[f'fwd_bwd_1M_8uneven_{name}_views_per_s']:.1f} views/s")
+    assert not rb.check()[0]
+    return out
+
+
+def importance_rate(torch, gs, rs, n, dev, K):
+    h = torch.zeros(n, device=dev)
+    for r in rs:
+        r.importance(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        rs[i % 8].importance(h)
+    torch.cuda.synchronize()
+    v = K / (time.perf_counter() - t0)
+    log(f"importance: {v:.1f} views/s (1M Gaussians, 1256x828)")
+    return {"views_per_s_1M_1256x828": v}
+
+
+def cpu_baseline(sc, cam, P, m=1024):
+    """The FP64 oracle on the host: projection of all Gaussians for one view plus m random
+    pixels; the frame time is extrapolated linearly in the pixel count."""
+    import oracle
+    log(f"cpu baseline: oracle, 1 view projection + {m} pixels")
+    rng = np.random.default_rng(0)
+    px = rng.integers(0, cam.width, m).astype(np.int32)
+    py = rng.integers(0, cam.height, m).astype(np.int32)
+    t0 = time.perf_counter()
+    proj = oracle.project(sc, cam, P)
+    t1 = time.perf_counter()
+    oracle.render(sc, cam, P, pixels=(px, py), proj=proj)
+    t2 = time.perf_counter()
+    frame = (t1 - t0) + (t2 - t1) * (cam.width * cam.height) / m
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"  projection {t1 - t0:.2f} s, {m} pixels {t2 - t1:.2f} s -> {1 / frame:.3g} frames/s")
+    return {"value": 1.0 / frame, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"1M-Gaussian projection of view 0 ({t1 - t0:.2f} s) + {m} random pixels ({t2 - t1:.2f} s), "
+                      f"frame time extrapolated to {cam.width * cam.height} pixels"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) Gaussian-splatting hot path of RadSplat
+ * (arXiv 2403.13806).
+ *
+ * The library renders a set of 3D Gaussians phi = {(p, k, s, o, q)} (Sec. 3.2)
+ * for pinhole cameras with front-to-back alpha compositing (eq. render-gs),
+ * computes the max-over-rays importance score used for pruning
+ * (eq. importance-score, Sec. 3.3), the per-camera-cluster visibility indicator
+ * lists used for test-time filtering (eq. importance-score-vis, Sec. 3.4), and the
+ * gradient of a rendered image with respect to every Gaussian parameter (the
+ * optimisation of phi in Sec. 3.2).
+ *
+ * Model (the paper inherits it from 3D Gaussian splatting and leaves these
+ * constants open; the values are the defaults of gs_params):
+ *   camera space      p_c = R p + t (x right, y down, z forward)
+ *   covariance        Sigma = R(q/|q|) diag(s)^2 R(q/|q|)^T
+ *   2D covariance     Sigma' = J R Sigma R^T J^T + lowpass * I, J the Jacobian
+ *                     of (fx x/z + cx, fy y/z + cy) at the mean
+ *   culling           z > znear, o >= alpha_min, |q| > 0, all finite, projected
+ *                     mean inside guard * (image half-size) of the image centre
+ *   support           pixel (px, py) is sampled at (px + 0.5, py + 0.5); with
+ *                     d = centre - mean2d, it is covered iff d^T Sigma'^-1 d <= q_max,
+ *                     q_max = min(kappa^2, 2 ln(o / alpha_min))
+ *   opacity           alpha = min(alpha_max, o exp(-d^T Sigma'^-1 d / 2))
+ *   colour            c = max(0, sum_{l<=deg,|m|<=l} k_lm Y_lm(dir) + 1/2), Y the
+ *                     real orthonormal SH basis (Condon-Shortley phase), dir the
+ *                     unit vector from the camera centre to the mean
+ *   order             covered Gaussians sorted by (FP32 camera z, index)
+ *   compositing       w_j = alpha_j T_j, T_j = prod_{k<j} (1 - alpha_k); the ray
+ *                     ends after the first entry that takes T below t_min (that
+ *                     entry is composited); C = sum_j w_j c_j + T_final * bg
+ * Tiles: a Gaussian is binned into every tile (tile_w x tile_h pixels) of the
+ * inclusive rectangle floor((u -/+ hx -/+ 2^-16) / tile_w) x floor((v -/+ hy -/+
+ * 2^-16) / tile_h) clamped to the grid, hx = sqrt(q_max Sigma'_xx),
+ * hy = sqrt(q_max Sigma'_yy): the exact bounding box of the support, so the image
+ * does not depend on the tile size.
+ *
+ * Conventions for every call:
+ *   - Pointers named in the argument structs are DEVICE pointers owned by the
+ *     caller; the library never allocates device memory. Scratch memory is a
+ *     caller-provided device workspace (gs_workspace_bytes).
+ *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued
+ *     asynchronously; no call synchronises the device.
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     returned as GS_ERR_INVALID_ARG / GS_ERR_UNSUPPORTED; a failed launch returns
+ *     GS_ERR_HIP. gs_last_error() gives a message for the calling thread.
+ *   - Pair-buffer overflow is detected on the device: gs_bin_sort writes the
+ *     number of pairs required to *bins->n_pairs and sets *bins->overflow to 1
+ *     when it exceeds bins->capacity. No write goes out of bounds; the results of
+ *     the later passes are then undefined and the caller must retry with a
+ *     larger capacity.
+ *   - Accumulating outputs (importance h, visibility bits, gradients) are
+ *     combined into what the buffer holds (max, OR, +=), so results over view
+ *     chunks compose; the caller initialises them.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG (-1)
+#define GS_ERR_CAPACITY (-2)
+#define GS_ERR_HIP (-3)
+#define GS_ERR_UNSUPPORTED (-4)
+
+/* Pinhole camera, world -> camera p_c = R p + t. 80 bytes. */
+typedef struct gs_camera {
+    float R[9]; /* row-major */
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height; /* pixels, >= 1 */
+    float znear;           /* near plane (camera z), > 0 */
+    int32_t reserved;      /* set to 0 */
+} gs_camera;
+
+/* Model constants (see the model above). Defaults: 0.3, 3, 1/255, 0.99, 1e-4, 1.3, {0,0,0}. */
+typedef struct gs_params {
+    float lowpass, kappa, alpha_min, alpha_max, t_min, guard;
+    float bg[3];
+} gs_params;
+
+/* Gaussian parameters, structure of arrays over n Gaussians (Sec. 3.2):
+ *   mean    [3][n]  position p
+ *   scale   [3][n]  linear scales s (> 0)
+ *   quat    [4][n]  rotation quaternion (w, x, y, z), any non-zero norm
+ *   opacity [n]     o in [0, 1]
+ *   sh      [(sh_degree+1)^2 * 3][n]; row (k*3 + c) = SH coefficient k (k = l*l+l+m)
+ *                   of colour channel c */
+typedef struct gs_gaussians {
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* sh;
+    int64_t n;
+    int32_t sh_degree; /* 0..3 */
+} gs_gaussians;
+
+/* Gradient buffers, same layout as gs_gaussians; the library adds into them. */
+typedef struct gs_gaussians_grad {
+    float* mean;
+    float* scale;
+    float* quat;
+    float* opacity;
+    float* sh;
+    int64_t n;
+    int32_t sh_degree;
+} gs_gaussians_grad;
+
+/* Projected Gaussian, 64 bytes, one per (view, Gaussian): everything a compositing
+ * pass needs. Conic (ca, cb, cc) = inverse of Sigma' as [[ca, cb], [cb, cc]]. */
+typedef struct gs_splat {
+    double u, v;
+    double ca, cb, cc;
+    double qmax;
+    float opacity;
+    float rgb[3];
+} gs_splat;
+
+/* A batch of views rendered together: views are laid out one after another in a
+ * global tile space and a global pixel space.
+ *   tile_offset[v]  first global tile of view v; tile_offset[n_views] = n_tiles.
+ *                   View v has ceil(W/tile_w) * ceil(H/tile_h) tiles, row-major.
+ *   pixel_offset[v] first global pixel of view v; pixel_offset[n_views] = n_pixels.
+ * Image buffers: rgb is [3 * n_pixels] with view v's planar [3][H][W] image at
+ * 3 * pixel_offset[v]; per-pixel buffers (t_final, n_last) are [n_pixels] with view
+ * v's [H][W] at pixel_offset[v]. gs_view_layout fills both offset tables on the host. */
+typedef struct gs_views {
+    const gs_camera* cams;       /* device [n_views] */
+    const int32_t* tile_offset;  /* device [n_views + 1] */
+    const int64_t* pixel_offset; /* device [n_views + 1] */
+    int32_t n_views;
+    int32_t tile_w, tile_h;      /* 8, 16 or 32 each; tile_w * tile_h in {64, 128, 256} */
+    int32_t n_tiles;
+    int64_t n_pixels;
+} gs_views;
+
+/* Per-(view, Gaussian) outputs of gs_preprocess, [n_views][n] each:
+ *   splat  records (written only where count > 0)
+ *   depth  FP32 camera z (the depth key)
+ *   rect   tile rectangle packed as tx0 | ty0 << 16 | tx1 << 32 | ty1 << 48 (inclusive)
+ *   count  number of tiles in rect; 0 when the Gaussian is culled or off-screen */
+typedef struct gs_projected {
+    gs_splat* splat;
+    float* depth;
+    uint64_t* rect;
+    uint32_t* count;
+    int64_t n; /* entries per view */
+} gs_projected;
+
+/* Binned (tile, depth, index) pairs sorted by key then value, and per-tile ranges.
+ *   keys    [capacity] key = global tile << 32 | bits(FP32 depth)
+ *   vals    [capacity] index of the Gaussian within its view (0 .. n-1)
+ *   ranges  [n_tiles][2] [start, end) of each tile in keys/vals
+ *   n_pairs device scalar: pairs required
+ *   overflow device scalar: 1 if n_pairs > capacity, else 0 */
+typedef struct gs_bins {
+    uint64_t* keys;
+    uint32_t* vals;
+    uint32_t* ranges;
+    uint64_t capacity; /* < 2^32 */
+    uint64_t* n_pairs;
+    uint32_t* overflow;
+} gs_bins;
+
+/* Host helper: fill tile_offset[n_views+1] and pixel_offset[n_views+1] (HOST arrays)
+ * for host cameras cams[n_views] and a tile size; returns GS_ERR_INVALID_ARG for bad
+ * sizes or a total tile count >= 2^31. */
+gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w, int32_t tile_h,
+                         int32_t* tile_offset, int64_t* pixel_offset);
+
+/* Device workspace bytes needed by gs_bin_sort / gs_render_bwd / gs_bits_to_list for n
+ * entries per view, n_views views, a pair capacity and n_tiles tiles. */
+size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
+
+/* Project every Gaussian (or the listed subset) into every view of `views` (Sec. 3.2:
+ * Sigma = R S S^T R^T, Sigma' = J M Sigma M^T J^T), evaluate its SH colour for the
+ * view direction (skipped when want_color == 0, rgb is then 0), its FP32 depth key and
+ * its tile rectangle. subset: device [n_subset] Gaussian indices in increasing order, or
+ * NULL for all; out->n must equal n_subset (or g->n). Entry j of each view refers to
+ * Gaussian subset[j] (or j). */
+gs_status gs_preprocess(const gs_gaussians* g, const gs_views* views, const gs_params* p, const int32_t* subset,
+                        int64_t n_subset, int32_t want_color, gs_projected* out, void* stream);
+
+/* Bin projected Gaussians into tiles and sort the pairs by (tile, depth, index) (the
+ * "correctly-sorted points" of eq. render-gs, per tile): exclusive scan of the
+ * per-Gaussian tile counts, key emission, LSD radix sort on the significant key bits,
+ * per-tile ranges. ws: device workspace of at least
+ * gs_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles). */
+gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Front-to-back compositing of every pixel of every view (eq. render-gs). Writes rgb
+ * [3 * n_pixels], t_final [n_pixels] (transmittance after the last composited entry)
+ * and n_last [n_pixels] (1 + position in keys/vals of the pixel's last composited
+ * entry, or its tile's range start when none); t_final and n_last are what
+ * gs_render_bwd needs. n_contrib (device [n_pixels], or NULL) receives the number of
+ * Gaussians composited into each pixel. */
+gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                        float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, void* stream);
+
+/* L1 photometric loss of a rendered batch against a target (the per-view training loss
+ * whose gradient drives gs_render_bwd): dl_drgb[i] = sign(rgb[i] - target[i]) * scale
+ * (sign(0) = 0) for i < n, and *loss_accum += scale * sum |rgb - target| (device scalar).
+ * scale is usually 1 / n (mean reduction). */
+gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, float scale, float* dl_drgb,
+                          float* loss_accum, void* stream);
+
+/* Gradient of L with respect to the Gaussian parameters given dL/d(rgb) (layout of
+ * rgb), accumulated (+=) into grad. Reverse traversal per pixel from n_last; the
+ * transmittance before each entry is recovered from t_final by division. proj must
+ * come from gs_preprocess with want_color = 1 and no subset. ws as for gs_bin_sort. */
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_projected* proj,
+                        const gs_bins* bins, const gs_params* p, const float* t_final, const uint32_t* n_last,
+                        const float* dl_drgb, gs_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Importance score (eq. importance-score): h[i] = max(h[i], max over the batch's pixels
+ * of the weight alpha*T with which Gaussian i is composited). h_accum: device [n]
+ * (n = proj->n; indices are view-entry indices, i.e. Gaussian indices without a
+ * subset). The prune mask of Sec. 3.3 is h < t_prune. */
+gs_status gs_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                        float* h_accum, void* stream);
+
+/* Cluster visibility (eq. importance-score-vis): for each view v with cluster
+ * c = view_cluster[v] (device [n_views], 0 <= c < k), set bit i of row c of bits_accum
+ * (device [k][ceil(n/32)] uint32, bit i%32 of word i/32) when Gaussian i is composited
+ * with weight alpha*T > t_cluster in some pixel of v (that is, the per-cluster max
+ * exceeds t_cluster). Bits are OR-ed into the buffer. */
+gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                                const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
+                                uint32_t* bits_accum, void* stream);
+
+/* Visibility-list compaction (Sec. 3.4, list-based rendering): write the indices of the
+ * set bits of bits_row (device [ceil(n/32)]) in increasing order to list (device [n]) and
+ * their number to *count (device int64). ws: at least gs_workspace_bytes(n, 1, 0, 0). */
+gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, int64_t* count, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
+ * iterations from a k-means++ seeding with the given seed, at most max_iter iterations
+ * or until assignments stop changing; ties go to the lowest centre; an empty cluster is
+ * re-seeded at the point farthest from its centre. pos: host [m][3]; centres: host
+ * [k][3]; assign: host [m]. */
+gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int32_t max_iter, double* centres,
+                    int32_t* assign);
+
+/* Host: index of the centre nearest to x (squared distance, ties to the lowest index),
+ * the cluster whose list renders a test view (Sec. 3.4). */
+int32_t gs_nearest_centre(const double* centres, int32_t k, const double* x);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

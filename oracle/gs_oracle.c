@@ -212,7 +212,6 @@ void or_project(const double* mean, const double* scale, const double* quat, con
         for (int k = 0; k < 3; ++k) finite &= isfinite(p[k]) && isfinite(s[k]);
         for (int k = 0; k < 4; ++k) finite &= isfinite(q[k]);
         finite &= isfinite(op);
-        for (int k = 0; k < nb * 3; ++k) finite &= isfinite(sh[(int64_t)k * n + i]);
         if (!finite) continue;
         double x = (((R[0] * p[0]) + (R[1] * p[1])) + (R[2] * p[2])) + t[0];
         double y = (((R[3] * p[0]) + (R[4] * p[1])) + (R[5] * p[2])) + t[1];

@@ -1,0 +1,356 @@
+// C ABI entry points (include/gs.h): argument checking, workspace layout and launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+static thread_local char g_err[512] = "";
+
+gs_status set_error(gs_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+gs_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return GS_OK;
+}
+
+// launchers defined next to their kernels
+gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_params*, const int32_t*, int64_t, int,
+                            gs_projected*, hipStream_t);
+gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
+                                const float*, gs_gaussians_grad*, hipStream_t);
+gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t);
+size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity);
+size_t list_workspace_bytes(int64_t n);
+gs_status launch_bits_to_list(const uint32_t*, int64_t, int32_t*, int64_t*, void*, hipStream_t);
+gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
+gs_status launch_render_fwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*, float*,
+                            uint32_t*, uint32_t*, hipStream_t);
+gs_status launch_l1(const float*, const float*, int64_t, float, float*, float*, hipStream_t);
+gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
+                            hipStream_t);
+gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
+                            float, uint32_t*, hipStream_t);
+gs_status launch_render_bwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const float*,
+                            const uint32_t*, const float*, float*, hipStream_t);
+
+static size_t bwd_workspace_bytes(int64_t n, int32_t n_views) {
+    return sizeof(float) * 9 * (size_t)n * (size_t)n_views;
+}
+
+static bool tile_ok(int tw, int th) {
+    auto ok = [](int x) { return x == 8 || x == 16 || x == 32; };
+    return ok(tw) && ok(th) && tw * th <= 256;
+}
+
+static gs_status check_views(const gs_views* v) {
+    if (!v) return set_error(GS_ERR_INVALID_ARG, "views is NULL");
+    if (v->n_views < 1) return set_error(GS_ERR_INVALID_ARG, "n_views must be >= 1 (got %d)", v->n_views);
+    if (v->n_views > 65535) return set_error(GS_ERR_UNSUPPORTED, "at most 65535 views per call (got %d)", v->n_views);
+    if (!v->cams || !v->tile_offset || !v->pixel_offset)
+        return set_error(GS_ERR_INVALID_ARG, "views has a NULL device table");
+    if (!tile_ok(v->tile_w, v->tile_h))
+        return set_error(GS_ERR_UNSUPPORTED, "tile %dx%d: each side must be 8, 16 or 32 and the area <= 256",
+                         v->tile_w, v->tile_h);
+    if (v->n_tiles < 0 || v->n_pixels < 0) return set_error(GS_ERR_INVALID_ARG, "negative tile or pixel count");
+    return GS_OK;
+}
+
+static gs_status check_params(const gs_params* p) {
+    if (!p) return set_error(GS_ERR_INVALID_ARG, "params is NULL");
+    if (!(p->alpha_min > 0.f) || !(p->alpha_max > 0.f) || !(p->alpha_max < 1.f) || !(p->t_min >= 0.f) ||
+        !(p->kappa > 0.f) || !(p->lowpass >= 0.f) || !(p->guard > 0.f))
+        return set_error(GS_ERR_INVALID_ARG, "params out of range (need alpha_min > 0, 0 < alpha_max < 1, "
+                                             "t_min >= 0, kappa > 0, lowpass >= 0, guard > 0)");
+    return GS_OK;
+}
+
+static gs_status check_gaussians(const gs_gaussians* g) {
+    if (!g) return set_error(GS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0) return set_error(GS_ERR_INVALID_ARG, "negative Gaussian count");
+    if (g->n >= (int64_t)1 << 31) return set_error(GS_ERR_UNSUPPORTED, "at most 2^31-1 Gaussians");
+    if (g->sh_degree < 0 || g->sh_degree > 3)
+        return set_error(GS_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity))
+        return set_error(GS_ERR_INVALID_ARG, "Gaussian parameter pointer is NULL");
+    return GS_OK;
+}
+
+static gs_status check_projected(const gs_projected* p, bool need_splat) {
+    if (!p) return set_error(GS_ERR_INVALID_ARG, "projected is NULL");
+    if (p->n < 0) return set_error(GS_ERR_INVALID_ARG, "negative entry count");
+    if (p->n > 0 && (!p->count || !p->rect || !p->depth || (need_splat && !p->splat)))
+        return set_error(GS_ERR_INVALID_ARG, "projected buffer pointer is NULL");
+    return GS_OK;
+}
+
+static gs_status check_bins(const gs_bins* b) {
+    if (!b) return set_error(GS_ERR_INVALID_ARG, "bins is NULL");
+    if (!b->ranges || !b->n_pairs || !b->overflow || (b->capacity > 0 && (!b->keys || !b->vals)))
+        return set_error(GS_ERR_INVALID_ARG, "bins buffer pointer is NULL");
+    if (b->capacity >= ((uint64_t)1 << 32)) return set_error(GS_ERR_UNSUPPORTED, "capacity must be < 2^32");
+    return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_err; }
+
+gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w, int32_t tile_h,
+                         int32_t* tile_offset, int64_t* pixel_offset) {
+    if (!cams || !tile_offset || !pixel_offset || n_views < 1)
+        return set_error(GS_ERR_INVALID_ARG, "gs_view_layout: NULL table or n_views < 1");
+    if (!tile_ok(tile_w, tile_h)) return set_error(GS_ERR_UNSUPPORTED, "gs_view_layout: unsupported tile size");
+    int64_t tiles = 0, pix = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int W = cams[v].width, H = cams[v].height;
+        if (W < 1 || H < 1 || W > 65535 * 8 || H > 65535 * 8)
+            return set_error(GS_ERR_INVALID_ARG, "view %d: bad size %dx%d", v, W, H);
+        tile_offset[v] = (int32_t)tiles;
+        pixel_offset[v] = pix;
+        tiles += (int64_t)div_up(W, tile_w) * div_up(H, tile_h);
+        pix += (int64_t)W * H;
+        if (tiles >= ((int64_t)1 << 31)) return set_error(GS_ERR_UNSUPPORTED, "more than 2^31 tiles in a batch");
+    }
+    tile_offset[n_views] = (int32_t)tiles;
+    pixel_offset[n_views] = pix;
+    return GS_OK;
+}
+
+size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
+    (void)n_tiles;
+    if (n < 0 || n_views < 0) return 0;
+    size_t b = sort_workspace_bytes(n, n_views, capacity);
+    b = std::max(b, bwd_workspace_bytes(n, n_views));
+    b = std::max(b, list_workspace_bytes(n));
+    return b;
+}
+
+gs_status gs_preprocess(const gs_gaussians* g, const gs_views* views, const gs_params* p, const int32_t* subset,
+                        int64_t n_subset, int32_t want_color, gs_projected* out, void* stream) {
+    gs_status st;
+    if ((st = check_gaussians(g)) || (st = check_views(views)) || (st = check_params(p)) ||
+        (st = check_projected(out, true)))
+        return st;
+    const int64_t n = subset ? n_subset : g->n;
+    if (subset && (n_subset < 0 || n_subset > g->n))
+        return set_error(GS_ERR_INVALID_ARG, "n_subset %lld outside [0, %lld]", (long long)n_subset, (long long)g->n);
+    if (out->n != n)
+        return set_error(GS_ERR_INVALID_ARG, "projected->n = %lld but %lld entries per view are produced",
+                         (long long)out->n, (long long)n);
+    if (want_color && g->n > 0 && !g->sh) return set_error(GS_ERR_INVALID_ARG, "sh is NULL with want_color");
+    return launch_preprocess(g, views, p, subset, n, want_color, out, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws, size_t ws_bytes,
+                      void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, false)) || (st = check_views(views)) || (st = check_bins(bins))) return st;
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);
+}
+
+gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                        float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if (views->n_pixels > 0 && (!rgb || !t_final || !n_last))
+        return set_error(GS_ERR_INVALID_ARG, "output image pointer is NULL");
+    return launch_render_fwd(proj, views, bins, p, rgb, t_final, n_last, n_contrib, (hipStream_t)stream);
+}
+
+gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, float scale, float* dl_drgb,
+                          float* loss_accum, void* stream) {
+    if (n < 0 || (n > 0 && (!rgb || !target || !dl_drgb)))
+        return set_error(GS_ERR_INVALID_ARG, "gs_l1_loss_grad: bad arguments");
+    return launch_l1(rgb, target, n, scale, dl_drgb, loss_accum, (hipStream_t)stream);
+}
+
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_projected* proj, const gs_bins* bins,
+                        const gs_params* p, const float* t_final, const uint32_t* n_last, const float* dl_drgb,
+                        gs_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream) {
+    gs_status st;
+    if ((st = check_gaussians(g)) || (st = check_views(views)) || (st = check_projected(proj, true)) ||
+        (st = check_bins(bins)) || (st = check_params(p)))
+        return st;
+    if (!grad || grad->n != g->n || grad->sh_degree != g->sh_degree)
+        return set_error(GS_ERR_INVALID_ARG, "grad buffers missing or shaped unlike the Gaussians");
+    if (g->n > 0 && (!grad->mean || !grad->scale || !grad->quat || !grad->opacity || !grad->sh || !g->sh))
+        return set_error(GS_ERR_INVALID_ARG, "gradient or SH pointer is NULL");
+    if (proj->n != g->n)
+        return set_error(GS_ERR_INVALID_ARG, "backward needs a projection of all Gaussians (no subset)");
+    if (views->n_pixels > 0 && (!t_final || !n_last || !dl_drgb))
+        return set_error(GS_ERR_INVALID_ARG, "t_final, n_last or dl_drgb is NULL");
+    const size_t need = bwd_workspace_bytes(g->n, views->n_views);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    float* g2 = (float*)ws;
+    if ((st = launch_fill_f32(g2, 9 * g->n * (int64_t)views->n_views, 0.f, s))) return st;
+    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, g2, s))) return st;
+    return launch_preprocess_bwd(g, views, p, proj, g2, grad, s);
+}
+
+gs_status gs_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                        float* h_accum, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if (proj->n > 0 && !h_accum) return set_error(GS_ERR_INVALID_ARG, "h_accum is NULL");
+    return launch_importance(proj, views, bins, p, h_accum, (hipStream_t)stream);
+}
+
+gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                                const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
+                                uint32_t* bits_accum, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if (k < 1) return set_error(GS_ERR_INVALID_ARG, "k must be >= 1 (got %d)", k);
+    if (!view_cluster || (proj->n > 0 && !bits_accum))
+        return set_error(GS_ERR_INVALID_ARG, "view_cluster or bits_accum is NULL");
+    if (!(t_cluster >= 0.f)) return set_error(GS_ERR_INVALID_ARG, "t_cluster must be >= 0");
+    return launch_visibility(proj, views, bins, p, view_cluster, t_cluster, bits_accum, (hipStream_t)stream);
+}
+
+gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, int64_t* count, void* ws,
+                          size_t ws_bytes, void* stream) {
+    if (n < 0 || !count || (n > 0 && (!bits_row || !list)))
+        return set_error(GS_ERR_INVALID_ARG, "gs_bits_to_list: bad arguments");
+    const size_t need = list_workspace_bytes(n);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    return launch_bits_to_list(bits_row, n, list, count, ws, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// camera clustering on the host (a few hundred points; no device work)
+// ---------------------------------------------------------------------------------------
+static uint64_t splitmix64(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static double uniform01(uint64_t& s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+static double d2(const double* a, const double* b) {
+    const double x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
+    return x * x + y * y + z * z;
+}
+
+int32_t gs_nearest_centre(const double* centres, int32_t k, const double* x) {
+    if (!centres || !x || k < 1) return -1;
+    int32_t best = 0;
+    double bd = d2(centres, x);
+    for (int32_t c = 1; c < k; ++c) {
+        const double d = d2(centres + 3 * c, x);
+        if (d < bd) {
+            bd = d;
+            best = c;
+        }
+    }
+    return best;
+}
+
+gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int32_t max_iter, double* centres,
+                    int32_t* assign) {
+    if (!pos || !centres || !assign || m < 1 || k < 1 || k > m || max_iter < 0)
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans: need 1 <= k <= m and non-NULL buffers");
+    uint64_t s = seed;
+    // k-means++ seeding
+    std::vector<double> dist(m);
+    int32_t first = (int32_t)(splitmix64(s) % (uint64_t)m);
+    for (int e = 0; e < 3; ++e) centres[e] = pos[3 * first + e];
+    for (int32_t i = 0; i < m; ++i) dist[i] = d2(pos + 3 * i, centres);
+    for (int32_t c = 1; c < k; ++c) {
+        double tot = 0;
+        for (int32_t i = 0; i < m; ++i) tot += dist[i];
+        int32_t pick = m - 1;
+        if (tot > 0) {
+            const double r = uniform01(s) * tot;
+            double acc = 0;
+            for (int32_t i = 0; i < m; ++i) {
+                acc += dist[i];
+                if (acc > r) {
+                    pick = i;
+                    break;
+                }
+            }
+        } else {
+            pick = (int32_t)(splitmix64(s) % (uint64_t)m);
+        }
+        for (int e = 0; e < 3; ++e) centres[3 * c + e] = pos[3 * pick + e];
+        for (int32_t i = 0; i < m; ++i) dist[i] = std::min(dist[i], d2(pos + 3 * i, centres + 3 * c));
+    }
+    // Lloyd iterations
+    for (int32_t i = 0; i < m; ++i) assign[i] = -1;
+    std::vector<double> sum(3 * (size_t)k);
+    std::vector<int32_t> cnt(k);
+    for (int32_t it = 0; it < std::max(1, max_iter); ++it) {
+        bool changed = false;
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t c = gs_nearest_centre(centres, k, pos + 3 * i);
+            if (c != assign[i]) {
+                assign[i] = c;
+                changed = true;
+            }
+        }
+        if (!changed && it > 0) break;
+        std::fill(sum.begin(), sum.end(), 0.0);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t c = assign[i];
+            for (int e = 0; e < 3; ++e) sum[3 * c + e] += pos[3 * i + e];
+            cnt[c]++;
+        }
+        for (int32_t c = 0; c < k; ++c) {
+            if (cnt[c] > 0) {
+                for (int e = 0; e < 3; ++e) centres[3 * c + e] = sum[3 * c + e] / cnt[c];
+            } else {
+                // empty cluster: re-seed at the point farthest from its assigned centre
+                int32_t far = 0;
+                double fd = -1;
+                for (int32_t i = 0; i < m; ++i) {
+                    const double d = d2(pos + 3 * i, centres + 3 * assign[i]);
+                    if (d > fd) {
+                        fd = d;
+                        far = i;
+                    }
+                }
+                for (int e = 0; e < 3; ++e) centres[3 * c + e] = pos[3 * far + e];
+            }
+        }
+        if (it + 1 >= max_iter) {
+            for (int32_t i = 0; i < m; ++i) assign[i] = gs_nearest_centre(centres, k, pos + 3 * i);
+            break;
+        }
+    }
+    return GS_OK;
+}
+
+}  // extern "C"

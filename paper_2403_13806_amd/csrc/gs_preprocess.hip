@@ -1,0 +1,496 @@
+// Projection of 3D Gaussians into pinhole views (Sec. 3.2: Sigma = R S S^T R^T,
+// Sigma' = J M Sigma M^T J^T) and its reverse-mode derivative.
+//
+// One thread per (view, Gaussian). Everything that decides a key or a pixel's support
+// (camera-space mean, projected mean, 2D covariance, conic, support radius, tile
+// rectangle) is computed in FP64: on CDNA4 an FP64 FMA issues at the same rate as an
+// unpacked FP32 one, and FP64 geometry makes the tile keys reproducible bit for bit.
+// Contraction into FMAs is switched off for that part so every operation is the
+// correctly rounded IEEE operation in the stated order. SH colour is FP32.
+#include <math.h>
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+// ---------------------------------------------------------------------------------------
+// Real SH basis up to degree 3 (orthonormal, Condon-Shortley phase), index l*l + l + m,
+// written as polynomials in the unit direction (x, y, z):
+//   C0 = 1/(2 sqrt(pi)), C1 = sqrt(3/(4 pi)), C2a = sqrt(15/(4 pi)), C2b = sqrt(5/(16 pi)),
+//   C2c = sqrt(15/(16 pi)), C3a = sqrt(35/(32 pi)), C3b = sqrt(105/(4 pi)),
+//   C3c = sqrt(21/(32 pi)), C3d = sqrt(7/(16 pi)), C3e = sqrt(105/(16 pi)).
+// ---------------------------------------------------------------------------------------
+#define SH_C0 0.28209479177387814f
+#define SH_C1 0.4886025119029199f
+#define SH_C2A 1.0925484305920792f
+#define SH_C2B 0.31539156525252005f
+#define SH_C2C 0.5462742152960396f
+#define SH_C3A 0.5900435899266435f
+#define SH_C3B 2.890611442640554f
+#define SH_C3C 0.4570457994644658f
+#define SH_C3D 0.3731763325901154f
+#define SH_C3E 1.445305721320277f
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float Y[16]) {
+    Y[0] = SH_C0;
+    if (deg < 1) return;
+    Y[1] = -SH_C1 * y;
+    Y[2] = SH_C1 * z;
+    Y[3] = -SH_C1 * x;
+    if (deg < 2) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = SH_C2A * x * y;
+    Y[5] = -SH_C2A * y * z;
+    Y[6] = SH_C2B * (3.f * zz - 1.f);
+    Y[7] = -SH_C2A * x * z;
+    Y[8] = SH_C2C * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -SH_C3A * y * (3.f * xx - yy);
+    Y[10] = SH_C3B * x * y * z;
+    Y[11] = -SH_C3C * y * (5.f * zz - 1.f);
+    Y[12] = SH_C3D * z * (5.f * zz - 3.f);
+    Y[13] = -SH_C3C * x * (5.f * zz - 1.f);
+    Y[14] = SH_C3E * z * (xx - yy);
+    Y[15] = -SH_C3A * x * (xx - 3.f * yy);
+}
+
+// gradient of each basis polynomial above with respect to (x, y, z)
+__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, float G[16][3]) {
+    G[0][0] = G[0][1] = G[0][2] = 0.f;
+    if (deg < 1) return;
+    G[1][0] = 0.f; G[1][1] = -SH_C1; G[1][2] = 0.f;
+    G[2][0] = 0.f; G[2][1] = 0.f; G[2][2] = SH_C1;
+    G[3][0] = -SH_C1; G[3][1] = 0.f; G[3][2] = 0.f;
+    if (deg < 2) return;
+    G[4][0] = SH_C2A * y; G[4][1] = SH_C2A * x; G[4][2] = 0.f;
+    G[5][0] = 0.f; G[5][1] = -SH_C2A * z; G[5][2] = -SH_C2A * y;
+    G[6][0] = 0.f; G[6][1] = 0.f; G[6][2] = SH_C2B * 6.f * z;
+    G[7][0] = -SH_C2A * z; G[7][1] = 0.f; G[7][2] = -SH_C2A * x;
+    G[8][0] = SH_C2C * 2.f * x; G[8][1] = -SH_C2C * 2.f * y; G[8][2] = 0.f;
+    if (deg < 3) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    G[9][0] = -SH_C3A * 6.f * x * y; G[9][1] = -SH_C3A * (3.f * xx - 3.f * yy); G[9][2] = 0.f;
+    G[10][0] = SH_C3B * y * z; G[10][1] = SH_C3B * x * z; G[10][2] = SH_C3B * x * y;
+    G[11][0] = 0.f; G[11][1] = -SH_C3C * (5.f * zz - 1.f); G[11][2] = -SH_C3C * 10.f * y * z;
+    G[12][0] = 0.f; G[12][1] = 0.f; G[12][2] = SH_C3D * (15.f * zz - 3.f);
+    G[13][0] = -SH_C3C * (5.f * zz - 1.f); G[13][1] = 0.f; G[13][2] = -SH_C3C * 10.f * x * z;
+    G[14][0] = SH_C3E * 2.f * x * z; G[14][1] = -SH_C3E * 2.f * y * z; G[14][2] = SH_C3E * (xx - yy);
+    G[15][0] = -SH_C3A * (3.f * xx - 3.f * yy); G[15][1] = SH_C3A * 6.f * x * y; G[15][2] = 0.f;
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 projection of one Gaussian into one camera.
+// ---------------------------------------------------------------------------------------
+struct Proj {
+    double x, y, z;      // camera-space mean
+    double u, v;         // projected mean
+    double qn;           // |q|
+    double qh[4];        // q / |q|
+    double Rq[3][3];     // rotation of the Gaussian
+    double Sg[3][3];     // 3D covariance
+    double T[2][3];      // J R
+    double sxx, sxy, syy;
+    double det;
+    double qmax, hx, hy;
+};
+
+// Returns false when the Gaussian is culled. The operation order below is part of the
+// tile-key definition; do not reassociate.
+__device__ bool project_one(const gs_camera& cam, const gs_params& p, const float* __restrict__ mean,
+                            const float* __restrict__ scale, const float* __restrict__ quat,
+                            const float* __restrict__ opac, int64_t n_all, int64_t i, Proj& P, double& o) {
+#pragma clang fp contract(off)
+    const double p0 = mean[i], p1 = mean[n_all + i], p2 = mean[2 * n_all + i];
+    const double s0 = scale[i], s1 = scale[n_all + i], s2 = scale[2 * n_all + i];
+    const double q0 = quat[i], q1 = quat[n_all + i], q2 = quat[2 * n_all + i], q3 = quat[3 * n_all + i];
+    o = opac[i];
+    if (!(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
+          isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) && isfinite(o)))
+        return false;
+    const double R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5],
+                 R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
+    P.x = (((R0 * p0) + (R1 * p1)) + (R2 * p2)) + (double)cam.t[0];
+    P.y = (((R3 * p0) + (R4 * p1)) + (R5 * p2)) + (double)cam.t[1];
+    P.z = (((R6 * p0) + (R7 * p1)) + (R8 * p2)) + (double)cam.t[2];
+    if (!(P.z > (double)cam.znear)) return false;
+    if (!(o >= (double)p.alpha_min)) return false;
+    const double fx = cam.fx, fy = cam.fy;
+    P.u = ((fx * P.x) / P.z) + (double)cam.cx;
+    P.v = ((fy * P.y) / P.z) + (double)cam.cy;
+    const double hw = 0.5 * (double)cam.width, hh = 0.5 * (double)cam.height;
+    const double guard = p.guard;
+    if (!(fabs(P.u - hw) <= guard * hw)) return false;
+    if (!(fabs(P.v - hh) <= guard * hh)) return false;
+    P.qn = sqrt((((q0 * q0) + (q1 * q1)) + (q2 * q2)) + (q3 * q3));
+    if (!(P.qn > 0.0)) return false;
+    const double w = q0 / P.qn, x = q1 / P.qn, y = q2 / P.qn, z = q3 / P.qn;
+    P.qh[0] = w; P.qh[1] = x; P.qh[2] = y; P.qh[3] = z;
+    P.Rq[0][0] = 1.0 - 2.0 * ((y * y) + (z * z));
+    P.Rq[0][1] = 2.0 * ((x * y) - (w * z));
+    P.Rq[0][2] = 2.0 * ((x * z) + (w * y));
+    P.Rq[1][0] = 2.0 * ((x * y) + (w * z));
+    P.Rq[1][1] = 1.0 - 2.0 * ((x * x) + (z * z));
+    P.Rq[1][2] = 2.0 * ((y * z) - (w * x));
+    P.Rq[2][0] = 2.0 * ((x * z) - (w * y));
+    P.Rq[2][1] = 2.0 * ((y * z) + (w * x));
+    P.Rq[2][2] = 1.0 - 2.0 * ((x * x) + (y * y));
+    const double ss[3] = {s0 * s0, s1 * s1, s2 * s2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            P.Sg[a][b] = (((P.Rq[a][0] * ss[0]) * P.Rq[b][0]) + ((P.Rq[a][1] * ss[1]) * P.Rq[b][1])) +
+                         ((P.Rq[a][2] * ss[2]) * P.Rq[b][2]);
+    const double J00 = fx / P.z, J02 = -((fx * P.x) / (P.z * P.z));
+    const double J11 = fy / P.z, J12 = -((fy * P.y) / (P.z * P.z));
+    const double Rc[9] = {R0, R1, R2, R3, R4, R5, R6, R7, R8};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.T[0][k] = (J00 * Rc[0 * 3 + k]) + (J02 * Rc[2 * 3 + k]);
+        P.T[1][k] = (J11 * Rc[1 * 3 + k]) + (J12 * Rc[2 * 3 + k]);
+    }
+    double M[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            M[a][l] = ((P.T[a][0] * P.Sg[0][l]) + (P.T[a][1] * P.Sg[1][l])) + (P.T[a][2] * P.Sg[2][l]);
+    const double S00 = ((M[0][0] * P.T[0][0]) + (M[0][1] * P.T[0][1])) + (M[0][2] * P.T[0][2]);
+    const double S01 = ((M[0][0] * P.T[1][0]) + (M[0][1] * P.T[1][1])) + (M[0][2] * P.T[1][2]);
+    const double S11 = ((M[1][0] * P.T[1][0]) + (M[1][1] * P.T[1][1])) + (M[1][2] * P.T[1][2]);
+    const double lp = p.lowpass;
+    P.sxx = S00 + lp;
+    P.syy = S11 + lp;
+    P.sxy = S01;
+    P.det = (P.sxx * P.syy) - (P.sxy * P.sxy);
+    if (!(P.det > 0.0)) return false;
+    const double kappa = p.kappa;
+    P.qmax = kappa * kappa;
+    const double ql = 2.0 * log(o / (double)p.alpha_min);
+    if (ql < P.qmax) P.qmax = ql;
+    P.hx = sqrt(P.qmax * P.sxx);
+    P.hy = sqrt(P.qmax * P.syy);
+    return true;
+}
+
+// unit direction (world) from the camera centre C = -R^T t to the mean, and |mean - C|
+__device__ __forceinline__ void view_dir(const gs_camera& cam, double p0, double p1, double p2, float d[3],
+                                         double& len) {
+    double C[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        C[k] = -((((double)cam.R[0 * 3 + k] * cam.t[0]) + ((double)cam.R[1 * 3 + k] * cam.t[1])) +
+                 ((double)cam.R[2 * 3 + k] * cam.t[2]));
+    const double a = p0 - C[0], b = p1 - C[1], c = p2 - C[2];
+    len = sqrt(a * a + b * b + c * c);
+    d[0] = (float)(a / len);
+    d[1] = (float)(b / len);
+    d[2] = (float)(c / len);
+}
+
+struct PreArgs {
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opac;
+    const float* sh;
+    int64_t n_all;
+    int deg;
+    const gs_camera* cams;
+    gs_params p;
+    int tile_w, tile_h;
+    const int32_t* subset;
+    int64_t n;
+    int want_color;
+    gs_splat* splat;
+    float* depth;
+    uint64_t* rect;
+    uint32_t* count;
+};
+
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t i = a.subset ? (int64_t)a.subset[j] : j;
+    const int64_t o = (int64_t)v * a.n + j;
+    if (i < 0 || i >= a.n_all) {  // a subset index outside the scene selects nothing
+        a.count[o] = 0u;
+        return;
+    }
+    const gs_camera cam = a.cams[v];
+    Proj P;
+    double op;
+    if (!project_one(cam, a.p, a.mean, a.scale, a.quat, a.opac, a.n_all, i, P, op)) {
+        a.count[o] = 0u;
+        return;
+    }
+    // tile rectangle of the support's bounding box, widened by 2^-16 px
+    double rx0, rx1, ry0, ry1;
+    {
+#pragma clang fp contract(off)
+        const double eps = 1.0 / 65536.0;
+        const double tw = a.tile_w, th = a.tile_h;
+        rx0 = floor(((P.u - P.hx) - eps) / tw);
+        rx1 = floor(((P.u + P.hx) + eps) / tw);
+        ry0 = floor(((P.v - P.hy) - eps) / th);
+        ry1 = floor(((P.v + P.hy) + eps) / th);
+    }
+    const int tiles_x = div_up(cam.width, a.tile_w), tiles_y = div_up(cam.height, a.tile_h);
+    rx0 = fmax(rx0, 0.0);
+    ry0 = fmax(ry0, 0.0);
+    rx1 = fmin(rx1, (double)(tiles_x - 1));
+    ry1 = fmin(ry1, (double)(tiles_y - 1));
+    uint32_t cnt = 0;
+    if (rx1 >= rx0 && ry1 >= ry0) cnt = (uint32_t)((rx1 - rx0 + 1.0) * (ry1 - ry0 + 1.0));
+    a.count[o] = cnt;
+    if (cnt == 0) return;
+    a.depth[o] = (float)P.z;
+    a.rect[o] = (uint64_t)(uint32_t)rx0 | ((uint64_t)(uint32_t)ry0 << 16) | ((uint64_t)(uint32_t)rx1 << 32) |
+                ((uint64_t)(uint32_t)ry1 << 48);
+    float rgb[3] = {0.f, 0.f, 0.f};
+    if (a.want_color) {
+        float d[3];
+        double len;
+        view_dir(cam, a.mean[i], a.mean[a.n_all + i], a.mean[2 * a.n_all + i], d, len);
+        float Y[16];
+        sh_basis(a.deg, d[0], d[1], d[2], Y);
+        const int nb = (a.deg + 1) * (a.deg + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.f;
+            for (int k = 0; k < nb; ++k) acc += a.sh[(int64_t)(k * 3 + c) * a.n_all + i] * Y[k];
+            rgb[c] = fmaxf(acc + 0.5f, 0.f);
+        }
+    }
+    gs_splat s;
+    s.u = P.u;
+    s.v = P.v;
+    s.ca = P.syy / P.det;
+    s.cb = -P.sxy / P.det;
+    s.cc = P.sxx / P.det;
+    s.qmax = P.qmax;
+    s.opacity = (float)op;
+    s.rgb[0] = rgb[0];
+    s.rgb[1] = rgb[1];
+    s.rgb[2] = rgb[2];
+    const double4* src = reinterpret_cast<const double4*>(&s);
+    double4* dst = reinterpret_cast<double4*>(a.splat + o);
+    dst[0] = src[0];
+    dst[1] = src[1];
+}
+
+// ---------------------------------------------------------------------------------------
+// Reverse mode: chain per-(view, Gaussian) gradients of the 2D quantities (u, v, conic
+// a, b, c, opacity, rgb) to the parameters. One thread per Gaussian, looping over the
+// views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
+// ---------------------------------------------------------------------------------------
+struct PreBwdArgs {
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opac;
+    const float* sh;
+    int64_t n;
+    int deg;
+    const gs_camera* cams;
+    int n_views;
+    gs_params p;
+    const uint32_t* count;   // [V][n]
+    const float* g2;         // [9][V*n]
+    float* gmean;
+    float* gscale;
+    float* gquat;
+    float* gopac;
+    float* gsh;
+};
+
+__global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t VN = (int64_t)a.n_views * a.n;
+    double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
+    float gsh[48];
+    const int nb = (a.deg + 1) * (a.deg + 1);
+#pragma unroll
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    bool any = false;
+    for (int v = 0; v < a.n_views; ++v) {
+        const int64_t o = (int64_t)v * a.n + i;
+        if (a.count[o] == 0) continue;
+        const float gu = a.g2[0 * VN + o], gv = a.g2[1 * VN + o], gA = a.g2[2 * VN + o], gB = a.g2[3 * VN + o],
+                    gC = a.g2[4 * VN + o], gO = a.g2[5 * VN + o];
+        const float gcol[3] = {a.g2[6 * VN + o], a.g2[7 * VN + o], a.g2[8 * VN + o]};
+        any = true;
+        const gs_camera cam = a.cams[v];
+        Proj P;
+        double op;
+        if (!project_one(cam, a.p, a.mean, a.scale, a.quat, a.opac, a.n, i, P, op)) continue;
+        go += gO;
+        const double ca = P.syy / P.det, cb = -P.sxy / P.det, cc = P.sxx / P.det;
+        // conic Q = Sigma'^-1; for a symmetric perturbation dSigma', dQ = -Q dSigma' Q.
+        // With G = [[gA, gB/2], [gB/2, gC]] the gradient w.r.t. Sigma' is -Q G Q.
+        const double g00 = gA, g01 = 0.5 * gB, g11 = gC;
+        const double QG00 = ca * g00 + cb * g01, QG01 = ca * g01 + cb * g11;
+        const double QG10 = cb * g00 + cc * g01, QG11 = cb * g01 + cc * g11;
+        const double H00 = -(QG00 * ca + QG01 * cb);
+        const double H01 = -(QG00 * cb + QG01 * cc);
+        const double H11 = -(QG10 * cb + QG11 * cc);
+        const double H[2][2] = {{H00, H01}, {H01, H11}};
+        // Sigma' = T Sigma T^T: dL/dSigma = T^T H T, dL/dT = 2 H T Sigma
+        double GS[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                GS[r][c] = P.T[0][r] * (H[0][0] * P.T[0][c] + H[0][1] * P.T[1][c]) +
+                           P.T[1][r] * (H[1][0] * P.T[0][c] + H[1][1] * P.T[1][c]);
+        double HT[2][3], GT[2][3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) HT[r][c] = H[r][0] * P.T[0][c] + H[r][1] * P.T[1][c];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                GT[r][c] = 2.0 * (HT[r][0] * P.Sg[0][c] + HT[r][1] * P.Sg[1][c] + HT[r][2] * P.Sg[2][c]);
+        // T = J R with J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]: dL/dJ = GT R^T
+        const float* Rc = cam.R;
+        double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            GJ00 += GT[0][k] * Rc[0 * 3 + k];
+            GJ02 += GT[0][k] * Rc[2 * 3 + k];
+            GJ11 += GT[1][k] * Rc[1 * 3 + k];
+            GJ12 += GT[1][k] * Rc[2 * 3 + k];
+        }
+        const double fx = cam.fx, fy = cam.fy, z = P.z, iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+        double gc[3];
+        gc[0] = -fx * iz2 * GJ02 + fx * iz * gu;
+        gc[1] = -fy * iz2 * GJ12 + fy * iz * gv;
+        gc[2] = -fx * iz2 * GJ00 + 2.0 * fx * P.x * iz3 * GJ02 - fy * iz2 * GJ11 + 2.0 * fy * P.y * iz3 * GJ12 -
+                fx * P.x * iz2 * gu - fy * P.y * iz2 * gv;
+        // world mean: p_c = R p + t
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gp[k] += Rc[k] * gc[0] + Rc[3 + k] * gc[1] + Rc[6 + k] * gc[2];
+        // Sigma = M M^T with M = Rq diag(s): dL/dM = 2 GS M
+        const double s[3] = {a.scale[i], a.scale[a.n + i], a.scale[2 * a.n + i]};
+        double GR[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double gm =
+                    2.0 * (GS[r][0] * P.Rq[0][c] * s[c] + GS[r][1] * P.Rq[1][c] * s[c] + GS[r][2] * P.Rq[2][c] * s[c]);
+                gs[c] += gm * P.Rq[r][c];
+                GR[r][c] = gm * s[c];
+            }
+        const double w = P.qh[0], x = P.qh[1], y = P.qh[2], zq = P.qh[3];
+        double gw = 2.0 * (-zq * GR[0][1] + y * GR[0][2] + zq * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+        double gx = 2.0 * (y * GR[0][1] + zq * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] +
+                           zq * GR[2][0] + w * GR[2][1] - 2.0 * x * GR[2][2]);
+        double gy = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + zq * GR[1][2] -
+                           w * GR[2][0] + zq * GR[2][1] - 2.0 * y * GR[2][2]);
+        double gz = 2.0 * (-2.0 * zq * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * zq * GR[1][1] +
+                           y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+        const double dot = w * gw + x * gx + y * gy + zq * gz;
+        gq[0] += (gw - w * dot) / P.qn;
+        gq[1] += (gx - x * dot) / P.qn;
+        gq[2] += (gy - y * dot) / P.qn;
+        gq[3] += (gz - zq * dot) / P.qn;
+        // colour through SH, including the view-direction dependence
+        float d[3];
+        double len;
+        view_dir(cam, a.mean[i], a.mean[a.n + i], a.mean[2 * a.n + i], d, len);
+        float Y[16], G[16][3];
+        sh_basis(a.deg, d[0], d[1], d[2], Y);
+        sh_basis_grad(a.deg, d[0], d[1], d[2], G);
+        float gd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.f;
+            for (int k = 0; k < nb; ++k) acc += a.sh[(int64_t)(k * 3 + c) * a.n + i] * Y[k];
+            if (!(acc + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
+            for (int k = 0; k < nb; ++k) {
+                gsh[k * 3 + c] += gcol[c] * Y[k];
+                const float kc = a.sh[(int64_t)(k * 3 + c) * a.n + i] * gcol[c];
+                gd[0] += kc * G[k][0];
+                gd[1] += kc * G[k][1];
+                gd[2] += kc * G[k][2];
+            }
+        }
+        const double dd = (double)d[0] * gd[0] + (double)d[1] * gd[1] + (double)d[2] * gd[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gp[k] += ((double)gd[k] - (double)d[k] * dd) / len;
+    }
+    if (!any) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.gmean[k * a.n + i] += (float)gp[k];
+        a.gscale[k * a.n + i] += (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] += (float)gq[k];
+    a.gopac[i] += (float)go;
+    for (int k = 0; k < nb * 3; ++k) a.gsh[(int64_t)k * a.n + i] += gsh[k];
+}
+
+// ---------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------
+gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const gs_params* p,
+                            const int32_t* subset, int64_t n, int want_color, gs_projected* out,
+                            hipStream_t stream) {
+    if (n == 0) return GS_OK;
+    PreArgs a;
+    a.mean = g->mean;
+    a.scale = g->scale;
+    a.quat = g->quat;
+    a.opac = g->opacity;
+    a.sh = g->sh;
+    a.n_all = g->n;
+    a.deg = g->sh_degree;
+    a.cams = views->cams;
+    a.p = *p;
+    a.tile_w = views->tile_w;
+    a.tile_h = views->tile_h;
+    a.subset = subset;
+    a.n = n;
+    a.want_color = want_color;
+    a.splat = out->splat;
+    a.depth = out->depth;
+    a.rect = out->rect;
+    a.count = out->count;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)views->n_views);
+    hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, stream, a);
+    return check_launch("preprocess");
+}
+
+gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, const gs_params* p,
+                                const gs_projected* proj, const float* g2, gs_gaussians_grad* grad,
+                                hipStream_t stream) {
+    if (g->n == 0) return GS_OK;
+    PreBwdArgs a;
+    a.mean = g->mean;
+    a.scale = g->scale;
+    a.quat = g->quat;
+    a.opac = g->opacity;
+    a.sh = g->sh;
+    a.n = g->n;
+    a.deg = g->sh_degree;
+    a.cams = views->cams;
+    a.n_views = views->n_views;
+    a.p = *p;
+    a.count = proj->count;
+    a.g2 = g2;
+    a.gmean = grad->mean;
+    a.gscale = grad->scale;
+    a.gquat = grad->quat;
+    a.gopac = grad->opacity;
+    a.gsh = grad->sh;
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g->n + 127) / 128)), dim3(128), 0, stream, a);
+    return check_launch("preprocess_bwd");
+}
+
+}  // namespace gs

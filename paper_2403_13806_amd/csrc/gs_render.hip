@@ -1,0 +1,408 @@
+// Per-tile front-to-back compositing (eq. render-gs) and the two passes built on the same
+// traversal: the max-over-rays importance score (eq. importance-score) and per-cluster
+// visibility bits (eq. importance-score-vis); plus the reverse traversal that gives the
+// gradients of the 2D quantities.
+//
+// One workgroup per tile, one pixel per lane. Each wave owns an 8x8 pixel block, so a
+// record whose support box misses that block is skipped by the whole wave at once. The
+// tile's sorted list is streamed through LDS in batches of one record per lane (64-byte
+// records, one coalesced load per lane). The support test d^T conic d <= q_max runs in
+// FP64 -- same issue rate as FP32 on CDNA4 -- so it agrees with an FP64 evaluation; the
+// exponential and the transmittance are FP32.
+#include <math.h>
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+enum { MODE_FWD = 0, MODE_IMPORTANCE = 1, MODE_VISIBILITY = 2 };
+
+struct RenderArgs {
+    const gs_splat* splat;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    const int32_t* tile_offset;
+    const int64_t* pixel_offset;
+    const gs_camera* cams;
+    int n_views;
+    int64_t n;
+    gs_params p;
+    float* rgb;
+    float* t_final;
+    uint32_t* n_last;
+    uint32_t* n_contrib;
+    float* h;
+    uint32_t* bits;
+    const int32_t* view_cluster;
+    int64_t words;
+    float t_cluster;
+    // backward
+    const float* dl_drgb;
+    const float* t_in;
+    const uint32_t* last_in;
+    float* g2;  // [9][n_views * n]
+};
+
+// conservative float box of the support (FP64 conic -> covariance diagonal), padded so
+// that no covered pixel centre can fall outside it
+__device__ __forceinline__ float4 support_box(const gs_splat& s) {
+    const double det = s.ca * s.cc - s.cb * s.cb;
+    const double hx = sqrt(s.qmax * s.cc / det), hy = sqrt(s.qmax * s.ca / det);
+    const float px = (float)hx * 1.0001f + 0.01f, py = (float)hy * 1.0001f + 0.01f;
+    return make_float4((float)s.u - px, (float)s.u + px, (float)s.v - py, (float)s.v + py);
+}
+
+__device__ __forceinline__ bool box_misses(const float4 b, float x0, float x1, float y0, float y1) {
+    return b.y < x0 || b.x > x1 || b.w < y0 || b.z > y1;
+}
+
+struct TileGeom {
+    int view, W, H, px, py, wave;
+    bool inside;
+    float wx0, wy0;  // centre of the wave's first pixel
+    int64_t pix;     // global pixel index
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
+    TileGeom g;
+    g.view = view_of_tile(a.tile_offset, a.n_views, tile);
+    g.W = a.cams[g.view].width;
+    g.H = a.cams[g.view].height;
+    const int tiles_x = div_up(g.W, TW);
+    const int local = tile - a.tile_offset[g.view];
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    const int t = threadIdx.x, l = t & 63;
+    g.wave = t >> 6;
+    const int bx = (g.wave % (TW / 8)) * 8, by = (g.wave / (TW / 8)) * 8;
+    g.px = tx * TW + bx + (l & 7);
+    g.py = ty * TH + by + (l >> 3);
+    g.inside = g.px < g.W && g.py < g.H;
+    g.wx0 = (float)(tx * TW + bx) + 0.5f;
+    g.wy0 = (float)(ty * TH + by) + 0.5f;
+    g.pix = a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
+    return g;
+}
+
+// FP64 support test and FP32 opacity of record s at pixel centre (xc, yc)
+__device__ __forceinline__ bool eval_alpha(const gs_splat& s, double xc, double yc, float amax, float& alpha,
+                                           float& G, float& dx, float& dy) {
+    const double ddx = xc - s.u, ddy = yc - s.v;
+    const double q = s.ca * ddx * ddx + 2.0 * s.cb * ddx * ddy + s.cc * ddy * ddy;
+    if (!(q <= s.qmax)) return false;
+    G = __expf(-0.5f * (float)q);
+    alpha = fminf(amax, s.opacity * G);
+    dx = (float)ddx;
+    dy = (float)ddy;
+    return true;
+}
+
+template <int TW, int TH, int MODE>
+__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ gs_splat rec[NT];
+    __shared__ float4 box[NT];
+    __shared__ uint32_t gid[NT];
+    const int tile = blockIdx.x;
+    const TileGeom g = tile_geom<TW, TH>(a, tile);
+    const int t = threadIdx.x, l = t & 63;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
+    const float x0 = g.wx0, x1 = g.wx0 + 7.f, y0 = g.wy0, y1 = g.wy0 + 7.f;
+    const float amax = a.p.alpha_max, tmin = a.p.t_min;
+    const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    bool done = !g.inside;
+    uint32_t last = start, ncomp = 0;
+    int cluster = 0;
+    if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
+    for (uint32_t base = start; base < end; base += NT) {
+        if (__syncthreads_and(done)) break;
+        const uint32_t k = base + t;
+        if (k < end) {
+            const uint32_t id = a.vals[k];
+            const gs_splat s = sp[id];
+            rec[t] = s;
+            box[t] = support_box(s);
+            gid[t] = id;
+        }
+        __syncthreads();
+        const int nb = (int)min((uint32_t)NT, end - base);
+        for (int j = 0; j < nb; ++j) {
+            if (box_misses(box[j], x0, x1, y0, y1)) continue;
+            if (ballot(!done) == 0) break;
+            float w = 0.f;
+            if (!done) {
+                const gs_splat& s = rec[j];
+                float al, G, dx, dy;
+                if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
+                    w = al * T;
+                    if (MODE == MODE_FWD) {
+                        C0 += w * s.rgb[0];
+                        C1 += w * s.rgb[1];
+                        C2 += w * s.rgb[2];
+                    }
+                    T = T * (1.f - al);
+                    last = base + j + 1;
+                    ++ncomp;
+                    if (T < tmin) done = true;
+                }
+            }
+            if (MODE == MODE_IMPORTANCE) {
+                if (ballot(w > 0.f)) {
+                    const float m = wave_max_nonneg(w);
+                    if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + gid[j], __float_as_uint(m));
+                }
+            }
+            if (MODE == MODE_VISIBILITY) {
+                if (ballot(w > a.t_cluster) != 0 && l == 0) {
+                    const uint32_t id = gid[j];
+                    atomicOr(a.bits + (int64_t)cluster * a.words + (id >> 5), 1u << (id & 31));
+                }
+            }
+        }
+    }
+    if (MODE == MODE_FWD && g.inside) {
+        const int64_t plane = (int64_t)g.W * g.H;
+        float* out = a.rgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
+        out[0] = C0 + T * a.p.bg[0];
+        out[plane] = C1 + T * a.p.bg[1];
+        out[2 * plane] = C2 + T * a.p.bg[2];
+        a.t_final[g.pix] = T;
+        a.n_last[g.pix] = last;
+        if (a.n_contrib) a.n_contrib[g.pix] = ncomp;
+    }
+}
+
+// Reverse traversal. For pixel entries in back-to-front order, with T the transmittance
+// after entry j and S the colour composited behind it (S starts at T_final * bg):
+//   T_j = T / (1 - alpha_j), w_j = alpha_j T_j,
+//   dL/dc_j = dL/dC * w_j,  dL/dalpha_j = sum_c dL/dC_c (T_j c_jc - S_c / (1 - alpha_j)),
+// then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
+// dx = xc - u. The nine per-record sums are reduced over the wave and added atomically
+// into g2[field][view * n + index].
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ gs_splat rec[NT];
+    __shared__ float4 box[NT];
+    __shared__ uint32_t gid[NT];
+    __shared__ uint32_t top_s;
+    const int tile = blockIdx.x;
+    const TileGeom g = tile_geom<TW, TH>(a, tile);
+    const int t = threadIdx.x, l = t & 63;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
+    const float x0 = g.wx0, x1 = g.wx0 + 7.f, y0 = g.wy0, y1 = g.wy0 + 7.f;
+    const float amax = a.p.alpha_max;
+    const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
+    float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
+    uint32_t last = start;
+    if (g.inside) {
+        T = a.t_in[g.pix];
+        last = a.last_in[g.pix];
+        const int64_t plane = (int64_t)g.W * g.H;
+        const float* d = a.dl_drgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
+        dC0 = d[0];
+        dC1 = d[plane];
+        dC2 = d[2 * plane];
+        S0 = T * a.p.bg[0];
+        S1 = T * a.p.bg[1];
+        S2 = T * a.p.bg[2];
+    }
+    last = min(last, end);  // never read past the tile's list, whatever n_last holds
+    if (t == 0) top_s = start;
+    __syncthreads();
+    if (g.inside && last > start) atomicMax(&top_s, last);
+    __syncthreads();
+    const uint32_t top = top_s;
+    const int64_t VN = (int64_t)a.n_views * a.n;
+    const int64_t vbase = (int64_t)g.view * a.n;
+    for (uint32_t hi = top; hi > start;) {
+        const uint32_t lo = (hi - start > (uint32_t)NT) ? hi - NT : start;
+        const uint32_t k = lo + t;
+        __syncthreads();
+        if (k < hi) {
+            const uint32_t id = a.vals[k];
+            const gs_splat s = sp[id];
+            rec[t] = s;
+            box[t] = support_box(s);
+            gid[t] = id;
+        }
+        __syncthreads();
+        for (int j = (int)(hi - lo) - 1; j >= 0; --j) {
+            if (box_misses(box[j], x0, x1, y0, y1)) continue;
+            const uint32_t pos = lo + j;
+            float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+            bool contrib = false;
+            if (g.inside && pos < last) {
+                const gs_splat& s = rec[j];
+                float al, G, dx, dy;
+                if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
+                    contrib = true;
+                    const float om = 1.f - al;
+                    T = T / om;
+                    const float w = al * T;
+                    gr = dC0 * w;
+                    gg = dC1 * w;
+                    gbl = dC2 * w;
+                    const float dA = dC0 * (T * s.rgb[0] - S0 / om) + dC1 * (T * s.rgb[1] - S1 / om) +
+                                     dC2 * (T * s.rgb[2] - S2 / om);
+                    S0 += w * s.rgb[0];
+                    S1 += w * s.rgb[1];
+                    S2 += w * s.rgb[2];
+                    if (s.opacity * G < amax) {
+                        go = dA * G;
+                        const float dq = -0.5f * al * dA;
+                        ga = dq * dx * dx;
+                        gb = dq * 2.f * dx * dy;
+                        gc = dq * dy * dy;
+                        gu = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
+                        gv = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
+                    }
+                }
+            }
+            if (ballot(contrib)) {
+                const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
+                            sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
+                            sbl = wave_sum(gbl);
+                if (l == 0) {
+                    const int64_t o = vbase + gid[j];
+                    atomicAdd(a.g2 + 0 * VN + o, su);
+                    atomicAdd(a.g2 + 1 * VN + o, sv);
+                    atomicAdd(a.g2 + 2 * VN + o, sa);
+                    atomicAdd(a.g2 + 3 * VN + o, sb);
+                    atomicAdd(a.g2 + 4 * VN + o, sc);
+                    atomicAdd(a.g2 + 5 * VN + o, so);
+                    atomicAdd(a.g2 + 6 * VN + o, sr);
+                    atomicAdd(a.g2 + 7 * VN + o, sg);
+                    atomicAdd(a.g2 + 8 * VN + o, sbl);
+                }
+            }
+        }
+        hi = lo;
+    }
+}
+
+// L1 loss and its gradient, one element per lane, one atomic per block for the loss
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const float* __restrict__ tgt, int64_t n,
+                                            float scale, float* __restrict__ dl, float* __restrict__ loss) {
+    __shared__ float part[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float e = 0.f;
+    if (i < n) {
+        const float d = rgb[i] - tgt[i];
+        dl[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+        e = fabsf(d);
+    }
+    const float s = wave_sum(e);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss) atomicAdd(loss, scale * ((part[0] + part[1]) + (part[2] + part[3])));
+}
+
+gs_status launch_l1(const float* rgb, const float* tgt, int64_t n, float scale, float* dl, float* loss,
+                    hipStream_t s) {
+    if (n == 0) return GS_OK;
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rgb, tgt, n, scale, dl, loss);
+    return check_launch("l1_loss_grad");
+}
+
+// ---------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------
+template <int MODE>
+static void launch_mode(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
+    const dim3 grid(n_tiles);
+#define GS_CASE(W_, H_)                                                                          \
+    if (tw == W_ && th == H_) {                                                                  \
+        hipLaunchKernelGGL((k_render<W_, H_, MODE>), grid, dim3(W_ * H_), 0, s, a);              \
+        return;                                                                                  \
+    }
+    GS_CASE(8, 8)
+    GS_CASE(16, 8)
+    GS_CASE(8, 16)
+    GS_CASE(16, 16)
+    GS_CASE(32, 8)
+    GS_CASE(8, 32)
+#undef GS_CASE
+}
+
+static void launch_bwd(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
+    const dim3 grid(n_tiles);
+#define GS_CASE(W_, H_)                                                                          \
+    if (tw == W_ && th == H_) {                                                                  \
+        hipLaunchKernelGGL((k_render_bwd<W_, H_>), grid, dim3(W_ * H_), 0, s, a);                \
+        return;                                                                                  \
+    }
+    GS_CASE(8, 8)
+    GS_CASE(16, 8)
+    GS_CASE(8, 16)
+    GS_CASE(16, 16)
+    GS_CASE(32, 8)
+    GS_CASE(8, 32)
+#undef GS_CASE
+}
+
+static RenderArgs base_args(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                            const gs_params* p) {
+    RenderArgs a = {};
+    a.splat = proj->splat;
+    a.vals = bins->vals;
+    a.ranges = bins->ranges;
+    a.tile_offset = views->tile_offset;
+    a.pixel_offset = views->pixel_offset;
+    a.cams = views->cams;
+    a.n_views = views->n_views;
+    a.n = proj->n;
+    a.p = *p;
+    return a;
+}
+
+gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                            float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.n_last = n_last;
+    a.n_contrib = n_contrib;
+    launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->n_tiles, s);
+    return check_launch("render_fwd");
+}
+
+gs_status launch_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                            float* h, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.h = h;
+    launch_mode<MODE_IMPORTANCE>(a, views->tile_w, views->tile_h, views->n_tiles, s);
+    return check_launch("importance");
+}
+
+gs_status launch_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                            const int32_t* view_cluster, float t_cluster, uint32_t* bits, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.bits = bits;
+    a.view_cluster = view_cluster;
+    a.words = (proj->n + 31) / 32;
+    a.t_cluster = t_cluster;
+    launch_mode<MODE_VISIBILITY>(a, views->tile_w, views->tile_h, views->n_tiles, s);
+    return check_launch("cluster_visibility");
+}
+
+gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
+                            const float* t_final, const uint32_t* n_last, const float* dl_drgb, float* g2,
+                            hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.t_in = t_final;
+    a.last_in = n_last;
+    a.dl_drgb = dl_drgb;
+    a.g2 = g2;
+    launch_bwd(a, views->tile_w, views->tile_h, views->n_tiles, s);
+    return check_launch("render_bwd");
+}
+
+}  // namespace gs

@@ -1,0 +1,425 @@
+"""Python binding of the splatting library: buffers come from PyTorch (device memory and
+streams), every computation is a call into libgs_hip.so (include/gs.h).
+
+  Gaussians, ViewBatch          device-side inputs (structure of arrays; batched views)
+  preprocess / bin_sort /       the C-ABI calls, one to one
+  render_fwd / render_bwd /
+  importance / cluster_visibility / bits_to_list
+  Renderer                      persistent buffers for repeated frames (fixed capacity,
+                                no host synchronisation per frame)
+  GSRender                      torch.autograd.Function over render_fwd / render_bwd
+  kmeans / nearest_centre       host camera clustering (Sec. 3.4)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DEFAULT_TILE = (16, 16)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+def make_params(p=None) -> L.gs_params:
+    """gs_params from any object with lowpass, kappa, alpha_min, alpha_max, t_min, guard, bg."""
+    s = L.gs_params()
+    if p is None:
+        s.lowpass, s.kappa, s.alpha_min, s.alpha_max, s.t_min, s.guard = 0.3, 3.0, 1.0 / 255.0, 0.99, 1e-4, 1.3
+        s.bg[:] = [0.0, 0.0, 0.0]
+        return s
+    s.lowpass, s.kappa, s.alpha_min, s.alpha_max = p.lowpass, p.kappa, p.alpha_min, p.alpha_max
+    s.t_min, s.guard = p.t_min, p.guard
+    s.bg[:] = list(p.bg)
+    return s
+
+
+@dataclass
+class Gaussians:
+    mean: torch.Tensor      # [3][n] float32
+    scale: torch.Tensor     # [3][n]
+    quat: torch.Tensor      # [4][n]
+    opacity: torch.Tensor   # [n]
+    sh: torch.Tensor        # [(d+1)^2*3][n]
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.opacity.shape[0])
+
+    @classmethod
+    def from_arrays(cls, mean, scale, quat, opacity, sh, sh_degree, device=None) -> "Gaussians":
+        dev = _dev(device)
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+                                      dtype=torch.float32).to(dev).contiguous()
+        return cls(f(mean), f(scale), f(quat), f(opacity), f(sh), int(sh_degree))
+
+    @classmethod
+    def from_scene(cls, scene, device=None) -> "Gaussians":
+        return cls.from_arrays(scene.mean, scene.scale, scene.quat, scene.opacity, scene.sh, scene.sh_degree, device)
+
+    def struct(self) -> L.gs_gaussians:
+        for t in (self.mean, self.scale, self.quat, self.opacity, self.sh):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError("Gaussian parameters must be contiguous float32 device tensors")
+        return L.gs_gaussians(_ptr(self.mean), _ptr(self.scale), _ptr(self.quat), _ptr(self.opacity), _ptr(self.sh),
+                              self.n, self.sh_degree)
+
+
+def camera_struct(cam) -> L.gs_camera:
+    c = L.gs_camera()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).reshape(-1)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(cam.znear)
+    c.reserved = 0
+    return c
+
+
+class ViewBatch:
+    """Views rendered in one call: cameras, tile size and the global tile/pixel layout."""
+
+    def __init__(self, cams: Sequence, tile: Tuple[int, int] = DEFAULT_TILE, device=None):
+        lib = L.load()
+        self.cams = list(cams)
+        self.n_views = len(self.cams)
+        self.tile = (int(tile[0]), int(tile[1]))
+        self.device = _dev(device)
+        arr = (L.gs_camera * self.n_views)(*[camera_struct(c) for c in self.cams])
+        toff = (ctypes.c_int32 * (self.n_views + 1))()
+        poff = (ctypes.c_int64 * (self.n_views + 1))()
+        L.check(lib.gs_view_layout(arr, self.n_views, self.tile[0], self.tile[1], toff, poff))
+        self.tile_offset_host = np.array(toff[:], np.int64)
+        self.pixel_offset_host = np.array(poff[:], np.int64)
+        self.n_tiles = int(self.tile_offset_host[-1])
+        self.n_pixels = int(self.pixel_offset_host[-1])
+        raw = bytes(arr)
+        self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        self.tile_offset = torch.tensor(self.tile_offset_host, dtype=torch.int32, device=self.device)
+        self.pixel_offset = torch.tensor(self.pixel_offset_host, dtype=torch.int64, device=self.device)
+        self.sizes = [(int(c.width), int(c.height)) for c in self.cams]
+
+    def struct(self) -> L.gs_views:
+        return L.gs_views(_ptr(self.cams_dev), _ptr(self.tile_offset), _ptr(self.pixel_offset), self.n_views,
+                          self.tile[0], self.tile[1], self.n_tiles, self.n_pixels)
+
+    def image(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
+        """View v's planar [3][H][W] image inside a global rgb buffer."""
+        W, H = self.sizes[v]
+        o = int(self.pixel_offset_host[v])
+        return rgb[3 * o:3 * o + 3 * W * H].view(3, H, W)
+
+    def plane(self, buf: torch.Tensor, v: int) -> torch.Tensor:
+        """View v's [H][W] slice of a per-pixel buffer (t_final, n_last)."""
+        W, H = self.sizes[v]
+        o = int(self.pixel_offset_host[v])
+        return buf[o:o + W * H].view(H, W)
+
+    def pack_images(self, images: Sequence) -> torch.Tensor:
+        """Concatenate per-view [3][H][W] images into the global rgb layout."""
+        return torch.cat([torch.as_tensor(im, dtype=torch.float32).reshape(-1) for im in images]).to(self.device)
+
+
+class Projected:
+    def __init__(self, n: int, n_views: int, device):
+        self.n = int(n)
+        self.n_views = int(n_views)
+        vn = max(self.n * self.n_views, 1)
+        self.splat = torch.empty(vn * L.SPLAT_BYTES, dtype=torch.uint8, device=device)
+        self.depth = torch.empty(vn, dtype=torch.float32, device=device)
+        self.rect = torch.empty(vn, dtype=torch.int64, device=device)
+        self.count = torch.empty(vn, dtype=torch.int32, device=device)
+
+    def struct(self) -> L.gs_projected:
+        return L.gs_projected(_ptr(self.splat), _ptr(self.depth), _ptr(self.rect), _ptr(self.count), self.n)
+
+    def splat_fields(self):
+        """Records as float64 [V*n][8] (u, v, ca, cb, cc, qmax, opacity|r, g|b bits)."""
+        return self.splat.view(torch.float64).view(-1, 8)
+
+
+class Bins:
+    def __init__(self, capacity: int, n_tiles: int, device):
+        self.capacity = int(capacity)
+        cap = max(self.capacity, 1)
+        self.keys = torch.empty(cap, dtype=torch.int64, device=device)
+        self.vals = torch.empty(cap, dtype=torch.int32, device=device)
+        self.ranges = torch.empty(max(2 * n_tiles, 2), dtype=torch.int32, device=device)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def struct(self) -> L.gs_bins:
+        return L.gs_bins(_ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), self.capacity, _ptr(self.n_pairs),
+                         _ptr(self.overflow))
+
+
+def workspace_bytes(n: int, n_views: int, capacity: int, n_tiles: int) -> int:
+    return int(L.load().gs_workspace_bytes(int(n), int(n_views), int(capacity), int(n_tiles)))
+
+
+def alloc_workspace(n, n_views, capacity, n_tiles, device) -> torch.Tensor:
+    return torch.empty(max(workspace_bytes(n, n_views, capacity, n_tiles), 256), dtype=torch.uint8, device=device)
+
+
+def preprocess(g: Gaussians, views: ViewBatch, params=None, subset: Optional[torch.Tensor] = None,
+               want_color: bool = True, out: Optional[Projected] = None) -> Projected:
+    lib = L.load()
+    n = g.n if subset is None else int(subset.shape[0])
+    if out is None:
+        out = Projected(n, views.n_views, views.device)
+    if subset is not None and not (subset.dtype == torch.int32 and subset.is_cuda and subset.is_contiguous()):
+        raise ValueError("subset must be a contiguous int32 device tensor")
+    p = make_params(params)
+    L.check(lib.gs_preprocess(ctypes.byref(g.struct()), ctypes.byref(views.struct()), ctypes.byref(p),
+                              _ptr(subset), n, int(bool(want_color)), ctypes.byref(out.struct()), _stream(views.device)))
+    return out
+
+
+def bin_sort(proj: Projected, views: ViewBatch, capacity: Optional[int] = None, bins: Optional[Bins] = None,
+             ws: Optional[torch.Tensor] = None, grow: bool = True) -> Bins:
+    """Bin and sort. With grow=True the pair count is read back (one host sync) and the call
+    is repeated with a larger buffer when the capacity was too small."""
+    lib = L.load()
+    if bins is None:
+        if capacity is None:
+            capacity = max(1 << 16, 4 * proj.n * views.n_views)
+        bins = Bins(capacity, views.n_tiles, views.device)
+    for _ in range(3):
+        need = workspace_bytes(proj.n, views.n_views, bins.capacity, views.n_tiles)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=views.device)
+        L.check(lib.gs_bin_sort(ctypes.byref(proj.struct()), ctypes.byref(views.struct()), ctypes.byref(bins.struct()),
+                                _ptr(ws), ws.numel(), _stream(views.device)))
+        if not grow:
+            return bins
+        if int(bins.overflow.item()) == 0:
+            return bins
+        need_pairs = int(bins.n_pairs.item())
+        bins = Bins(int(need_pairs * 1.125) + 4096, views.n_tiles, views.device)
+    raise RuntimeError("bin_sort: capacity growth did not converge")
+
+
+def render_fwd(proj: Projected, views: ViewBatch, bins: Bins, params=None, rgb=None, t_final=None, n_last=None,
+               n_contrib=None):
+    lib = L.load()
+    dev = views.device
+    if rgb is None:
+        rgb = torch.empty(3 * max(views.n_pixels, 1), dtype=torch.float32, device=dev)
+        t_final = torch.empty(max(views.n_pixels, 1), dtype=torch.float32, device=dev)
+        n_last = torch.empty(max(views.n_pixels, 1), dtype=torch.int32, device=dev)
+    p = make_params(params)
+    L.check(lib.gs_render_fwd(ctypes.byref(proj.struct()), ctypes.byref(views.struct()), ctypes.byref(bins.struct()),
+                              ctypes.byref(p), _ptr(rgb), _ptr(t_final), _ptr(n_last), _ptr(n_contrib), _stream(dev)))
+    return rgb, t_final, n_last
+
+
+def l1_loss_grad(rgb: torch.Tensor, target: torch.Tensor, dl_drgb: Optional[torch.Tensor] = None,
+                 loss: Optional[torch.Tensor] = None, scale: Optional[float] = None):
+    """L1 loss (mean over elements by default) and its gradient, both on the device."""
+    n = rgb.numel()
+    if dl_drgb is None:
+        dl_drgb = torch.empty_like(rgb)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=rgb.device)
+    s = 1.0 / max(n, 1) if scale is None else scale
+    L.check(L.load().gs_l1_loss_grad(_ptr(rgb), _ptr(target), n, float(s), _ptr(dl_drgb), _ptr(loss),
+                                     _stream(rgb.device)))
+    return loss, dl_drgb
+
+
+def render(g: Gaussians, views: ViewBatch, params=None, subset=None, capacity=None):
+    """Plain path: preprocess -> bin_sort (growing the pair buffer if needed) -> render_fwd."""
+    proj = preprocess(g, views, params, subset=subset)
+    bins = bin_sort(proj, views, capacity)
+    rgb, t, last = render_fwd(proj, views, bins, params)
+    return {"rgb": rgb, "t_final": t, "n_last": last, "proj": proj, "bins": bins}
+
+
+def importance(g: Gaussians, views: ViewBatch, params=None, h: Optional[torch.Tensor] = None, capacity=None):
+    """h = max(h, importance over the views' pixels) (eq. importance-score); h starts at 0."""
+    lib = L.load()
+    if h is None:
+        h = torch.zeros(max(g.n, 1), dtype=torch.float32, device=views.device)
+    proj = preprocess(g, views, params, want_color=False)
+    bins = bin_sort(proj, views, capacity)
+    p = make_params(params)
+    L.check(lib.gs_importance(ctypes.byref(proj.struct()), ctypes.byref(views.struct()), ctypes.byref(bins.struct()),
+                              ctypes.byref(p), _ptr(h), _stream(views.device)))
+    return h
+
+
+def prune_mask(h: torch.Tensor, t_prune: float) -> torch.Tensor:
+    """m_i = 1(h_i < t_prune): True marks a Gaussian to remove (Sec. 3.3)."""
+    return h < t_prune
+
+
+def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[int], k: int, t_cluster: float,
+                       params=None, bits: Optional[torch.Tensor] = None, capacity=None) -> torch.Tensor:
+    """OR into bits [k][ceil(n/32)] the per-cluster indicator lists (eq. importance-score-vis)."""
+    lib = L.load()
+    words = (g.n + 31) // 32
+    if bits is None:
+        bits = torch.zeros(max(k * words, 1), dtype=torch.int32, device=views.device)
+    vc = torch.as_tensor(np.asarray(view_cluster, np.int32), device=views.device)
+    proj = preprocess(g, views, params, want_color=False)
+    bins = bin_sort(proj, views, capacity)
+    p = make_params(params)
+    L.check(lib.gs_cluster_visibility(ctypes.byref(proj.struct()), ctypes.byref(views.struct()),
+                                      ctypes.byref(bins.struct()), ctypes.byref(p), _ptr(vc), int(k), float(t_cluster),
+                                      _ptr(bits), _stream(views.device)))
+    return bits
+
+
+def bits_to_list(bits_row: torch.Tensor, n: int) -> torch.Tensor:
+    """Sorted indices of the set bits of one visibility row (device int32 tensor)."""
+    lib = L.load()
+    dev = bits_row.device
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = alloc_workspace(n, 1, 0, 0, dev)
+    L.check(lib.gs_bits_to_list(_ptr(bits_row), int(n), _ptr(out), _ptr(cnt), _ptr(ws), ws.numel(), _stream(dev)))
+    return out[:int(cnt.item())]
+
+
+def render_bwd(g: Gaussians, views: ViewBatch, proj: Projected, bins: Bins, t_final, n_last, dl_drgb, params=None,
+               grad: Optional[Gaussians] = None, ws: Optional[torch.Tensor] = None) -> Gaussians:
+    """Add dL/dparams (given dL/drgb in the global image layout) into grad (zeros if None)."""
+    lib = L.load()
+    dev = views.device
+    if grad is None:
+        grad = Gaussians(torch.zeros_like(g.mean), torch.zeros_like(g.scale), torch.zeros_like(g.quat),
+                         torch.zeros_like(g.opacity), torch.zeros_like(g.sh), g.sh_degree)
+    need = workspace_bytes(g.n, views.n_views, 0, views.n_tiles)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity), _ptr(grad.sh),
+                             g.n, g.sh_degree)
+    p = make_params(params)
+    dl = dl_drgb.contiguous()
+    L.check(lib.gs_render_bwd(ctypes.byref(g.struct()), ctypes.byref(views.struct()), ctypes.byref(proj.struct()),
+                              ctypes.byref(bins.struct()), ctypes.byref(p), _ptr(t_final), _ptr(n_last), _ptr(dl),
+                              ctypes.byref(gg), _ptr(ws), ws.numel(), _stream(dev)))
+    return grad
+
+
+class GSRender(torch.autograd.Function):
+    """Differentiable render of a view batch: (mean, scale, quat, opacity, sh) -> rgb in the
+    global image layout. The backward is the hand-written reverse traversal."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, opacity, sh, views: ViewBatch, sh_degree: int, params=None):
+        g = Gaussians(mean.detach().contiguous(), scale.detach().contiguous(), quat.detach().contiguous(),
+                      opacity.detach().contiguous(), sh.detach().contiguous(), sh_degree)
+        out = render(g, views, params)
+        ctx.state = (g, views, out["proj"], out["bins"], out["t_final"], out["n_last"], params)
+        return out["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        g, views, proj, bins, t, last, params = ctx.state
+        grad = render_bwd(g, views, proj, bins, t, last, grad_rgb, params)
+        return grad.mean, grad.scale, grad.quat, grad.opacity, grad.sh, None, None, None
+
+
+def kmeans(pos: np.ndarray, k: int, seed: int = 3, max_iter: int = 100):
+    """FP64 k-means on camera positions [m][3] -> (centres [k][3], assignment [m])."""
+    lib = L.load()
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    m = pos.shape[0]
+    cen = np.zeros((k, 3), np.float64)
+    asg = np.zeros(m, np.int32)
+    L.check(lib.gs_kmeans(pos.ctypes.data_as(ctypes.c_void_p), m, int(k), int(seed), int(max_iter),
+                          cen.ctypes.data_as(ctypes.c_void_p), asg.ctypes.data_as(ctypes.c_void_p)))
+    return cen, asg
+
+
+def nearest_centre(centres: np.ndarray, x) -> int:
+    lib = L.load()
+    c = np.ascontiguousarray(centres, np.float64)
+    xx = np.ascontiguousarray(x, np.float64)
+    return int(lib.gs_nearest_centre(c.ctypes.data_as(ctypes.c_void_p), c.shape[0], xx.ctypes.data_as(ctypes.c_void_p)))
+
+
+class Renderer:
+    """Repeated frames of one view batch with persistent buffers: no allocation and no host
+    synchronisation per frame. The pair capacity is fixed at construction (from a first
+    sized run); check() reports whether any frame since construction overflowed it."""
+
+    def __init__(self, g: Gaussians, views: ViewBatch, params=None, capacity: Optional[int] = None,
+                 want_color: bool = True, headroom: float = 1.25):
+        self.g, self.views, self.params = g, views, params
+        self.p = make_params(params)
+        dev = views.device
+        self.proj = Projected(g.n, views.n_views, dev)
+        preprocess(g, views, params, want_color=want_color, out=self.proj)
+        if capacity is None:
+            b = bin_sort(self.proj, views)
+            capacity = int(int(b.n_pairs.item()) * headroom) + 4096
+        self.bins = Bins(capacity, views.n_tiles, dev)
+        self.ws = alloc_workspace(g.n, views.n_views, capacity, views.n_tiles, dev)
+        self.rgb = torch.empty(3 * max(views.n_pixels, 1), dtype=torch.float32, device=dev)
+        self.t_final = torch.empty(max(views.n_pixels, 1), dtype=torch.float32, device=dev)
+        self.n_last = torch.empty(max(views.n_pixels, 1), dtype=torch.int32, device=dev)
+        self.want_color = want_color
+        self._sg = g.struct()
+        self._sv = views.struct()
+        self._sp = self.proj.struct()
+        self._sb = self.bins.struct()
+        self.overflowed = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def _pre(self, stream):
+        lib = L.load()
+        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self.p), None,
+                                  self.g.n, int(self.want_color), ctypes.byref(self._sp), stream))
+        L.check(lib.gs_bin_sort(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
+                                _ptr(self.ws), self.ws.numel(), stream))
+
+    def forward(self):
+        s = _stream(self.views.device)
+        self._pre(s)
+        self.render_only(s)
+        return self.rgb
+
+    def render_only(self, s=None, n_contrib: Optional[torch.Tensor] = None):
+        """Compositing pass alone over the current bins (after forward() or _pre())."""
+        s = _stream(self.views.device) if s is None else s
+        L.check(L.load().gs_render_fwd(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
+                                       ctypes.byref(self.p), _ptr(self.rgb), _ptr(self.t_final), _ptr(self.n_last),
+                                       _ptr(n_contrib), s))
+
+    def importance(self, h: torch.Tensor):
+        s = _stream(self.views.device)
+        self._pre(s)
+        L.check(L.load().gs_importance(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
+                                       ctypes.byref(self.p), _ptr(h), s))
+        return h
+
+    def backward(self, dl_drgb: torch.Tensor, grad: Gaussians):
+        s = _stream(self.views.device)
+        gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity),
+                                 _ptr(grad.sh), self.g.n, self.g.sh_degree)
+        L.check(L.load().gs_render_bwd(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self._sp),
+                                       ctypes.byref(self._sb), ctypes.byref(self.p), _ptr(self.t_final),
+                                       _ptr(self.n_last), _ptr(dl_drgb), ctypes.byref(gg), _ptr(self.ws),
+                                       self.ws.numel(), s))
+        return grad
+
+    def check(self) -> Tuple[bool, int]:
+        """(overflowed, pairs of the last frame); synchronises."""
+        return bool(int(self.bins.overflow.item())), int(self.bins.n_pairs.item())

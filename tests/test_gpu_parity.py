@@ -1,0 +1,339 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Bars: tile keys and integer outputs bit-exact; images within 1e-4 absolute per channel;
+importance within 1e-5; gradients within 1e-3 relative. Pixels (Gaussians) inside the
+oracle's threshold band (tests/helpers.py) are excluded and counted; the count must stay
+below 1e-4 of the pixels (Gaussians), with a floor of 2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_13806_amd as gs
+import scenes
+from oracle import F
+from tests.helpers import (TOL_GRAD, TOL_H, TOL_IMAGE, band_runs, check_band, h_band, image_band,
+                           mismatch_limit, splat_table)
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+P = scenes.Params()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _case(name):
+    """Scenes used by several tests: small enough for the oracle, several tiles, ragged tails."""
+    if name == "plain":
+        return scenes.uniform_cube_scene(2000, seed=0), scenes.plain_view()
+    if name == "mixture":
+        sc = scenes.mixture_scene(8000, seed=5, sh_degree=3)
+        return sc, scenes.orbit_camera(0.4, 0.25, 4.0, 197, 141)
+    if name == "mixture_deg1":
+        sc = scenes.mixture_scene(6000, seed=6, sh_degree=1)
+        return sc, scenes.orbit_camera(2.0, -0.1, 4.0, 150, 110)
+    raise KeyError(name)
+
+
+CASES = ["plain", "mixture", "mixture_deg1"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_preprocess_matches_oracle(case):
+    sc, cam = _case(case)
+    _say(f"preprocess {case} n={sc.n} {cam.width}x{cam.height}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    proj = gs.preprocess(g, views, P)
+    torch.cuda.synchronize()
+    t = splat_table(proj)
+    ref = oracle.project(sc, cam, P, tile=(16, 16))
+    vis = (ref[:, F["vis"]] == 1) & (ref[:, F["count"]] > 0)
+    assert np.array_equal(t["count"] > 0, vis)
+    assert np.array_equal(t["count"][vis], ref[vis, F["count"]].astype(np.uint32))
+    rr = oracle.rects_of(ref)
+    assert np.array_equal(t["rect"][vis], rr[vis])
+    assert np.array_equal(t["depth"][vis], ref[vis, F["depth32"]].astype(np.float32))
+    for k in ("u", "v", "ca", "cb", "cc", "qmax"):
+        a, b = t[k][vis], ref[vis, F[k]]
+        assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1.0)), k
+    assert np.array_equal(t["opac"][vis], ref[vis, F["opac"]].astype(np.float32))
+    rgb_ref = ref[vis][:, [F["r"], F["g"], F["b"]]]
+    assert np.abs(t["rgb"][vis] - rgb_ref).max() < 1e-5
+    assert vis.sum() > 50
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_keys_bit_exact(case, tile):
+    sc, cam = _case(case)
+    _say(f"keys {case} tile={tile}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], tile, DEV)
+    proj = gs.preprocess(g, views, P)
+    bins = gs.bin_sort(proj, views)
+    torch.cuda.synchronize()
+    npairs = int(bins.n_pairs.item())
+    assert int(bins.overflow.item()) == 0
+    keys = bins.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = bins.vals[:npairs].cpu().numpy().view(np.uint32)
+    # given the GPU's own projected records ...
+    t = splat_table(proj)
+    rect = np.where((t["count"] > 0)[:, None], t["rect"], np.array([0, 0, -1, -1]))
+    k1, v1 = oracle.pairs([t["depth"]], [rect], [(cam.width, cam.height)], tile)
+    assert np.array_equal(keys, k1) and np.array_equal(vals, v1)
+    # ... and end to end from the oracle's FP64 projection
+    ref = oracle.project(sc, cam, P, tile=tile)
+    k2, v2 = oracle.pairs([ref[:, F["depth32"]]], [oracle.rects_of(ref)], [(cam.width, cam.height)], tile)
+    assert np.array_equal(keys, k2) and np.array_equal(vals, v2)
+    # tile ranges
+    ranges = bins.ranges.cpu().numpy().reshape(-1, 2)
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    for tid in range(views.n_tiles):
+        idx = np.nonzero(tiles == tid)[0]
+        if idx.size:
+            assert ranges[tid, 0] == idx[0] and ranges[tid, 1] == idx[-1] + 1
+        else:
+            assert ranges[tid, 0] == ranges[tid, 1]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_render_matches_oracle(case):
+    sc, cam = _case(case)
+    _say(f"render {case}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    out = gs.render(g, views, P)
+    torch.cuda.synchronize()
+    img = views.image(out["rgb"], 0).cpu().numpy().astype(np.float64)
+    T = views.plane(out["t_final"], 0).cpu().numpy().astype(np.float64)
+    _, runs = band_runs(sc, cam, P)
+    band = image_band(runs)
+    ref = runs[0]
+    mism = (np.abs(img - ref["rgb"]).max(0) > TOL_IMAGE) | (np.abs(T - ref["T"]) > TOL_IMAGE)
+    _say(f"  max err {np.abs(img - ref['rgb']).max():.2e}")
+    check_band(mism, band, f"render {case}")
+    # every pixel's composited prefix is nonempty somewhere and the scene is not empty
+    assert (ref["T"] < 0.5).sum() > 20
+
+
+def test_tile_size_invariance_bitwise():
+    sc, cam = _case("mixture")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    imgs = []
+    for tile in [(16, 16), (8, 8), (32, 8), (16, 8), (8, 32)]:
+        _say(f"tile invariance {tile}")
+        views = gs.ViewBatch([cam], tile, DEV)
+        out = gs.render(g, views, P)
+        imgs.append((out["rgb"].cpu().numpy(), out["t_final"].cpu().numpy()))
+    for a, b in imgs[1:]:
+        assert np.array_equal(a, imgs[0][0]) and np.array_equal(b, imgs[0][1])
+
+
+def test_batched_views_equal_single_views_bitwise():
+    sc = scenes.mixture_scene(6000, seed=7, sh_degree=3)
+    sizes = [(64, 48), (80, 60), (102, 77), (126, 83), (128, 72), (144, 96), (160, 106), (192, 108)]
+    cams = scenes.uneven_views(sizes)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("batched 8 uneven views")
+    vb = gs.ViewBatch(cams, (16, 16), DEV)
+    out = gs.render(g, vb, P)
+    for v, c in enumerate(cams):
+        one = gs.ViewBatch([c], (16, 16), DEV)
+        o1 = gs.render(g, one, P)
+        assert torch.equal(vb.image(out["rgb"], v), one.image(o1["rgb"], 0))
+        assert torch.equal(vb.plane(out["t_final"], v), one.plane(o1["t_final"], 0))
+
+
+@pytest.mark.parametrize("case", ["plain", "mixture"])
+def test_importance_matches_oracle(case):
+    sc, cam0 = _case(case)
+    W, H = cam0.width, cam0.height
+    cams = [cam0] + [scenes.orbit_camera(a, e, 4.0, W, H) for a, e in [(1.3, 0.1), (2.9, -0.2)]]
+    _say(f"importance {case}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    vb = gs.ViewBatch(cams, (16, 16), DEV)
+    h = gs.importance(g, vb, P)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().astype(np.float64)
+    hr = np.zeros(sc.n)
+    band = np.zeros(sc.n, bool)
+    for c in cams:
+        _, runs = band_runs(sc, c, P, want_h=True)
+        hr = np.maximum(hr, runs[0]["h"])
+        band |= h_band(runs)
+    err = np.abs(h - hr)
+    _say(f"  max err {err.max():.2e}")
+    check_band(err > TOL_H, band, f"importance {case}")
+    assert (hr > 0).sum() > 50
+    # the prune mask (Sec. 3.3) agrees except within 1e-5 of the threshold
+    t = 0.01
+    m_gpu = gs.prune_mask(torch.as_tensor(h), t).numpy()
+    m_ref = oracle.prune_mask(hr, t)
+    near = np.abs(hr - t) <= TOL_H
+    assert np.array_equal(m_gpu[~(near | band)], m_ref[~(near | band)])
+
+
+def test_cluster_visibility_matches_oracle():
+    sc = scenes.mixture_scene(5000, seed=8, sh_degree=0)
+    cams = [scenes.orbit_camera(2 * np.pi * k / 6, 0.1 * (k % 3), 4.0, 96, 72) for k in range(6)]
+    assign = [0, 0, 1, 1, 2, 2]
+    k = 3
+    t = 0.01
+    _say("cluster visibility")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    vb = gs.ViewBatch(cams, (16, 16), DEV)
+    bits = gs.cluster_visibility(g, vb, assign, k, t, P)
+    torch.cuda.synchronize()
+    words = (sc.n + 31) // 32
+    b = bits.cpu().numpy().view(np.uint32).reshape(k, words)
+    got = np.unpackbits(b.view(np.uint8).reshape(k, -1), axis=1, bitorder="little")[:, :sc.n].astype(bool)
+    ref = oracle.cluster_bits(sc, cams, assign, k, P, t)
+    # band: Gaussians whose per-cluster max is within reach of the threshold under the band
+    hc = np.zeros((k, sc.n))
+    band = np.zeros((k, sc.n), bool)
+    for v, c in enumerate(cams):
+        _, runs = band_runs(sc, c, P, want_h=True)
+        cl = assign[v]
+        hc[cl] = np.maximum(hc[cl], runs[0]["h"])
+        band[cl] |= h_band(runs)
+    band |= np.abs(hc - t) <= TOL_H
+    check_band(got != ref, band, "cluster bits")
+    # compaction of each row to a sorted index list
+    for c in range(k):
+        lst = gs.bits_to_list(bits[c * words:(c + 1) * words], sc.n).cpu().numpy()
+        assert np.array_equal(lst, np.nonzero(got[c])[0])
+
+
+def test_filtered_render_matches_oracle_on_subset():
+    sc, cam = _case("mixture")
+    rng = np.random.default_rng(3)
+    keep = np.sort(rng.choice(sc.n, sc.n // 2, replace=False)).astype(np.int32)
+    _say("subset render")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    out = gs.render(g, views, P, subset=torch.as_tensor(keep, device=DEV))
+    img = views.image(out["rgb"], 0).cpu().numpy().astype(np.float64)
+    sub = sc.subset(keep)
+    _, runs = band_runs(sub, cam, P)
+    band = image_band(runs)
+    check_band(np.abs(img - runs[0]["rgb"]).max(0) > TOL_IMAGE, band, "subset render")
+
+
+def _grad_check(got, ref, name):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nr = np.linalg.norm(ref)
+    rel = np.linalg.norm(got - ref) / max(nr, 1e-30)
+    rms = np.sqrt(np.mean(ref ** 2))
+    elem = np.abs(got - ref) <= TOL_GRAD * (np.abs(ref) + 1e-2 * rms)
+    _say(f"  grad {name}: rel {rel:.2e}, elements outside {np.sum(~elem)} of {elem.size}")
+    return rel, elem
+
+
+@pytest.mark.parametrize("case", ["plain", "mixture"])
+def test_backward_matches_oracle(case):
+    sc, cam = _case(case)
+    if case == "mixture":
+        sc = sc.subset(np.arange(3000))
+    rng = np.random.default_rng(11)
+    w = rng.uniform(-1, 1, (3, cam.height, cam.width)).astype(np.float32)
+    _say(f"backward {case}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    out = gs.render(g, views, P)
+    grad = gs.render_bwd(g, views, out["proj"], out["bins"], out["t_final"], out["n_last"],
+                         torch.as_tensor(w.reshape(-1), device=DEV), P)
+    torch.cuda.synchronize()
+    ref = oracle.render_bwd(sc, cam, P, w.astype(np.float64))
+    # pixels in the threshold band have a different composited set; exclude the Gaussians they touch
+    _, runs = band_runs(sc, cam, P)
+    band = image_band(runs)
+    img = views.image(out["rgb"], 0).cpu().numpy().astype(np.float64)
+    check_band(np.abs(img - runs[0]["rgb"]).max(0) > TOL_IMAGE, band, f"backward {case} forward image")
+    for name in ("mean", "scale", "quat", "opacity", "sh"):
+        rel, elem = _grad_check(getattr(grad, name).cpu().numpy(), ref[name], name)
+        assert rel <= TOL_GRAD, name
+        if band.sum() == 0:
+            assert elem.mean() >= 0.999, name
+
+
+def test_autograd_function_and_l1_loss():
+    sc, cam = _case("plain")
+    tgt = scenes.target_images([cam])[0]
+    _say("autograd")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    params = [t.clone().requires_grad_(True) for t in (g.mean, g.scale, g.quat, g.opacity, g.sh)]
+    rgb = gs.GSRender.apply(*params, views, g.sh_degree, P)
+    target = torch.as_tensor(tgt.reshape(-1), device=DEV)
+    loss = (rgb - target).abs().mean()
+    loss.backward()
+    img = rgb.detach().cpu().numpy().reshape(3, cam.height, cam.width).astype(np.float64)
+    dl = np.sign(img - tgt.astype(np.float64)) / img.size
+    ref = oracle.render_bwd(sc, cam, P, dl)
+    for t, name in zip(params, ("mean", "scale", "quat", "opacity", "sh")):
+        rel, _ = _grad_check(t.grad.cpu().numpy(), ref[name], name)
+        assert rel <= TOL_GRAD, name
+
+
+def test_degenerate_inputs():
+    _say("degenerate: empty scene, all culled, 1x1 view, overflow")
+    cam = scenes.plain_view()
+    empty = scenes.uniform_cube_scene(0)
+    g = gs.Gaussians.from_scene(empty, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    out = gs.render(g, views, P)
+    assert torch.all(out["rgb"] == 0) and torch.all(out["t_final"] == 1)
+    # every Gaussian behind the camera
+    sc = scenes.uniform_cube_scene(100, seed=1)
+    sc.mean[2] = -10.0
+    out = gs.render(gs.Gaussians.from_scene(sc, DEV), views, P)
+    assert torch.all(out["t_final"] == 1) and int(out["bins"].n_pairs.item()) == 0
+    # a 1x1 view
+    one = scenes.Camera(np.eye(3, dtype=np.float32), np.float32([0, 0, 4]), 100.0, 100.0, 0.5, 0.5, 1, 1)
+    sc2 = scenes.uniform_cube_scene(500, seed=2)
+    o1 = gs.render(gs.Gaussians.from_scene(sc2, DEV), gs.ViewBatch([one], (8, 8), DEV), P)
+    ref = oracle.render(sc2, one, P)
+    assert abs(float(o1["rgb"][0]) - ref["rgb"][0, 0, 0]) < TOL_IMAGE
+    # a pair buffer that is too small is reported, nothing is written out of bounds
+    g2 = gs.Gaussians.from_scene(sc2, DEV)
+    proj = gs.preprocess(g2, views, P)
+    bins = gs.Bins(4096, views.n_tiles, DEV)
+    bins.capacity = 16  # buffers hold 4096 entries; everything past 16 is a canary
+    bins.keys.fill_(7)
+    bins.vals.fill_(7)
+    gs.bin_sort(proj, views, bins=bins, grow=False)
+    torch.cuda.synchronize()
+    assert int(bins.overflow.item()) == 1 and int(bins.n_pairs.item()) > 16
+    assert torch.all(bins.keys[16:] == 7) and torch.all(bins.vals[16:] == 7)
+    rgb, t, _ = gs.render_fwd(proj, views, bins, P)
+    assert torch.all(t == 1)  # ranges stay empty after an overflow
+
+
+@pytest.mark.slow
+def test_full_size_sampled_pixels():
+    """1M Gaussians, 1256x828 (the benchmark frame): 192 sampled pixels against the oracle."""
+    sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+    cam = scenes.orbit_views(8)[0]
+    _say("full size 1M x 1256x828, sampled pixels")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    r = gs.Renderer(g, views, P)
+    rgb = r.forward()
+    torch.cuda.synchronize()
+    assert r.check()[0] is False
+    img = views.image(rgb, 0).cpu().numpy().astype(np.float64)
+    T = views.plane(r.t_final, 0).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    px = rng.integers(0, cam.width, 192).astype(np.int32)
+    py = rng.integers(0, cam.height, 192).astype(np.int32)
+    _, runs = band_runs(sc, cam, P, pixels=(px, py))
+    band = image_band(runs)
+    got = img[:, py, px].T
+    mism = (np.abs(got - runs[0]["rgb"]).max(1) > TOL_IMAGE) | (np.abs(T[py, px] - runs[0]["T"]) > TOL_IMAGE)
+    _say(f"  sampled max err {np.abs(got - runs[0]['rgb']).max():.2e}")
+    check_band(mism, band, "full-size sampled pixels")
