@@ -82,6 +82,8 @@ def main():
     P = scenes.Params()
     K, W = args.steps, args.warmup
 
+    copy_gbps = calib_copy(torch, dev)
+    log(f"device copy of 256 MiB: {copy_gbps:.0f} GB/s (read + write)")
     log("scene: 1M Gaussians, mixture-32, SH degree 3")
     sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
     cams = scenes.orbit_views(8)
@@ -172,7 +174,8 @@ def main():
                 "per_unit": f"{OPS_PER_COMPOSITE} lane-ops per composited (pixel, Gaussian)",
                 "units_per_launch": mc, "avg_launch_ms": avg["render_fwd"]}
 
-    extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3}
+    extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3,
+             "copy_256MiB_GBps": copy_gbps}
 
     if not args.quick:
         extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
@@ -192,6 +195,19 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def calib_copy(torch, dev, nbytes=256 << 20, reps=5):
+    """A plain device-to-device copy of known size: its measured rate is the practical HBM
+    ceiling, and its hardware byte counters calibrate the counters of the other kernels."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(reps):
+            dst.copy_(src)
+    return 2 * nbytes * reps / (tm.ms() * 1e-3) / 1e9
 
 
 def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):

@@ -45,10 +45,11 @@
  *     returned as GS_ERR_INVALID_ARG / GS_ERR_UNSUPPORTED; a failed launch returns
  *     GS_ERR_HIP. gs_last_error() gives a message for the calling thread.
  *   - Pair-buffer overflow is detected on the device: gs_bin_sort writes the
- *     number of pairs required to *bins->n_pairs and sets *bins->overflow to 1
- *     when it exceeds bins->capacity. No write goes out of bounds; the results of
- *     the later passes are then undefined and the caller must retry with a
- *     larger capacity.
+ *     number of pairs required to *bins->n_pairs and sets bit 0 of *bins->overflow
+ *     when it exceeds bins->capacity. No write goes out of bounds; the tile ranges
+ *     are then left empty and the caller must retry with a larger capacity. Bit 1
+ *     is set if a cross-block wait inside the sort ran out of its spin budget
+ *     (results invalid, nothing written out of bounds); the kernels never hang.
  *   - Accumulating outputs (importance h, visibility bits, gradients) are
  *     combined into what the buffer holds (max, OR, +=), so results over view
  *     chunks compose; the caller initialises them.
@@ -160,7 +161,7 @@ typedef struct gs_projected {
  *   vals    [capacity] index of the Gaussian within its view (0 .. n-1)
  *   ranges  [n_tiles][2] [start, end) of each tile in keys/vals
  *   n_pairs device scalar: pairs required
- *   overflow device scalar: 1 if n_pairs > capacity, else 0 */
+ *   overflow device scalar: 0 when the bins are valid (see the conventions above) */
 typedef struct gs_bins {
     uint64_t* keys;
     uint32_t* vals;

@@ -33,7 +33,7 @@ gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_param
 gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
                                 const float*, gs_gaussians_grad*, hipStream_t);
 gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t);
-size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity);
+size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
 gs_status launch_bits_to_list(const uint32_t*, int64_t, int32_t*, int64_t*, void*, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
@@ -135,9 +135,8 @@ gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w,
 }
 
 size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
-    (void)n_tiles;
     if (n < 0 || n_views < 0) return 0;
-    size_t b = sort_workspace_bytes(n, n_views, capacity);
+    size_t b = sort_workspace_bytes(n, n_views, capacity, n_tiles);
     b = std::max(b, bwd_workspace_bytes(n, n_views));
     b = std::max(b, list_workspace_bytes(n));
     return b;
@@ -163,7 +162,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* 
                       void* stream) {
     gs_status st;
     if ((st = check_projected(proj, false)) || (st = check_views(views)) || (st = check_bins(bins))) return st;
-    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity);
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
     if (ws_bytes < need || (need > 0 && !ws))
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
     return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);

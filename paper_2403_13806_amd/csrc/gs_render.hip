@@ -56,10 +56,24 @@ __device__ __forceinline__ bool box_misses(const float4 b, float x0, float x1, f
     return b.y < x0 || b.x > x1 || b.w < y0 || b.z > y1;
 }
 
+// bit w set when the support box meets the 8x8 pixel block of wave w (tile origin at the
+// pixel centre (ox, oy); waves tile the TW x TH tile row-major in 8x8 blocks)
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t wave_hits(const float4 b, float ox, float oy) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < (TW / 8) * (TH / 8); ++w) {
+        const float x0 = ox + (float)((w % (TW / 8)) * 8), y0 = oy + (float)((w / (TW / 8)) * 8);
+        if (!box_misses(b, x0, x0 + 7.f, y0, y0 + 7.f)) m |= 1u << w;
+    }
+    return m;
+}
+
 struct TileGeom {
     int view, W, H, px, py, wave;
     bool inside;
     float wx0, wy0;  // centre of the wave's first pixel
+    float ox, oy;    // centre of the tile's first pixel
     int64_t pix;     // global pixel index
 };
 
@@ -80,6 +94,8 @@ __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     g.inside = g.px < g.W && g.py < g.H;
     g.wx0 = (float)(tx * TW + bx) + 0.5f;
     g.wy0 = (float)(ty * TH + by) + 0.5f;
+    g.ox = (float)(tx * TW) + 0.5f;
+    g.oy = (float)(ty * TH) + 0.5f;
     g.pix = a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
     return g;
 }
@@ -101,14 +117,13 @@ template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
     constexpr int NT = TW * TH;
     __shared__ gs_splat rec[NT];
-    __shared__ float4 box[NT];
     __shared__ uint32_t gid[NT];
+    __shared__ uint8_t hit[NT];
     const int tile = blockIdx.x;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
-    const int t = threadIdx.x, l = t & 63;
+    const int t = threadIdx.x, l = t & 63, w = g.wave;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
-    const float x0 = g.wx0, x1 = g.wx0 + 7.f, y0 = g.wy0, y1 = g.wy0 + 7.f;
     const float amax = a.p.alpha_max, tmin = a.p.t_min;
     const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -118,48 +133,56 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
     if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
     for (uint32_t base = start; base < end; base += NT) {
         if (__syncthreads_and(done)) break;
+        // stage one record per lane and mark the wave blocks its support box meets
         const uint32_t k = base + t;
+        uint32_t hm = 0;
         if (k < end) {
             const uint32_t id = a.vals[k];
             const gs_splat s = sp[id];
             rec[t] = s;
-            box[t] = support_box(s);
             gid[t] = id;
+            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
         }
+        hit[t] = (uint8_t)hm;
         __syncthreads();
-        const int nb = (int)min((uint32_t)NT, end - base);
-        for (int j = 0; j < nb; ++j) {
-            if (box_misses(box[j], x0, x1, y0, y1)) continue;
-            if (ballot(!done) == 0) break;
-            float w = 0.f;
-            if (!done) {
-                const gs_splat& s = rec[j];
-                float al, G, dx, dy;
-                if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
-                    w = al * T;
-                    if (MODE == MODE_FWD) {
-                        C0 += w * s.rgb[0];
-                        C1 += w * s.rgb[1];
-                        C2 += w * s.rgb[2];
+        // each wave walks only the entries that meet its 8x8 block, in list order
+#pragma unroll 1
+        for (int c = 0; c < NT / 64; ++c) {
+            uint64_t m = ballot((hit[c * 64 + l] >> w) & 1u);
+            while (m) {
+                const int j = c * 64 + (int)__builtin_ctzll(m);
+                m &= m - 1;
+                float wgt = 0.f;
+                if (!done) {
+                    const gs_splat& s = rec[j];
+                    float al, G, dx, dy;
+                    if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
+                        wgt = al * T;
+                        if (MODE == MODE_FWD) {
+                            C0 += wgt * s.rgb[0];
+                            C1 += wgt * s.rgb[1];
+                            C2 += wgt * s.rgb[2];
+                        }
+                        T = T * (1.f - al);
+                        last = base + j + 1;
+                        ++ncomp;
+                        if (T < tmin) done = true;
                     }
-                    T = T * (1.f - al);
-                    last = base + j + 1;
-                    ++ncomp;
-                    if (T < tmin) done = true;
+                }
+                if (MODE == MODE_IMPORTANCE) {
+                    if (ballot(wgt > 0.f)) {
+                        const float mx = wave_max_nonneg(wgt);
+                        if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + gid[j], __float_as_uint(mx));
+                    }
+                }
+                if (MODE == MODE_VISIBILITY) {
+                    if (ballot(wgt > a.t_cluster) != 0 && l == 0) {
+                        const uint32_t id = gid[j];
+                        atomicOr(a.bits + (int64_t)cluster * a.words + (id >> 5), 1u << (id & 31));
+                    }
                 }
             }
-            if (MODE == MODE_IMPORTANCE) {
-                if (ballot(w > 0.f)) {
-                    const float m = wave_max_nonneg(w);
-                    if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + gid[j], __float_as_uint(m));
-                }
-            }
-            if (MODE == MODE_VISIBILITY) {
-                if (ballot(w > a.t_cluster) != 0 && l == 0) {
-                    const uint32_t id = gid[j];
-                    atomicOr(a.bits + (int64_t)cluster * a.words + (id >> 5), 1u << (id & 31));
-                }
-            }
+            if (ballot(!done) == 0) break;
         }
     }
     if (MODE == MODE_FWD && g.inside) {
@@ -185,15 +208,14 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
     constexpr int NT = TW * TH;
     __shared__ gs_splat rec[NT];
-    __shared__ float4 box[NT];
     __shared__ uint32_t gid[NT];
+    __shared__ uint8_t hit[NT];
     __shared__ uint32_t top_s;
     const int tile = blockIdx.x;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
-    const int t = threadIdx.x, l = t & 63;
+    const int t = threadIdx.x, l = t & 63, w = g.wave;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
-    const float x0 = g.wx0, x1 = g.wx0 + 7.f, y0 = g.wy0, y1 = g.wy0 + 7.f;
     const float amax = a.p.alpha_max;
     const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
     float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
@@ -222,61 +244,70 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
         const uint32_t lo = (hi - start > (uint32_t)NT) ? hi - NT : start;
         const uint32_t k = lo + t;
         __syncthreads();
+        uint32_t hm = 0;
         if (k < hi) {
             const uint32_t id = a.vals[k];
             const gs_splat s = sp[id];
             rec[t] = s;
-            box[t] = support_box(s);
             gid[t] = id;
+            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
         }
+        hit[t] = (uint8_t)hm;
         __syncthreads();
-        for (int j = (int)(hi - lo) - 1; j >= 0; --j) {
-            if (box_misses(box[j], x0, x1, y0, y1)) continue;
-            const uint32_t pos = lo + j;
-            float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-            bool contrib = false;
-            if (g.inside && pos < last) {
-                const gs_splat& s = rec[j];
-                float al, G, dx, dy;
-                if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
-                    contrib = true;
-                    const float om = 1.f - al;
-                    T = T / om;
-                    const float w = al * T;
-                    gr = dC0 * w;
-                    gg = dC1 * w;
-                    gbl = dC2 * w;
-                    const float dA = dC0 * (T * s.rgb[0] - S0 / om) + dC1 * (T * s.rgb[1] - S1 / om) +
-                                     dC2 * (T * s.rgb[2] - S2 / om);
-                    S0 += w * s.rgb[0];
-                    S1 += w * s.rgb[1];
-                    S2 += w * s.rgb[2];
-                    if (s.opacity * G < amax) {
-                        go = dA * G;
-                        const float dq = -0.5f * al * dA;
-                        ga = dq * dx * dx;
-                        gb = dq * 2.f * dx * dy;
-                        gc = dq * dy * dy;
-                        gu = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
-                        gv = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
+        // entries that meet this wave's block, back to front
+#pragma unroll 1
+        for (int c = NT / 64 - 1; c >= 0; --c) {
+            uint64_t m = ballot((hit[c * 64 + l] >> w) & 1u);
+            while (m) {
+                const int b = 63 - (int)__builtin_clzll(m);
+                m &= ~(1ull << b);
+                const int j = c * 64 + b;
+                const uint32_t pos = lo + j;
+                float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+                bool contrib = false;
+                if (g.inside && pos < last) {
+                    const gs_splat& s = rec[j];
+                    float al, G, dx, dy;
+                    if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
+                        contrib = true;
+                        const float om = 1.f - al;
+                        T = T / om;
+                        const float wt = al * T;
+                        gr = dC0 * wt;
+                        gg = dC1 * wt;
+                        gbl = dC2 * wt;
+                        const float dA = dC0 * (T * s.rgb[0] - S0 / om) + dC1 * (T * s.rgb[1] - S1 / om) +
+                                         dC2 * (T * s.rgb[2] - S2 / om);
+                        S0 += wt * s.rgb[0];
+                        S1 += wt * s.rgb[1];
+                        S2 += wt * s.rgb[2];
+                        if (s.opacity * G < amax) {
+                            go = dA * G;
+                            const float dq = -0.5f * al * dA;
+                            ga = dq * dx * dx;
+                            gb = dq * 2.f * dx * dy;
+                            gc = dq * dy * dy;
+                            gu = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
+                            gv = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
+                        }
                     }
                 }
-            }
-            if (ballot(contrib)) {
-                const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
-                            sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
-                            sbl = wave_sum(gbl);
-                if (l == 0) {
-                    const int64_t o = vbase + gid[j];
-                    atomicAdd(a.g2 + 0 * VN + o, su);
-                    atomicAdd(a.g2 + 1 * VN + o, sv);
-                    atomicAdd(a.g2 + 2 * VN + o, sa);
-                    atomicAdd(a.g2 + 3 * VN + o, sb);
-                    atomicAdd(a.g2 + 4 * VN + o, sc);
-                    atomicAdd(a.g2 + 5 * VN + o, so);
-                    atomicAdd(a.g2 + 6 * VN + o, sr);
-                    atomicAdd(a.g2 + 7 * VN + o, sg);
-                    atomicAdd(a.g2 + 8 * VN + o, sbl);
+                if (ballot(contrib)) {
+                    const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
+                                sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
+                                sbl = wave_sum(gbl);
+                    if (l == 0) {
+                        const int64_t o = vbase + gid[j];
+                        atomicAdd(a.g2 + 0 * VN + o, su);
+                        atomicAdd(a.g2 + 1 * VN + o, sv);
+                        atomicAdd(a.g2 + 2 * VN + o, sa);
+                        atomicAdd(a.g2 + 3 * VN + o, sb);
+                        atomicAdd(a.g2 + 4 * VN + o, sc);
+                        atomicAdd(a.g2 + 5 * VN + o, so);
+                        atomicAdd(a.g2 + 6 * VN + o, sr);
+                        atomicAdd(a.g2 + 7 * VN + o, sg);
+                        atomicAdd(a.g2 + 8 * VN + o, sbl);
+                    }
                 }
             }
         }
