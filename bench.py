@@ -180,6 +180,9 @@ def main():
     if not args.quick:
         extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
         extra["importance"] = importance_rate(torch, gs, rs, n, dev, K)
+        del rs
+        extra["importance_150_views"] = importance_pass(torch, gs, scenes, P, dev)
+        extra["house_filtering"] = filtered_pass(torch, gs, scenes, P, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -239,27 +242,19 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):
     out["fwd_bwd_200k_1view_views_per_s"] = K / (time.perf_counter() - t0)
     log(f"  {out['fwd_bwd_200k_1view_views_per_s']:.1f} views/s")
 
-    # --- 1M Gaussians, 8 uneven views: batched (one call chain) vs one view at a time ---
-    log("fwd+bwd: 1M Gaussians, 8 uneven views, batched vs per view")
+    # --- 1M Gaussians, 8 uneven views: batched vs one view at a time ---
+    from paper_2403_13806_amd.train import FwdBwdStep, StepConfig, autotune, time_step
+    log("fwd+bwd: 1M Gaussians, 8 uneven views; plain = 8 sequential per-view steps at 16x16")
     cams = scenes.uneven_views()
     tg = scenes.target_images(cams)
-    vb = gs.ViewBatch(cams, (16, 16), dev)
-    rb = gs.Renderer(g1m, vb, P)
-    tb = vb.pack_images(tg)
     gradb = gs.Gaussians(torch.zeros_like(g1m.mean), torch.zeros_like(g1m.scale), torch.zeros_like(g1m.quat),
                          torch.zeros_like(g1m.opacity), torch.zeros_like(g1m.sh), 3)
-    dlb = torch.empty_like(tb)
     lb = torch.zeros(1, device=dev)
     singles = []
     for v, c in enumerate(cams):
         rv = gs.Renderer(g1m, gs.ViewBatch([c], (16, 16), dev), P)
         tv = torch.as_tensor(tg[v].reshape(-1), device=dev)
         singles.append((rv, tv, torch.empty_like(tv)))
-
-    def batched():
-        rgb = rb.forward()
-        gs.l1_loss_grad(rgb[:tb.numel()], tb, dlb, lb)
-        rb.backward(dlb, gradb)
 
     def plain():
         for rv, tv, dv in singles:
@@ -268,17 +263,35 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):
             rv.backward(dv, gradb)
 
     kk = max(3, K // 8)
-    for fn, name in ((batched, "batched"), (plain, "plain")):
-        for _ in range(2):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(kk):
-            fn()
-        torch.cuda.synchronize()
-        out[f"fwd_bwd_1M_8uneven_{name}_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
-        log(f"  {name}: {out[f'fwd_bwd_1M_8uneven_{name}_views_per_s']:.1f} views/s")
-    assert not rb.check()[0]
+    for _ in range(2):
+        plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(kk):
+        plain()
+    torch.cuda.synchronize()
+    out["fwd_bwd_1M_8uneven_plain_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
+    log(f"  plain per-view: {out['fwd_bwd_1M_8uneven_plain_views_per_s']:.1f} views/s")
+    del singles
+    # batched, same default launch, not captured
+    eager = FwdBwdStep(g1m, cams, tg, P, StepConfig(16, 16, 1, False), device=dev)
+    out["fwd_bwd_1M_8uneven_batched_views_per_s"] = 8 / (time_step(eager, kk) * 1e-3)
+    log(f"  batched, 16x16, eager: {out['fwd_bwd_1M_8uneven_batched_views_per_s']:.1f} views/s")
+    assert eager.ok()
+    del eager
+    # batched, autotuned launch configuration, captured in a hipGraph and replayed
+    log("  autotuning the batched step")
+    cfg = autotune(g1m, cams, tg, P, reps=3, use_cache=False, device=dev, log=log)
+    step = FwdBwdStep(g1m, cams, tg, P, cfg, device=dev).capture()
+    t0 = time.perf_counter()
+    for _ in range(kk):
+        step.run()
+    torch.cuda.synchronize()
+    out["fwd_bwd_1M_8uneven_batched_graph_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
+    out["fwd_bwd_1M_8uneven_batched_graph_config"] = {"tile": list(cfg.tile), "batch_depth": cfg.batch_depth,
+                                                      "persistent": cfg.persistent}
+    log(f"  batched, {cfg}, hipGraph: {out['fwd_bwd_1M_8uneven_batched_graph_views_per_s']:.1f} views/s")
+    assert step.ok()
     return out
 
 
@@ -294,6 +307,88 @@ def importance_rate(torch, gs, rs, n, dev, K):
     v = K / (time.perf_counter() - t0)
     log(f"importance: {v:.1f} views/s (1M Gaussians, 1256x828)")
     return {"views_per_s_1M_1256x828": v}
+
+
+def importance_pass(torch, gs, scenes, P, dev, chunk=10):
+    """Pruning score over all training rays: 500k Gaussians (mixture, SH-3), 150 orbit views
+    at 1256x828 in batches of `chunk` views, persistent longest-first launch; h = max over all
+    pixels of all views of alpha*T, mask h < 0.01."""
+    log("importance: 500k Gaussians, 150 views at 1256x828")
+    sc = scenes.mixture_scene(500_000, seed=0, sh_degree=3)
+    cams = scenes.orbit_views(150)
+    g = gs.Gaussians.from_scene(sc, dev)
+    rs = [gs.Renderer(g, gs.ViewBatch(cams[i:i + chunk], (16, 16), dev, persistent=True), P, want_color=False)
+          for i in range(0, len(cams), chunk)]
+    h = torch.zeros(g.n, device=dev)
+    for r in rs:
+        r.importance(h)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h.zero_()
+        for r in rs:
+            r.importance(h)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    assert all(not r.check()[0] for r in rs)
+    hh = h.cpu().numpy()
+    kept = {str(t): int((hh >= t).sum()) for t in (0.001, 0.005, 0.01, 0.03, 0.1, 0.25)}
+    out = {"views_per_s": len(cams) / dt, "ms_all_views": dt * 1e3, "gaussians": g.n,
+           "kept_at_t_prune": kept, "pruned_at_0.01": int((hh < 0.01).sum()), "never_composited": int((hh == 0).sum())}
+    log(f"  {out['views_per_s']:.0f} views/s, kept at 0.01: {kept['0.01']} of {g.n}")
+    return out
+
+
+def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01):
+    """Test-time visibility filtering at house scale: 5M Gaussians in 12 rooms, 640 training
+    cameras at 1920x1080 clustered into 64 by k-means, per-cluster lists at h > t_cluster, a
+    300-frame 1920x1080 path rendered with and without the lists."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    log(f"house: {n} Gaussians, 640 training views, k={k}, t_cluster={t_cluster}")
+    sc = scenes.house_scene(n)
+    train = scenes.house_training_views(640)
+    path = scenes.house_test_path(300)
+    g = gs.Gaussians.from_scene(sc, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vf = gs.VisibilityFilter(g, train, k=k, t_cluster=t_cluster, params=P, chunk=8, device=dev)
+    torch.cuda.synchronize()
+    t_vis = time.perf_counter() - t0
+    sizes = np.array([int(x.shape[0]) for x in vf.lists])
+    frame_lists = [vf.list_for(c) for c in path]
+    pr = PathRenderer(g, path, P, device=dev, max_entries=g.n)
+    # unfiltered and filtered frame rates over the whole path
+    rates, imgs = {}, {}
+    for name, lists in (("unfiltered", [None] * len(path)), ("filtered", frame_lists)):
+        for f in range(3):
+            pr.frame(f, lists[f])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(len(path)):
+            pr.frame(f, lists[f])
+        torch.cuda.synchronize()
+        rates[name] = len(path) / (time.perf_counter() - t0)
+    # validation pass (untimed): capacity, and filtered vs unfiltered image difference
+    maxd, psnr = 0.0, []
+    for f in range(0, len(path), 25):
+        a = pr.frame(f, None).clone()
+        assert pr.ok()
+        b = pr.frame(f, frame_lists[f]).clone()
+        assert pr.ok()
+        d = (a - b).abs()
+        maxd = max(maxd, float(d.max()))
+        mse = float((d * d).mean())
+        psnr.append(10 * np.log10(1.0 / max(mse, 1e-20)))
+    out = {"gaussians": n, "train_views": len(train), "k": k, "t_cluster": t_cluster,
+           "visibility_pass_s": t_vis, "train_views_per_s": len(train) / t_vis,
+           "list_size_mean": float(sizes.mean()), "list_size_max": int(sizes.max()),
+           "unfiltered_fps": rates["unfiltered"], "filtered_fps": rates["filtered"],
+           "speedup": rates["filtered"] / rates["unfiltered"],
+           "filtered_vs_unfiltered_max_abs": maxd, "filtered_vs_unfiltered_psnr_min": float(min(psnr))}
+    log(f"  lists mean {sizes.mean():.0f}; unfiltered {rates['unfiltered']:.0f} fps, filtered "
+        f"{rates['filtered']:.0f} fps; max |diff| {maxd:.3g}, min PSNR {min(psnr):.1f} dB")
+    return out
 
 
 def cpu_baseline(sc, cam, P, m=1024):

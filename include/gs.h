@@ -141,6 +141,8 @@ typedef struct gs_views {
     int32_t tile_w, tile_h;      /* 8, 16 or 32 each; tile_w * tile_h in {64, 128, 256} */
     int32_t n_tiles;
     int64_t n_pixels;
+    int32_t batch_depth;         /* list records staged per lane per batch in compositing: 1 or 2 */
+    int32_t persistent;          /* 1: compositing runs as a persistent grid over bins->queue */
 } gs_views;
 
 /* Per-(view, Gaussian) outputs of gs_preprocess, [n_views][n] each:
@@ -161,7 +163,10 @@ typedef struct gs_projected {
  *   vals    [capacity] index of the Gaussian within its view (0 .. n-1)
  *   ranges  [n_tiles][2] [start, end) of each tile in keys/vals
  *   n_pairs device scalar: pairs required
- *   overflow device scalar: 0 when the bins are valid (see the conventions above) */
+ *   overflow device scalar: 0 when the bins are valid (see the conventions above)
+ *   queue   [n_tiles] or NULL: when set, gs_bin_sort also writes every tile id ordered by
+ *           decreasing list length (by powers of two; order within a power is unspecified),
+ *           the work order of the persistent compositing launch */
 typedef struct gs_bins {
     uint64_t* keys;
     uint32_t* vals;
@@ -169,6 +174,7 @@ typedef struct gs_bins {
     uint64_t capacity; /* < 2^32 */
     uint64_t* n_pairs;
     uint32_t* overflow;
+    uint32_t* queue;
 } gs_bins;
 
 /* Host helper: fill tile_offset[n_views+1] and pixel_offset[n_views+1] (HOST arrays)

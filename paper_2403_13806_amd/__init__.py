@@ -4,7 +4,8 @@ The computation lives in libgs_hip.so (C ABI in include/gs.h, HIP kernels in csr
 this package only marshals PyTorch device buffers into those calls.
 """
 from ._lib import GSError, load  # noqa: F401
-from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, alloc_workspace,  # noqa: F401
+from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, VisibilityFilter,  # noqa: F401
+                    alloc_workspace,
                     bin_sort, bits_to_list, cluster_visibility, importance, kmeans, l1_loss_grad, make_params,
                     nearest_centre,
                     preprocess, prune_mask, render, render_bwd, render_fwd, workspace_bytes)

@@ -66,6 +66,16 @@ static gs_status check_views(const gs_views* v) {
         return set_error(GS_ERR_UNSUPPORTED, "tile %dx%d: each side must be 8, 16 or 32 and the area <= 256",
                          v->tile_w, v->tile_h);
     if (v->n_tiles < 0 || v->n_pixels < 0) return set_error(GS_ERR_INVALID_ARG, "negative tile or pixel count");
+    if (v->batch_depth != 1 && v->batch_depth != 2)
+        return set_error(GS_ERR_UNSUPPORTED, "batch_depth must be 1 or 2 (got %d)", v->batch_depth);
+    if (v->persistent != 0 && v->persistent != 1)
+        return set_error(GS_ERR_INVALID_ARG, "persistent must be 0 or 1 (got %d)", v->persistent);
+    return GS_OK;
+}
+
+static gs_status check_queue(const gs_views* v, const gs_bins* b) {
+    if (v->persistent && !b->queue)
+        return set_error(GS_ERR_INVALID_ARG, "persistent compositing needs bins->queue (built by gs_bin_sort)");
     return GS_OK;
 }
 
@@ -174,6 +184,7 @@ gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const g
     if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
         (st = check_params(p)))
         return st;
+    if ((st = check_queue(views, bins))) return st;
     if (views->n_pixels > 0 && (!rgb || !t_final || !n_last))
         return set_error(GS_ERR_INVALID_ARG, "output image pointer is NULL");
     return launch_render_fwd(proj, views, bins, p, rgb, t_final, n_last, n_contrib, (hipStream_t)stream);
@@ -199,6 +210,7 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_p
         return set_error(GS_ERR_INVALID_ARG, "gradient or SH pointer is NULL");
     if (proj->n != g->n)
         return set_error(GS_ERR_INVALID_ARG, "backward needs a projection of all Gaussians (no subset)");
+    if ((st = check_queue(views, bins))) return st;
     if (views->n_pixels > 0 && (!t_final || !n_last || !dl_drgb))
         return set_error(GS_ERR_INVALID_ARG, "t_final, n_last or dl_drgb is NULL");
     const size_t need = bwd_workspace_bytes(g->n, views->n_views);
@@ -218,6 +230,7 @@ gs_status gs_importance(const gs_projected* proj, const gs_views* views, const g
         (st = check_params(p)))
         return st;
     if (proj->n > 0 && !h_accum) return set_error(GS_ERR_INVALID_ARG, "h_accum is NULL");
+    if ((st = check_queue(views, bins))) return st;
     return launch_importance(proj, views, bins, p, h_accum, (hipStream_t)stream);
 }
 
@@ -232,6 +245,7 @@ gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views,
     if (!view_cluster || (proj->n > 0 && !bits_accum))
         return set_error(GS_ERR_INVALID_ARG, "view_cluster or bits_accum is NULL");
     if (!(t_cluster >= 0.f)) return set_error(GS_ERR_INVALID_ARG, "t_cluster must be >= 0");
+    if ((st = check_queue(views, bins))) return st;
     return launch_visibility(proj, views, bins, p, view_cluster, t_cluster, bits_accum, (hipStream_t)stream);
 }
 

@@ -94,16 +94,34 @@ struct Proj {
     double qmax, hx, hy;
 };
 
+// The eleven geometric parameters of one Gaussian (position, scale, quaternion, opacity).
+struct Geom {
+    float p[3], s[3], q[4], o;
+};
+
+__device__ __forceinline__ Geom load_geom(const float* __restrict__ mean, const float* __restrict__ scale,
+                                          const float* __restrict__ quat, const float* __restrict__ opac,
+                                          int64_t n_all, int64_t i) {
+    Geom g;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        g.p[k] = mean[k * n_all + i];
+        g.s[k] = scale[k * n_all + i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g.q[k] = quat[k * n_all + i];
+    g.o = opac[i];
+    return g;
+}
+
 // Returns false when the Gaussian is culled. The operation order below is part of the
 // tile-key definition; do not reassociate.
-__device__ bool project_one(const gs_camera& cam, const gs_params& p, const float* __restrict__ mean,
-                            const float* __restrict__ scale, const float* __restrict__ quat,
-                            const float* __restrict__ opac, int64_t n_all, int64_t i, Proj& P, double& o) {
+__device__ bool project_vals(const gs_camera& cam, const gs_params& p, const Geom& gm, Proj& P, double& o) {
 #pragma clang fp contract(off)
-    const double p0 = mean[i], p1 = mean[n_all + i], p2 = mean[2 * n_all + i];
-    const double s0 = scale[i], s1 = scale[n_all + i], s2 = scale[2 * n_all + i];
-    const double q0 = quat[i], q1 = quat[n_all + i], q2 = quat[2 * n_all + i], q3 = quat[3 * n_all + i];
-    o = opac[i];
+    const double p0 = gm.p[0], p1 = gm.p[1], p2 = gm.p[2];
+    const double s0 = gm.s[0], s1 = gm.s[1], s2 = gm.s[2];
+    const double q0 = gm.q[0], q1 = gm.q[1], q2 = gm.q[2], q3 = gm.q[3];
+    o = gm.o;
     if (!(isfinite(p0) && isfinite(p1) && isfinite(p2) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
           isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) && isfinite(o)))
         return false;
@@ -173,6 +191,13 @@ __device__ bool project_one(const gs_camera& cam, const gs_params& p, const floa
     return true;
 }
 
+__device__ __forceinline__ bool project_one(const gs_camera& cam, const gs_params& p, const float* __restrict__ mean,
+                                            const float* __restrict__ scale, const float* __restrict__ quat,
+                                            const float* __restrict__ opac, int64_t n_all, int64_t i, Proj& P,
+                                            double& o) {
+    return project_vals(cam, p, load_geom(mean, scale, quat, opac, n_all, i), P, o);
+}
+
 // unit direction (world) from the camera centre C = -R^T t to the mean, and |mean - C|
 __device__ __forceinline__ void view_dir(const gs_camera& cam, double p0, double p1, double p2, float d[3],
                                          double& len) {
@@ -208,6 +233,10 @@ struct PreArgs {
     uint32_t* count;
 };
 
+// DEG and COLOR are compile-time so the SH coefficients of the lane's Gaussian are loaded
+// into registers together with the geometry, before the projection math: every load of the
+// lane is in flight at once instead of the SH loads waiting behind the FP64 chain.
+template <int DEG, bool COLOR>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -219,9 +248,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         return;
     }
     const gs_camera cam = a.cams[v];
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    // every load of the lane is issued here, then waited for once
+    const Geom gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n_all, i);
+    float shv[COLOR ? NB * 3 : 1];
+    if (COLOR) {
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) shv[k] = a.sh[(int64_t)k * a.n_all + i];
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
+    }
     Proj P;
     double op;
-    if (!project_one(cam, a.p, a.mean, a.scale, a.quat, a.opac, a.n_all, i, P, op)) {
+    if (!project_vals(cam, a.p, gm, P, op)) {
         a.count[o] = 0u;
         return;
     }
@@ -249,17 +288,17 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     a.rect[o] = (uint64_t)(uint32_t)rx0 | ((uint64_t)(uint32_t)ry0 << 16) | ((uint64_t)(uint32_t)rx1 << 32) |
                 ((uint64_t)(uint32_t)ry1 << 48);
     float rgb[3] = {0.f, 0.f, 0.f};
-    if (a.want_color) {
+    if (COLOR) {
         float d[3];
         double len;
-        view_dir(cam, a.mean[i], a.mean[a.n_all + i], a.mean[2 * a.n_all + i], d, len);
+        view_dir(cam, gm.p[0], gm.p[1], gm.p[2], d, len);
         float Y[16];
-        sh_basis(a.deg, d[0], d[1], d[2], Y);
-        const int nb = (a.deg + 1) * (a.deg + 1);
+        sh_basis(DEG, d[0], d[1], d[2], Y);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             float acc = 0.f;
-            for (int k = 0; k < nb; ++k) acc += a.sh[(int64_t)(k * 3 + c) * a.n_all + i] * Y[k];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
             rgb[c] = fmaxf(acc + 0.5f, 0.f);
         }
     }
@@ -463,7 +502,16 @@ gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const 
     a.rect = out->rect;
     a.count = out->count;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)views->n_views);
-    hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, stream, a);
+    if (!want_color) {
+        hipLaunchKernelGGL((k_preprocess<0, false>), grid, dim3(256), 0, stream, a);
+    } else {
+        switch (g->sh_degree) {
+            case 0: hipLaunchKernelGGL((k_preprocess<0, true>), grid, dim3(256), 0, stream, a); break;
+            case 1: hipLaunchKernelGGL((k_preprocess<1, true>), grid, dim3(256), 0, stream, a); break;
+            case 2: hipLaunchKernelGGL((k_preprocess<2, true>), grid, dim3(256), 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_preprocess<3, true>), grid, dim3(256), 0, stream, a); break;
+        }
+    }
     return check_launch("preprocess");
 }
 

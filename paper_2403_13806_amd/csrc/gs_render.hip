@@ -3,13 +3,23 @@
 // visibility bits (eq. importance-score-vis); plus the reverse traversal that gives the
 // gradients of the 2D quantities.
 //
-// One workgroup per tile, one pixel per lane. Each wave owns an 8x8 pixel block, so a
-// record whose support box misses that block is skipped by the whole wave at once. The
-// tile's sorted list is streamed through LDS in batches of one record per lane (64-byte
-// records, one coalesced load per lane). The support test d^T conic d <= q_max runs in
-// FP64 -- same issue rate as FP32 on CDNA4 -- so it agrees with an FP64 evaluation; the
-// exponential and the transmittance are FP32.
+// One workgroup per tile, one pixel per lane. Each wave owns an 8x8 pixel block. The
+// tile's sorted list is streamed through LDS in batches of DEPTH records per lane (64-byte
+// records, coalesced loads); while a batch is staged, each loading lane marks which wave
+// blocks its record's support box meets, and each wave then walks only its hits (ballot
+// masks and scalar bit scans), so records that miss a block cost that wave nothing. The
+// support test d^T conic d <= q_max runs in FP64 -- same issue rate as FP32 on CDNA4 -- so
+// it agrees with an FP64 evaluation; the exponential and the transmittance are FP32.
+//
+// Launch forms: one workgroup per tile, or persistent -- a grid of (CUs x occupancy)
+// workgroups walking a list of tiles ordered longest-first (LPT), workgroup b taking
+// entries b, 2G-1-b, 2G+b, ... (boustrophedon), so no shared counter has to be reset
+// between launches and a captured graph can replay the launch as is.
 #include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "gs_device.hpp"
 
@@ -41,6 +51,9 @@ struct RenderArgs {
     const float* t_in;
     const uint32_t* last_in;
     float* g2;  // [9][n_views * n]
+    // persistent form
+    const uint32_t* queue;  // tiles, longest list first
+    int n_tiles;
 };
 
 // conservative float box of the support (FP64 conic -> covariance diagonal), padded so
@@ -113,15 +126,42 @@ __device__ __forceinline__ bool eval_alpha(const gs_splat& s, double xc, double 
     return true;
 }
 
-template <int TW, int TH, int MODE>
-__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
+
+template <int TW, int TH, int DEPTH>
+struct Smem {
+    static constexpr int NT = TW * TH;
+    static constexpr int BD = NT * DEPTH;  // records per batch
+    gs_splat rec[BD];
+    uint32_t gid[BD];
+    uint8_t hit[BD];
+    uint32_t top;
+};
+
+// stage records [base, base + cnt) of the tile's list; mark the wave blocks each one meets
+template <int TW, int TH, int DEPTH>
+__device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, const gs_splat* sp,
+                                      uint32_t base, uint32_t cnt, const TileGeom& g) {
     constexpr int NT = TW * TH;
-    __shared__ gs_splat rec[NT];
-    __shared__ uint32_t gid[NT];
-    __shared__ uint8_t hit[NT];
-    const int tile = blockIdx.x;
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+        const uint32_t q = threadIdx.x + d * NT;
+        uint32_t hm = 0;
+        if (q < cnt) {
+            const uint32_t id = a.vals[base + q];
+            const gs_splat s = sp[id];
+            sm.rec[q] = s;
+            sm.gid[q] = id;
+            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
+        }
+        sm.hit[q] = (uint8_t)hm;
+    }
+}
+
+template <int TW, int TH, int DEPTH, int MODE>
+__device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
+    constexpr int BD = TW * TH * DEPTH;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
-    const int t = threadIdx.x, l = t & 63, w = g.wave;
+    const int l = threadIdx.x & 63, w = g.wave;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
     const float amax = a.p.alpha_max, tmin = a.p.t_min;
@@ -131,30 +171,20 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
     uint32_t last = start, ncomp = 0;
     int cluster = 0;
     if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
-    for (uint32_t base = start; base < end; base += NT) {
+    for (uint32_t base = start; base < end; base += BD) {
         if (__syncthreads_and(done)) break;
-        // stage one record per lane and mark the wave blocks its support box meets
-        const uint32_t k = base + t;
-        uint32_t hm = 0;
-        if (k < end) {
-            const uint32_t id = a.vals[k];
-            const gs_splat s = sp[id];
-            rec[t] = s;
-            gid[t] = id;
-            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
-        }
-        hit[t] = (uint8_t)hm;
+        stage<TW, TH, DEPTH>(sm, a, sp, base, min((uint32_t)BD, end - base), g);
         __syncthreads();
         // each wave walks only the entries that meet its 8x8 block, in list order
 #pragma unroll 1
-        for (int c = 0; c < NT / 64; ++c) {
-            uint64_t m = ballot((hit[c * 64 + l] >> w) & 1u);
+        for (int c = 0; c < BD / 64; ++c) {
+            uint64_t m = ballot((sm.hit[c * 64 + l] >> w) & 1u);
             while (m) {
                 const int j = c * 64 + (int)__builtin_ctzll(m);
                 m &= m - 1;
                 float wgt = 0.f;
                 if (!done) {
-                    const gs_splat& s = rec[j];
+                    const gs_splat& s = sm.rec[j];
                     float al, G, dx, dy;
                     if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
                         wgt = al * T;
@@ -172,12 +202,12 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
                         const float mx = wave_max_nonneg(wgt);
-                        if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + gid[j], __float_as_uint(mx));
+                        if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + sm.gid[j], __float_as_uint(mx));
                     }
                 }
                 if (MODE == MODE_VISIBILITY) {
                     if (ballot(wgt > a.t_cluster) != 0 && l == 0) {
-                        const uint32_t id = gid[j];
+                        const uint32_t id = sm.gid[j];
                         atomicOr(a.bits + (int64_t)cluster * a.words + (id >> 5), 1u << (id & 31));
                     }
                 }
@@ -185,6 +215,7 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
             if (ballot(!done) == 0) break;
         }
     }
+    __syncthreads();  // the staging area is reused by the next tile of a persistent workgroup
     if (MODE == MODE_FWD && g.inside) {
         const int64_t plane = (int64_t)g.W * g.H;
         float* out = a.rgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
@@ -204,14 +235,9 @@ __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
 // then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
 // dx = xc - u. The nine per-record sums are reduced over the wave and added atomically
 // into g2[field][view * n + index].
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
-    constexpr int NT = TW * TH;
-    __shared__ gs_splat rec[NT];
-    __shared__ uint32_t gid[NT];
-    __shared__ uint8_t hit[NT];
-    __shared__ uint32_t top_s;
-    const int tile = blockIdx.x;
+template <int TW, int TH, int DEPTH>
+__device__ void bwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
+    constexpr int BD = TW * TH * DEPTH;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
     const int t = threadIdx.x, l = t & 63, w = g.wave;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -232,32 +258,23 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
         S1 = T * a.p.bg[1];
         S2 = T * a.p.bg[2];
     }
-    last = min(last, end);  // never read past the tile's list, whatever n_last holds
-    if (t == 0) top_s = start;
+    last = min(max(last, start), end);  // never read outside the tile's list, whatever n_last holds
+    if (t == 0) sm.top = start;
     __syncthreads();
-    if (g.inside && last > start) atomicMax(&top_s, last);
+    if (g.inside && last > start) atomicMax(&sm.top, last);
     __syncthreads();
-    const uint32_t top = top_s;
+    const uint32_t top = sm.top;
     const int64_t VN = (int64_t)a.n_views * a.n;
     const int64_t vbase = (int64_t)g.view * a.n;
     for (uint32_t hi = top; hi > start;) {
-        const uint32_t lo = (hi - start > (uint32_t)NT) ? hi - NT : start;
-        const uint32_t k = lo + t;
+        const uint32_t lo = (hi - start > (uint32_t)BD) ? hi - BD : start;
         __syncthreads();
-        uint32_t hm = 0;
-        if (k < hi) {
-            const uint32_t id = a.vals[k];
-            const gs_splat s = sp[id];
-            rec[t] = s;
-            gid[t] = id;
-            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
-        }
-        hit[t] = (uint8_t)hm;
+        stage<TW, TH, DEPTH>(sm, a, sp, lo, hi - lo, g);
         __syncthreads();
         // entries that meet this wave's block, back to front
 #pragma unroll 1
-        for (int c = NT / 64 - 1; c >= 0; --c) {
-            uint64_t m = ballot((hit[c * 64 + l] >> w) & 1u);
+        for (int c = BD / 64 - 1; c >= 0; --c) {
+            uint64_t m = ballot((sm.hit[c * 64 + l] >> w) & 1u);
             while (m) {
                 const int b = 63 - (int)__builtin_clzll(m);
                 m &= ~(1ull << b);
@@ -266,7 +283,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
                 float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
                 bool contrib = false;
                 if (g.inside && pos < last) {
-                    const gs_splat& s = rec[j];
+                    const gs_splat& s = sm.rec[j];
                     float al, G, dx, dy;
                     if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
                         contrib = true;
@@ -297,7 +314,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
                                 sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
                                 sbl = wave_sum(gbl);
                     if (l == 0) {
-                        const int64_t o = vbase + gid[j];
+                        const int64_t o = vbase + sm.gid[j];
                         atomicAdd(a.g2 + 0 * VN + o, su);
                         atomicAdd(a.g2 + 1 * VN + o, sv);
                         atomicAdd(a.g2 + 2 * VN + o, sa);
@@ -312,6 +329,42 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
             }
         }
         hi = lo;
+    }
+    __syncthreads();
+}
+
+// tile of the i-th work item of workgroup b in the persistent form (boustrophedon rounds)
+__device__ __forceinline__ int persistent_item(int r, int b, int G) {
+    return r * G + ((r & 1) ? G - 1 - b : b);
+}
+
+template <int TW, int TH, int DEPTH, int MODE>
+__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
+    __shared__ Smem<TW, TH, DEPTH> sm;
+    if (a.queue == nullptr) {
+        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, blockIdx.x);
+        return;
+    }
+    const int G = gridDim.x, b = blockIdx.x;
+    for (int r = 0;; ++r) {
+        const int item = persistent_item(r, b, G);
+        if (item >= a.n_tiles) break;
+        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, (int)a.queue[item]);
+    }
+}
+
+template <int TW, int TH, int DEPTH>
+__global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
+    __shared__ Smem<TW, TH, DEPTH> sm;
+    if (a.queue == nullptr) {
+        bwd_tile<TW, TH, DEPTH>(sm, a, blockIdx.x);
+        return;
+    }
+    const int G = gridDim.x, b = blockIdx.x;
+    for (int r = 0;; ++r) {
+        const int item = persistent_item(r, b, G);
+        if (item >= a.n_tiles) break;
+        bwd_tile<TW, TH, DEPTH>(sm, a, (int)a.queue[item]);
     }
 }
 
@@ -342,37 +395,69 @@ gs_status launch_l1(const float* rgb, const float* tgt, int64_t n, float scale, 
 // ---------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------
-template <int MODE>
-static void launch_mode(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
-    const dim3 grid(n_tiles);
-#define GS_CASE(W_, H_)                                                                          \
-    if (tw == W_ && th == H_) {                                                                  \
-        hipLaunchKernelGGL((k_render<W_, H_, MODE>), grid, dim3(W_ * H_), 0, s, a);              \
-        return;                                                                                  \
+// workgroups of a persistent launch: CUs x resident workgroups of this kernel per CU. The
+// device queries run on the first launch of each kernel on each device and are cached, so
+// later launches (for instance inside a captured graph) make no runtime query.
+static int persistent_grid(const void* fn, int threads, int n_tiles) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return n_tiles;
+    int slots = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find({fn, dev});
+        if (it != cache.end()) slots = it->second;
     }
-    GS_CASE(8, 8)
-    GS_CASE(16, 8)
-    GS_CASE(8, 16)
-    GS_CASE(16, 16)
-    GS_CASE(32, 8)
-    GS_CASE(8, 32)
-#undef GS_CASE
+    if (slots == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        slots = cus * per_cu;
+        std::lock_guard<std::mutex> lock(mu);
+        cache[{fn, dev}] = slots;
+    }
+    return std::max(1, std::min(n_tiles, slots));
 }
 
-static void launch_bwd(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
-    const dim3 grid(n_tiles);
-#define GS_CASE(W_, H_)                                                                          \
-    if (tw == W_ && th == H_) {                                                                  \
-        hipLaunchKernelGGL((k_render_bwd<W_, H_>), grid, dim3(W_ * H_), 0, s, a);                \
-        return;                                                                                  \
+template <typename K>
+static void launch_tiles(K kernel, const RenderArgs& a, int threads, int n_tiles, hipStream_t s) {
+    const int grid = a.queue ? persistent_grid(reinterpret_cast<const void*>(kernel), threads, n_tiles) : n_tiles;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, a);
+}
+
+template <int MODE>
+static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int n_tiles, hipStream_t s) {
+#define GS_CASE(W_, H_, D_)                                                                      \
+    if (tw == W_ && th == H_ && depth == D_) {                                                   \
+        launch_tiles(k_render<W_, H_, D_, MODE>, a, W_ * H_, n_tiles, s);                        \
+        return true;                                                                             \
     }
-    GS_CASE(8, 8)
-    GS_CASE(16, 8)
-    GS_CASE(8, 16)
-    GS_CASE(16, 16)
-    GS_CASE(32, 8)
-    GS_CASE(8, 32)
+    GS_CASE(8, 8, 1) GS_CASE(8, 8, 2)
+    GS_CASE(16, 8, 1) GS_CASE(16, 8, 2)
+    GS_CASE(8, 16, 1) GS_CASE(8, 16, 2)
+    GS_CASE(16, 16, 1) GS_CASE(16, 16, 2)
+    GS_CASE(32, 8, 1) GS_CASE(32, 8, 2)
+    GS_CASE(8, 32, 1) GS_CASE(8, 32, 2)
 #undef GS_CASE
+    return false;
+}
+
+static bool launch_bwd(const RenderArgs& a, int tw, int th, int depth, int n_tiles, hipStream_t s) {
+#define GS_CASE(W_, H_, D_)                                                                      \
+    if (tw == W_ && th == H_ && depth == D_) {                                                   \
+        launch_tiles(k_render_bwd<W_, H_, D_>, a, W_ * H_, n_tiles, s);                          \
+        return true;                                                                             \
+    }
+    GS_CASE(8, 8, 1) GS_CASE(8, 8, 2)
+    GS_CASE(16, 8, 1) GS_CASE(16, 8, 2)
+    GS_CASE(8, 16, 1) GS_CASE(8, 16, 2)
+    GS_CASE(16, 16, 1) GS_CASE(16, 16, 2)
+    GS_CASE(32, 8, 1) GS_CASE(32, 8, 2)
+    GS_CASE(8, 32, 1) GS_CASE(8, 32, 2)
+#undef GS_CASE
+    return false;
 }
 
 static RenderArgs base_args(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
@@ -387,7 +472,14 @@ static RenderArgs base_args(const gs_projected* proj, const gs_views* views, con
     a.n_views = views->n_views;
     a.n = proj->n;
     a.p = *p;
+    a.queue = views->persistent ? bins->queue : nullptr;
+    a.n_tiles = views->n_tiles;
     return a;
+}
+
+static gs_status finish(bool launched, const char* what) {
+    if (!launched) return set_error(GS_ERR_UNSUPPORTED, "%s: no kernel for this tile size and batch depth", what);
+    return check_launch(what);
 }
 
 gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -398,8 +490,8 @@ gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, con
     a.t_final = t_final;
     a.n_last = n_last;
     a.n_contrib = n_contrib;
-    launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->n_tiles, s);
-    return check_launch("render_fwd");
+    return finish(launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s),
+                  "render_fwd");
 }
 
 gs_status launch_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -407,8 +499,9 @@ gs_status launch_importance(const gs_projected* proj, const gs_views* views, con
     if (views->n_tiles == 0) return GS_OK;
     RenderArgs a = base_args(proj, views, bins, p);
     a.h = h;
-    launch_mode<MODE_IMPORTANCE>(a, views->tile_w, views->tile_h, views->n_tiles, s);
-    return check_launch("importance");
+    return finish(
+        launch_mode<MODE_IMPORTANCE>(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s),
+        "importance");
 }
 
 gs_status launch_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -419,8 +512,9 @@ gs_status launch_visibility(const gs_projected* proj, const gs_views* views, con
     a.view_cluster = view_cluster;
     a.words = (proj->n + 31) / 32;
     a.t_cluster = t_cluster;
-    launch_mode<MODE_VISIBILITY>(a, views->tile_w, views->tile_h, views->n_tiles, s);
-    return check_launch("cluster_visibility");
+    return finish(
+        launch_mode<MODE_VISIBILITY>(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s),
+        "cluster_visibility");
 }
 
 gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -432,8 +526,7 @@ gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, con
     a.last_in = n_last;
     a.dl_drgb = dl_drgb;
     a.g2 = g2;
-    launch_bwd(a, views->tile_w, views->tile_h, views->n_tiles, s);
-    return check_launch("render_bwd");
+    return finish(launch_bwd(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s), "render_bwd");
 }
 
 }  // namespace gs

@@ -433,6 +433,11 @@ __global__ __launch_bounds__(BLK) void k_os_pass(PassArgs a) {
     }
 }
 
+__global__ void k_iota(uint32_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
 __global__ void k_ranges(const uint64_t* __restrict__ keys, const uint64_t* n_pairs, uint64_t capacity,
                          const uint32_t* overflow, uint32_t* __restrict__ ranges, int n_tiles) {
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,6 +448,58 @@ __global__ void k_ranges(const uint64_t* __restrict__ keys, const uint64_t* n_pa
     if (tile >= (uint32_t)n_tiles) return;
     if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != tile) ranges[2 * tile] = (uint32_t)k;
     if (k + 1 == count || (uint32_t)(keys[k + 1] >> 32) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// Longest-first tile order for the persistent compositing launch: tiles are bucketed by
+// bit length of their list size (33 buckets) and laid out from the longest bucket down.
+// ---------------------------------------------------------------------------------------
+constexpr int LPT_B = 33;
+
+__device__ __forceinline__ int lpt_bucket(const uint32_t* ranges, int tile) {
+    const uint32_t c = ranges[2 * tile + 1] - ranges[2 * tile];
+    return c ? 32 - __clz(c) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_lpt_hist(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                  uint32_t* __restrict__ bh) {
+    __shared__ uint32_t lh[LPT_B];
+    const int t = threadIdx.x;
+    if (t < LPT_B) lh[t] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * 256 + t; i < n_tiles; i += gridDim.x * 256) atomicAdd(&lh[lpt_bucket(ranges, i)], 1u);
+    __syncthreads();
+    if (t < LPT_B && lh[t]) atomicAdd(&bh[t], lh[t]);
+}
+
+__global__ __launch_bounds__(256) void k_lpt_scatter(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                     const uint32_t* __restrict__ bh, uint32_t* __restrict__ fill,
+                                                     uint32_t* __restrict__ queue) {
+    __shared__ uint32_t lh[LPT_B], lbase[LPT_B], goff[LPT_B];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int b = LPT_B - 1; b >= 0; --b) {
+            goff[b] = acc;
+            acc += bh[b];
+        }
+    }
+    if (t < LPT_B) lh[t] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * 256 + t;
+    int b = 0;
+    uint32_t lr = 0;
+    if (i < n_tiles) {
+        b = lpt_bucket(ranges, i);
+        lr = atomicAdd(&lh[b], 1u);
+    }
+    __syncthreads();
+    if (t < LPT_B) lbase[t] = lh[t] ? atomicAdd(&fill[t], lh[t]) : 0u;
+    __syncthreads();
+    if (i < n_tiles) {
+        const uint32_t pos = goff[b] + lbase[b] + lr;
+        if (pos < (uint32_t)n_tiles) queue[pos] = (uint32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -457,7 +514,7 @@ int key_bits(int n_tiles) {
 }
 
 struct SortLayout {
-    size_t offs, ctrl, scan_ctrl, tickets, ghist, status, ctrl_end, keys_alt, vals_alt, total;
+    size_t offs, ctrl, scan_ctrl, tickets, ghist, lpt, status, ctrl_end, keys_alt, vals_alt, total;
     int64_t nb_sort, nb_scan;
     int passes;
 };
@@ -479,6 +536,8 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     p = align256(p + sizeof(uint32_t) * MAX_PASSES);
     L.ghist = p;
     p = align256(p + sizeof(uint32_t) * 256 * MAX_PASSES);
+    L.lpt = p;
+    p = align256(p + sizeof(uint32_t) * 2 * LPT_B);
     L.status = p;
     p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
     L.ctrl_end = p;
@@ -492,6 +551,21 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
 
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
     return sort_layout(n, n_views, capacity, n_tiles).total;
+}
+
+// tile work order (only when the caller asked for one); lpt = zeroed [2][LPT_B] counters,
+// or NULL when there are no pairs at all (then the identity order is as good as any)
+static gs_status launch_lpt(const gs_views* views, gs_bins* bins, uint32_t* lpt, hipStream_t stream) {
+    if (!bins->queue || views->n_tiles == 0) return check_launch("bin_sort");
+    const unsigned g = (unsigned)((views->n_tiles + 255) / 256);
+    if (!lpt) {
+        hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, stream, bins->queue, views->n_tiles);
+        return check_launch("bin_sort");
+    }
+    hipLaunchKernelGGL(k_lpt_hist, dim3(std::min(g, 1024u)), dim3(256), 0, stream, bins->ranges, views->n_tiles, lpt);
+    hipLaunchKernelGGL(k_lpt_scatter, dim3(g), dim3(256), 0, stream, bins->ranges, views->n_tiles, lpt, lpt + LPT_B,
+                       bins->queue);
+    return check_launch("bin_sort");
 }
 
 gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws,
@@ -520,7 +594,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     f.p[3] = (uint32_t*)(w + L.ctrl);
     f.n[3] = vn == 0 ? 0 : (int64_t)((L.ctrl_end - L.ctrl) / 4);
     if ((st = launch_zero4(f, stream))) return st;
-    if (vn == 0) return GS_OK;
+    if (vn == 0) return launch_lpt(views, bins, nullptr, stream);
     if ((st = launch_scan(proj->count, offs, vn, scan_ctrl, bins->n_pairs, bins->overflow, bins->capacity, stream)))
         return st;
     const int passes = L.passes;
@@ -543,7 +617,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     e.keys = k0;
     e.vals = v0;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
-    if (L.nb_sort == 0) return check_launch("bin_sort");
+    if (L.nb_sort == 0) return launch_lpt(views, bins, (uint32_t*)(w + L.lpt), stream);
     const unsigned hist_blocks = (unsigned)std::min<int64_t>(L.nb_sort * 4, 1024);
     hipLaunchKernelGGL(k_os_hist, dim3(hist_blocks), dim3(BLK), 0, stream, k0, bins->n_pairs, bins->capacity, passes,
                        ghist);
@@ -567,7 +641,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     const unsigned g = (unsigned)((bins->capacity + 255) / 256);
     hipLaunchKernelGGL(k_ranges, dim3(g), dim3(256), 0, stream, bins->keys, bins->n_pairs, bins->capacity,
                        bins->overflow, bins->ranges, views->n_tiles);
-    return check_launch("bin_sort");
+    return launch_lpt(views, bins, (uint32_t*)(w + L.lpt), stream);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -95,11 +95,14 @@ def camera_struct(cam) -> L.gs_camera:
 class ViewBatch:
     """Views rendered in one call: cameras, tile size and the global tile/pixel layout."""
 
-    def __init__(self, cams: Sequence, tile: Tuple[int, int] = DEFAULT_TILE, device=None):
+    def __init__(self, cams: Sequence, tile: Tuple[int, int] = DEFAULT_TILE, device=None, batch_depth: int = 1,
+                 persistent: bool = False):
         lib = L.load()
         self.cams = list(cams)
         self.n_views = len(self.cams)
         self.tile = (int(tile[0]), int(tile[1]))
+        self.batch_depth = int(batch_depth)
+        self.persistent = bool(persistent)
         self.device = _dev(device)
         arr = (L.gs_camera * self.n_views)(*[camera_struct(c) for c in self.cams])
         toff = (ctypes.c_int32 * (self.n_views + 1))()
@@ -117,7 +120,8 @@ class ViewBatch:
 
     def struct(self) -> L.gs_views:
         return L.gs_views(_ptr(self.cams_dev), _ptr(self.tile_offset), _ptr(self.pixel_offset), self.n_views,
-                          self.tile[0], self.tile[1], self.n_tiles, self.n_pixels)
+                          self.tile[0], self.tile[1], self.n_tiles, self.n_pixels, self.batch_depth,
+                          int(self.persistent))
 
     def image(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
         """View v's planar [3][H][W] image inside a global rgb buffer."""
@@ -163,10 +167,11 @@ class Bins:
         self.ranges = torch.empty(max(2 * n_tiles, 2), dtype=torch.int32, device=device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        self.queue = torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device)
 
     def struct(self) -> L.gs_bins:
         return L.gs_bins(_ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), self.capacity, _ptr(self.n_pairs),
-                         _ptr(self.overflow))
+                         _ptr(self.overflow), _ptr(self.queue))
 
 
 def workspace_bytes(n: int, n_views: int, capacity: int, n_tiles: int) -> int:
@@ -362,17 +367,19 @@ class Renderer:
     sized run); check() reports whether any frame since construction overflowed it."""
 
     def __init__(self, g: Gaussians, views: ViewBatch, params=None, capacity: Optional[int] = None,
-                 want_color: bool = True, headroom: float = 1.25):
+                 want_color: bool = True, headroom: float = 1.25, subset: Optional[torch.Tensor] = None):
         self.g, self.views, self.params = g, views, params
         self.p = make_params(params)
         dev = views.device
-        self.proj = Projected(g.n, views.n_views, dev)
-        preprocess(g, views, params, want_color=want_color, out=self.proj)
+        self.subset = subset
+        self.n_entries = g.n if subset is None else int(subset.shape[0])
+        self.proj = Projected(self.n_entries, views.n_views, dev)
+        preprocess(g, views, params, subset=subset, want_color=want_color, out=self.proj)
         if capacity is None:
             b = bin_sort(self.proj, views)
             capacity = int(int(b.n_pairs.item()) * headroom) + 4096
         self.bins = Bins(capacity, views.n_tiles, dev)
-        self.ws = alloc_workspace(g.n, views.n_views, capacity, views.n_tiles, dev)
+        self.ws = alloc_workspace(self.n_entries, views.n_views, capacity, views.n_tiles, dev)
         self.rgb = torch.empty(3 * max(views.n_pixels, 1), dtype=torch.float32, device=dev)
         self.t_final = torch.empty(max(views.n_pixels, 1), dtype=torch.float32, device=dev)
         self.n_last = torch.empty(max(views.n_pixels, 1), dtype=torch.int32, device=dev)
@@ -385,8 +392,9 @@ class Renderer:
 
     def _pre(self, stream):
         lib = L.load()
-        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self.p), None,
-                                  self.g.n, int(self.want_color), ctypes.byref(self._sp), stream))
+        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self.p),
+                                  _ptr(self.subset), self.n_entries, int(self.want_color), ctypes.byref(self._sp),
+                                  stream))
         L.check(lib.gs_bin_sort(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
                                 _ptr(self.ws), self.ws.numel(), stream))
 
@@ -411,6 +419,8 @@ class Renderer:
         return h
 
     def backward(self, dl_drgb: torch.Tensor, grad: Gaussians):
+        if self.subset is not None:
+            raise ValueError("the backward needs a projection of every Gaussian (no subset)")
         s = _stream(self.views.device)
         gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity),
                                  _ptr(grad.sh), self.g.n, self.g.sh_degree)
@@ -423,3 +433,92 @@ class Renderer:
     def check(self) -> Tuple[bool, int]:
         """(overflowed, pairs of the last frame); synchronises."""
         return bool(int(self.bins.overflow.item())), int(self.bins.n_pairs.item())
+
+
+class VisibilityFilter:
+    """Viewpoint-based visibility filtering (Sec. 3.4): k-means clusters of the training
+    camera positions; per cluster, the indicator list of the Gaussians composited with weight
+    above t_cluster in some training view of the cluster (eq. importance-score-vis); a test
+    view is rendered with the list of the cluster centre nearest to its camera centre."""
+
+    def __init__(self, g: Gaussians, train_cams: Sequence, k: int = 64, t_cluster: float = 0.001, params=None,
+                 chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None):
+        dev = _dev(device)
+        self.g, self.k, self.t_cluster, self.params, self.tile, self.device = g, k, t_cluster, params, tile, dev
+        pos = np.stack([c.position for c in train_cams])
+        self.centres, self.assign = kmeans(pos, k, seed=seed)
+        words = (g.n + 31) // 32
+        self.bits = torch.zeros(max(k * words, 1), dtype=torch.int32, device=dev)
+        for c0 in range(0, len(train_cams), chunk):
+            vb = ViewBatch(train_cams[c0:c0 + chunk], tile, dev)
+            cluster_visibility(g, vb, self.assign[c0:c0 + chunk], k, t_cluster, params, bits=self.bits)
+        self.lists = [bits_to_list(self.bits[c * words:(c + 1) * words], g.n) for c in range(k)]
+
+    def cluster_of(self, cam) -> int:
+        return nearest_centre(self.centres, cam.position)
+
+    def list_for(self, cam) -> torch.Tensor:
+        return self.lists[self.cluster_of(cam)]
+
+    def render(self, cam, capacity=None):
+        views = ViewBatch([cam], self.tile, self.device)
+        return render(self.g, views, self.params, subset=self.list_for(cam), capacity=capacity)
+
+
+class PathRenderer:
+    """Frames of a camera path (all of one resolution) rendered with one set of buffers and no
+    host synchronisation per frame: the cameras of every frame are uploaded once and each
+    frame points the view batch at its own camera. A frame may render only a subset of the
+    Gaussians (a visibility list). The pair capacity is fixed; ok() reports overflows."""
+
+    def __init__(self, g: Gaussians, cams: Sequence, params=None, tile: Tuple[int, int] = DEFAULT_TILE,
+                 capacity: Optional[int] = None, max_entries: Optional[int] = None, device=None,
+                 persistent: bool = False, batch_depth: int = 1):
+        dev = _dev(device)
+        self.g, self.params, self.device = g, params, dev
+        self.p = make_params(params)
+        self.views = ViewBatch([cams[0]], tile, dev, batch_depth, persistent)
+        if any((c.width, c.height) != (cams[0].width, cams[0].height) for c in cams):
+            raise ValueError("every frame of a path must have the same resolution")
+        arr = (L.gs_camera * len(cams))(*[camera_struct(c) for c in cams])
+        self.cams_all = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(dev)
+        self.n_frames = len(cams)
+        self.max_entries = g.n if max_entries is None else int(max_entries)
+        self.proj = Projected(self.max_entries, 1, dev)
+        if capacity is None:
+            preprocess(g, self.views, params, out=self._proj_n(g.n))
+            b = bin_sort(self._proj_n(g.n), self.views)
+            capacity = int(int(b.n_pairs.item()) * 2.0) + 65536
+        self.bins = Bins(capacity, self.views.n_tiles, dev)
+        self.ws = alloc_workspace(self.max_entries, 1, capacity, self.views.n_tiles, dev)
+        self.rgb = torch.empty(3 * self.views.n_pixels, dtype=torch.float32, device=dev)
+        self.t_final = torch.empty(self.views.n_pixels, dtype=torch.float32, device=dev)
+        self.n_last = torch.empty(self.views.n_pixels, dtype=torch.int32, device=dev)
+        self._sg = g.struct()
+        self._sb = self.bins.struct()
+
+    def _proj_n(self, n):
+        self.proj.n = n
+        return self.proj
+
+    def frame(self, f: int, subset: Optional[torch.Tensor] = None):
+        """Enqueue frame f (optionally with only the listed Gaussians); returns the rgb buffer."""
+        lib = L.load()
+        n = self.g.n if subset is None else int(subset.shape[0])
+        if n > self.max_entries:
+            raise ValueError("subset larger than max_entries")
+        sv = self.views.struct()
+        sv.cams = ctypes.c_void_p(self.cams_all.data_ptr() + ctypes.sizeof(L.gs_camera) * f)
+        sp = self._proj_n(n).struct()
+        s = _stream(self.device)
+        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(sv), ctypes.byref(self.p), _ptr(subset), n, 1,
+                                  ctypes.byref(sp), s))
+        L.check(lib.gs_bin_sort(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(self._sb), _ptr(self.ws),
+                                self.ws.numel(), s))
+        L.check(lib.gs_render_fwd(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(self._sb), ctypes.byref(self.p),
+                                  _ptr(self.rgb), _ptr(self.t_final), _ptr(self.n_last), None, s))
+        return self.rgb
+
+    def ok(self) -> bool:
+        """True when the last frame fit the pair buffer (synchronises)."""
+        return int(self.bins.overflow.item()) == 0

@@ -236,50 +236,50 @@ def house_scene(n, seed=SEED_GAUSSIANS, sh_degree=3) -> Scene:
     rooms = [(f, rx, rz) for f in range(2) for rx in range(3) for rz in range(2)]
     n_surf = int(round(0.6 * n))
     n_clut = n - n_surf
-    # surfaces: (room, face) pairs with area weights; faces: floor, ceiling, 4 walls
-    faces = []
-    for r, (f, rx, rz) in enumerate(rooms):
+    # faces: kind 0 floor, 1 ceiling, 2 wall x = x0, 3 wall x = x0 + 10, 4 wall z = z0, 5 wall z = z0 + 10
+    f_org, f_kind, f_inner, f_area = [], [], [], []
+    for (f, rx, rz) in rooms:
         o = _room_origin(f, rx, rz)
-        faces.append((r, "floor", o, ROOM * ROOM))
-        faces.append((r, "ceil", o, ROOM * ROOM))
-        for w in ("x0", "x1", "z0", "z1"):
-            faces.append((r, w, o, ROOM * FLOOR_H))
-    area = np.array([fc[3] for fc in faces])
-    which = rng.choice(len(faces), n_surf, p=area / area.sum())
+        for kind in range(6):
+            inner = {2: rx > 0, 3: rx < 2, 4: rz > 0, 5: rz < 1}.get(kind, False)
+            f_org.append(o)
+            f_kind.append(kind)
+            f_inner.append(inner)
+            f_area.append(ROOM * ROOM if kind < 2 else ROOM * FLOOR_H)
+    f_org, f_kind, f_inner, f_area = (np.array(f_org), np.array(f_kind), np.array(f_inner), np.array(f_area))
+    which = rng.choice(len(f_kind), n_surf, p=f_area / f_area.sum())
     pts = np.empty((n_surf, 3))
     normal_axis = np.empty(n_surf, np.int64)
     todo = np.arange(n_surf)
     while todo.size:
+        fc = which[todo]
         a = rng.uniform(0, 1, todo.size)
         b = rng.uniform(0, 1, todo.size)
-        keep = np.ones(todo.size, bool)
-        for j, idx in enumerate(todo):
-            r, kind, o, _ = faces[which[idx]]
-            f, rx, rz = rooms[r]
-            if kind in ("floor", "ceil"):
-                y = o[1] if kind == "floor" else o[1] - FLOOR_H
-                pts[idx] = (o[0] + a[j] * ROOM, y, o[2] + b[j] * ROOM)
-                normal_axis[idx] = 1
-            else:
-                h = o[1] - b[j] * FLOOR_H
-                if kind in ("x0", "x1"):
-                    x = o[0] + (0 if kind == "x0" else ROOM)
-                    zc = o[2] + a[j] * ROOM
-                    pts[idx] = (x, h, zc)
-                    normal_axis[idx] = 0
-                    interior = (kind == "x1" and rx < 2) or (kind == "x0" and rx > 0)
-                    along = zc - o[2]
-                else:
-                    z = o[2] + (0 if kind == "z0" else ROOM)
-                    xc = o[0] + a[j] * ROOM
-                    pts[idx] = (xc, h, z)
-                    normal_axis[idx] = 2
-                    interior = (kind == "z1" and rz < 1) or (kind == "z0" and rz > 0)
-                    along = xc - o[0]
-                # 1 m wide, 2 m high doorway in the middle of each interior wall
-                if interior and abs(along - ROOM / 2) < 0.5 and (o[1] - h) < 2.0:
-                    keep[j] = False
-        todo = todo[~keep]
+        o, kind = f_org[fc], f_kind[fc]
+        p = np.empty((todo.size, 3))
+        ax = np.empty(todo.size, np.int64)
+        flat = kind < 2
+        p[flat, 0] = o[flat, 0] + a[flat] * ROOM
+        p[flat, 1] = o[flat, 1] - FLOOR_H * (kind[flat] == 1)
+        p[flat, 2] = o[flat, 2] + b[flat] * ROOM
+        ax[flat] = 1
+        h = o[:, 1] - b * FLOOR_H  # wall height coordinate (y points down)
+        xw = (kind == 2) | (kind == 3)
+        p[xw, 0] = o[xw, 0] + ROOM * (kind[xw] == 3)
+        p[xw, 1] = h[xw]
+        p[xw, 2] = o[xw, 2] + a[xw] * ROOM
+        ax[xw] = 0
+        zw = (kind == 4) | (kind == 5)
+        p[zw, 0] = o[zw, 0] + a[zw] * ROOM
+        p[zw, 1] = h[zw]
+        p[zw, 2] = o[zw, 2] + ROOM * (kind[zw] == 5)
+        ax[zw] = 2
+        # 1 m wide, 2 m high doorway in the middle of each interior wall
+        door = f_inner[fc] & ~flat & (np.abs(a * ROOM - ROOM / 2) < 0.5) & ((o[:, 1] - h) < 2.0)
+        keep = ~door
+        pts[todo[keep]] = p[keep]
+        normal_axis[todo[keep]] = ax[keep]
+        todo = todo[door]
     surf_scale = np.exp(rng.normal(-3.5, 0.5, (3, n_surf)))
     surf_scale[normal_axis, np.arange(n_surf)] = np.exp(-6.0)
     surf_quat = np.zeros((4, n_surf))
@@ -288,12 +288,11 @@ def house_scene(n, seed=SEED_GAUSSIANS, sh_degree=3) -> Scene:
     surf_quat[0] = np.cos(ang)
     surf_quat[1 + normal_axis, np.arange(n_surf)] = np.sin(ang)
     surf_opac = _sigmoid(rng.normal(2.0, 1.0, n_surf))
-    # clutter: 8 clusters per room, std 0.2 - 0.8 m, kept inside the room
-    n_cl = 8
+    # clutter: 8 clusters per room, std 0.2 - 0.8 m, inside the room
     centres = []
     for (f, rx, rz) in rooms:
         o = _room_origin(f, rx, rz)
-        for _ in range(n_cl):
+        for _ in range(8):
             centres.append(o + np.array([rng.uniform(1, ROOM - 1), -rng.uniform(0.3, 2.0), rng.uniform(1, ROOM - 1)]))
     centres = np.array(centres)
     cstd = rng.uniform(0.2, 0.8, len(centres))

@@ -337,3 +337,107 @@ def test_full_size_sampled_pixels():
     mism = (np.abs(got - runs[0]["rgb"]).max(1) > TOL_IMAGE) | (np.abs(T[py, px] - runs[0]["T"]) > TOL_IMAGE)
     _say(f"  sampled max err {np.abs(got - runs[0]['rgb']).max():.2e}")
     check_band(mism, band, "full-size sampled pixels")
+
+
+@pytest.mark.parametrize("tile,depth,persistent", [((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 2, False),
+                                                   ((16, 8), 1, True)])
+def test_launch_forms_bitwise(tile, depth, persistent):
+    """Batch depth and the persistent longest-first launch change who composites a tile and
+    how its list is staged, never the arithmetic: images, T and importance are bitwise equal."""
+    sc = scenes.mixture_scene(6000, seed=7, sh_degree=3)
+    cams = scenes.uneven_views([(64, 48), (126, 83), (160, 106), (192, 108)])
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say(f"launch form tile={tile} depth={depth} persistent={persistent}")
+    ref_v = gs.ViewBatch(cams, (16, 16), DEV)
+    ref = gs.render(g, ref_v, P)
+    h_ref = gs.importance(g, ref_v, P)
+    vb = gs.ViewBatch(cams, tile, DEV, batch_depth=depth, persistent=persistent)
+    out = gs.render(g, vb, P)
+    h = gs.importance(g, vb, P)
+    assert torch.equal(out["rgb"], ref["rgb"]) and torch.equal(out["t_final"], ref["t_final"])
+    assert torch.equal(h, h_ref)
+    if persistent:
+        q = out["bins"].queue[:vb.n_tiles].cpu().numpy()
+        assert np.array_equal(np.sort(q), np.arange(vb.n_tiles))  # every tile exactly once
+        rg = out["bins"].ranges.view(-1, 2).cpu().numpy().astype(np.int64)
+        lens = rg[q, 1] - rg[q, 0]
+        bl = np.where(lens > 0, np.floor(np.log2(np.maximum(lens, 1))) + 1, 0)
+        assert np.all(np.diff(bl) <= 0)  # longest first, by powers of two
+
+
+def test_graph_replay_matches_eager():
+    """A captured fwd + L1 + bwd step replayed several times, with eager work in between,
+    reproduces the eager step: images bitwise, gradients to FP32 atomic-order rounding."""
+    from paper_2403_13806_amd.train import FwdBwdStep, StepConfig
+    sc = scenes.mixture_scene(20000, seed=9, sh_degree=3)
+    cams = scenes.uneven_views([(64, 48), (126, 83), (160, 106), (192, 108)])
+    tg = scenes.target_images(cams)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("graph replay")
+    eager = FwdBwdStep(g, cams, tg, P, StepConfig(16, 8, 2, True), device=DEV)
+    eager.run()
+    torch.cuda.synchronize()
+    ref_rgb = eager.r.rgb.clone()
+    ref_g = [t.clone() for t in (eager.grad.mean, eager.grad.scale, eager.grad.quat, eager.grad.opacity, eager.grad.sh)]
+    ref_loss = float(eager.loss.item())
+    step = FwdBwdStep(g, cams, tg, P, StepConfig(16, 8, 2, True), device=DEV).capture()
+    for rep in range(3):
+        step.run()
+        torch.cuda.synchronize()
+        assert torch.equal(step.r.rgb, ref_rgb), rep
+        for a, b in zip((step.grad.mean, step.grad.scale, step.grad.quat, step.grad.opacity, step.grad.sh), ref_g):
+            assert torch.linalg.norm(a - b) <= 1e-5 * torch.linalg.norm(b) + 1e-12, rep
+        assert abs(float(step.loss.item()) - ref_loss) <= 1e-6 * abs(ref_loss)
+        # eager work between replays
+        eager.run()
+        torch.cuda.synchronize()
+    assert step.ok()
+
+
+def test_autotune_picks_a_valid_config(tmp_path, monkeypatch):
+    from paper_2403_13806_amd.train import StepConfig, autotune
+    monkeypatch.setenv("GS_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    sc = scenes.mixture_scene(5000, seed=10, sh_degree=1)
+    cams = scenes.uneven_views([(64, 48), (96, 72)])
+    tg = scenes.target_images(cams)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    cands = [StepConfig(16, 16, 1, False), StepConfig(8, 8, 2, True)]
+    cfg = autotune(g, cams, tg, P, candidates=cands, reps=2, device=DEV)
+    assert cfg in cands
+    assert autotune(g, cams, tg, P, candidates=cands, reps=2, device=DEV) == cfg  # cached
+
+
+def test_visibility_filter_and_path_renderer():
+    """Camera clustering, per-cluster lists (eq. importance-score-vis) against the oracle, and
+    list-based rendering of a camera path against the plain render of the same subset."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    sc = scenes.house_scene(12000, seed=4, sh_degree=1)
+    train = scenes.house_training_views(12, width=96, height=54)
+    path = scenes.house_test_path(6, width=96, height=54)
+    k, t = 3, 0.01
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("visibility filter")
+    vf = gs.VisibilityFilter(g, train, k=k, t_cluster=t, params=P, chunk=5, device=DEV)
+    torch.cuda.synchronize()
+    ref = oracle.cluster_bits(sc, train, vf.assign, k, P, t)
+    for c in range(k):
+        got = np.zeros(sc.n, bool)
+        got[vf.lists[c].cpu().numpy()] = True
+        mism = got != ref[c]
+        # entries within reach of the threshold are excused, like every band check
+        hc = np.zeros(sc.n)
+        for v, cam in enumerate(train):
+            if vf.assign[v] == c:
+                hc = np.maximum(hc, oracle.render(sc, cam, P, want_h=True)["h"])
+        check_band(mism, np.abs(hc - t) <= TOL_H * 10, f"cluster {c} list")
+    # path frames: same image as a plain render with the same subset, bitwise
+    pr = PathRenderer(g, path, P, device=DEV)
+    for f, cam in enumerate(path):
+        lst = vf.list_for(cam)
+        a = pr.frame(f, lst).clone()
+        assert pr.ok()
+        b = gs.render(g, gs.ViewBatch([cam], (16, 16), DEV), P, subset=lst)["rgb"]
+        assert torch.equal(a, b), f
+        a0 = pr.frame(f, None).clone()
+        b0 = gs.render(g, gs.ViewBatch([cam], (16, 16), DEV), P)["rgb"]
+        assert torch.equal(a0, b0), f

@@ -33,8 +33,8 @@ def test_library_exports_every_declared_entry_point():
 def test_struct_layout_sizes():
     assert ctypes.sizeof(L.gs_camera) == 80
     assert ctypes.sizeof(L.gs_params) == 36
-    assert ctypes.sizeof(L.gs_views) == 48
-    assert ctypes.sizeof(L.gs_bins) == 48
+    assert ctypes.sizeof(L.gs_views) == 56
+    assert ctypes.sizeof(L.gs_bins) == 56
 
 
 def test_view_layout():
@@ -69,6 +69,7 @@ def _dummy_views(tile=(16, 16)):
     v = L.gs_views()
     v.cams = v.tile_offset = v.pixel_offset = ctypes.c_void_p(16)
     v.n_views, v.tile_w, v.tile_h, v.n_tiles, v.n_pixels = 1, tile[0], tile[1], 48, 12288
+    v.batch_depth, v.persistent = 1, 0
     return v
 
 
@@ -99,7 +100,7 @@ def test_argument_errors_are_reported_before_launch():
     g.n = 10
     # capacity must stay below 2^32; the workspace must be large enough
     b = L.gs_bins(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 32, ctypes.c_void_p(16),
-                  ctypes.c_void_p(16))
+                  ctypes.c_void_p(16), None)
     assert lib.gs_bin_sort(R(out), R(v), R(b), ctypes.c_void_p(16), 1 << 40, None) == L.GS_ERR_UNSUPPORTED
     b.capacity = 1000
     assert lib.gs_bin_sort(R(out), R(v), R(b), ctypes.c_void_p(16), 10, None) == L.GS_ERR_INVALID_ARG
@@ -115,6 +116,14 @@ def test_argument_errors_are_reported_before_launch():
     assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
     assert lib.gs_bits_to_list(None, 10, None, None, None, 0, None) == L.GS_ERR_INVALID_ARG
+    # batch depth and the persistent form
+    v3 = _dummy_views()
+    v3.batch_depth = 3
+    assert lib.gs_preprocess(R(g), R(v3), R(p), None, 0, 1, R(out), None) == L.GS_ERR_UNSUPPORTED
+    v4 = _dummy_views()
+    v4.persistent = 1  # bins has no queue
+    assert lib.gs_importance(R(out), R(v4), R(b), R(p), ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
+    assert b"queue" in lib.gs_last_error()
 
 
 def test_kmeans_recovers_separated_groups():
