@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--only", choices=["batched", "importance", "house"], default=None,
+                    help="run one secondary workload alone (for profiling) and print its numbers")
     return ap.parse_args()
 
 
@@ -81,6 +83,17 @@ def main():
     dev = torch.device("cuda:0")
     P = scenes.Params()
     K, W = args.steps, args.warmup
+    if args.only:
+        if args.only == "batched":
+            sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+            g = gs.Gaussians.from_scene(sc, dev)
+            res = fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W, tune=False)
+        elif args.only == "importance":
+            res = importance_pass(torch, gs, scenes, P, dev)
+        else:
+            res = filtered_pass(torch, gs, scenes, P, dev)
+        print(json.dumps({"only": args.only, **res}), flush=True)
+        return
 
     copy_gbps = calib_copy(torch, dev)
     log(f"device copy of 256 MiB: {copy_gbps:.0f} GB/s (read + write)")
@@ -213,7 +226,7 @@ def calib_copy(torch, dev, nbytes=256 << 20, reps=5):
     return 2 * nbytes * reps / (tm.ms() * 1e-3) / 1e9
 
 
-def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):
+def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W, tune=True):
     out = {}
     # --- 200k Gaussians, one 1256x828 view, forward + L1 + backward ---
     log("fwd+bwd: 200k Gaussians, 1256x828")
@@ -280,8 +293,11 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W):
     assert eager.ok()
     del eager
     # batched, autotuned launch configuration, captured in a hipGraph and replayed
-    log("  autotuning the batched step")
-    cfg = autotune(g1m, cams, tg, P, reps=3, use_cache=False, device=dev, log=log)
+    if tune:
+        log("  autotuning the batched step")
+        cfg = autotune(g1m, cams, tg, P, reps=3, use_cache=False, device=dev, log=log)
+    else:
+        cfg = StepConfig(16, 16, 1, False)
     step = FwdBwdStep(g1m, cams, tg, P, cfg, device=dev).capture()
     t0 = time.perf_counter()
     for _ in range(kk):

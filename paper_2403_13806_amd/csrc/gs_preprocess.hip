@@ -323,6 +323,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 // Reverse mode: chain per-(view, Gaussian) gradients of the 2D quantities (u, v, conic
 // a, b, c, opacity, rgb) to the parameters. One thread per Gaussian, looping over the
 // views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
+// This kernel covers position (through u, v and J), scale, rotation and opacity; the
+// colour part follows in k_preprocess_bwd_sh.
 // ---------------------------------------------------------------------------------------
 struct PreBwdArgs {
     const float* mean;
@@ -349,17 +351,13 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
     if (i >= a.n) return;
     const int64_t VN = (int64_t)a.n_views * a.n;
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-    float gsh[48];
-    const int nb = (a.deg + 1) * (a.deg + 1);
-#pragma unroll
-    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
     bool any = false;
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t o = (int64_t)v * a.n + i;
         if (a.count[o] == 0) continue;
         const float gu = a.g2[0 * VN + o], gv = a.g2[1 * VN + o], gA = a.g2[2 * VN + o], gB = a.g2[3 * VN + o],
                     gC = a.g2[4 * VN + o], gO = a.g2[5 * VN + o];
-        const float gcol[3] = {a.g2[6 * VN + o], a.g2[7 * VN + o], a.g2[8 * VN + o]};
+        if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) continue;
         any = true;
         const gs_camera cam = a.cams[v];
         Proj P;
@@ -438,22 +436,60 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         gq[1] += (gx - x * dot) / P.qn;
         gq[2] += (gy - y * dot) / P.qn;
         gq[3] += (gz - zq * dot) / P.qn;
-        // colour through SH, including the view-direction dependence
+    }
+    if (!any) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.gmean[k * a.n + i] += (float)gp[k];
+        a.gscale[k * a.n + i] += (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] += (float)gq[k];
+    a.gopac[i] += (float)go;
+}
+
+// Colour part of the reverse mode: SH coefficient gradients and the mean gradient through
+// the view direction. Split from the geometric part so that neither kernel carries the
+// other's registers (the SH-3 accumulators alone are 48 floats).
+template <int DEG>
+__global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t VN = (int64_t)a.n_views * a.n;
+    float shv[NB * 3], gsh[NB * 3];
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) {
+        shv[k] = a.sh[(int64_t)k * a.n + i];
+        gsh[k] = 0.f;
+    }
+    const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
+    double gp[3] = {0, 0, 0};
+    bool any = false;
+    for (int v = 0; v < a.n_views; ++v) {
+        const int64_t o = (int64_t)v * a.n + i;
+        if (a.count[o] == 0) continue;
+        const float gcol[3] = {a.g2[6 * VN + o], a.g2[7 * VN + o], a.g2[8 * VN + o]};
+        if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+        any = true;
+        const gs_camera cam = a.cams[v];
         float d[3];
         double len;
-        view_dir(cam, a.mean[i], a.mean[a.n + i], a.mean[2 * a.n + i], d, len);
+        view_dir(cam, px, py, pz, d, len);
         float Y[16], G[16][3];
-        sh_basis(a.deg, d[0], d[1], d[2], Y);
-        sh_basis_grad(a.deg, d[0], d[1], d[2], G);
+        sh_basis(DEG, d[0], d[1], d[2], Y);
+        sh_basis_grad(DEG, d[0], d[1], d[2], G);
         float gd[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             float acc = 0.f;
-            for (int k = 0; k < nb; ++k) acc += a.sh[(int64_t)(k * 3 + c) * a.n + i] * Y[k];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
             if (!(acc + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
-            for (int k = 0; k < nb; ++k) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
                 gsh[k * 3 + c] += gcol[c] * Y[k];
-                const float kc = a.sh[(int64_t)(k * 3 + c) * a.n + i] * gcol[c];
+                const float kc = shv[k * 3 + c] * gcol[c];
                 gd[0] += kc * G[k][0];
                 gd[1] += kc * G[k][1];
                 gd[2] += kc * G[k][2];
@@ -465,14 +501,9 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
     }
     if (!any) return;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a.gmean[k * a.n + i] += (float)gp[k];
-        a.gscale[k * a.n + i] += (float)gs[k];
-    }
+    for (int k = 0; k < 3; ++k) a.gmean[k * a.n + i] += (float)gp[k];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] += (float)gq[k];
-    a.gopac[i] += (float)go;
-    for (int k = 0; k < nb * 3; ++k) a.gsh[(int64_t)k * a.n + i] += gsh[k];
+    for (int k = 0; k < NB * 3; ++k) a.gsh[(int64_t)k * a.n + i] += gsh[k];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -537,7 +568,14 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gquat = grad->quat;
     a.gopac = grad->opacity;
     a.gsh = grad->sh;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g->n + 127) / 128)), dim3(128), 0, stream, a);
+    const dim3 grid((unsigned)((g->n + 127) / 128));
+    hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(128), 0, stream, a);
+    switch (g->sh_degree) {
+        case 0: hipLaunchKernelGGL((k_preprocess_bwd_sh<0>), grid, dim3(128), 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((k_preprocess_bwd_sh<1>), grid, dim3(128), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((k_preprocess_bwd_sh<2>), grid, dim3(128), 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_preprocess_bwd_sh<3>), grid, dim3(128), 0, stream, a); break;
+    }
     return check_launch("preprocess_bwd");
 }
 

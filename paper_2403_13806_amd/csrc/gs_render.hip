@@ -137,6 +137,12 @@ struct Smem {
     uint32_t top;
 };
 
+// the backward also accumulates, per staged record, the nine 2D-gradient sums of all waves
+template <int TW, int TH, int DEPTH>
+struct SmemBwd : Smem<TW, TH, DEPTH> {
+    float acc[Smem<TW, TH, DEPTH>::BD * 9];
+};
+
 // stage records [base, base + cnt) of the tile's list; mark the wave blocks each one meets
 template <int TW, int TH, int DEPTH>
 __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, const gs_splat* sp,
@@ -236,8 +242,9 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
 // dx = xc - u. The nine per-record sums are reduced over the wave and added atomically
 // into g2[field][view * n + index].
 template <int TW, int TH, int DEPTH>
-__device__ void bwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
-    constexpr int BD = TW * TH * DEPTH;
+__device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
+    constexpr int NT = TW * TH;
+    constexpr int BD = NT * DEPTH;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
     const int t = threadIdx.x, l = t & 63, w = g.wave;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -266,6 +273,7 @@ __device__ void bwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
     const uint32_t top = sm.top;
     const int64_t VN = (int64_t)a.n_views * a.n;
     const int64_t vbase = (int64_t)g.view * a.n;
+    for (int q = t; q < BD * 9; q += NT) sm.acc[q] = 0.f;
     for (uint32_t hi = top; hi > start;) {
         const uint32_t lo = (hi - start > (uint32_t)BD) ? hi - BD : start;
         __syncthreads();
@@ -313,20 +321,21 @@ __device__ void bwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                     const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
                                 sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
                                 sbl = wave_sum(gbl);
-                    if (l == 0) {
-                        const int64_t o = vbase + sm.gid[j];
-                        atomicAdd(a.g2 + 0 * VN + o, su);
-                        atomicAdd(a.g2 + 1 * VN + o, sv);
-                        atomicAdd(a.g2 + 2 * VN + o, sa);
-                        atomicAdd(a.g2 + 3 * VN + o, sb);
-                        atomicAdd(a.g2 + 4 * VN + o, sc);
-                        atomicAdd(a.g2 + 5 * VN + o, so);
-                        atomicAdd(a.g2 + 6 * VN + o, sr);
-                        atomicAdd(a.g2 + 7 * VN + o, sg);
-                        atomicAdd(a.g2 + 8 * VN + o, sbl);
-                    }
+                    // lanes 0..8 add one field each into the record's LDS accumulator
+                    const float v = l == 0 ? su : l == 1 ? sv : l == 2 ? sa : l == 3 ? sb : l == 4 ? sc
+                                  : l == 5 ? so : l == 6 ? sr : l == 7 ? sg : sbl;
+                    if (l < 9) atomicAdd(&sm.acc[j * 9 + l], v);
                 }
             }
+        }
+        __syncthreads();
+        // one global atomic per (tile, record, field) for the whole workgroup
+        const uint32_t cnt = hi - lo;
+        for (int q = t; q < BD * 9; q += NT) {
+            const int j = q / 9, f = q - 9 * (q / 9);
+            const float v = sm.acc[q];
+            if ((uint32_t)j < cnt && v != 0.f) atomicAdd(a.g2 + f * VN + vbase + sm.gid[j], v);
+            sm.acc[q] = 0.f;
         }
         hi = lo;
     }
@@ -338,46 +347,45 @@ __device__ __forceinline__ int persistent_item(int r, int b, int G) {
     return r * G + ((r & 1) ? G - 1 - b : b);
 }
 
+// tile of round r of workgroup b: the workgroup's own tile in the one-per-tile form, the
+// r-th boustrophedon item of the longest-first list in the persistent form; -1 when done
+__device__ __forceinline__ int tile_of_round(const RenderArgs& a, int r) {
+    const int b = blockIdx.x;
+    if (a.queue == nullptr) return r == 0 ? b : -1;
+    const int item = persistent_item(r, b, gridDim.x);
+    return item < a.n_tiles ? (int)a.queue[item] : -1;
+}
+
 template <int TW, int TH, int DEPTH, int MODE>
 __global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
     __shared__ Smem<TW, TH, DEPTH> sm;
-    if (a.queue == nullptr) {
-        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, blockIdx.x);
-        return;
-    }
-    const int G = gridDim.x, b = blockIdx.x;
     for (int r = 0;; ++r) {
-        const int item = persistent_item(r, b, G);
-        if (item >= a.n_tiles) break;
-        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, (int)a.queue[item]);
+        const int tile = tile_of_round(a, r);
+        if (tile < 0) break;
+        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, tile);
     }
 }
 
 template <int TW, int TH, int DEPTH>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
-    __shared__ Smem<TW, TH, DEPTH> sm;
-    if (a.queue == nullptr) {
-        bwd_tile<TW, TH, DEPTH>(sm, a, blockIdx.x);
-        return;
-    }
-    const int G = gridDim.x, b = blockIdx.x;
+    __shared__ SmemBwd<TW, TH, DEPTH> sm;
     for (int r = 0;; ++r) {
-        const int item = persistent_item(r, b, G);
-        if (item >= a.n_tiles) break;
-        bwd_tile<TW, TH, DEPTH>(sm, a, (int)a.queue[item]);
+        const int tile = tile_of_round(a, r);
+        if (tile < 0) break;
+        bwd_tile<TW, TH, DEPTH>(sm, a, tile);
     }
 }
 
-// L1 loss and its gradient, one element per lane, one atomic per block for the loss
+// L1 loss and its gradient: grid-stride over the elements, one atomic per workgroup for
+// the loss (the grid is bounded, so the loss word sees at most a few thousand atomics)
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const float* __restrict__ tgt, int64_t n,
                                             float scale, float* __restrict__ dl, float* __restrict__ loss) {
     __shared__ float part[4];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float e = 0.f;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const float d = rgb[i] - tgt[i];
         dl[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-        e = fabsf(d);
+        e += fabsf(d);
     }
     const float s = wave_sum(e);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
@@ -388,7 +396,8 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
 gs_status launch_l1(const float* rgb, const float* tgt, int64_t n, float scale, float* dl, float* loss,
                     hipStream_t s) {
     if (n == 0) return GS_OK;
-    hipLaunchKernelGGL(k_l1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rgb, tgt, n, scale, dl, loss);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_l1, dim3(grid), dim3(256), 0, s, rgb, tgt, n, scale, dl, loss);
     return check_launch("l1_loss_grad");
 }
 
