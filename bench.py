@@ -181,9 +181,12 @@ def main():
     work = {"visible_per_view": mv, "pairs_per_view": mp, "composited_per_view": mc,
             "tested_per_view": mt, "composited_per_pixel": mc / npx, "tested_per_composited": mt / max(mc, 1)}
     log(f"stages (ms): {json.dumps({k: round(v, 4) for k, v in avg.items()})}; work {json.dumps(work)}")
-    roofline = {"bound": "alu", "kernel": "k_render<16,16,fwd>", "achieved": ops_render / avg["render_fwd"] / 1e9,
+    roofline = {"bound": "alu", "kernel": "k_render<16,16,1,0>", "achieved": ops_render / avg["render_fwd"] / 1e9,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-ops/s",
-                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": None,
+                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": recorded_traffic(),
+                "traffic_unit": "bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+                "alg_bytes_per_launch": bytes_render,
+                "hbm_frac": bytes_render / avg["render_fwd"] / 1e-3 / PEAK_HBM,
                 "per_unit": f"{OPS_PER_COMPOSITE} lane-ops per composited (pixel, Gaussian)",
                 "units_per_launch": mc, "avg_launch_ms": avg["render_fwd"]}
 
@@ -211,6 +214,25 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "render_fwd_1M_1256x828_traffic.md")
+TRAFFIC_SOURCES = ("paper_2403_13806_amd/csrc/gs_render.hip", "paper_2403_13806_amd/csrc/gs_device.hpp",
+                   "include/gs.h")
+
+
+def recorded_traffic():
+    """HBM bytes per compositing launch from the committed counter record, or None when the
+    compositing sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = dict(l.split(": ", 1) for l in open(TRAFFIC_RECORD).read().splitlines() if ": " in l)
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != h:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def calib_copy(torch, dev, nbytes=256 << 20, reps=5):
@@ -356,19 +378,21 @@ def importance_pass(torch, gs, scenes, P, dev, chunk=10):
     return out
 
 
-def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01):
+def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, extra=32):
     """Test-time visibility filtering at house scale: 5M Gaussians in 12 rooms, 640 training
     cameras at 1920x1080 clustered into 64 by k-means, per-cluster lists at h > t_cluster, a
     300-frame 1920x1080 path rendered with and without the lists."""
     from paper_2403_13806_amd.splat import PathRenderer
-    log(f"house: {n} Gaussians, 640 training views, k={k}, t_cluster={t_cluster}")
+    log(f"house: {n} Gaussians, 640 training views + {extra} random views per cluster, k={k}, "
+        f"t_cluster={t_cluster}")
     sc = scenes.house_scene(n)
     train = scenes.house_training_views(640)
     path = scenes.house_test_path(300)
     g = gs.Gaussians.from_scene(sc, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    vf = gs.VisibilityFilter(g, train, k=k, t_cluster=t_cluster, params=P, chunk=8, device=dev)
+    vf = gs.VisibilityFilter(g, train, k=k, t_cluster=t_cluster, params=P, chunk=8, device=dev,
+                             extra_per_cluster=extra)
     torch.cuda.synchronize()
     t_vis = time.perf_counter() - t0
     sizes = np.array([int(x.shape[0]) for x in vf.lists])
@@ -396,8 +420,8 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01):
         maxd = max(maxd, float(d.max()))
         mse = float((d * d).mean())
         psnr.append(10 * np.log10(1.0 / max(mse, 1e-20)))
-    out = {"gaussians": n, "train_views": len(train), "k": k, "t_cluster": t_cluster,
-           "visibility_pass_s": t_vis, "train_views_per_s": len(train) / t_vis,
+    out = {"gaussians": n, "train_views": len(train), "extra_views_per_cluster": extra, "k": k,
+           "t_cluster": t_cluster, "visibility_pass_s": t_vis, "views_per_s": vf.views_used / t_vis,
            "list_size_mean": float(sizes.mean()), "list_size_max": int(sizes.max()),
            "unfiltered_fps": rates["unfiltered"], "filtered_fps": rates["filtered"],
            "speedup": rates["filtered"] / rates["unfiltered"],

@@ -435,23 +435,75 @@ class Renderer:
         return bool(int(self.bins.overflow.item())), int(self.bins.n_pairs.item())
 
 
+@dataclass
+class PinholeCamera:
+    """A camera in the form the binding reads (world -> camera p_c = R p + t)."""
+    R: np.ndarray
+    t: np.ndarray
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    znear: float = 0.2
+
+    @property
+    def position(self) -> np.ndarray:
+        return -(np.asarray(self.R, np.float64).T @ np.asarray(self.t, np.float64))
+
+
+def _camera_at(position, yaw, pitch, like) -> PinholeCamera:
+    """Camera at `position` looking along (yaw, pitch) (y down), intrinsics copied from `like`."""
+    fwd = np.array([np.cos(pitch) * np.sin(yaw), -np.sin(pitch), np.cos(pitch) * np.cos(yaw)])
+    down = np.array([0.0, 1.0, 0.0])
+    y = down - np.dot(down, fwd) * fwd
+    y /= np.linalg.norm(y)
+    x = np.cross(y, fwd)
+    R = np.stack([x, y, fwd]).astype(np.float32)
+    t = (-R.astype(np.float64) @ np.asarray(position, np.float64)).astype(np.float32)
+    return PinholeCamera(R, t, like.fx, like.fy, like.cx, like.cy, like.width, like.height, like.znear)
+
+
 class VisibilityFilter:
     """Viewpoint-based visibility filtering (Sec. 3.4): k-means clusters of the training
     camera positions; per cluster, the indicator list of the Gaussians composited with weight
-    above t_cluster in some training view of the cluster (eq. importance-score-vis); a test
-    view is rendered with the list of the cluster centre nearest to its camera centre."""
+    above t_cluster in some view of the cluster (eq. importance-score-vis); a test view is
+    rendered with the list of the cluster centre nearest to its camera centre.
+
+    extra_per_cluster random cameras are added to every cluster's views, as the method does
+    for robustness to test views: each sits at a random member camera's position moved by a
+    uniform offset in a ball of radius `jitter`, looks in a random direction (yaw uniform,
+    pitch uniform in +-max_pitch) and copies that member's intrinsics."""
 
     def __init__(self, g: Gaussians, train_cams: Sequence, k: int = 64, t_cluster: float = 0.001, params=None,
-                 chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None):
+                 chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None,
+                 extra_per_cluster: int = 0, jitter: float = 1.0, max_pitch: float = np.deg2rad(30.0)):
         dev = _dev(device)
         self.g, self.k, self.t_cluster, self.params, self.tile, self.device = g, k, t_cluster, params, tile, dev
         pos = np.stack([c.position for c in train_cams])
         self.centres, self.assign = kmeans(pos, k, seed=seed)
+        views, owner = list(train_cams), list(self.assign)
+        if extra_per_cluster > 0:
+            rng = np.random.default_rng(seed)
+            for c in range(k):
+                members = np.nonzero(self.assign == c)[0]
+                if members.size == 0:
+                    continue
+                for _ in range(extra_per_cluster):
+                    m = train_cams[int(rng.choice(members))]
+                    off = rng.standard_normal(3)
+                    off *= jitter * rng.uniform() ** (1.0 / 3.0) / max(np.linalg.norm(off), 1e-12)
+                    views.append(_camera_at(m.position + off, rng.uniform(0, 2 * np.pi),
+                                            rng.uniform(-max_pitch, max_pitch), m))
+                    owner.append(c)
+        self.views_used = len(views)
         words = (g.n + 31) // 32
         self.bits = torch.zeros(max(k * words, 1), dtype=torch.int32, device=dev)
-        for c0 in range(0, len(train_cams), chunk):
-            vb = ViewBatch(train_cams[c0:c0 + chunk], tile, dev)
-            cluster_visibility(g, vb, self.assign[c0:c0 + chunk], k, t_cluster, params, bits=self.bits)
+        owner = np.asarray(owner, np.int32)
+        for c0 in range(0, len(views), chunk):
+            vb = ViewBatch(views[c0:c0 + chunk], tile, dev)
+            cluster_visibility(g, vb, owner[c0:c0 + chunk], k, t_cluster, params, bits=self.bits)
         self.lists = [bits_to_list(self.bits[c * words:(c + 1) * words], g.n) for c in range(k)]
 
     def cluster_of(self, cam) -> int:

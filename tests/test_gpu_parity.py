@@ -441,3 +441,19 @@ def test_visibility_filter_and_path_renderer():
         a0 = pr.frame(f, None).clone()
         b0 = gs.render(g, gs.ViewBatch([cam], (16, 16), DEV), P)["rgb"]
         assert torch.equal(a0, b0), f
+
+
+def test_visibility_filter_extra_cameras_only_add():
+    """Extra random cameras per cluster (Sec. 3.4) only add views to a cluster, so each
+    cluster's list can only grow (the per-cluster max is monotone in the view set)."""
+    sc = scenes.house_scene(8000, seed=5, sh_degree=0)
+    train = scenes.house_training_views(10, width=80, height=45)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("visibility filter with extra cameras")
+    a = gs.VisibilityFilter(g, train, k=2, t_cluster=0.01, params=P, device=DEV)
+    b = gs.VisibilityFilter(g, train, k=2, t_cluster=0.01, params=P, device=DEV, extra_per_cluster=3)
+    assert b.views_used == len(train) + 6
+    for c in range(2):
+        sa = set(a.lists[c].cpu().numpy().tolist())
+        sb = set(b.lists[c].cpu().numpy().tolist())
+        assert sa <= sb
