@@ -197,9 +197,10 @@ gs_status gs_preprocess(const gs_gaussians* g, const gs_views* views, const gs_p
                         int64_t n_subset, int32_t want_color, gs_projected* out, void* stream);
 
 /* Bin projected Gaussians into tiles and sort the pairs by (tile, depth, index) (the
- * "correctly-sorted points" of eq. render-gs, per tile): exclusive scan of the
- * per-Gaussian tile counts, key emission, LSD radix sort on the significant key bits,
- * per-tile ranges. ws: device workspace of at least
+ * "correctly-sorted points" of eq. render-gs, per tile): pair counts per tile, their
+ * exclusive scan (tile ranges, pair total, capacity check), a scatter of the pairs into
+ * their tiles' ranges, and a sort of each tile's list by (FP32 depth bits, index) in LDS.
+ * The result is deterministic. ws: device workspace of at least
  * gs_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles). */
 gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws, size_t ws_bytes,
                       void* stream);

@@ -56,28 +56,31 @@ struct RenderArgs {
     int n_tiles;
 };
 
-// conservative float box of the support (FP64 conic -> covariance diagonal), padded so
-// that no covered pixel centre can fall outside it
-__device__ __forceinline__ float4 support_box(const gs_splat& s) {
-    const double det = s.ca * s.cc - s.cb * s.cb;
-    const double hx = sqrt(s.qmax * s.cc / det), hy = sqrt(s.qmax * s.ca / det);
-    const float px = (float)hx * 1.0001f + 0.01f, py = (float)hy * 1.0001f + 0.01f;
-    return make_float4((float)s.u - px, (float)s.u + px, (float)s.v - py, (float)s.v + py);
-}
-
-__device__ __forceinline__ bool box_misses(const float4 b, float x0, float x1, float y0, float y1) {
-    return b.y < x0 || b.x > x1 || b.w < y0 || b.z > y1;
-}
-
-// bit w set when the support box meets the 8x8 pixel block of wave w (tile origin at the
-// pixel centre (ox, oy); waves tile the TW x TH tile row-major in 8x8 blocks)
+// bit w set when the support ellipse d^T conic d <= q_max meets the rectangle spanned by
+// the pixel centres of wave w's 8x8 block (waves tile the TW x TH tile row-major in 8x8
+// blocks; (ox, oy) is the centre of the tile's first pixel). q is a positive-definite
+// quadratic with its minimum at the projected mean, so over a rectangle that does not hold
+// the mean its minimum lies on an edge facing the mean: the vertical edge at x = clamp(u)
+// or the horizontal edge at y = clamp(v). Along a vertical edge at offset ex the minimum is
+// at the offset -(b/c) ex clamped to the edge, along a horizontal edge at -(b/a) ey. Both
+// candidate points lie in the rectangle and one of them is the minimiser, so the smaller
+// of the two values is the minimum of q over the rectangle. The relative and absolute
+// margins cover the rounding of these evaluations against the per-pixel test, so a block
+// that holds a covered pixel centre is always marked.
 template <int TW, int TH>
-__device__ __forceinline__ uint32_t wave_hits(const float4 b, float ox, float oy) {
+__device__ __forceinline__ uint32_t wave_hits(const gs_splat& s, double ox, double oy) {
+    const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
+    const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
     uint32_t m = 0;
-#pragma unroll
+#pragma unroll 1
     for (int w = 0; w < (TW / 8) * (TH / 8); ++w) {
-        const float x0 = ox + (float)((w % (TW / 8)) * 8), y0 = oy + (float)((w / (TW / 8)) * 8);
-        if (!box_misses(b, x0, x0 + 7.f, y0, y0 + 7.f)) m |= 1u << w;
+        const double x0 = ox + (double)((w % (TW / 8)) * 8) - s.u, x1 = x0 + 7.0;
+        const double y0 = oy + (double)((w / (TW / 8)) * 8) - s.v, y1 = y0 + 7.0;
+        const double ex = fmin(fmax(0.0, x0), x1), ey = fmin(fmax(0.0, y0), y1);
+        const double fy = fmin(fmax(kx * ex, y0), y1), fx = fmin(fmax(ky * ey, x0), x1);
+        const double q1 = s.ca * ex * ex + 2.0 * s.cb * ex * fy + s.cc * fy * fy;
+        const double q2 = s.ca * fx * fx + 2.0 * s.cb * fx * ey + s.cc * ey * ey;
+        if (fmin(q1, q2) <= lim) m |= 1u << w;
     }
     return m;
 }
@@ -85,8 +88,7 @@ __device__ __forceinline__ uint32_t wave_hits(const float4 b, float ox, float oy
 struct TileGeom {
     int view, W, H, px, py, wave;
     bool inside;
-    float wx0, wy0;  // centre of the wave's first pixel
-    float ox, oy;    // centre of the tile's first pixel
+    double ox, oy;   // centre of the tile's first pixel
     int64_t pix;     // global pixel index
 };
 
@@ -105,27 +107,23 @@ __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     g.px = tx * TW + bx + (l & 7);
     g.py = ty * TH + by + (l >> 3);
     g.inside = g.px < g.W && g.py < g.H;
-    g.wx0 = (float)(tx * TW + bx) + 0.5f;
-    g.wy0 = (float)(ty * TH + by) + 0.5f;
-    g.ox = (float)(tx * TW) + 0.5f;
-    g.oy = (float)(ty * TH) + 0.5f;
+    g.ox = (double)(tx * TW) + 0.5;
+    g.oy = (double)(ty * TH) + 0.5;
     g.pix = a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
     return g;
 }
 
-// FP64 support test and FP32 opacity of record s at pixel centre (xc, yc)
-__device__ __forceinline__ bool eval_alpha(const gs_splat& s, double xc, double yc, float amax, float& alpha,
-                                           float& G, float& dx, float& dy) {
-    const double ddx = xc - s.u, ddy = yc - s.v;
-    const double q = s.ca * ddx * ddx + 2.0 * s.cb * ddx * ddy + s.cc * ddy * ddy;
-    if (!(q <= s.qmax)) return false;
-    G = __expf(-0.5f * (float)q);
-    alpha = fminf(amax, s.opacity * G);
-    dx = (float)ddx;
-    dy = (float)ddy;
-    return true;
+// d^T conic d at the offset (dx, dy) of a pixel centre from the projected mean: FP64, one
+// fixed order of operations shared by every traversal, so the forward pass, the importance
+// pass and the reverse traversal take identical support and opacity decisions
+__device__ __forceinline__ double quad(const gs_splat& s, double dx, double dy) {
+    return fma(s.cc * dy, dy, dx * fma(2.0 * s.cb, dy, s.ca * dx));
 }
 
+// exp(-q/2) in FP32, as 2^(q * (-log2(e) / 2))
+__device__ __forceinline__ float falloff(double q) {
+    return __builtin_amdgcn_exp2f((float)q * -0.72134752044448170368f);
+}
 
 template <int TW, int TH, int DEPTH>
 struct Smem {
@@ -152,12 +150,12 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
     for (int d = 0; d < DEPTH; ++d) {
         const uint32_t q = threadIdx.x + d * NT;
         uint32_t hm = 0;
-        if (q < cnt) {
-            const uint32_t id = a.vals[base + q];
+        const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
+        if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
             const gs_splat s = sp[id];
             sm.rec[q] = s;
             sm.gid[q] = id;
-            hm = wave_hits<TW, TH>(support_box(s), g.ox, g.oy);
+            hm = wave_hits<TW, TH>(s, g.ox, g.oy);
         }
         sm.hit[q] = (uint8_t)hm;
     }
@@ -188,23 +186,23 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
             while (m) {
                 const int j = c * 64 + (int)__builtin_ctzll(m);
                 m &= m - 1;
-                float wgt = 0.f;
-                if (!done) {
-                    const gs_splat& s = sm.rec[j];
-                    float al, G, dx, dy;
-                    if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
-                        wgt = al * T;
-                        if (MODE == MODE_FWD) {
-                            C0 += wgt * s.rgb[0];
-                            C1 += wgt * s.rgb[1];
-                            C2 += wgt * s.rgb[2];
-                        }
-                        T = T * (1.f - al);
-                        last = base + j + 1;
-                        ++ncomp;
-                        if (T < tmin) done = true;
-                    }
+                const gs_splat& s = sm.rec[j];
+                const double q = quad(s, xc - s.u, yc - s.v);
+                const bool in = !done && q <= s.qmax;
+                if (ballot(in) == 0) continue;
+                const float al = in ? fminf(amax, s.opacity * falloff(q)) : 0.f;
+                const float wgt = al * T;
+                if (MODE == MODE_FWD && in) {
+                    C0 += wgt * s.rgb[0];
+                    C1 += wgt * s.rgb[1];
+                    C2 += wgt * s.rgb[2];
                 }
+                T = T * (1.f - al);
+                if (in) {
+                    last = base + j + 1;
+                    ++ncomp;
+                }
+                done = done || T < tmin;
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
                         const float mx = wave_max_nonneg(wgt);
@@ -234,19 +232,65 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
     }
 }
 
+// Nine per-lane values summed over each row of 16 lanes by a transposing butterfly: at
+// every step a lane adds its partner's copy of half of the fields it still holds and keeps
+// that half, so after four steps each lane holds the row sum of one field. Lane i keeps
+// the upper half at the steps pairing it with i^1, i^2, i^7 and i^15 when s1 = b0^b2,
+// s2 = b1^b2, s3 = b2^b3 and s4 = b3 are set (b the bits of i within the row): partners
+// differ in the selector of their own step and agree in every earlier one, so they hold the
+// same fields when they exchange. The field ends up as f = s1 + 2 s2 + 4 s3 + 8 s4; fields
+// 9..15 are zero padding. Must be called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ float pair_add(float x) {
+    return x + __int_as_float(dpp<CTRL>(__float_as_int(x)));
+}
+
+__device__ __forceinline__ int row_sum9_field(int lane) {
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    return (b0 ^ b2) + 2 * (b1 ^ b2) + 4 * (b2 ^ b3) + 8 * b3;
+}
+
+__device__ __forceinline__ float row_sum9(const float (&v)[9], int lane) {
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool s1 = b0 ^ b2, s2 = b1 ^ b2, s3 = b2 ^ b3, s4 = b3;
+    // every cross-lane add is computed by all lanes before the selects (a DPP read inside a
+    // divergent branch would see inactive source lanes)
+    float w[5], x[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float lo = pair_add<0xB1>(v[2 * k]), hi = pair_add<0xB1>(v[2 * k + 1]);
+        w[k] = s1 ? hi : lo;
+    }
+    const float w4 = pair_add<0xB1>(v[8]);
+    w[4] = s1 ? 0.f : w4;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float lo = pair_add<0x4E>(w[2 * k]), hi = pair_add<0x4E>(w[2 * k + 1]);
+        x[k] = s2 ? hi : lo;
+    }
+    const float x2 = pair_add<0x4E>(w[4]);
+    x[2] = s2 ? 0.f : x2;
+    const float y0l = pair_add<0x141>(x[0]), y0h = pair_add<0x141>(x[1]), y1l = pair_add<0x141>(x[2]);
+    const float y0 = s3 ? y0h : y0l, y1 = s3 ? 0.f : y1l;
+    const float zl = pair_add<0x140>(y0), zh = pair_add<0x140>(y1);
+    return s4 ? zh : zl;
+}
+
 // Reverse traversal. For pixel entries in back-to-front order, with T the transmittance
 // after entry j and S the colour composited behind it (S starts at T_final * bg):
 //   T_j = T / (1 - alpha_j), w_j = alpha_j T_j,
 //   dL/dc_j = dL/dC * w_j,  dL/dalpha_j = sum_c dL/dC_c (T_j c_jc - S_c / (1 - alpha_j)),
 // then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
-// dx = xc - u. The nine per-record sums are reduced over the wave and added atomically
-// into g2[field][view * n + index].
+// dx = xc - u. The nine per-record sums are reduced over each row of the wave into the
+// record's LDS accumulator; one global atomic per (tile, record, field) adds the workgroup's
+// sums into g2[field][view * n + index].
 template <int TW, int TH, int DEPTH>
 __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
     constexpr int NT = TW * TH;
     constexpr int BD = NT * DEPTH;
     const TileGeom g = tile_geom<TW, TH>(a, tile);
     const int t = threadIdx.x, l = t & 63, w = g.wave;
+    const int fld = row_sum9_field(l);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
     const float amax = a.p.alpha_max;
@@ -288,43 +332,43 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 m &= ~(1ull << b);
                 const int j = c * 64 + b;
                 const uint32_t pos = lo + j;
-                float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+                float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // u v a b c o r g b
                 bool contrib = false;
                 if (g.inside && pos < last) {
                     const gs_splat& s = sm.rec[j];
-                    float al, G, dx, dy;
-                    if (eval_alpha(s, xc, yc, amax, al, G, dx, dy)) {
+                    const double ddx = xc - s.u, ddy = yc - s.v;
+                    const double q = quad(s, ddx, ddy);
+                    if (q <= s.qmax) {
                         contrib = true;
-                        const float om = 1.f - al;
-                        T = T / om;
+                        const float G = falloff(q);
+                        const float al = fminf(amax, s.opacity * G);
+                        const float r = __builtin_amdgcn_rcpf(1.f - al);
+                        T = T * r;
                         const float wt = al * T;
-                        gr = dC0 * wt;
-                        gg = dC1 * wt;
-                        gbl = dC2 * wt;
-                        const float dA = dC0 * (T * s.rgb[0] - S0 / om) + dC1 * (T * s.rgb[1] - S1 / om) +
-                                         dC2 * (T * s.rgb[2] - S2 / om);
+                        v[6] = dC0 * wt;
+                        v[7] = dC1 * wt;
+                        v[8] = dC2 * wt;
+                        const float dA = dC0 * (T * s.rgb[0] - S0 * r) + dC1 * (T * s.rgb[1] - S1 * r) +
+                                         dC2 * (T * s.rgb[2] - S2 * r);
                         S0 += wt * s.rgb[0];
                         S1 += wt * s.rgb[1];
                         S2 += wt * s.rgb[2];
                         if (s.opacity * G < amax) {
-                            go = dA * G;
+                            const float dx = (float)ddx, dy = (float)ddy;
+                            v[5] = dA * G;
                             const float dq = -0.5f * al * dA;
-                            ga = dq * dx * dx;
-                            gb = dq * 2.f * dx * dy;
-                            gc = dq * dy * dy;
-                            gu = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
-                            gv = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
+                            v[2] = dq * dx * dx;
+                            v[3] = dq * 2.f * dx * dy;
+                            v[4] = dq * dy * dy;
+                            v[0] = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
+                            v[1] = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
                         }
                     }
                 }
                 if (ballot(contrib)) {
-                    const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
-                                sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
-                                sbl = wave_sum(gbl);
-                    // lanes 0..8 add one field each into the record's LDS accumulator
-                    const float v = l == 0 ? su : l == 1 ? sv : l == 2 ? sa : l == 3 ? sb : l == 4 ? sc
-                                  : l == 5 ? so : l == 6 ? sr : l == 7 ? sg : sbl;
-                    if (l < 9) atomicAdd(&sm.acc[j * 9 + l], v);
+                    // per-row sums, one field per lane; four rows add into the record's slot
+                    const float z = row_sum9(v, l);
+                    if (fld < 9) atomicAdd(&sm.acc[j * 9 + fld], z);
                 }
             }
         }
@@ -356,8 +400,9 @@ __device__ __forceinline__ int tile_of_round(const RenderArgs& a, int r) {
     return item < a.n_tiles ? (int)a.queue[item] : -1;
 }
 
+// at most 64 VGPRs, so that eight waves fit on each SIMD
 template <int TW, int TH, int DEPTH, int MODE>
-__global__ __launch_bounds__(TW* TH) void k_render(RenderArgs a) {
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_render(RenderArgs a) {
     __shared__ Smem<TW, TH, DEPTH> sm;
     for (int r = 0;; ++r) {
         const int tile = tile_of_round(a, r);

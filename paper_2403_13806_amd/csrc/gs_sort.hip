@@ -1,20 +1,25 @@
-// Tile binning and the (tile, depth, index) sort that gives every tile its
-// front-to-back list ("correctly-sorted points", eq. render-gs):
+// Tile binning and the (tile, depth, index) order that gives every tile its front-to-back
+// list ("correctly-sorted points", eq. render-gs):
 //   scan     exclusive prefix sum of the per-(view, Gaussian) tile counts in one pass:
 //            4096 items per block, wave DPP scan -> block scan -> decoupled look-back
 //            across blocks in launch-ticket order; the last block writes the pair total
 //            and the capacity check
 //   emit     load-balanced: the pairs of a wave's 64 Gaussians are contiguous in the
-//            output, so lanes walk that range 64 pairs at a time and find their
-//            Gaussian by a 6-step binary search over the wave's offsets in LDS; keys
-//            (global tile << 32 | FP32 depth bits) are written coalesced, in index order,
-//            so a stable sort breaks depth ties by index
-//   sort     onesweep LSD radix sort, 8-bit digits over the significant key bits: one
-//            kernel builds the global digit histograms of all passes, then one kernel per
-//            pass ranks its 4096 items stably (8 ballots per wave), resolves the digit
-//            offsets of earlier blocks by decoupled look-back, and scatters through LDS
-//            so that global writes are coalesced runs
-//   ranges   [start, end) of every tile in the sorted list
+//            output, so lanes walk that range 64 pairs at a time and find their Gaussian
+//            by a 6-step binary search over the wave's offsets in LDS; each pair is the
+//            global tile id (key) and FP32 depth bits << 32 | Gaussian index (value)
+//   group    onesweep LSD radix sort on the tile id (ceil(tile bits / 8) passes of 8 bits):
+//            one kernel builds the digit histograms of all passes, then one kernel per pass
+//            ranks its 4096 items (8 ballots per wave), resolves the digit offsets of earlier
+//            blocks by decoupled look-back, and scatters through LDS so that global writes
+//            are coalesced runs
+//   ranges   [start, end) of every tile in the grouped list
+//   sort     one workgroup per tile sorts the tile's list by its unique 64-bit (depth bits,
+//            index) values in LDS with a bitonic network (the result does not depend on the
+//            order the grouping left) and writes the keys (tile << 32 | depth bits) and the
+//            Gaussian indices; lists longer than the small buffer go to a second kernel with a
+//            larger one, which sorts lists longer than that in chunks and merges the chunks
+//            (merge path) through a scratch buffer
 // Every wait on another block is bounded: a wait that exceeds its spin budget sets bit 1
 // of the overflow word (results invalid) instead of hanging.
 #include <algorithm>
@@ -27,7 +32,6 @@ constexpr int BLK = 256;                 // threads per scan / sort block
 constexpr int IPT = 16;                  // items per thread
 constexpr int TILE_ITEMS = BLK * IPT;    // items per block
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
-constexpr int MAX_PASSES = 8;
 
 // chained-scan status word: flag in the two top bits, value below
 constexpr uint64_t ST_AGG = 1ull << 62;
@@ -210,21 +214,20 @@ gs_status launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* ct
 }
 
 // ---------------------------------------------------------------------------------------
-// Key emission
+// Pair emission
 // ---------------------------------------------------------------------------------------
 struct EmitArgs {
     const uint32_t* count;
-    const uint32_t* offs;
+    const uint32_t* offs;  // exclusive pair offsets in entry order
     const uint64_t* rect;
     const float* depth;
     const gs_camera* cams;
     const int32_t* tile_offset;
-    int64_t n;
+    int64_t n;             // Gaussians per view
     int tile_w;
     const uint32_t* overflow;
-    uint64_t capacity;
-    uint64_t* keys;
-    uint32_t* vals;
+    uint32_t* tkey;        // global tile of each pair
+    uint64_t* tval;        // FP32 depth bits << 32 | Gaussian index
 };
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
@@ -263,45 +266,46 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 #pragma unroll
         for (int step = 32; step > 0; step >>= 1)
             if (L + step <= last && wo[L + step] <= g) L += step;
-        const uint64_t rr = s_rect[w * 64 + L];
+        const int q = w * 64 + L;
+        const uint64_t rr = s_rect[q];
         const uint32_t x0 = rr & 0xffff, y0 = (rr >> 16) & 0xffff, x1 = (rr >> 32) & 0xffff;
         const uint32_t wd = x1 - x0 + 1;
         const uint32_t k = g - wo[L];
-        const uint32_t ty = y0 + k / wd, tx = x0 + k % wd;
-        a.keys[g] = ((uint64_t)(tbase + ty * tiles_x + tx) << 32) | s_db[w * 64 + L];
-        a.vals[g] = (uint32_t)(j0 + L);
+        a.tkey[g] = tbase + (y0 + k / wd) * tiles_x + x0 + k % wd;
+        a.tval[g] = ((uint64_t)s_db[q] << 32) | (uint32_t)(j0 + L);
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Onesweep radix sort
+// Onesweep LSD radix sort of u32 tile keys carrying u64 values
 // ---------------------------------------------------------------------------------------
 // global digit histograms of every pass (ghist [passes][256], zero on entry). Each thread
-// reads a contiguous run of keys; consecutive keys mostly come from one Gaussian (same
-// depth digits) or neighbouring tiles (same high tile digits), so equal digits are merged
-// in registers and one LDS atomic is issued per run.
+// reads a contiguous run of keys; consecutive keys often share digits (pairs of one
+// Gaussian lie in neighbouring tiles), so equal digits are merged in registers and one LDS
+// atomic is issued per run.
 constexpr int HIST_RUN = 16;
+constexpr int KEY_PASSES = 4;
 
-__global__ __launch_bounds__(256) void k_os_hist(const uint64_t* __restrict__ keys, const uint64_t* n_pairs,
-                                                 uint64_t capacity, int passes, uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[MAX_PASSES][256];
+__global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ keys, const uint64_t* n_items,
+                                                 uint64_t bound, int passes, uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[KEY_PASSES][256];
     const int t = threadIdx.x;
-    for (int p = 0; p < MAX_PASSES; ++p) h[p][t] = 0;
+    for (int p = 0; p < KEY_PASSES; ++p) h[p][t] = 0;
     __syncthreads();
-    const uint64_t count = min(*n_pairs, capacity);
+    const uint64_t count = min(*n_items, bound);
     const uint64_t stride = (uint64_t)gridDim.x * BLK * HIST_RUN;
     for (uint64_t b0 = ((uint64_t)blockIdx.x * BLK + t) * HIST_RUN; b0 < count; b0 += stride) {
         const uint64_t b1 = min(b0 + HIST_RUN, count);
-        uint64_t prev = keys[b0];
-        uint32_t cnt[MAX_PASSES];
+        uint32_t prev = keys[b0];
+        uint32_t cnt[KEY_PASSES];
 #pragma unroll
-        for (int p = 0; p < MAX_PASSES; ++p) cnt[p] = 1;
+        for (int p = 0; p < KEY_PASSES; ++p) cnt[p] = 1;
         for (uint64_t i = b0 + 1; i < b1; ++i) {
-            const uint64_t k = keys[i];
+            const uint32_t k = keys[i];
 #pragma unroll
-            for (int p = 0; p < MAX_PASSES; ++p) {
+            for (int p = 0; p < KEY_PASSES; ++p) {
                 if (p >= passes) continue;
-                const uint32_t dp = (uint32_t)(prev >> (8 * p)) & 255u, dk = (uint32_t)(k >> (8 * p)) & 255u;
+                const uint32_t dp = (prev >> (8 * p)) & 255u, dk = (k >> (8 * p)) & 255u;
                 if (dp == dk) {
                     ++cnt[p];
                 } else {
@@ -312,8 +316,8 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint64_t* __restrict__ ke
             prev = k;
         }
 #pragma unroll
-        for (int p = 0; p < MAX_PASSES; ++p)
-            if (p < passes) atomicAdd(&h[p][(uint32_t)(prev >> (8 * p)) & 255u], cnt[p]);
+        for (int p = 0; p < KEY_PASSES; ++p)
+            if (p < passes) atomicAdd(&h[p][(prev >> (8 * p)) & 255u], cnt[p]);
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p)
@@ -321,12 +325,12 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint64_t* __restrict__ ke
 }
 
 struct PassArgs {
-    const uint64_t* kin;
-    const uint32_t* vin;
-    uint64_t* kout;
-    uint32_t* vout;
-    const uint64_t* n_pairs;
-    uint64_t capacity;
+    const uint32_t* kin;
+    const void* vin;  // V[]
+    uint32_t* kout;
+    void* vout;       // V[] (u32 in the last tile pass)
+    const uint64_t* n_items;
+    uint64_t bound;
     int shift;
     const uint32_t* ghist;  // this pass's 256 digit counts
     uint64_t* status;       // [nblocks][256], zero on entry
@@ -334,39 +338,42 @@ struct PassArgs {
     uint32_t* err;
 };
 
-// Each wave ranks its own contiguous 64*IPT items with wave-private digit counters (no
-// block barrier inside the ranking loop); wave offsets per digit are combined once.
+// One stable counting pass on an 8-bit digit of u32 keys carrying values of type V. Each
+// wave ranks its own contiguous 64*IPT items with wave-private digit counters (no block
+// barrier inside the ranking loop); wave offsets per digit are combined once.
+template <typename V>
 __global__ __launch_bounds__(BLK) void k_os_pass(PassArgs a) {
     __shared__ uint32_t bid_s;
     __shared__ uint32_t wcnt[BLK / 64][256];
     __shared__ uint32_t ds[256];
     __shared__ int64_t dbase[256];
     __shared__ uint32_t wsum[BLK / 64];
-    __shared__ uint64_t lk[TILE_ITEMS];
-    __shared__ uint32_t lv[TILE_ITEMS];
+    __shared__ uint32_t lk[TILE_ITEMS];
+    __shared__ V lv[TILE_ITEMS];
+    const V* vin = (const V*)a.vin;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     if (t == 0) bid_s = atomicAdd(a.ticket, 1u);
     __syncthreads();
     const uint32_t bid = bid_s;
-    const uint64_t count = min(*a.n_pairs, a.capacity);
+    const uint64_t count = min(*a.n_items, a.bound);
     const uint64_t base = (uint64_t)bid * TILE_ITEMS;
     if (base >= count) return;  // blocks past the data; no block waits on them
 #pragma unroll
     for (int k = 0; k < 4; ++k) wcnt[w][l + 64 * k] = 0;
     const uint64_t wbase = base + (uint64_t)w * (64 * IPT);
-    uint64_t key[IPT];
-    uint32_t val[IPT], lr[IPT];
+    uint32_t key[IPT], lr[IPT];
+    V val[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const uint64_t i = wbase + r * 64 + l;
         const bool valid = i < count;
-        key[r] = valid ? a.kin[i] : 0ull;
-        val[r] = valid ? a.vin[i] : 0u;
+        key[r] = valid ? a.kin[i] : 0u;
+        val[r] = valid ? vin[i] : (V)0;
     }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const bool valid = wbase + r * 64 + l < count;
-        const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+        const uint32_t d = (key[r] >> a.shift) & 255u;
         uint64_t m = ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -410,7 +417,7 @@ __global__ __launch_bounds__(BLK) void k_os_pass(PassArgs a) {
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         if (wbase + r * 64 + l < count) {
-            const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+            const uint32_t d = (key[r] >> a.shift) & 255u;
             const uint32_t q = ds[d] + wcnt[w][d] + lr[r];
             lk[q] = key[r];
             lv[q] = val[r];
@@ -422,32 +429,183 @@ __global__ __launch_bounds__(BLK) void k_os_pass(PassArgs a) {
     for (int r = 0; r < IPT; ++r) {
         const uint32_t q = r * BLK + t;
         if (q < nitems) {
-            const uint64_t k = lk[q];
-            const uint32_t d = (uint32_t)(k >> a.shift) & 255u;
+            const uint32_t k = lk[q];
+            const uint32_t d = (k >> a.shift) & 255u;
             const int64_t pos = dbase[d] + (int64_t)q;
             if (pos >= 0 && (uint64_t)pos < count) {  // always true unless a look-back timed out
                 a.kout[pos] = k;
-                a.vout[pos] = lv[q];
+                ((V*)a.vout)[pos] = lv[q];
             }
         }
+    }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* n_pairs, uint64_t capacity,
+                         const uint32_t* overflow, uint32_t* __restrict__ ranges, int n_tiles) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (*overflow) return;
+    const uint64_t count = min(*n_pairs, capacity);
+    if (k >= count) return;
+    const uint32_t tile = tkeys[k];
+    if (tile >= (uint32_t)n_tiles) return;
+    if (k == 0 || tkeys[k - 1] != tile) ranges[2 * tile] = (uint32_t)k;
+    if (k + 1 == count || tkeys[k + 1] != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-tile sort by (depth bits, index)
+// ---------------------------------------------------------------------------------------
+constexpr int SMALL_LIST = 2048;  // 16 KB of LDS per workgroup
+constexpr int LARGE_LIST = 8192;  // 64 KB
+
+struct TileSortArgs {
+    uint64_t* pairs;    // values grouped by tile; also the merge buffer of very long lists
+    uint64_t* scratch;  // [capacity]
+    const uint32_t* ranges;
+    int n_tiles;
+    uint64_t capacity;
+    const uint32_t* overflow;
+    uint64_t* keys;
+    uint32_t* vals;
+    uint32_t* n_deferred;  // number of deferred tiles (zero on entry)
+    uint32_t* deferred;    // [n_tiles] their ids
+};
+
+// the LDS writes of this wave are visible to its later LDS reads (no other wave involved)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ascending bitonic sort of s[0, N) by a 256-thread workgroup (N a power of two >= 2).
+// Pair i of a stage goes to thread i mod 256, so in a stage of stride j <= 64 the pairs of
+// one wave (i = 64 c + lane, c = wave mod 4) stay inside the 128-element chunks c of that
+// wave: those stages need no workgroup barrier, only the wider ones do.
+__device__ void bitonic_lds(uint64_t* s, int N) {
+    for (int k = 2; k <= N; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const bool wide = j > 64;
+            if (wide) __syncthreads();
+            for (int i = threadIdx.x; i < (N >> 1); i += 256) {
+                const int lo = 2 * i - (i & (j - 1)), hi = lo + j;
+                const uint64_t x = s[lo], y = s[hi];
+                if ((x > y) == ((lo & k) == 0)) {
+                    s[lo] = y;
+                    s[hi] = x;
+                }
+            }
+            if (wide)
+                __syncthreads();
+            else
+                wave_sync();
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int pow2_at_least(int x) {
+    int p = 2;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// sort src[0, len) (len <= cap) through the LDS buffer s into s[0, len)
+__device__ void sort_in_lds(uint64_t* s, const uint64_t* src, int len) {
+    const int N = pow2_at_least(len);
+    for (int i = threadIdx.x; i < N; i += 256) s[i] = i < len ? src[i] : ~0ull;
+    __syncthreads();
+    bitonic_lds(s, N);
+}
+
+__device__ void write_tile(const TileSortArgs& a, int tile, uint32_t start, const uint64_t* s, int len) {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint64_t x = s[i];
+        a.keys[start + i] = ((uint64_t)tile << 32) | (x >> 32);
+        a.vals[start + i] = (uint32_t)x;
+    }
+}
+
+// number of elements taken from A among the first d of the merge of sorted A and B
+// (keys are unique)
+__device__ __forceinline__ int merge_split(const uint64_t* A, int na, const uint64_t* B, int nb, int d) {
+    int lo = max(0, d - nb), hi = min(d, na);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] < B[d - 1 - mid])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
+    __shared__ uint64_t s[SMALL_LIST];
+    const int tile = blockIdx.x, t = threadIdx.x;
+    if (*a.overflow) return;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    if (end <= start || (uint64_t)end > a.capacity) return;
+    const uint32_t len = end - start;
+    if (len > (uint32_t)SMALL_LIST) {
+        if (t == 0) a.deferred[atomicAdd(a.n_deferred, 1u)] = (uint32_t)tile;
+        return;
+    }
+    sort_in_lds(s, a.pairs + start, (int)len);
+    write_tile(a, tile, start, s, (int)len);
+}
+
+// deferred (long) lists; a grid-stride loop over them
+__global__ __launch_bounds__(256) void k_tile_sort_large(TileSortArgs a) {
+    __shared__ uint64_t s[LARGE_LIST];
+    if (*a.overflow) return;
+    const uint32_t nd = min(*a.n_deferred, (uint32_t)a.n_tiles);
+    for (uint32_t it = blockIdx.x; it < nd; it += gridDim.x) {
+        const int tile = (int)a.deferred[it];
+        const uint32_t start = a.ranges[2 * tile];
+        const int len = (int)(a.ranges[2 * tile + 1] - start);
+        if (len <= LARGE_LIST) {
+            sort_in_lds(s, a.pairs + start, len);
+            write_tile(a, tile, start, s, len);
+            __syncthreads();
+            continue;
+        }
+        // sorted chunks of LARGE_LIST into scratch, then pairwise merges back and forth
+        uint64_t* src = a.scratch + start;
+        uint64_t* dst = a.pairs + start;
+        for (int c0 = 0; c0 < len; c0 += LARGE_LIST) {
+            const int cl = min(LARGE_LIST, len - c0);
+            sort_in_lds(s, a.pairs + start + c0, cl);
+            for (int i = threadIdx.x; i < cl; i += blockDim.x) src[c0 + i] = s[i];
+            __syncthreads();
+        }
+        for (int wd = LARGE_LIST; wd < len; wd <<= 1) {
+            for (int m0 = 0; m0 < len; m0 += 2 * wd) {
+                const int na = min(wd, len - m0), nb = max(0, min(wd, len - m0 - wd));
+                const uint64_t* A = src + m0;
+                const uint64_t* B = A + na;
+                const int M = na + nb;
+                const int d0 = (int)((int64_t)M * threadIdx.x / blockDim.x);
+                const int d1 = (int)((int64_t)M * (threadIdx.x + 1) / blockDim.x);
+                int i = merge_split(A, na, B, nb, d0), j = d0 - i;
+                for (int d = d0; d < d1; ++d) {
+                    const bool takeA = j >= nb || (i < na && A[i] < B[j]);
+                    dst[m0 + d] = takeA ? A[i++] : B[j++];
+                }
+            }
+            __syncthreads();
+            uint64_t* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        write_tile(a, tile, start, src, len);
+        __syncthreads();
     }
 }
 
 __global__ void k_iota(uint32_t* __restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (uint32_t)i;
-}
-
-__global__ void k_ranges(const uint64_t* __restrict__ keys, const uint64_t* n_pairs, uint64_t capacity,
-                         const uint32_t* overflow, uint32_t* __restrict__ ranges, int n_tiles) {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (*overflow) return;
-    const uint64_t count = min(*n_pairs, capacity);
-    if (k >= count) return;
-    const uint32_t tile = (uint32_t)(keys[k] >> 32);
-    if (tile >= (uint32_t)n_tiles) return;
-    if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != tile) ranges[2 * tile] = (uint32_t)k;
-    if (k + 1 == count || (uint32_t)(keys[k + 1] >> 32) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -507,44 +665,56 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint32_t* __restrict_
 // ---------------------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int key_bits(int n_tiles) {
+static int tile_bits(int n_tiles) {
     int b = 0;
     while (b < 31 && (1u << b) < (uint32_t)n_tiles) ++b;
-    return 32 + b;
+    return b;
 }
 
 struct SortLayout {
-    size_t offs, ctrl, scan_ctrl, tickets, ghist, lpt, status, ctrl_end, keys_alt, vals_alt, total;
-    int64_t nb_sort, nb_scan;
+    // control block, cleared at the start of every gs_bin_sort: scan chain, pass tickets,
+    // digit histograms, deferred-tile count, LPT counters, pass status tables
+    size_t ctrl, scan, tickets, ghist, n_deferred, lpt, status, ctrl_end;
+    size_t offs, deferred, tk0, tk1, tv0, tv1, total;
+    int64_t nb_scan, nb_sort;
     int passes;
 };
 
 SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
     SortLayout L;
     const int64_t vn = n * (int64_t)n_views;
-    L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
+    const size_t nt = (size_t)std::max(n_tiles, 1);
     L.nb_scan = scan_blocks(vn);
-    L.passes = (key_bits(std::max(n_tiles, 1)) + 7) / 8;
+    L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
+    L.passes = std::max(1, (tile_bits(std::max(n_tiles, 1)) + 7) / 8);
     size_t p = 0;
-    L.offs = p;
-    p = align256(p + sizeof(uint32_t) * (size_t)vn);
-    // control block, cleared at the start of every gs_bin_sort
     L.ctrl = p;
-    L.scan_ctrl = p;
+    L.scan = p;
     p = align256(p + sizeof(uint64_t) * ((size_t)L.nb_scan + 1));
     L.tickets = p;
-    p = align256(p + sizeof(uint32_t) * MAX_PASSES);
+    p = align256(p + sizeof(uint32_t) * KEY_PASSES);
     L.ghist = p;
-    p = align256(p + sizeof(uint32_t) * 256 * MAX_PASSES);
+    p = align256(p + sizeof(uint32_t) * 256 * KEY_PASSES);
+    L.n_deferred = p;
+    p = align256(p + sizeof(uint32_t));
     L.lpt = p;
     p = align256(p + sizeof(uint32_t) * 2 * LPT_B);
     L.status = p;
     p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
     L.ctrl_end = p;
-    L.keys_alt = p;
-    p = align256(p + sizeof(uint64_t) * (size_t)capacity);
-    L.vals_alt = p;
-    p = align256(p + sizeof(uint32_t) * (size_t)capacity);
+    L.offs = p;
+    p = align256(p + sizeof(uint32_t) * (size_t)vn);
+    L.deferred = p;
+    p = align256(p + sizeof(uint32_t) * nt);
+    const size_t k4 = sizeof(uint32_t) * (size_t)capacity, v8 = sizeof(uint64_t) * (size_t)capacity;
+    L.tk0 = p;
+    p = align256(p + k4);
+    L.tk1 = p;
+    p = align256(p + k4);
+    L.tv0 = p;
+    p = align256(p + v8);
+    L.tv1 = p;
+    p = align256(p + v8);
     L.total = p;
     return L;
 }
@@ -574,13 +744,8 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     const int64_t vn = n * (int64_t)views->n_views;
     SortLayout L = sort_layout(n, views->n_views, bins->capacity, views->n_tiles);
     char* w = (char*)ws;
-    uint32_t* offs = (uint32_t*)(w + L.offs);
-    uint64_t* scan_ctrl = (uint64_t*)(w + L.scan_ctrl);
-    uint32_t* tickets = (uint32_t*)(w + L.tickets);
-    uint32_t* ghist = (uint32_t*)(w + L.ghist);
-    uint64_t* status = (uint64_t*)(w + L.status);
-    uint64_t* kalt = (uint64_t*)(w + L.keys_alt);
-    uint32_t* valt = (uint32_t*)(w + L.vals_alt);
+    auto U32 = [&](size_t off) { return (uint32_t*)(w + off); };
+    auto U64 = [&](size_t off) { return (uint64_t*)(w + off); };
 
     // ranges start empty; flags, pair count and the control block start at zero
     gs_status st;
@@ -591,21 +756,20 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     f.n[1] = 1;
     f.p[2] = (uint32_t*)bins->n_pairs;
     f.n[2] = 2;
-    f.p[3] = (uint32_t*)(w + L.ctrl);
+    f.p[3] = U32(L.ctrl);
     f.n[3] = vn == 0 ? 0 : (int64_t)((L.ctrl_end - L.ctrl) / 4);
     if ((st = launch_zero4(f, stream))) return st;
-    if (vn == 0) return launch_lpt(views, bins, nullptr, stream);
-    if ((st = launch_scan(proj->count, offs, vn, scan_ctrl, bins->n_pairs, bins->overflow, bins->capacity, stream)))
+    if (vn == 0 || views->n_tiles == 0) return launch_lpt(views, bins, nullptr, stream);
+
+    // 1. pair offsets in entry order, pair total, capacity check
+    if ((st = launch_scan(proj->count, U32(L.offs), vn, U64(L.scan), bins->n_pairs, bins->overflow, bins->capacity,
+                          stream)))
         return st;
-    const int passes = L.passes;
-    // with an even number of passes the result lands where the keys were emitted
-    uint64_t* k0 = (passes % 2 == 0) ? bins->keys : kalt;
-    uint32_t* v0 = (passes % 2 == 0) ? bins->vals : valt;
-    uint64_t* k1 = (passes % 2 == 0) ? kalt : bins->keys;
-    uint32_t* v1 = (passes % 2 == 0) ? valt : bins->vals;
+    if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
+    // 2. pairs (tile; depth bits, index)
     EmitArgs e;
     e.count = proj->count;
-    e.offs = offs;
+    e.offs = U32(L.offs);
     e.rect = proj->rect;
     e.depth = proj->depth;
     e.cams = views->cams;
@@ -613,35 +777,54 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     e.n = n;
     e.tile_w = views->tile_w;
     e.overflow = bins->overflow;
-    e.capacity = bins->capacity;
-    e.keys = k0;
-    e.vals = v0;
+    e.tkey = U32(L.tk0);
+    e.tval = U64(L.tv0);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
-    if (L.nb_sort == 0) return launch_lpt(views, bins, (uint32_t*)(w + L.lpt), stream);
-    const unsigned hist_blocks = (unsigned)std::min<int64_t>(L.nb_sort * 4, 1024);
-    hipLaunchKernelGGL(k_os_hist, dim3(hist_blocks), dim3(BLK), 0, stream, k0, bins->n_pairs, bins->capacity, passes,
-                       ghist);
-    for (int pass = 0; pass < passes; ++pass) {
+    // 3. grouped by tile
+    const int np = L.passes;
+    uint32_t* ghist = U32(L.ghist);
+    const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort * 4, 1024);
+    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np, ghist);
+    uint32_t* kin = U32(L.tk0);
+    uint64_t* vin = U64(L.tv0);
+    uint32_t* kalt = U32(L.tk1);
+    uint64_t* valt = U64(L.tv1);
+    for (int pass = 0; pass < np; ++pass) {
         PassArgs pa;
-        pa.kin = k0;
-        pa.vin = v0;
-        pa.kout = k1;
-        pa.vout = v1;
-        pa.n_pairs = bins->n_pairs;
-        pa.capacity = bins->capacity;
+        pa.kin = kin;
+        pa.vin = vin;
+        pa.kout = kalt;
+        pa.vout = valt;
+        pa.n_items = bins->n_pairs;
+        pa.bound = bins->capacity;
         pa.shift = 8 * pass;
         pa.ghist = ghist + 256 * pass;
-        pa.status = status + (size_t)256 * L.nb_sort * pass;
-        pa.ticket = tickets + pass;
+        pa.status = U64(L.status) + (size_t)256 * L.nb_sort * pass;
+        pa.ticket = U32(L.tickets) + pass;
         pa.err = bins->overflow;
-        hipLaunchKernelGGL(k_os_pass, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
-        std::swap(k0, k1);
-        std::swap(v0, v1);
+        hipLaunchKernelGGL(k_os_pass<uint64_t>, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
+        std::swap(kin, kalt);
+        std::swap(vin, valt);
     }
-    const unsigned g = (unsigned)((bins->capacity + 255) / 256);
-    hipLaunchKernelGGL(k_ranges, dim3(g), dim3(256), 0, stream, bins->keys, bins->n_pairs, bins->capacity,
-                       bins->overflow, bins->ranges, views->n_tiles);
-    return launch_lpt(views, bins, (uint32_t*)(w + L.lpt), stream);
+    // 4. tile ranges
+    const unsigned rg = (unsigned)((bins->capacity + 255) / 256);
+    hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, stream, kin, bins->n_pairs, bins->capacity, bins->overflow,
+                       bins->ranges, views->n_tiles);
+    // 5. each tile's list by (depth, index); keys and values
+    TileSortArgs ta;
+    ta.pairs = vin;
+    ta.scratch = valt;
+    ta.ranges = bins->ranges;
+    ta.n_tiles = views->n_tiles;
+    ta.capacity = bins->capacity;
+    ta.overflow = bins->overflow;
+    ta.keys = bins->keys;
+    ta.vals = bins->vals;
+    ta.n_deferred = U32(L.n_deferred);
+    ta.deferred = U32(L.deferred);
+    hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)views->n_tiles), dim3(256), 0, stream, ta);
+    hipLaunchKernelGGL(k_tile_sort_large, dim3((unsigned)std::min(views->n_tiles, 512)), dim3(256), 0, stream, ta);
+    return launch_lpt(views, bins, U32(L.lpt), stream);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -159,7 +159,10 @@ class Projected:
 
 
 class Bins:
-    def __init__(self, capacity: int, n_tiles: int, device):
+    """Sorted pairs and tile ranges; `queue` (the longest-first tile order) is only built
+    when asked for: persistent compositing launches need it."""
+
+    def __init__(self, capacity: int, n_tiles: int, device, queue: bool = True):
         self.capacity = int(capacity)
         cap = max(self.capacity, 1)
         self.keys = torch.empty(cap, dtype=torch.int64, device=device)
@@ -167,7 +170,7 @@ class Bins:
         self.ranges = torch.empty(max(2 * n_tiles, 2), dtype=torch.int32, device=device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
-        self.queue = torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device)
+        self.queue = torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device) if queue else None
 
     def struct(self) -> L.gs_bins:
         return L.gs_bins(_ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), self.capacity, _ptr(self.n_pairs),
@@ -204,7 +207,7 @@ def bin_sort(proj: Projected, views: ViewBatch, capacity: Optional[int] = None, 
     if bins is None:
         if capacity is None:
             capacity = max(1 << 16, 4 * proj.n * views.n_views)
-        bins = Bins(capacity, views.n_tiles, views.device)
+        bins = Bins(capacity, views.n_tiles, views.device, queue=views.persistent)
     for _ in range(3):
         need = workspace_bytes(proj.n, views.n_views, bins.capacity, views.n_tiles)
         if ws is None or ws.numel() < need:
@@ -216,7 +219,7 @@ def bin_sort(proj: Projected, views: ViewBatch, capacity: Optional[int] = None, 
         if int(bins.overflow.item()) == 0:
             return bins
         need_pairs = int(bins.n_pairs.item())
-        bins = Bins(int(need_pairs * 1.125) + 4096, views.n_tiles, views.device)
+        bins = Bins(int(need_pairs * 1.125) + 4096, views.n_tiles, views.device, queue=bins.queue is not None)
     raise RuntimeError("bin_sort: capacity growth did not converge")
 
 
@@ -378,7 +381,7 @@ class Renderer:
         if capacity is None:
             b = bin_sort(self.proj, views)
             capacity = int(int(b.n_pairs.item()) * headroom) + 4096
-        self.bins = Bins(capacity, views.n_tiles, dev)
+        self.bins = Bins(capacity, views.n_tiles, dev, queue=views.persistent)
         self.ws = alloc_workspace(self.n_entries, views.n_views, capacity, views.n_tiles, dev)
         self.rgb = torch.empty(3 * max(views.n_pixels, 1), dtype=torch.float32, device=dev)
         self.t_final = torch.empty(max(views.n_pixels, 1), dtype=torch.float32, device=dev)
@@ -541,7 +544,7 @@ class PathRenderer:
             preprocess(g, self.views, params, out=self._proj_n(g.n))
             b = bin_sort(self._proj_n(g.n), self.views)
             capacity = int(int(b.n_pairs.item()) * 2.0) + 65536
-        self.bins = Bins(capacity, self.views.n_tiles, dev)
+        self.bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.persistent)
         self.ws = alloc_workspace(self.max_entries, 1, capacity, self.views.n_tiles, dev)
         self.rgb = torch.empty(3 * self.views.n_pixels, dtype=torch.float32, device=dev)
         self.t_final = torch.empty(self.views.n_pixels, dtype=torch.float32, device=dev)

@@ -100,6 +100,43 @@ def test_keys_bit_exact(case, tile):
             assert ranges[tid, 0] == ranges[tid, 1]
 
 
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_long_tile_lists(n):
+    """Thousands of Gaussians packed around the image centre (a corner of four 16x16
+    tiles): tile lists longer than the small per-tile sort buffer (> 2048 entries) and, at
+    n = 20000, longer than the large one (> 8192: chunked sort and merges). Keys, values
+    and ranges bit-exact; image within the tolerance."""
+    sc = scenes.uniform_cube_scene(n, seed=7)
+    sc.mean = (sc.mean * np.float32(0.03)).astype(np.float32)
+    cam = scenes.plain_view()
+    _say(f"long tile lists n={n}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    proj = gs.preprocess(g, views, P)
+    bins = gs.bin_sort(proj, views)
+    torch.cuda.synchronize()
+    npairs = int(bins.n_pairs.item())
+    assert int(bins.overflow.item()) == 0
+    keys = bins.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = bins.vals[:npairs].cpu().numpy().view(np.uint32)
+    ref = oracle.project(sc, cam, P)
+    k2, v2 = oracle.pairs([ref[:, F["depth32"]]], [oracle.rects_of(ref)], [(cam.width, cam.height)], (16, 16))
+    lens = np.bincount((k2 >> np.uint64(32)).astype(np.int64), minlength=views.n_tiles)
+    _say(f"  longest tile list {lens.max()}")
+    assert lens.max() > (8192 if n == 20000 else 2048)
+    assert np.array_equal(keys, k2) and np.array_equal(vals, v2)
+    ranges = bins.ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    assert np.array_equal(ranges[:, 1] - ranges[:, 0], lens)
+    assert np.array_equal(ranges[lens > 0, 0], starts[lens > 0])
+    out = gs.render(g, views, P)
+    torch.cuda.synchronize()
+    img = views.image(out["rgb"], 0).cpu().numpy().astype(np.float64)
+    _, runs = band_runs(sc, cam, P)
+    mism = np.abs(img - runs[0]["rgb"]).max(0) > TOL_IMAGE
+    check_band(mism, image_band(runs), f"long lists {n}")
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_render_matches_oracle(case):
     sc, cam = _case(case)

@@ -60,7 +60,7 @@ def test_workspace_bytes_grows_with_inputs():
     assert a > 0
     assert lib.gs_workspace_bytes(2000, 1, 10000, 100) >= a
     assert lib.gs_workspace_bytes(1000, 1, 20000, 100) > a
-    assert lib.gs_workspace_bytes(1000, 2, 10000, 100) > a
+    assert lib.gs_workspace_bytes(1000, 2, 10000, 100) >= a
     # the backward's 2D gradients: 9 floats per (view, Gaussian)
     assert lib.gs_workspace_bytes(10 ** 6, 4, 0, 1) >= 36 * 4 * 10 ** 6
 
