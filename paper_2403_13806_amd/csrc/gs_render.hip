@@ -186,23 +186,27 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
             while (m) {
                 const int j = c * 64 + (int)__builtin_ctzll(m);
                 m &= m - 1;
-                const gs_splat& s = sm.rec[j];
+                // the whole record is read up front and the body is branch-free apart from the
+                // wave-uniform skip, so no LDS wait sits inside a divergent region
+                const gs_splat s = sm.rec[j];
+                // opacity and colour are requested together with the geometry
+                asm volatile("" ::"v"(s.opacity), "v"(s.rgb[0]), "v"(s.rgb[1]), "v"(s.rgb[2]));
                 const double q = quad(s, xc - s.u, yc - s.v);
-                const bool in = !done && q <= s.qmax;
+                const bool in = (q <= s.qmax) & !done;
                 if (ballot(in) == 0) continue;
                 const float al = in ? fminf(amax, s.opacity * falloff(q)) : 0.f;
                 const float wgt = al * T;
-                if (MODE == MODE_FWD && in) {
-                    C0 += wgt * s.rgb[0];
-                    C1 += wgt * s.rgb[1];
-                    C2 += wgt * s.rgb[2];
+                if (MODE == MODE_FWD) {
+                    // a select, not wgt * rgb alone: an infinite colour must not reach pixels
+                    // the Gaussian does not cover
+                    C0 = in ? fmaf(wgt, s.rgb[0], C0) : C0;
+                    C1 = in ? fmaf(wgt, s.rgb[1], C1) : C1;
+                    C2 = in ? fmaf(wgt, s.rgb[2], C2) : C2;
                 }
                 T = T * (1.f - al);
-                if (in) {
-                    last = base + j + 1;
-                    ++ncomp;
-                }
-                done = done || T < tmin;
+                last = in ? base + j + 1 : last;
+                ncomp += in ? 1u : 0u;
+                done = done | (T < tmin);
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
                         const float mx = wave_max_nonneg(wgt);
@@ -332,40 +336,39 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 m &= ~(1ull << b);
                 const int j = c * 64 + b;
                 const uint32_t pos = lo + j;
-                float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // u v a b c o r g b
-                bool contrib = false;
-                if (g.inside && pos < last) {
-                    const gs_splat& s = sm.rec[j];
-                    const double ddx = xc - s.u, ddy = yc - s.v;
-                    const double q = quad(s, ddx, ddy);
-                    if (q <= s.qmax) {
-                        contrib = true;
-                        const float G = falloff(q);
-                        const float al = fminf(amax, s.opacity * G);
-                        const float r = __builtin_amdgcn_rcpf(1.f - al);
-                        T = T * r;
-                        const float wt = al * T;
-                        v[6] = dC0 * wt;
-                        v[7] = dC1 * wt;
-                        v[8] = dC2 * wt;
-                        const float dA = dC0 * (T * s.rgb[0] - S0 * r) + dC1 * (T * s.rgb[1] - S1 * r) +
-                                         dC2 * (T * s.rgb[2] - S2 * r);
-                        S0 += wt * s.rgb[0];
-                        S1 += wt * s.rgb[1];
-                        S2 += wt * s.rgb[2];
-                        if (s.opacity * G < amax) {
-                            const float dx = (float)ddx, dy = (float)ddy;
-                            v[5] = dA * G;
-                            const float dq = -0.5f * al * dA;
-                            v[2] = dq * dx * dx;
-                            v[3] = dq * 2.f * dx * dy;
-                            v[4] = dq * dy * dy;
-                            v[0] = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
-                            v[1] = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
-                        }
-                    }
-                }
-                if (ballot(contrib)) {
+                // whole record up front; branch-free body apart from the wave-uniform skip
+                const gs_splat s = sm.rec[j];
+                asm volatile("" ::"v"(s.opacity), "v"(s.rgb[0]), "v"(s.rgb[1]), "v"(s.rgb[2]));
+                const double ddx = xc - s.u, ddy = yc - s.v;
+                const double q = quad(s, ddx, ddy);
+                const bool contrib = (q <= s.qmax) & g.inside & (pos < last);
+                if (ballot(contrib) == 0) continue;
+                const float G = falloff(q);
+                const float og = s.opacity * G;
+                const float al = contrib ? fminf(amax, og) : 0.f;
+                const float r = __builtin_amdgcn_rcpf(1.f - al);
+                T = contrib ? T * r : T;
+                const float wt = al * T;
+                const float dA = dC0 * (T * s.rgb[0] - S0 * r) + dC1 * (T * s.rgb[1] - S1 * r) +
+                                 dC2 * (T * s.rgb[2] - S2 * r);
+                S0 = contrib ? fmaf(wt, s.rgb[0], S0) : S0;
+                S1 = contrib ? fmaf(wt, s.rgb[1], S1) : S1;
+                S2 = contrib ? fmaf(wt, s.rgb[2], S2) : S2;
+                // u v a b c o r g b; the geometric terms vanish where alpha is clamped
+                const bool free_a = contrib & (og < amax);
+                const float dx = (float)ddx, dy = (float)ddy;
+                const float dq = free_a ? -0.5f * al * dA : 0.f;
+                float v[9];
+                v[0] = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
+                v[1] = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
+                v[2] = dq * dx * dx;
+                v[3] = dq * 2.f * dx * dy;
+                v[4] = dq * dy * dy;
+                v[5] = free_a ? dA * G : 0.f;
+                v[6] = contrib ? dC0 * wt : 0.f;
+                v[7] = contrib ? dC1 * wt : 0.f;
+                v[8] = contrib ? dC2 * wt : 0.f;
+                {
                     // per-row sums, one field per lane; four rows add into the record's slot
                     const float z = row_sum9(v, l);
                     if (fld < 9) atomicAdd(&sm.acc[j * 9 + fld], z);
