@@ -540,19 +540,112 @@ __device__ __forceinline__ int merge_split(const uint64_t* A, int na, const uint
     return lo;
 }
 
+// Stable LSD radix sort of one tile's list (len <= SMALL_LIST) by its FP32 depth bits,
+// 8-bit digits, in LDS. The grouping passes keep emission order inside a tile, which is
+// increasing Gaussian index, so equal depths end in index order: the (depth, index) order.
+// Wave w owns the contiguous items [w C, (w + 1) C) (C a multiple of 64) and ranks them
+// with wave-private digit counters, as the grouping passes do; passes whose digit is the
+// same for every item of the tile are skipped.
+constexpr int RS_ROUNDS = SMALL_LIST / BLK;  // items per thread
+
 __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
-    __shared__ uint64_t s[SMALL_LIST];
-    const int tile = blockIdx.x, t = threadIdx.x;
+    __shared__ uint32_t sk[SMALL_LIST], sv[SMALL_LIST];
+    __shared__ uint32_t wcnt[BLK / 64][256];
+    __shared__ uint32_t ds[256];
+    __shared__ uint32_t wsum[BLK / 64];
+    __shared__ uint32_t diff;
+    const int tile = blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
     if (*a.overflow) return;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     if (end <= start || (uint64_t)end > a.capacity) return;
-    const uint32_t len = end - start;
-    if (len > (uint32_t)SMALL_LIST) {
+    const int len = (int)(end - start);
+    if (len > SMALL_LIST) {
         if (t == 0) a.deferred[atomicAdd(a.n_deferred, 1u)] = (uint32_t)tile;
         return;
     }
-    sort_in_lds(s, a.pairs + start, (int)len);
-    write_tile(a, tile, start, s, (int)len);
+    const uint64_t* src = a.pairs + start;
+    const int C = (((len + 3) >> 2) + 63) & ~63;
+    const int R = C >> 6;
+    const int wb = w * C;
+    if (t == 0) diff = 0;
+    const uint32_t k0 = (uint32_t)(src[0] >> 32);
+    uint32_t key[RS_ROUNDS], val[RS_ROUNDS], lr[RS_ROUNDS];
+    uint32_t dx = 0;
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int i = wb + 64 * r + l;
+        const bool valid = r < R && i < len;
+        const uint64_t x = valid ? src[i] : 0ull;
+        key[r] = (uint32_t)(x >> 32);
+        val[r] = (uint32_t)x;
+        if (valid) dx |= key[r] ^ k0;
+    }
+    __syncthreads();
+    if (dx) atomicOr(&diff, dx);
+    __syncthreads();
+    const uint32_t dmask = diff;
+    for (int shift = 0; shift < 32; shift += 8) {
+        if (((dmask >> shift) & 255u) == 0) continue;  // the same for the whole workgroup
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wcnt[w][l + 64 * k] = 0;
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            const bool valid = wb + 64 * r + l < len;
+            const uint32_t d = (key[r] >> shift) & 255u;
+            uint64_t m = ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool on = (d >> bit) & 1u;
+                const uint64_t bb = ballot(on);
+                m &= on ? bb : ~bb;
+            }
+            const uint32_t rank = mask_rank(m);
+            const uint32_t old = valid ? wcnt[w][d] : 0u;
+            lr[r] = old + rank;
+            if (valid && rank == 0) wcnt[w][d] = old + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < BLK / 64; ++k) {
+            const uint32_t c = wcnt[k][t];
+            wcnt[k][t] = mine;
+            mine += c;
+        }
+        uint32_t tot;
+        ds[t] = block_excl_scan(mine, tot, wsum);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            if (wb + 64 * r + l < len) {
+                const uint32_t d = (key[r] >> shift) & 255u;
+                const uint32_t q = ds[d] + wcnt[w][d] + lr[r];
+                sk[q] = key[r];
+                sv[q] = val[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            const int i = wb + 64 * r + l;
+            if (i < len) {
+                key[r] = sk[i];
+                val[r] = sv[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        if (r >= R) break;
+        const int i = wb + 64 * r + l;
+        if (i < len) {
+            a.keys[start + i] = ((uint64_t)tile << 32) | key[r];
+            a.vals[start + i] = val[r];
+        }
+    }
 }
 
 // deferred (long) lists; a grid-stride loop over them
