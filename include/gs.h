@@ -116,7 +116,8 @@ typedef struct gs_gaussians_grad {
 } gs_gaussians_grad;
 
 /* Projected Gaussian, 64 bytes, one per (view, Gaussian): everything a compositing
- * pass needs. Conic (ca, cb, cc) = inverse of Sigma' as [[ca, cb], [cb, cc]]. */
+ * pass needs. Conic (ca, cb, cc) = inverse of Sigma' as [[ca, cb], [cb, cc]]. rgb is
+ * max(0, sum k Y + 1/2) in FP32, saturated at the largest finite FP32 value. */
 typedef struct gs_splat {
     double u, v;
     double ca, cb, cc;

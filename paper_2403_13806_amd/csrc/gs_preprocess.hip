@@ -299,7 +299,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             float acc = 0.f;
 #pragma unroll
             for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
-            rgb[c] = fmaxf(acc + 0.5f, 0.f);
+            // finite in FP32 (overflow saturates), so a zero weight always contributes zero
+            rgb[c] = fminf(fmaxf(acc + 0.5f, 0.f), 3.402823466e38f);
         }
     }
     gs_splat s;

@@ -120,6 +120,9 @@ __device__ __forceinline__ double quad(const gs_splat& s, double dx, double dy) 
     return fma(s.cc * dy, dy, dx * fma(2.0 * s.cb, dy, s.ca * dx));
 }
 
+// min(alpha_max, o G) for o G >= 0 in one instruction
+__device__ __forceinline__ float clamp_alpha(float og, float amax) { return __builtin_amdgcn_fmed3f(og, 0.f, amax); }
+
 // exp(-q/2) in FP32, as 2^(q * (-log2(e) / 2))
 __device__ __forceinline__ float falloff(double q) {
     return __builtin_amdgcn_exp2f((float)q * -0.72134752044448170368f);
@@ -194,14 +197,12 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                 const double q = quad(s, xc - s.u, yc - s.v);
                 const bool in = (q <= s.qmax) & !done;
                 if (ballot(in) == 0) continue;
-                const float al = in ? fminf(amax, s.opacity * falloff(q)) : 0.f;
+                const float al = in ? clamp_alpha(s.opacity * falloff(q), amax) : 0.f;
                 const float wgt = al * T;
-                if (MODE == MODE_FWD) {
-                    // a select, not wgt * rgb alone: an infinite colour must not reach pixels
-                    // the Gaussian does not cover
-                    C0 = in ? fmaf(wgt, s.rgb[0], C0) : C0;
-                    C1 = in ? fmaf(wgt, s.rgb[1], C1) : C1;
-                    C2 = in ? fmaf(wgt, s.rgb[2], C2) : C2;
+                if (MODE == MODE_FWD) {  // colours are finite, so wgt = 0 adds exactly nothing
+                    C0 = fmaf(wgt, s.rgb[0], C0);
+                    C1 = fmaf(wgt, s.rgb[1], C1);
+                    C2 = fmaf(wgt, s.rgb[2], C2);
                 }
                 T = T * (1.f - al);
                 last = in ? base + j + 1 : last;
@@ -345,15 +346,15 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 if (ballot(contrib) == 0) continue;
                 const float G = falloff(q);
                 const float og = s.opacity * G;
-                const float al = contrib ? fminf(amax, og) : 0.f;
+                const float al = contrib ? clamp_alpha(og, amax) : 0.f;
                 const float r = __builtin_amdgcn_rcpf(1.f - al);
                 T = contrib ? T * r : T;
                 const float wt = al * T;
                 const float dA = dC0 * (T * s.rgb[0] - S0 * r) + dC1 * (T * s.rgb[1] - S1 * r) +
                                  dC2 * (T * s.rgb[2] - S2 * r);
-                S0 = contrib ? fmaf(wt, s.rgb[0], S0) : S0;
-                S1 = contrib ? fmaf(wt, s.rgb[1], S1) : S1;
-                S2 = contrib ? fmaf(wt, s.rgb[2], S2) : S2;
+                S0 = fmaf(wt, s.rgb[0], S0);  // wt = 0 where the entry does not contribute
+                S1 = fmaf(wt, s.rgb[1], S1);
+                S2 = fmaf(wt, s.rgb[2], S2);
                 // u v a b c o r g b; the geometric terms vanish where alpha is clamped
                 const bool free_a = contrib & (og < amax);
                 const float dx = (float)ddx, dy = (float)ddy;
@@ -403,9 +404,10 @@ __device__ __forceinline__ int tile_of_round(const RenderArgs& a, int r) {
     return item < a.n_tiles ? (int)a.queue[item] : -1;
 }
 
-// at most 64 VGPRs, so that eight waves fit on each SIMD
+// single-depth batches: at most 64 VGPRs, so that eight waves fit on each SIMD
 template <int TW, int TH, int DEPTH, int MODE>
-__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_render(RenderArgs a) {
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(DEPTH == 1 ? 8 : 1, 8))) void k_render(
+    RenderArgs a) {
     __shared__ Smem<TW, TH, DEPTH> sm;
     for (int r = 0;; ++r) {
         const int tile = tile_of_round(a, r);

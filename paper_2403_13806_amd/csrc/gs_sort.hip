@@ -233,6 +233,7 @@ struct EmitArgs {
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_off[256], s_db[256];
     __shared__ uint64_t s_rect[256];
+    __shared__ double s_inv[256];  // 1 / rectangle width
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
     if (*a.overflow) return;  // the same for every thread
     const int64_t j0 = (int64_t)blockIdx.x * 256 + w * 64;  // first Gaussian of this wave
@@ -251,6 +252,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     s_off[t] = off;
     s_db[t] = db;
     s_rect[t] = r;
+    s_inv[t] = 1.0 / (double)((uint32_t)(r >> 32 & 0xffff) - (uint32_t)(r & 0xffff) + 1u);
     __syncthreads();
     if (j0 >= a.n) return;
     // the wave's pairs occupy [first offset, last offset + last count)
@@ -271,7 +273,17 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         const uint32_t x0 = rr & 0xffff, y0 = (rr >> 16) & 0xffff, x1 = (rr >> 32) & 0xffff;
         const uint32_t wd = x1 - x0 + 1;
         const uint32_t k = g - wo[L];
-        a.tkey[g] = tbase + (y0 + k / wd) * tiles_x + x0 + k % wd;
+        // k / wd through FP64 (exact to within one for k < 2^32), then corrected
+        uint32_t ky = (uint32_t)((double)k * s_inv[q]);
+        uint32_t kx = k - ky * wd;
+        if ((int32_t)kx < 0) {
+            --ky;
+            kx += wd;
+        } else if (kx >= wd) {
+            ++ky;
+            kx -= wd;
+        }
+        a.tkey[g] = tbase + (y0 + ky) * tiles_x + x0 + kx;
         a.tval[g] = ((uint64_t)s_db[q] << 32) | (uint32_t)(j0 + L);
     }
 }
@@ -876,7 +888,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     // 3. grouped by tile
     const int np = L.passes;
     uint32_t* ghist = U32(L.ghist);
-    const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort * 4, 1024);
+    const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort, 1024);
     hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np, ghist);
     uint32_t* kin = U32(L.tk0);
     uint64_t* vin = U64(L.tv0);
