@@ -163,9 +163,12 @@ def main():
     npx = rs[0].views.n_pixels
     n = g.n
     mp, mc, mt, mv = (float(np.mean(x)) for x in (pairs, composites, tested, visible))
-    passes = (32 + int(np.ceil(np.log2(rs[0].views.n_tiles))) + 7) // 8
+    passes = max(1, (int(np.ceil(np.log2(rs[0].views.n_tiles))) + 7) // 8)  # tile-grouping radix passes
     bytes_pre = 4 * n * (3 + 3 + 4 + 1 + 48) + 4 * n + mv * (SPLAT + 4 + 8)
-    bytes_sort = 3 * 4 * n + mp * (12 + passes * (8 + 24)) + rs[0].views.n_tiles * 8
+    # scan (count in, offset out), emit (count + offset per entry, rect + depth per visible entry,
+    # 12 B per pair out), digit histogram (4 B per pair), grouping passes (12 B in + 12 B out per
+    # pair each), ranges (4 B per pair), per-tile sort (8 B in, 12 B out per pair)
+    bytes_sort = (4 + 4 + 8) * n + 12 * mv + mp * (12 + 4 + passes * 24 + 4 + 20) + rs[0].views.n_tiles * 8
     bytes_render = mp * (4 + SPLAT) + npx * (12 + 4 + 4) + rs[0].views.n_tiles * 8
     ops_render = OPS_PER_COMPOSITE * mc
     stage_rows = {
