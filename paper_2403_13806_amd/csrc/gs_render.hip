@@ -67,20 +67,25 @@ struct RenderArgs {
 // of the two values is the minimum of q over the rectangle. The relative and absolute
 // margins cover the rounding of these evaluations against the per-pixel test, so a block
 // that holds a covered pixel centre is always marked.
-template <int TW, int TH>
+// QUARTERS: test the four 4x4 quarters of every wave block instead (bit 4 w + quarter,
+// quarters numbered row-major inside the block).
+template <int TW, int TH, bool QUARTERS = false>
 __device__ __forceinline__ uint32_t wave_hits(const gs_splat& s, double ox, double oy) {
+    constexpr int NB = (TW / 8) * (TH / 8) * (QUARTERS ? 4 : 1);
+    constexpr double SIDE = QUARTERS ? 3.0 : 7.0;
     const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
     const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
     uint32_t m = 0;
 #pragma unroll 1
-    for (int w = 0; w < (TW / 8) * (TH / 8); ++w) {
-        const double x0 = ox + (double)((w % (TW / 8)) * 8) - s.u, x1 = x0 + 7.0;
-        const double y0 = oy + (double)((w / (TW / 8)) * 8) - s.v, y1 = y0 + 7.0;
+    for (int bit = 0; bit < NB; ++bit) {
+        const int w = QUARTERS ? bit >> 2 : bit, qd = QUARTERS ? bit & 3 : 0;
+        const double x0 = ox + (double)((w % (TW / 8)) * 8 + (qd & 1) * 4) - s.u, x1 = x0 + SIDE;
+        const double y0 = oy + (double)((w / (TW / 8)) * 8 + (qd >> 1) * 4) - s.v, y1 = y0 + SIDE;
         const double ex = fmin(fmax(0.0, x0), x1), ey = fmin(fmax(0.0, y0), y1);
         const double fy = fmin(fmax(kx * ex, y0), y1), fx = fmin(fmax(ky * ey, x0), x1);
         const double q1 = s.ca * ex * ex + 2.0 * s.cb * ex * fy + s.cc * fy * fy;
         const double q2 = s.ca * fx * fx + 2.0 * s.cb * fx * ey + s.cc * ey * ey;
-        if (fmin(q1, q2) <= lim) m |= 1u << w;
+        if (fmin(q1, q2) <= lim) m |= 1u << bit;
     }
     return m;
 }
@@ -92,7 +97,8 @@ struct TileGeom {
     int64_t pix;     // global pixel index
 };
 
-template <int TW, int TH>
+// QUARTERS: lanes 16 q .. 16 q + 15 of a wave hold quarter q (4x4, row-major) of its block
+template <int TW, int TH, bool QUARTERS = false>
 __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     TileGeom g;
     g.view = view_of_tile(a.tile_offset, a.n_views, tile);
@@ -104,8 +110,14 @@ __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     const int t = threadIdx.x, l = t & 63;
     g.wave = t >> 6;
     const int bx = (g.wave % (TW / 8)) * 8, by = (g.wave / (TW / 8)) * 8;
-    g.px = tx * TW + bx + (l & 7);
-    g.py = ty * TH + by + (l >> 3);
+    if (QUARTERS) {
+        const int qd = l >> 4, sl = l & 15;
+        g.px = tx * TW + bx + (qd & 1) * 4 + (sl & 3);
+        g.py = ty * TH + by + (qd >> 1) * 4 + (sl >> 2);
+    } else {
+        g.px = tx * TW + bx + (l & 7);
+        g.py = ty * TH + by + (l >> 3);
+    }
     g.inside = g.px < g.W && g.py < g.H;
     g.ox = (double)(tx * TW) + 0.5;
     g.oy = (double)(ty * TH) + 0.5;
@@ -142,6 +154,7 @@ struct Smem {
 template <int TW, int TH, int DEPTH>
 struct SmemBwd : Smem<TW, TH, DEPTH> {
     float acc[Smem<TW, TH, DEPTH>::BD * 9];
+    uint16_t hitq[Smem<TW, TH, DEPTH>::BD];  // quarter masks
 };
 
 // stage records [base, base + cnt) of the tile's list; mark the wave blocks each one meets
@@ -161,6 +174,26 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
             hm = wave_hits<TW, TH>(s, g.ox, g.oy);
         }
         sm.hit[q] = (uint8_t)hm;
+    }
+}
+
+// the backward's staging: quarter masks
+template <int TW, int TH, int DEPTH>
+__device__ __forceinline__ void stage_q(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, const gs_splat* sp,
+                                        uint32_t base, uint32_t cnt, const TileGeom& g) {
+    constexpr int NT = TW * TH;
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+        const uint32_t q = threadIdx.x + d * NT;
+        uint32_t hm = 0;
+        const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
+        if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
+            const gs_splat s = sp[id];
+            sm.rec[q] = s;
+            sm.gid[q] = id;
+            hm = wave_hits<TW, TH, true>(s, g.ox, g.oy);
+        }
+        sm.hitq[q] = (uint16_t)hm;
     }
 }
 
@@ -286,14 +319,15 @@ __device__ __forceinline__ float row_sum9(const float (&v)[9], int lane) {
 //   T_j = T / (1 - alpha_j), w_j = alpha_j T_j,
 //   dL/dc_j = dL/dC * w_j,  dL/dalpha_j = sum_c dL/dC_c (T_j c_jc - S_c / (1 - alpha_j)),
 // then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
-// dx = xc - u. The nine per-record sums are reduced over each row of the wave into the
-// record's LDS accumulator; one global atomic per (tile, record, field) adds the workgroup's
-// sums into g2[field][view * n + index].
+// dx = xc - u. Each row of 16 lanes holds a 4x4 quarter of the wave's block and walks only
+// the entries that meet its quarter, so one iteration serves up to four entries; the nine
+// per-entry sums are reduced over the row into the entry's LDS accumulator, and one global
+// atomic per (tile, entry, field) adds the workgroup's sums into g2[field][view * n + index].
 template <int TW, int TH, int DEPTH>
 __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
     constexpr int NT = TW * TH;
     constexpr int BD = NT * DEPTH;
-    const TileGeom g = tile_geom<TW, TH>(a, tile);
+    const TileGeom g = tile_geom<TW, TH, true>(a, tile);
     const int t = threadIdx.x, l = t & 63, w = g.wave;
     const int fld = row_sum9_field(l);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -326,15 +360,21 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
     for (uint32_t hi = top; hi > start;) {
         const uint32_t lo = (hi - start > (uint32_t)BD) ? hi - BD : start;
         __syncthreads();
-        stage<TW, TH, DEPTH>(sm, a, sp, lo, hi - lo, g);
+        stage_q<TW, TH, DEPTH>(sm, a, sp, lo, hi - lo, g);
         __syncthreads();
         // entries that meet this wave's block, back to front
 #pragma unroll 1
         for (int c = BD / 64 - 1; c >= 0; --c) {
-            uint64_t m = ballot((sm.hit[c * 64 + l] >> w) & 1u);
-            while (m) {
-                const int b = 63 - (int)__builtin_clzll(m);
-                m &= ~(1ull << b);
+            // each quarter (one row of 16 lanes) walks the entries that meet its 4x4 pixels
+            const uint32_t hq = sm.hitq[c * 64 + l] >> (4 * w);
+            const uint64_t m0 = ballot(hq & 1u), m1 = ballot((hq >> 1) & 1u), m2 = ballot((hq >> 2) & 1u),
+                           m3 = ballot((hq >> 3) & 1u);
+            const int qd = l >> 4;
+            uint64_t m = qd == 0 ? m0 : qd == 1 ? m1 : qd == 2 ? m2 : m3;  // the same in a quarter
+            while (ballot(m != 0)) {
+                const bool act = m != 0;
+                const int b = act ? 63 - (int)__builtin_clzll(m) : 0;
+                m = act ? m & ~(1ull << b) : 0ull;
                 const int j = c * 64 + b;
                 const uint32_t pos = lo + j;
                 // whole record up front; branch-free body apart from the wave-uniform skip
@@ -342,7 +382,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 asm volatile("" ::"v"(s.opacity), "v"(s.rgb[0]), "v"(s.rgb[1]), "v"(s.rgb[2]));
                 const double ddx = xc - s.u, ddy = yc - s.v;
                 const double q = quad(s, ddx, ddy);
-                const bool contrib = (q <= s.qmax) & g.inside & (pos < last);
+                const bool contrib = act & (q <= s.qmax) & g.inside & (pos < last);
                 if (ballot(contrib) == 0) continue;
                 const float G = falloff(q);
                 const float og = s.opacity * G;
@@ -369,11 +409,9 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 v[6] = contrib ? dC0 * wt : 0.f;
                 v[7] = contrib ? dC1 * wt : 0.f;
                 v[8] = contrib ? dC2 * wt : 0.f;
-                {
-                    // per-row sums, one field per lane; four rows add into the record's slot
-                    const float z = row_sum9(v, l);
-                    if (fld < 9) atomicAdd(&sm.acc[j * 9 + fld], z);
-                }
+                // per-quarter sums, one field per lane, added into that quarter's entry
+                const float z = row_sum9(v, l);
+                if (act & (fld < 9)) atomicAdd(&sm.acc[j * 9 + fld], z);
             }
         }
         __syncthreads();
