@@ -147,6 +147,7 @@ struct Smem {
     gs_splat rec[BD];
     uint32_t gid[BD];
     uint8_t hit[BD];
+    uint32_t hacc[BD];  // importance: max weight bits per staged record; visibility: flag
     uint32_t top;
 };
 
@@ -213,7 +214,12 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
     if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
     for (uint32_t base = start; base < end; base += BD) {
         if (__syncthreads_and(done)) break;
-        stage<TW, TH, DEPTH>(sm, a, sp, base, min((uint32_t)BD, end - base), g);
+        const uint32_t cnt = min((uint32_t)BD, end - base);
+        stage<TW, TH, DEPTH>(sm, a, sp, base, cnt, g);
+        if (MODE != MODE_FWD) {
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) sm.hacc[threadIdx.x + d * TW * TH] = 0u;
+        }
         __syncthreads();
         // each wave walks only the entries that meet its 8x8 block, in list order
 #pragma unroll 1
@@ -241,20 +247,39 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                 last = in ? base + j + 1 : last;
                 ncomp += in ? 1u : 0u;
                 done = done | (T < tmin);
+                // per staged record, combined over the workgroup's waves in LDS
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
                         const float mx = wave_max_nonneg(wgt);
-                        if (l == 0) atomicMax(reinterpret_cast<unsigned int*>(a.h) + sm.gid[j], __float_as_uint(mx));
+                        if (l == 0) atomicMax(&sm.hacc[j], __float_as_uint(mx));
                     }
                 }
                 if (MODE == MODE_VISIBILITY) {
-                    if (ballot(wgt > a.t_cluster) != 0 && l == 0) {
-                        const uint32_t id = sm.gid[j];
-                        atomicOr(a.bits + (int64_t)cluster * a.words + (id >> 5), 1u << (id & 31));
-                    }
+                    if (ballot(wgt > a.t_cluster) != 0 && l == 0) atomicOr(&sm.hacc[j], 1u);
                 }
             }
             if (ballot(!done) == 0) break;
+        }
+        if (MODE != MODE_FWD) {
+            // one device-wide atomic per (tile, record) at most, and none when the value held
+            // already covers it (a stale read can only cause a redundant atomic)
+            __syncthreads();
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                const uint32_t q = threadIdx.x + d * TW * TH;
+                const uint32_t v = sm.hacc[q];
+                if (q < cnt && v != 0u) {
+                    const uint32_t id = sm.gid[q];
+                    if (MODE == MODE_IMPORTANCE) {
+                        unsigned int* hp = reinterpret_cast<unsigned int*>(a.h) + id;
+                        if (v > *hp) atomicMax(hp, v);
+                    } else {
+                        uint32_t* bp = a.bits + (int64_t)cluster * a.words + (id >> 5);
+                        const uint32_t bit = 1u << (id & 31);
+                        if (!(*bp & bit)) atomicOr(bp, bit);
+                    }
+                }
+            }
         }
     }
     __syncthreads();  // the staging area is reused by the next tile of a persistent workgroup
