@@ -30,6 +30,7 @@ PEAK_HBM = 8.0e12
 # (2 sub, 3 mul, 2 fma, 1 cmp = 8) + opacity and blend in FP32 (cvt, scale, exp = 4 slots,
 # mul, min, weight, 3 fma colour, 1 - alpha, transmittance, stop test = 15)
 OPS_PER_COMPOSITE = 23
+TILE = (16, 32)  # tile of the headline frames (fastest measured: fewer pairs to sort than 16x16)
 SPLAT = 64
 
 
@@ -101,7 +102,7 @@ def main():
     sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
     cams = scenes.orbit_views(8)
     g = gs.Gaussians.from_scene(sc, dev)
-    rs = [gs.Renderer(g, gs.ViewBatch([c], (16, 16), dev), P) for c in cams]
+    rs = [gs.Renderer(g, gs.ViewBatch([c], TILE, dev), P) for c in cams]
     torch.cuda.synchronize()
 
     # ---------------- headline: plain forward frames/s ----------------
@@ -151,10 +152,10 @@ def main():
         composites.append(int(ncontrib.sum().item()))
         visible.append(int((r.proj.count > 0).sum().item()))
         cam = r.views.cams[0]
-        tx = (cam.width + 15) // 16
+        tx = (cam.width + TILE[0] - 1) // TILE[0]
         py, px = torch.meshgrid(torch.arange(cam.height, device=dev), torch.arange(cam.width, device=dev),
                                 indexing="ij")
-        tile = ((py // 16) * tx + px // 16).reshape(-1)
+        tile = ((py // TILE[1]) * tx + px // TILE[0]).reshape(-1)
         rg = r.bins.ranges.view(-1, 2).long()
         st, en = rg[tile, 0], rg[tile, 1]
         stopped = r.t_final < P.t_min
@@ -184,9 +185,9 @@ def main():
     work = {"visible_per_view": mv, "pairs_per_view": mp, "composited_per_view": mc,
             "tested_per_view": mt, "composited_per_pixel": mc / npx, "tested_per_composited": mt / max(mc, 1)}
     log(f"stages (ms): {json.dumps({k: round(v, 4) for k, v in avg.items()})}; work {json.dumps(work)}")
-    roofline = {"bound": "alu", "kernel": "k_render<16,16,1,0>", "achieved": ops_render / avg["render_fwd"] / 1e9,
+    roofline = {"bound": "alu", "kernel": f"k_render<{TILE[0]},{TILE[1]},1,0>", "achieved": ops_render / avg["render_fwd"] / 1e9,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-ops/s",
-                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": recorded_traffic(),
+                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": recorded_traffic(f"k_render<{TILE[0]},{TILE[1]},1,0>"),
                 "traffic_unit": "bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
                 "alg_bytes_per_launch": bytes_render,
                 "hbm_frac": bytes_render / avg["render_fwd"] / 1e-3 / PEAK_HBM,
@@ -213,7 +214,7 @@ def main():
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "1M Gaussians (mixture of 32 clusters, SH degree 3), 1256x828, 8 orbit views, "
                                "plain forward per frame", "gaussians": n, "width": 1256, "height": 828,
-                   "views": 8, "tile": "16x16", "parallelism": "single GPU"},
+                   "views": 8, "tile": f"{TILE[0]}x{TILE[1]}", "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
@@ -224,16 +225,17 @@ TRAFFIC_SOURCES = ("paper_2403_13806_amd/csrc/gs_render.hip", "paper_2403_13806_
                    "include/gs.h")
 
 
-def recorded_traffic():
+def recorded_traffic(kernel):
     """HBM bytes per compositing launch from the committed counter record, or None when the
-    compositing sources changed since the counters were taken."""
+    compositing sources changed since the counters were taken or the record is of another
+    kernel instance."""
     import hashlib
     try:
         rec = dict(l.split(": ", 1) for l in open(TRAFFIC_RECORD).read().splitlines() if ": " in l)
         h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
     except OSError:
         return None
-    if rec.get("source_sha256") != h:
+    if rec.get("source_sha256") != h or rec.get("kernel") != kernel:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -358,7 +360,7 @@ def importance_pass(torch, gs, scenes, P, dev, chunk=10):
     sc = scenes.mixture_scene(500_000, seed=0, sh_degree=3)
     cams = scenes.orbit_views(150)
     g = gs.Gaussians.from_scene(sc, dev)
-    rs = [gs.Renderer(g, gs.ViewBatch(cams[i:i + chunk], (16, 16), dev, persistent=True), P, want_color=False)
+    rs = [gs.Renderer(g, gs.ViewBatch(cams[i:i + chunk], TILE, dev, persistent=True), P, want_color=False)
           for i in range(0, len(cams), chunk)]
     h = torch.zeros(g.n, device=dev)
     for r in rs:

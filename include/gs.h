@@ -139,10 +139,11 @@ typedef struct gs_views {
     const int32_t* tile_offset;  /* device [n_views + 1] */
     const int64_t* pixel_offset; /* device [n_views + 1] */
     int32_t n_views;
-    int32_t tile_w, tile_h;      /* 8, 16 or 32 each; tile_w * tile_h in {64, 128, 256} */
+    int32_t tile_w, tile_h;      /* 8, 16 or 32 each (one workgroup thread per tile pixel) */
     int32_t n_tiles;
     int64_t n_pixels;
-    int32_t batch_depth;         /* list records staged per lane per batch in compositing: 1 or 2 */
+    int32_t batch_depth;         /* list records staged per lane per batch in compositing: 1 or 2
+                                    (2 only for tiles of at most 512 pixels) */
     int32_t persistent;          /* 1: compositing runs as a persistent grid over bins->queue */
 } gs_views;
 

@@ -53,7 +53,7 @@ static size_t bwd_workspace_bytes(int64_t n, int32_t n_views) {
 
 static bool tile_ok(int tw, int th) {
     auto ok = [](int x) { return x == 8 || x == 16 || x == 32; };
-    return ok(tw) && ok(th) && tw * th <= 256;
+    return ok(tw) && ok(th);
 }
 
 static gs_status check_views(const gs_views* v) {
@@ -63,11 +63,12 @@ static gs_status check_views(const gs_views* v) {
     if (!v->cams || !v->tile_offset || !v->pixel_offset)
         return set_error(GS_ERR_INVALID_ARG, "views has a NULL device table");
     if (!tile_ok(v->tile_w, v->tile_h))
-        return set_error(GS_ERR_UNSUPPORTED, "tile %dx%d: each side must be 8, 16 or 32 and the area <= 256",
-                         v->tile_w, v->tile_h);
+        return set_error(GS_ERR_UNSUPPORTED, "tile %dx%d: each side must be 8, 16 or 32", v->tile_w, v->tile_h);
     if (v->n_tiles < 0 || v->n_pixels < 0) return set_error(GS_ERR_INVALID_ARG, "negative tile or pixel count");
     if (v->batch_depth != 1 && v->batch_depth != 2)
         return set_error(GS_ERR_UNSUPPORTED, "batch_depth must be 1 or 2 (got %d)", v->batch_depth);
+    if (v->batch_depth == 2 && v->tile_w * v->tile_h > 512)
+        return set_error(GS_ERR_UNSUPPORTED, "batch_depth 2 needs a tile of at most 512 pixels (LDS)");
     if (v->persistent != 0 && v->persistent != 1)
         return set_error(GS_ERR_INVALID_ARG, "persistent must be 0 or 1 (got %d)", v->persistent);
     return GS_OK;

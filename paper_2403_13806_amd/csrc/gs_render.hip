@@ -70,12 +70,12 @@ struct RenderArgs {
 // QUARTERS: test the four 4x4 quarters of every wave block instead (bit 4 w + quarter,
 // quarters numbered row-major inside the block).
 template <int TW, int TH, bool QUARTERS = false>
-__device__ __forceinline__ uint32_t wave_hits(const gs_splat& s, double ox, double oy) {
+__device__ __forceinline__ uint64_t wave_hits(const gs_splat& s, double ox, double oy) {
     constexpr int NB = (TW / 8) * (TH / 8) * (QUARTERS ? 4 : 1);
     constexpr double SIDE = QUARTERS ? 3.0 : 7.0;
     const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
     const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
-    uint32_t m = 0;
+    uint64_t m = 0;
 #pragma unroll 1
     for (int bit = 0; bit < NB; ++bit) {
         const int w = QUARTERS ? bit >> 2 : bit, qd = QUARTERS ? bit & 3 : 0;
@@ -85,7 +85,7 @@ __device__ __forceinline__ uint32_t wave_hits(const gs_splat& s, double ox, doub
         const double fy = fmin(fmax(kx * ex, y0), y1), fx = fmin(fmax(ky * ey, x0), x1);
         const double q1 = s.ca * ex * ex + 2.0 * s.cb * ex * fy + s.cc * fy * fy;
         const double q2 = s.ca * fx * fx + 2.0 * s.cb * fx * ey + s.cc * ey * ey;
-        if (fmin(q1, q2) <= lim) m |= 1u << bit;
+        if (fmin(q1, q2) <= lim) m |= 1ull << bit;
     }
     return m;
 }
@@ -146,7 +146,7 @@ struct Smem {
     static constexpr int BD = NT * DEPTH;  // records per batch
     gs_splat rec[BD];
     uint32_t gid[BD];
-    uint8_t hit[BD];
+    uint16_t hit[BD];   // bit w: the record meets wave w's 8x8 block (up to 16 waves)
     uint32_t hacc[BD];  // importance: max weight bits per staged record; visibility: flag
     uint32_t top;
 };
@@ -155,7 +155,7 @@ struct Smem {
 template <int TW, int TH, int DEPTH>
 struct SmemBwd : Smem<TW, TH, DEPTH> {
     float acc[Smem<TW, TH, DEPTH>::BD * 9];
-    uint16_t hitq[Smem<TW, TH, DEPTH>::BD];  // quarter masks
+    uint64_t hitq[Smem<TW, TH, DEPTH>::BD];  // quarter masks, bit 4 w + quarter
 };
 
 // stage records [base, base + cnt) of the tile's list; mark the wave blocks each one meets
@@ -166,7 +166,7 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
         const uint32_t q = threadIdx.x + d * NT;
-        uint32_t hm = 0;
+        uint64_t hm = 0;
         const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
         if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
             const gs_splat s = sp[id];
@@ -174,7 +174,7 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
             sm.gid[q] = id;
             hm = wave_hits<TW, TH>(s, g.ox, g.oy);
         }
-        sm.hit[q] = (uint8_t)hm;
+        sm.hit[q] = (uint16_t)hm;
     }
 }
 
@@ -186,7 +186,7 @@ __device__ __forceinline__ void stage_q(SmemBwd<TW, TH, DEPTH>& sm, const Render
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
         const uint32_t q = threadIdx.x + d * NT;
-        uint32_t hm = 0;
+        uint64_t hm = 0;
         const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
         if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
             const gs_splat s = sp[id];
@@ -194,7 +194,7 @@ __device__ __forceinline__ void stage_q(SmemBwd<TW, TH, DEPTH>& sm, const Render
             sm.gid[q] = id;
             hm = wave_hits<TW, TH, true>(s, g.ox, g.oy);
         }
-        sm.hitq[q] = (uint16_t)hm;
+        sm.hitq[q] = hm;
     }
 }
 
@@ -391,7 +391,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
 #pragma unroll 1
         for (int c = BD / 64 - 1; c >= 0; --c) {
             // each quarter (one row of 16 lanes) walks the entries that meet its 4x4 pixels
-            const uint32_t hq = sm.hitq[c * 64 + l] >> (4 * w);
+            const uint32_t hq = (uint32_t)(sm.hitq[c * 64 + l] >> (4 * w));
             const uint64_t m0 = ballot(hq & 1u), m1 = ballot((hq >> 1) & 1u), m2 = ballot((hq >> 2) & 1u),
                            m3 = ballot((hq >> 3) & 1u);
             const int qd = l >> 4;
@@ -562,6 +562,9 @@ static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int n_ti
     GS_CASE(16, 16, 1) GS_CASE(16, 16, 2)
     GS_CASE(32, 8, 1) GS_CASE(32, 8, 2)
     GS_CASE(8, 32, 1) GS_CASE(8, 32, 2)
+    GS_CASE(32, 16, 1) GS_CASE(32, 16, 2)
+    GS_CASE(16, 32, 1) GS_CASE(16, 32, 2)
+    GS_CASE(32, 32, 1)
 #undef GS_CASE
     return false;
 }
@@ -578,6 +581,9 @@ static bool launch_bwd(const RenderArgs& a, int tw, int th, int depth, int n_til
     GS_CASE(16, 16, 1) GS_CASE(16, 16, 2)
     GS_CASE(32, 8, 1) GS_CASE(32, 8, 2)
     GS_CASE(8, 32, 1) GS_CASE(8, 32, 2)
+    GS_CASE(32, 16, 1) GS_CASE(32, 16, 2)
+    GS_CASE(16, 32, 1) GS_CASE(16, 32, 2)
+    GS_CASE(32, 32, 1)
 #undef GS_CASE
     return false;
 }

@@ -21,7 +21,7 @@ import torch
 
 from . import _lib as L
 
-DEFAULT_TILE = (16, 16)
+DEFAULT_TILE = (16, 32)
 
 
 def _ptr(t: Optional[torch.Tensor]):

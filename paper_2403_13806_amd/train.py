@@ -36,8 +36,8 @@ class StepConfig:
         return (self.tile_w, self.tile_h)
 
 
-CANDIDATES = [StepConfig(tw, th, d, p) for (tw, th) in [(16, 16), (16, 8), (8, 8), (32, 8)] for d in (1, 2)
-              for p in (False, True)]
+CANDIDATES = ([StepConfig(tw, th, d, p) for (tw, th) in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16)]
+               for d in (1, 2) for p in (False, True)] + [StepConfig(32, 32, 1, False)])
 
 
 def zero_grads(g: Gaussians) -> Gaussians:

@@ -161,7 +161,7 @@ def test_tile_size_invariance_bitwise():
     sc, cam = _case("mixture")
     g = gs.Gaussians.from_scene(sc, DEV)
     imgs = []
-    for tile in [(16, 16), (8, 8), (32, 8), (16, 8), (8, 32)]:
+    for tile in [(16, 16), (8, 8), (32, 8), (16, 8), (8, 32), (32, 16), (16, 32), (32, 32)]:
         _say(f"tile invariance {tile}")
         views = gs.ViewBatch([cam], tile, DEV)
         out = gs.render(g, views, P)

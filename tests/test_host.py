@@ -50,7 +50,8 @@ def test_view_layout():
     assert list(to) == exp_t and list(po) == exp_p
     assert po[len(cams)] == 8_693_600
     assert gs.load().gs_view_layout(vb_t, len(cams), 12, 16, to, po) == L.GS_ERR_UNSUPPORTED
-    assert gs.load().gs_view_layout(vb_t, len(cams), 32, 32, to, po) == L.GS_ERR_UNSUPPORTED
+    assert gs.load().gs_view_layout(vb_t, len(cams), 32, 32, to, po) == 0  # tiles up to 32x32
+    assert gs.load().gs_view_layout(vb_t, len(cams), 64, 8, to, po) == L.GS_ERR_UNSUPPORTED
     assert gs.load().gs_view_layout(vb_t, 0, 16, 16, to, po) == L.GS_ERR_INVALID_ARG
 
 
@@ -120,6 +121,10 @@ def test_argument_errors_are_reported_before_launch():
     v3 = _dummy_views()
     v3.batch_depth = 3
     assert lib.gs_preprocess(R(g), R(v3), R(p), None, 0, 1, R(out), None) == L.GS_ERR_UNSUPPORTED
+    v5 = _dummy_views((32, 32))  # tiles up to 32x32; batch depth 2 only up to 512 pixels
+    v5.batch_depth = 2
+    assert lib.gs_preprocess(R(g), R(v5), R(p), None, 0, 1, R(out), None) == L.GS_ERR_UNSUPPORTED
+    assert b"512" in lib.gs_last_error()
     v4 = _dummy_views()
     v4.persistent = 1  # bins has no queue
     assert lib.gs_importance(R(out), R(v4), R(b), R(p), ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
