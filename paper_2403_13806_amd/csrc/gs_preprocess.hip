@@ -365,7 +365,8 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         double op;
         if (!project_one(cam, a.p, a.mean, a.scale, a.quat, a.opac, a.n, i, P, op)) continue;
         go += gO;
-        const double ca = P.syy / P.det, cb = -P.sxy / P.det, cc = P.sxx / P.det;
+        const double idet = 1.0 / P.det;
+        const double ca = P.syy * idet, cb = -P.sxy * idet, cc = P.sxx * idet;
         // conic Q = Sigma'^-1; for a symmetric perturbation dSigma', dQ = -Q dSigma' Q.
         // With G = [[gA, gB/2], [gB/2, gC]] the gradient w.r.t. Sigma' is -Q G Q.
         const double g00 = gA, g01 = 0.5 * gB, g11 = gC;
@@ -433,10 +434,11 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         double gz = 2.0 * (-2.0 * zq * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * zq * GR[1][1] +
                            y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
         const double dot = w * gw + x * gx + y * gy + zq * gz;
-        gq[0] += (gw - w * dot) / P.qn;
-        gq[1] += (gx - x * dot) / P.qn;
-        gq[2] += (gy - y * dot) / P.qn;
-        gq[3] += (gz - zq * dot) / P.qn;
+        const double iqn = 1.0 / P.qn;
+        gq[0] += (gw - w * dot) * iqn;
+        gq[1] += (gx - x * dot) * iqn;
+        gq[2] += (gy - y * dot) * iqn;
+        gq[3] += (gz - zq * dot) * iqn;
     }
     if (!any) return;
 #pragma unroll
