@@ -420,16 +420,17 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 S0 = fmaf(wt, s.rgb[0], S0);  // wt = 0 where the entry does not contribute
                 S1 = fmaf(wt, s.rgb[1], S1);
                 S2 = fmaf(wt, s.rgb[2], S2);
-                // u v a b c o r g b; the geometric terms vanish where alpha is clamped
+                // dq dx, dq dy (turned into the u, v gradients with the conic once per record
+                // in the flush), a b c o r g b; the geometric terms vanish where alpha is clamped
                 const bool free_a = contrib & (og < amax);
                 const float dx = (float)ddx, dy = (float)ddy;
                 const float dq = free_a ? -0.5f * al * dA : 0.f;
                 float v[9];
-                v[0] = -2.f * dq * ((float)s.ca * dx + (float)s.cb * dy);
-                v[1] = -2.f * dq * ((float)s.cb * dx + (float)s.cc * dy);
-                v[2] = dq * dx * dx;
-                v[3] = dq * 2.f * dx * dy;
-                v[4] = dq * dy * dy;
+                v[0] = dq * dx;
+                v[1] = dq * dy;
+                v[2] = v[0] * dx;
+                v[3] = 2.f * v[0] * dy;
+                v[4] = v[1] * dy;
                 v[5] = free_a ? dA * G : 0.f;
                 v[6] = contrib ? dC0 * wt : 0.f;
                 v[7] = contrib ? dC1 * wt : 0.f;
@@ -440,13 +441,24 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
             }
         }
         __syncthreads();
-        // one global atomic per (tile, record, field) for the whole workgroup
+        // one global atomic per (tile, record, field) for the whole workgroup; the sums of
+        // dq dx and dq dy become dL/du = -2 (a sx + b sy), dL/dv = -2 (b sx + c sy)
         const uint32_t cnt = hi - lo;
-        for (int q = t; q < BD * 9; q += NT) {
-            const int j = q / 9, f = q - 9 * (q / 9);
-            const float v = sm.acc[q];
-            if ((uint32_t)j < cnt && v != 0.f) atomicAdd(a.g2 + f * VN + vbase + sm.gid[j], v);
-            sm.acc[q] = 0.f;
+        for (int j = t; j < BD; j += NT) {
+            float f9[9];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) {
+                f9[f] = sm.acc[j * 9 + f];
+                sm.acc[j * 9 + f] = 0.f;
+            }
+            if ((uint32_t)j >= cnt) continue;
+            const float sx = f9[0], sy = f9[1];
+            f9[0] = -2.f * ((float)sm.rec[j].ca * sx + (float)sm.rec[j].cb * sy);
+            f9[1] = -2.f * ((float)sm.rec[j].cb * sx + (float)sm.rec[j].cc * sy);
+            const int64_t gi = vbase + sm.gid[j];
+#pragma unroll
+            for (int f = 0; f < 9; ++f)
+                if (f9[f] != 0.f) atomicAdd(a.g2 + f * VN + gi, f9[f]);
         }
         hi = lo;
     }

@@ -298,6 +298,26 @@ def test_backward_matches_oracle(case):
             assert elem.mean() >= 0.999, name
 
 
+@pytest.mark.parametrize("tile,depth", [((8, 8), 1), ((32, 16), 2), ((16, 32), 1), ((32, 32), 1)])
+def test_backward_tile_shapes(tile, depth):
+    """The reverse traversal at other tile shapes and batch depths (one to sixteen waves per
+    workgroup, quarter lists of up to 64 bits) against the oracle gradient."""
+    sc, cam = _case("plain")
+    rng = np.random.default_rng(12)
+    w = rng.uniform(-1, 1, (3, cam.height, cam.width)).astype(np.float32)
+    _say(f"backward tile={tile} depth={depth}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], tile, DEV, batch_depth=depth)
+    out = gs.render(g, views, P)
+    grad = gs.render_bwd(g, views, out["proj"], out["bins"], out["t_final"], out["n_last"],
+                         torch.as_tensor(w.reshape(-1), device=DEV), P)
+    torch.cuda.synchronize()
+    ref = oracle.render_bwd(sc, cam, P, w.astype(np.float64))
+    for name in ("mean", "scale", "quat", "opacity", "sh"):
+        rel, _ = _grad_check(getattr(grad, name).cpu().numpy(), ref[name], name)
+        assert rel <= TOL_GRAD, name
+
+
 def test_autograd_function_and_l1_loss():
     sc, cam = _case("plain")
     tgt = scenes.target_images([cam])[0]
@@ -377,7 +397,7 @@ def test_full_size_sampled_pixels():
 
 
 @pytest.mark.parametrize("tile,depth,persistent", [((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 2, False),
-                                                   ((16, 8), 1, True)])
+                                                   ((16, 8), 1, True), ((32, 16), 2, True), ((32, 32), 1, True)])
 def test_launch_forms_bitwise(tile, depth, persistent):
     """Batch depth and the persistent longest-first launch change who composites a tile and
     how its list is staged, never the arithmetic: images, T and importance are bitwise equal."""
