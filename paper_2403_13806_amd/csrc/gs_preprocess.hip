@@ -54,28 +54,44 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
     Y[15] = -SH_C3A * x * (xx - 3.f * yy);
 }
 
-// gradient of each basis polynomial above with respect to (x, y, z)
-__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, float G[16][3]) {
-    G[0][0] = G[0][1] = G[0][2] = 0.f;
+// sum_k (s k_k) grad Y_k(x, y, z): the gradient of each basis polynomial above with respect
+// to (x, y, z), contracted with the weights s k_k as it is formed (no 16 x 3 table is held)
+__device__ __forceinline__ void sh_wgrad(int deg, float x, float y, float z, const float* kk, float sc, float gd[3]) {
+    float w[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = (k < (deg + 1) * (deg + 1)) ? kk[k] * sc : 0.f;
+    gd[0] = gd[1] = gd[2] = 0.f;
     if (deg < 1) return;
-    G[1][0] = 0.f; G[1][1] = -SH_C1; G[1][2] = 0.f;
-    G[2][0] = 0.f; G[2][1] = 0.f; G[2][2] = SH_C1;
-    G[3][0] = -SH_C1; G[3][1] = 0.f; G[3][2] = 0.f;
+    gd[1] -= SH_C1 * w[1];
+    gd[2] += SH_C1 * w[2];
+    gd[0] -= SH_C1 * w[3];
     if (deg < 2) return;
-    G[4][0] = SH_C2A * y; G[4][1] = SH_C2A * x; G[4][2] = 0.f;
-    G[5][0] = 0.f; G[5][1] = -SH_C2A * z; G[5][2] = -SH_C2A * y;
-    G[6][0] = 0.f; G[6][1] = 0.f; G[6][2] = SH_C2B * 6.f * z;
-    G[7][0] = -SH_C2A * z; G[7][1] = 0.f; G[7][2] = -SH_C2A * x;
-    G[8][0] = SH_C2C * 2.f * x; G[8][1] = -SH_C2C * 2.f * y; G[8][2] = 0.f;
+    gd[0] += SH_C2A * y * w[4];
+    gd[1] += SH_C2A * x * w[4];
+    gd[1] -= SH_C2A * z * w[5];
+    gd[2] -= SH_C2A * y * w[5];
+    gd[2] += SH_C2B * 6.f * z * w[6];
+    gd[0] -= SH_C2A * z * w[7];
+    gd[2] -= SH_C2A * x * w[7];
+    gd[0] += SH_C2C * 2.f * x * w[8];
+    gd[1] -= SH_C2C * 2.f * y * w[8];
     if (deg < 3) return;
-    float xx = x * x, yy = y * y, zz = z * z;
-    G[9][0] = -SH_C3A * 6.f * x * y; G[9][1] = -SH_C3A * (3.f * xx - 3.f * yy); G[9][2] = 0.f;
-    G[10][0] = SH_C3B * y * z; G[10][1] = SH_C3B * x * z; G[10][2] = SH_C3B * x * y;
-    G[11][0] = 0.f; G[11][1] = -SH_C3C * (5.f * zz - 1.f); G[11][2] = -SH_C3C * 10.f * y * z;
-    G[12][0] = 0.f; G[12][1] = 0.f; G[12][2] = SH_C3D * (15.f * zz - 3.f);
-    G[13][0] = -SH_C3C * (5.f * zz - 1.f); G[13][1] = 0.f; G[13][2] = -SH_C3C * 10.f * x * z;
-    G[14][0] = SH_C3E * 2.f * x * z; G[14][1] = -SH_C3E * 2.f * y * z; G[14][2] = SH_C3E * (xx - yy);
-    G[15][0] = -SH_C3A * (3.f * xx - 3.f * yy); G[15][1] = SH_C3A * 6.f * x * y; G[15][2] = 0.f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gd[0] -= SH_C3A * 6.f * x * y * w[9];
+    gd[1] -= SH_C3A * (3.f * xx - 3.f * yy) * w[9];
+    gd[0] += SH_C3B * y * z * w[10];
+    gd[1] += SH_C3B * x * z * w[10];
+    gd[2] += SH_C3B * x * y * w[10];
+    gd[1] -= SH_C3C * (5.f * zz - 1.f) * w[11];
+    gd[2] -= SH_C3C * 10.f * y * z * w[11];
+    gd[2] += SH_C3D * (15.f * zz - 3.f) * w[12];
+    gd[0] -= SH_C3C * (5.f * zz - 1.f) * w[13];
+    gd[2] -= SH_C3C * 10.f * x * z * w[13];
+    gd[0] += SH_C3E * 2.f * x * z * w[14];
+    gd[1] -= SH_C3E * 2.f * y * z * w[14];
+    gd[2] += SH_C3E * (xx - yy) * w[14];
+    gd[0] -= SH_C3A * (3.f * xx - 3.f * yy) * w[15];
+    gd[1] += SH_C3A * 6.f * x * y * w[15];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -453,60 +469,68 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
 
 // Colour part of the reverse mode: SH coefficient gradients and the mean gradient through
 // the view direction. Split from the geometric part so that neither kernel carries the
-// other's registers (the SH-3 accumulators alone are 48 floats).
+// other's registers. Three waves per workgroup, one per colour channel, each holding that
+// channel's coefficients of the same 64 Gaussians (16 values at SH-3 instead of 48); the
+// channels' mean-gradient parts are added through LDS at the end.
 template <int DEG>
-__global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
+__global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
-    if (i >= a.n) return;
+    __shared__ float s_gp[3][3][64];
+    __shared__ uint32_t s_any[3][64];
+    const int c = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + l;
+    const bool valid = i < a.n;
     const int64_t VN = (int64_t)a.n_views * a.n;
-    float shv[NB * 3], gsh[NB * 3];
+    float shv[NB], gsh[NB];
 #pragma unroll
-    for (int k = 0; k < NB * 3; ++k) {
-        shv[k] = a.sh[(int64_t)k * a.n + i];
+    for (int k = 0; k < NB; ++k) {
+        shv[k] = valid ? a.sh[(int64_t)(k * 3 + c) * a.n + i] : 0.f;
         gsh[k] = 0.f;
     }
-    const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (valid) {
+        px = a.mean[i];
+        py = a.mean[a.n + i];
+        pz = a.mean[2 * a.n + i];
+    }
     double gp[3] = {0, 0, 0};
     bool any = false;
-    for (int v = 0; v < a.n_views; ++v) {
+    for (int v = 0; valid && v < a.n_views; ++v) {
         const int64_t o = (int64_t)v * a.n + i;
         if (a.count[o] == 0) continue;
-        const float gcol[3] = {a.g2[6 * VN + o], a.g2[7 * VN + o], a.g2[8 * VN + o]};
-        if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+        const float gc = a.g2[(6 + c) * VN + o];
+        if (gc == 0.f) continue;
         any = true;
         const gs_camera cam = a.cams[v];
         float d[3];
         double len;
         view_dir(cam, px, py, pz, d, len);
-        float Y[16], G[16][3];
+        float Y[16];
         sh_basis(DEG, d[0], d[1], d[2], Y);
-        sh_basis_grad(DEG, d[0], d[1], d[2], G);
-        float gd[3] = {0.f, 0.f, 0.f};
+        float acc = 0.f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float acc = 0.f;
+        for (int k = 0; k < NB; ++k) acc += shv[k] * Y[k];
+        if (!(acc + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
 #pragma unroll
-            for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
-            if (!(acc + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                gsh[k * 3 + c] += gcol[c] * Y[k];
-                const float kc = shv[k * 3 + c] * gcol[c];
-                gd[0] += kc * G[k][0];
-                gd[1] += kc * G[k][1];
-                gd[2] += kc * G[k][2];
-            }
-        }
+        for (int k = 0; k < NB; ++k) gsh[k] += gc * Y[k];
+        float gd[3];
+        sh_wgrad(DEG, d[0], d[1], d[2], shv, gc, gd);
         const double dd = (double)d[0] * gd[0] + (double)d[1] * gd[1] + (double)d[2] * gd[2];
 #pragma unroll
         for (int k = 0; k < 3; ++k) gp[k] += ((double)gd[k] - (double)d[k] * dd) / len;
     }
-    if (!any) return;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.gmean[k * a.n + i] += (float)gp[k];
+    for (int k = 0; k < 3; ++k) s_gp[c][k][l] = (float)gp[k];
+    s_any[c][l] = any ? 1u : 0u;
+    if (any) {
 #pragma unroll
-    for (int k = 0; k < NB * 3; ++k) a.gsh[(int64_t)k * a.n + i] += gsh[k];
+        for (int k = 0; k < NB; ++k) a.gsh[(int64_t)(k * 3 + c) * a.n + i] += gsh[k];
+    }
+    __syncthreads();
+    if (c == 0 && valid && (s_any[0][l] | s_any[1][l] | s_any[2][l])) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.gmean[k * a.n + i] += s_gp[0][k][l] + s_gp[1][k][l] + s_gp[2][k][l];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -573,11 +597,13 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gsh = grad->sh;
     const dim3 grid((unsigned)((g->n + 127) / 128));
     hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(128), 0, stream, a);
+    // colour part: 64 Gaussians x 3 channels per workgroup
+    const dim3 gsh((unsigned)((g->n + 63) / 64));
     switch (g->sh_degree) {
-        case 0: hipLaunchKernelGGL((k_preprocess_bwd_sh<0>), grid, dim3(128), 0, stream, a); break;
-        case 1: hipLaunchKernelGGL((k_preprocess_bwd_sh<1>), grid, dim3(128), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL((k_preprocess_bwd_sh<2>), grid, dim3(128), 0, stream, a); break;
-        default: hipLaunchKernelGGL((k_preprocess_bwd_sh<3>), grid, dim3(128), 0, stream, a); break;
+        case 0: hipLaunchKernelGGL((k_preprocess_bwd_sh<0>), gsh, dim3(192), 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((k_preprocess_bwd_sh<1>), gsh, dim3(192), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((k_preprocess_bwd_sh<2>), gsh, dim3(192), 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_preprocess_bwd_sh<3>), gsh, dim3(192), 0, stream, a); break;
     }
     return check_launch("preprocess_bwd");
 }
