@@ -30,6 +30,11 @@ PEAK_HBM = 8.0e12
 # (2 sub, 3 mul, 2 fma, 1 cmp = 8) + opacity and blend in FP32 (cvt, scale, exp = 4 slots,
 # mul, min, weight, 3 fma colour, 1 - alpha, transmittance, stop test = 15)
 OPS_PER_COMPOSITE = 23
+# importance / visibility: support test 8, opacity 8, weight 1, transmittance and stop 3 = 20;
+# reverse: support test 8, opacity 8, transmittance recovery 5, weight and colour sums 7,
+# dL/dalpha 9, the nine 2D-gradient terms 10 = 47 (per composited evaluation)
+OPS_PER_IMPORTANCE = 20
+OPS_PER_BACKWARD = 47
 TILE = (16, 32)  # tile of the headline frames (fastest measured: fewer pairs to sort than 16x16)
 SPLAT = 64
 
@@ -128,9 +133,17 @@ def main():
     from paper_2403_13806_amd import _lib as L
     from paper_2403_13806_amd.splat import _ptr, _stream
     lib = L.load()
-    stages = {"preprocess": [], "bin_sort": [], "render_fwd": []}
+    stages = {"preprocess": [], "bin_sort": [], "render_fwd": [], "importance": [], "visibility": [], "backward": []}
     pairs, composites, tested, visible = [], [], [], []
     ncontrib = torch.empty(rs[0].views.n_pixels, dtype=torch.int32, device=dev)
+    h_buf = torch.zeros(g.n, dtype=torch.float32, device=dev)
+    bits_buf = torch.zeros((g.n + 31) // 32, dtype=torch.int32, device=dev)
+    one_cluster = torch.zeros(1, dtype=torch.int32, device=dev)
+    from paper_2403_13806_amd.train import zero_grads
+    gbuf = zero_grads(g)
+    gg = L.gs_gaussians_grad(_ptr(gbuf.mean), _ptr(gbuf.scale), _ptr(gbuf.quat), _ptr(gbuf.opacity), _ptr(gbuf.sh),
+                             g.n, g.sh_degree)
+    dl_buf = torch.full((3 * rs[0].views.n_pixels,), 1e-6, dtype=torch.float32, device=dev)
     reps = max(3, K // 8)
     for r in rs:
         s = _stream(dev)
@@ -143,9 +156,23 @@ def main():
                                         r.ws.numel(), s))
             with Timer(torch) as c:
                 r.render_only(s, ncontrib)
+            # the traversals built on the same lists: importance, cluster visibility, reverse
+            with Timer(torch) as d:
+                L.check(lib.gs_importance(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                          ctypes.byref(r.p), _ptr(h_buf), s))
+            with Timer(torch) as e:
+                L.check(lib.gs_cluster_visibility(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                                  ctypes.byref(r.p), _ptr(one_cluster), 1, 0.01, _ptr(bits_buf), s))
+            with Timer(torch) as f:
+                L.check(lib.gs_render_bwd(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r._sp),
+                                          ctypes.byref(r._sb), ctypes.byref(r.p), _ptr(r.t_final), _ptr(r.n_last),
+                                          _ptr(dl_buf), ctypes.byref(gg), _ptr(r.ws), r.ws.numel(), s))
             stages["preprocess"].append(a.ms())
             stages["bin_sort"].append(b.ms())
             stages["render_fwd"].append(c.ms())
+            stages["importance"].append(d.ms())
+            stages["visibility"].append(e.ms())
+            stages["backward"].append(f.ms())
         # work counts of this view
         npairs = int(r.bins.n_pairs.item())
         pairs.append(npairs)
@@ -172,6 +199,7 @@ def main():
     bytes_sort = (4 + 4 + 8) * n + 12 * mv + mp * (12 + 4 + passes * 24 + 4 + 20) + rs[0].views.n_tiles * 8
     bytes_render = mp * (4 + SPLAT) + npx * (12 + 4 + 4) + rs[0].views.n_tiles * 8
     ops_render = OPS_PER_COMPOSITE * mc
+    ops_imp, ops_bwd = OPS_PER_IMPORTANCE * mc, OPS_PER_BACKWARD * mc
     stage_rows = {
         "preprocess": {"ms": avg["preprocess"], "alg_GBps": bytes_pre / avg["preprocess"] / 1e6,
                        "hbm_frac": bytes_pre / avg["preprocess"] / 1e-3 / PEAK_HBM},
@@ -181,6 +209,14 @@ def main():
                        "alu_frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS,
                        "alg_GBps": bytes_render / avg["render_fwd"] / 1e6,
                        "hbm_frac": bytes_render / avg["render_fwd"] / 1e-3 / PEAK_HBM},
+        # same composited evaluations as the forward (the stop rule is the same)
+        "importance": {"ms": avg["importance"], "alg_Tops": ops_imp / avg["importance"] / 1e9,
+                       "alu_frac": ops_imp / avg["importance"] / 1e-3 / PEAK_LANE_OPS},
+        "visibility": {"ms": avg["visibility"], "alg_Tops": ops_imp / avg["visibility"] / 1e9,
+                       "alu_frac": ops_imp / avg["visibility"] / 1e-3 / PEAK_LANE_OPS},
+        # the whole reverse call: 2D-gradient traversal plus the parameter chains
+        "backward": {"ms": avg["backward"], "alg_Tops": ops_bwd / avg["backward"] / 1e9,
+                     "alu_frac": ops_bwd / avg["backward"] / 1e-3 / PEAK_LANE_OPS},
     }
     work = {"visible_per_view": mv, "pairs_per_view": mp, "composited_per_view": mc,
             "tested_per_view": mt, "composited_per_pixel": mc / npx, "tested_per_composited": mt / max(mc, 1)}
@@ -196,6 +232,7 @@ def main():
 
     extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3,
              "copy_256MiB_GBps": copy_gbps}
+    extra["prune"] = prune_pass(torch, gs, g, h_buf, dev)
 
     if not args.quick:
         extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
@@ -238,6 +275,42 @@ def recorded_traffic(kernel):
     if rec.get("source_sha256") != h or rec.get("kernel") != kernel:
         return None
     return float(rec["traffic_bytes_per_launch"])
+
+
+def prune_pass(torch, gs, g, h, dev, t_prune=0.01, reps=5):
+    """Pruning as a training loop would run it: the Gaussian parameters and two optimizer
+    moments per parameter (177 FP32 planes at SH-3) compacted by h >= t_prune."""
+    import ctypes
+    from paper_2403_13806_amd import _lib as L
+    from paper_2403_13806_amd.splat import _ptr, _stream, alloc_workspace
+    n = g.n
+    planes = [g.mean, g.scale, g.quat, g.opacity, g.sh]
+    moments = [torch.zeros_like(t) for t in planes for _ in range(2)]
+    rows_in = [r for t in planes + moments for r in t.reshape(-1, n)]
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in rows_in]
+    kept = torch.empty(n, dtype=torch.int32, device=dev)
+    n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = alloc_workspace(n, 1, 0, 0, dev)
+    vp = ctypes.c_void_p * len(rows_in)
+    pin, pout = vp(*[r.data_ptr() for r in rows_in]), vp(*[o.data_ptr() for o in outs])
+    call = lambda: L.check(L.load().gs_prune(_ptr(h), n, t_prune, pin, pout, len(rows_in), _ptr(kept), _ptr(n_kept),
+                                             _ptr(ws), ws.numel(), _stream(dev)))
+    call()
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(reps):
+            call()
+    ms = tm.ms() / reps
+    nk = int(n_kept.item())
+    alg = 4 * n + nk * (4 + 8 * len(rows_in))  # h in; per kept Gaussian its index and each plane in + out
+    # as a stream compaction: every plane read whole (a kept fraction this size touches every
+    # cache line in random storage order), the kept part written
+    stream = 4 * n + 4 * len(rows_in) * (n + nk)
+    log(f"prune: {len(rows_in)} planes, kept {nk} of {n}, {ms:.3f} ms, {alg / ms / 1e6:.0f} GB/s kept-only, "
+        f"{stream / ms / 1e6:.0f} GB/s as a stream")
+    return {"planes": len(rows_in), "gaussians": n, "kept": nk, "t_prune": t_prune, "ms": ms,
+            "alg_GBps": alg / ms / 1e6, "hbm_frac": alg / ms / 1e-3 / PEAK_HBM,
+            "stream_GBps": stream / ms / 1e6, "stream_hbm_frac": stream / ms / 1e-3 / PEAK_HBM}
 
 
 def calib_copy(torch, dev, nbytes=256 << 20, reps=5):
@@ -375,10 +448,11 @@ def importance_pass(torch, gs, scenes, P, dev, chunk=10):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     assert all(not r.check()[0] for r in rs)
+    # kept-vs-threshold curve from the prune-mask kernel (mask = h < t)
+    kept = {str(t): int(g.n - gs.prune_mask(h, t).sum().item()) for t in (0.001, 0.005, 0.01, 0.03, 0.1, 0.25)}
     hh = h.cpu().numpy()
-    kept = {str(t): int((hh >= t).sum()) for t in (0.001, 0.005, 0.01, 0.03, 0.1, 0.25)}
     out = {"views_per_s": len(cams) / dt, "ms_all_views": dt * 1e3, "gaussians": g.n,
-           "kept_at_t_prune": kept, "pruned_at_0.01": int((hh < 0.01).sum()), "never_composited": int((hh == 0).sum())}
+           "kept_at_t_prune": kept, "pruned_at_0.01": g.n - kept["0.01"], "never_composited": int((hh == 0).sum())}
     log(f"  {out['views_per_s']:.0f} views/s, kept at 0.01: {kept['0.01']} of {g.n}")
     return out
 

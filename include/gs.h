@@ -185,7 +185,7 @@ typedef struct gs_bins {
 gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w, int32_t tile_h,
                          int32_t* tile_offset, int64_t* pixel_offset);
 
-/* Device workspace bytes needed by gs_bin_sort / gs_render_bwd / gs_bits_to_list for n
+/* Device workspace bytes needed by gs_bin_sort / gs_render_bwd / gs_bits_to_list / gs_prune for n
  * entries per view, n_views views, a pair capacity and n_tiles tiles. */
 size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 
@@ -252,6 +252,22 @@ gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views,
  * their number to *count (device int64). ws: at least gs_workspace_bytes(n, 1, 0, 0). */
 gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, int64_t* count, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* Prune mask (Sec. 3.3): mask[i] = 1 when h[i] < t_prune (Gaussian i is removed), else 0;
+ * h: device [n] FP32 (a NaN counts as pruned), mask: device [n] bytes. */
+gs_status gs_prune_mask(const float* h, int64_t n, float t_prune, uint8_t* mask, void* stream);
+
+/* Pruning (Sec. 3.3, eq. importance-score and the mask h < t_prune): keep Gaussian i when
+ * h[i] >= t_prune (device [n] FP32; a NaN is not kept) and compact n_planes FP32 planes of
+ * length n in index order, planes_out[p][k] = planes_in[p][kept[k]]: the parameters and any
+ * per-Gaussian state that must follow them (optimizer moments, ...). planes_in, planes_out:
+ * HOST arrays of n_planes DEVICE pointers, caller-owned, each output at least [n] and none
+ * aliasing an input plane. kept: device [n] int32, the kept indices in increasing order;
+ * *n_kept: device int64, their number. ws: device workspace of at least
+ * gs_workspace_bytes(n, 1, 0, 0). Asynchronous on the stream; argument errors are reported
+ * before anything is enqueued. */
+gs_status gs_prune(const float* h, int64_t n, float t_prune, const float* const* planes_in, float* const* planes_out,
+                   int32_t n_planes, int32_t* kept, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream);
 
 /* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
  * iterations from a k-means++ seeding with the given seed, at most max_iter iterations

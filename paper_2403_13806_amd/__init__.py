@@ -8,4 +8,5 @@ from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, V
                     alloc_workspace,
                     bin_sort, bits_to_list, cluster_visibility, importance, kmeans, l1_loss_grad, make_params,
                     nearest_centre,
-                    preprocess, prune_mask, render, render_bwd, render_fwd, workspace_bytes)
+                    preprocess, prune, prune_gaussians, prune_mask, render, render_bwd, render_fwd,
+                    workspace_bytes)

@@ -64,7 +64,7 @@ SPLAT_BYTES = 64
 
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_nearest_centre",
-           "gs_l1_loss_grad", "gs_last_error"]
+           "gs_l1_loss_grad", "gs_prune_mask", "gs_prune", "gs_last_error"]
 
 _lib = None
 
@@ -108,6 +108,11 @@ def load(path: str = LIB_PATH):
     L.gs_cluster_visibility.restype = i32
     L.gs_bits_to_list.argtypes = [c_void_p, i64, c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]
     L.gs_bits_to_list.restype = i32
+    L.gs_prune_mask.argtypes = [c_void_p, i64, f32, c_void_p, c_void_p]
+    L.gs_prune_mask.restype = i32
+    L.gs_prune.argtypes = [c_void_p, i64, f32, P(c_void_p), P(c_void_p), i32, c_void_p, c_void_p, c_void_p,
+                           ctypes.c_size_t, c_void_p]
+    L.gs_prune.restype = i32
     L.gs_kmeans.argtypes = [c_void_p, i32, i32, u64, i32, c_void_p, c_void_p]
     L.gs_kmeans.restype = i32
     L.gs_nearest_centre.argtypes = [c_void_p, i32, c_void_p]

@@ -36,6 +36,10 @@ gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*,
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
 gs_status launch_bits_to_list(const uint32_t*, int64_t, int32_t*, int64_t*, void*, hipStream_t);
+size_t prune_workspace_bytes(int64_t n);
+gs_status launch_prune_mask(const float*, int64_t, float, uint8_t*, hipStream_t);
+gs_status launch_prune(const float*, int64_t, float, const float* const*, float* const*, int32_t, int32_t*, int64_t*,
+                       void*, size_t, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
 gs_status launch_render_fwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*, float*,
                             uint32_t*, uint32_t*, hipStream_t);
@@ -150,6 +154,7 @@ size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t
     size_t b = sort_workspace_bytes(n, n_views, capacity, n_tiles);
     b = std::max(b, bwd_workspace_bytes(n, n_views));
     b = std::max(b, list_workspace_bytes(n));
+    b = std::max(b, prune_workspace_bytes(n) + list_workspace_bytes(n));
     return b;
 }
 
@@ -258,6 +263,32 @@ gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, in
     if (ws_bytes < need || (need > 0 && !ws))
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
     return launch_bits_to_list(bits_row, n, list, count, ws, (hipStream_t)stream);
+}
+
+gs_status gs_prune_mask(const float* h, int64_t n, float t_prune, uint8_t* mask, void* stream) {
+    if (n < 0 || (n > 0 && (!h || !mask))) return set_error(GS_ERR_INVALID_ARG, "gs_prune_mask: bad arguments");
+    if (!(t_prune == t_prune)) return set_error(GS_ERR_INVALID_ARG, "gs_prune_mask: t_prune is NaN");
+    return launch_prune_mask(h, n, t_prune, mask, (hipStream_t)stream);
+}
+
+gs_status gs_prune(const float* h, int64_t n, float t_prune, const float* const* planes_in, float* const* planes_out,
+                   int32_t n_planes, int32_t* kept, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || n_planes < 0 || !n_kept || (n > 0 && (!h || !kept)) || (n_planes > 0 && (!planes_in || !planes_out)))
+        return set_error(GS_ERR_INVALID_ARG, "gs_prune: bad arguments");
+    if (n >= ((int64_t)1 << 31)) return set_error(GS_ERR_UNSUPPORTED, "gs_prune: at most 2^31-1 Gaussians");
+    if (!(t_prune == t_prune)) return set_error(GS_ERR_INVALID_ARG, "gs_prune: t_prune is NaN");
+    for (int p = 0; p < n_planes; ++p) {
+        if (n > 0 && (!planes_in[p] || !planes_out[p]))
+            return set_error(GS_ERR_INVALID_ARG, "gs_prune: plane %d is NULL", p);
+        for (int q = 0; q < n_planes; ++q)
+            if (n > 0 && planes_out[p] == planes_in[q])
+                return set_error(GS_ERR_INVALID_ARG, "gs_prune: output plane %d aliases input plane %d", p, q);
+    }
+    const size_t need = prune_workspace_bytes(n) + list_workspace_bytes(n);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    return launch_prune(h, n, t_prune, planes_in, planes_out, n_planes, kept, n_kept, ws, prune_workspace_bytes(n),
+                        (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -36,6 +36,11 @@ def _dev(device):
     return torch.device(device if device is not None else "cuda")
 
 
+def _check_f32(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+
+
 def make_params(p=None) -> L.gs_params:
     """gs_params from any object with lowpass, kappa, alpha_min, alpha_max, t_min, guard, bg."""
     s = L.gs_params()
@@ -274,7 +279,50 @@ def importance(g: Gaussians, views: ViewBatch, params=None, h: Optional[torch.Te
 
 def prune_mask(h: torch.Tensor, t_prune: float) -> torch.Tensor:
     """m_i = 1(h_i < t_prune): True marks a Gaussian to remove (Sec. 3.3)."""
-    return h < t_prune
+    _check_f32(h, "h")
+    mask = torch.empty(h.numel(), dtype=torch.uint8, device=h.device)
+    L.check(L.load().gs_prune_mask(_ptr(h), h.numel(), float(t_prune), _ptr(mask), _stream(h.device)))
+    return mask.bool()
+
+
+def prune(h: torch.Tensor, t_prune: float, planes: Sequence[torch.Tensor]):
+    """Remove the Gaussians with h < t_prune from every per-Gaussian FP32 plane (Sec. 3.3):
+    returns (compacted planes, kept indices). A plane is a tensor whose last dimension has
+    length n (for example mean [3, n], sh [48, n], or an optimizer moment shaped like a
+    parameter). Reads the kept count back (one host synchronisation)."""
+    _check_f32(h, "h")
+    n = h.numel()
+    dev = h.device
+    rows_in, shapes = [], []
+    for t in planes:
+        _check_f32(t, "plane")
+        if t.shape[-1] != n:
+            raise ValueError(f"plane of shape {tuple(t.shape)} does not end in n = {n}")
+        r = t.reshape(-1, n)
+        rows_in.extend(r[k] for k in range(r.shape[0]))
+        shapes.append(tuple(t.shape[:-1]))
+    outs = [torch.empty((int(np.prod(sh, dtype=np.int64)), n), dtype=torch.float32, device=dev) for sh in shapes]
+    rows_out = [o[k] for o in outs for k in range(o.shape[0])]
+    kept = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = alloc_workspace(n, 1, 0, 0, dev)
+    vp = ctypes.c_void_p * max(len(rows_in), 1)
+    pin = vp(*[r.data_ptr() for r in rows_in])
+    pout = vp(*[r.data_ptr() for r in rows_out])
+    L.check(L.load().gs_prune(_ptr(h), n, float(t_prune), pin, pout, len(rows_in), _ptr(kept), _ptr(n_kept), _ptr(ws),
+                              ws.numel(), _stream(dev)))
+    nk = int(n_kept.item())
+    res = [o[:, :nk].reshape(*sh, nk).clone() if nk else o[:, :0].reshape(*sh, 0) for o, sh in zip(outs, shapes)]
+    return res, kept[:nk]
+
+
+def prune_gaussians(g: "Gaussians", h: torch.Tensor, t_prune: float, extra: Sequence[torch.Tensor] = ()):
+    """Pruned copy of the Gaussians (and of any per-Gaussian state in `extra`), plus the kept
+    indices."""
+    planes = [g.mean, g.scale, g.quat, g.opacity, g.sh, *extra]
+    out, kept = prune(h, t_prune, planes)
+    pg = Gaussians(out[0], out[1], out[2], out[3], out[4], g.sh_degree)
+    return pg, kept, out[5:]
 
 
 def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[int], k: int, t_cluster: float,

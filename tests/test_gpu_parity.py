@@ -208,7 +208,7 @@ def test_importance_matches_oracle(case):
     assert (hr > 0).sum() > 50
     # the prune mask (Sec. 3.3) agrees except within 1e-5 of the threshold
     t = 0.01
-    m_gpu = gs.prune_mask(torch.as_tensor(h), t).numpy()
+    m_gpu = gs.prune_mask(torch.as_tensor(h.astype(np.float32), device=DEV), t).cpu().numpy()
     m_ref = oracle.prune_mask(hr, t)
     near = np.abs(hr - t) <= TOL_H
     assert np.array_equal(m_gpu[~(near | band)], m_ref[~(near | band)])
@@ -514,3 +514,46 @@ def test_visibility_filter_extra_cameras_only_add():
         sa = set(a.lists[c].cpu().numpy().tolist())
         sb = set(b.lists[c].cpu().numpy().tolist())
         assert sa <= sb
+
+
+def test_prune_compaction_matches_numpy():
+    """Pruning (Sec. 3.3) keeps h >= t_prune; every plane is compacted in index order,
+    bit-exact against NumPy boolean indexing; the kept list and the mask are exact."""
+    rng = np.random.default_rng(21)
+    n = 10007
+    h = rng.uniform(0, 0.03, n).astype(np.float32)
+    h[rng.integers(0, n, 300)] = 0.0
+    h[rng.integers(0, n, 50)] = np.float32(0.01)  # exactly at the threshold: kept
+    h[rng.integers(0, n, 5)] = np.nan  # pruned
+    sc = scenes.mixture_scene(n, seed=3, sh_degree=3)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    extra = [torch.as_tensor(rng.standard_normal((3, n)).astype(np.float32), device=DEV) for _ in range(2)]
+    ht = torch.as_tensor(h, device=DEV)
+    for t in (0.01, -1.0, 1.0):
+        _say(f"prune t={t}")
+        pg, kept, ex = gs.prune_gaussians(g, ht, t, extra)
+        mask = gs.prune_mask(ht, t).cpu().numpy()
+        keep = h >= np.float32(t)
+        assert np.array_equal(mask, ~keep)
+        assert np.array_equal(kept.cpu().numpy(), np.nonzero(keep)[0])
+        for got, ref in [(pg.mean, sc.mean), (pg.scale, sc.scale), (pg.quat, sc.quat), (pg.opacity, sc.opacity),
+                         (pg.sh, sc.sh)] + [(a, b.cpu().numpy()) for a, b in zip(ex, extra)]:
+            assert np.array_equal(got.cpu().numpy(), ref[..., keep])
+        assert pg.n == int(keep.sum())
+
+
+def test_pruning_unseen_gaussians_keeps_renders_bitwise():
+    """The Gaussians with h = 0 over a set of views are never composited in them, so
+    removing them (compaction keeps index order, hence every tie-break) leaves each of
+    those renders bitwise unchanged."""
+    sc = scenes.mixture_scene(20000, seed=4, sh_degree=3)
+    cams = scenes.orbit_views(4, 160, 106)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    vb = gs.ViewBatch(cams, (16, 16), DEV)
+    h = gs.importance(g, vb, P)
+    pg, kept, _ = gs.prune_gaussians(g, h, float(np.nextafter(np.float32(0), np.float32(1))))
+    _say(f"pruned to {pg.n} of {g.n}")
+    assert 0 < pg.n < g.n
+    a = gs.render(g, vb, P)
+    b = gs.render(pg, vb, P)
+    assert torch.equal(a["rgb"], b["rgb"]) and torch.equal(a["t_final"], b["t_final"])

@@ -131,6 +131,22 @@ def test_argument_errors_are_reported_before_launch():
     assert b"queue" in lib.gs_last_error()
 
 
+def test_prune_argument_errors():
+    lib = gs.load()
+    vp = ctypes.c_void_p * 2
+    pin = vp(16, 32)
+    pout = vp(48, 16)  # output 1 aliases input 0
+    kept, cnt, ws = ctypes.c_void_p(64), ctypes.c_void_p(80), ctypes.c_void_p(96)
+    assert lib.gs_prune(ctypes.c_void_p(16), 10, 0.01, pin, pout, 2, kept, cnt, ws, 1 << 20, None) == L.GS_ERR_INVALID_ARG
+    assert b"aliases" in lib.gs_last_error()
+    assert lib.gs_prune(ctypes.c_void_p(16), 10, float("nan"), pin, vp(48, 64), 2, kept, cnt, ws, 1 << 20,
+                        None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_prune(ctypes.c_void_p(16), 10, 0.01, pin, vp(48, 64), 2, kept, cnt, ws, 0, None) == L.GS_ERR_INVALID_ARG
+    assert b"workspace" in lib.gs_last_error()
+    assert lib.gs_prune(None, 10, 0.01, pin, vp(48, 64), 2, kept, cnt, ws, 1 << 20, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_prune_mask(None, 10, 0.01, ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
+
+
 def test_kmeans_recovers_separated_groups():
     rng = np.random.default_rng(0)
     centres = np.array([[0, 0, 0], [10, 0, 0], [0, 10, 0], [0, 0, 10]], float)
