@@ -14,6 +14,9 @@ computes and which passage of the paper it follows:
                (eq. importance-score-vis)
   render_bwd   exact a.e. gradient of the image w.r.t. all Gaussian parameters
   pairs        the (tile, depth, index) key list the binning step must produce
+
+The training loss of Sec. 3.2 ((1 - lambda) L2 + lambda D-SSIM) and its gradient are in
+``oracle.loss`` (numpy, FP64).
 """
 from __future__ import annotations
 
