@@ -233,6 +233,7 @@ def main():
     extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3,
              "copy_256MiB_GBps": copy_gbps}
     extra["prune"] = prune_pass(torch, gs, g, h_buf, dev)
+    extra["loss_l2_dssim"] = loss_pass(torch, gs, scenes, dev)
 
     if not args.quick:
         extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
@@ -311,6 +312,28 @@ def prune_pass(torch, gs, g, h, dev, t_prune=0.01, reps=5):
     return {"planes": len(rows_in), "gaussians": n, "kept": nk, "t_prune": t_prune, "ms": ms,
             "alg_GBps": alg / ms / 1e6, "hbm_frac": alg / ms / 1e-3 / PEAK_HBM,
             "stream_GBps": stream / ms / 1e6, "stream_hbm_frac": stream / ms / 1e-3 / PEAK_HBM}
+
+
+def loss_pass(torch, gs, scenes, dev, reps=20):
+    """The Sec. 3.2 training loss (1 - 0.2) L2 + 0.2 D-SSIM and its gradient for one
+    1256 x 828 view (three planes): two HBM-bound launches, 44 algorithmic bytes per pixel
+    and plane (8 read and 12 written by the statistics launch, 20 read and 4 written by the
+    gradient launch)."""
+    x, y = scenes.image_pair(3, 828, 1256)
+    xt, yt = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    dl = torch.empty_like(xt)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(gs.ssim_workspace_bytes(3, 828, 1256), dtype=torch.uint8, device=dev)
+    gs.ssim_loss_grad(xt, yt, dl, loss, ws=ws)
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(reps):
+            gs.ssim_loss_grad(xt, yt, dl, loss, ws=ws)
+    ms = tm.ms() / reps
+    alg = 44 * x.size
+    log(f"loss (L2 + D-SSIM): 3 x 828 x 1256, {ms:.4f} ms, {alg / ms / 1e6:.0f} GB/s algorithmic")
+    return {"planes": 3, "height": 828, "width": 1256, "ms": ms, "alg_bytes": alg,
+            "alg_GBps": alg / ms / 1e6, "hbm_frac": alg / ms / 1e-3 / PEAK_HBM}
 
 
 def calib_copy(torch, dev, nbytes=256 << 20, reps=5):

@@ -223,6 +223,26 @@ gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const g
 gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, float scale, float* dl_drgb,
                           float* loss_accum, void* stream);
 
+/* Training loss of the point representation (Sec. 3.2): a weighted sum of the squared error
+ * and the structural dissimilarity of the render x against the target y,
+ *   L = (1 - lambda) sum (x - y)^2 / n_norm + lambda sum (1 - SSIM(x, y)) / n_norm
+ * (the paper weighs the two terms with lambda = 0.2). SSIM is the per-pixel structural
+ * similarity of Wang et al.: local means, variances and covariance from an 11 x 11 Gaussian
+ * window of standard deviation 1.5 with zero padding outside the plane, C1 = 0.01^2,
+ * C2 = 0.03^2 (intensities in [0, 1]). Each sum runs over the n_planes planes [height][width]
+ * of img and target (contiguous, plane after plane; a view's planar [3][H][W] image is three
+ * planes). n_norm is the element count the mean runs over: pass the batch total to each
+ * call of a batch of views of different sizes, so the calls compose.
+ *   dl_dimg     device [n_planes][height][width], written: dL/dx (must not alias img/target)
+ *   loss_accum  device scalar or NULL: *loss_accum += this call's part of L
+ *   ws          device workspace of at least gs_ssim_workspace_bytes(n_planes, height, width)
+ * Errors: n_planes outside [0, 65535], a non-positive size or n_norm, lambda outside [0, 1],
+ * NULL pointers or a short workspace return GS_ERR_INVALID_ARG before anything is enqueued. */
+size_t gs_ssim_workspace_bytes(int32_t n_planes, int32_t height, int32_t width);
+gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_planes, int32_t height, int32_t width,
+                            int64_t n_norm, float lambda, float* dl_dimg, float* loss_accum, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* Gradient of L with respect to the Gaussian parameters given dL/d(rgb) (layout of
  * rgb), accumulated (+=) into grad. Reverse traversal per pixel from n_last; the
  * transmittance before each entry is recovered from t_final by division. proj must

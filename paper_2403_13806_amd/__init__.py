@@ -9,4 +9,4 @@ from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, V
                     bin_sort, bits_to_list, cluster_visibility, importance, kmeans, l1_loss_grad, make_params,
                     nearest_centre,
                     preprocess, prune, prune_gaussians, prune_mask, render, render_bwd, render_fwd,
-                    workspace_bytes)
+                    ssim_loss_grad, ssim_workspace_bytes, workspace_bytes)

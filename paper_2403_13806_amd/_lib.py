@@ -64,7 +64,8 @@ SPLAT_BYTES = 64
 
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_nearest_centre",
-           "gs_l1_loss_grad", "gs_prune_mask", "gs_prune", "gs_last_error"]
+           "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
+           "gs_last_error"]
 
 _lib = None
 
@@ -97,6 +98,11 @@ def load(path: str = LIB_PATH):
                                 c_void_p, c_void_p, c_void_p]
     L.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, i64, f32, c_void_p, c_void_p, c_void_p]
     L.gs_l1_loss_grad.restype = i32
+    L.gs_ssim_workspace_bytes.argtypes = [i32, i32, i32]
+    L.gs_ssim_workspace_bytes.restype = ctypes.c_size_t
+    L.gs_ssim_loss_grad.argtypes = [c_void_p, c_void_p, i32, i32, i32, i64, f32, c_void_p, c_void_p, c_void_p,
+                                    ctypes.c_size_t, c_void_p]
+    L.gs_ssim_loss_grad.restype = i32
     L.gs_render_fwd.restype = i32
     L.gs_render_bwd.argtypes = [P(gs_gaussians), P(gs_views), P(gs_projected), P(gs_bins), P(gs_params), c_void_p,
                                 c_void_p, c_void_p, P(gs_gaussians_grad), c_void_p, ctypes.c_size_t, c_void_p]

@@ -44,6 +44,9 @@ gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
 gs_status launch_render_fwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*, float*,
                             uint32_t*, uint32_t*, hipStream_t);
 gs_status launch_l1(const float*, const float*, int64_t, float, float*, float*, hipStream_t);
+size_t ssim_workspace_bytes(int32_t, int32_t, int32_t);
+gs_status launch_ssim_loss_grad(const float*, const float*, int32_t, int32_t, int32_t, int64_t, float, float*, float*,
+                                void*, hipStream_t);
 gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
                             hipStream_t);
 gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
@@ -201,6 +204,31 @@ gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, floa
     if (n < 0 || (n > 0 && (!rgb || !target || !dl_drgb)))
         return set_error(GS_ERR_INVALID_ARG, "gs_l1_loss_grad: bad arguments");
     return launch_l1(rgb, target, n, scale, dl_drgb, loss_accum, (hipStream_t)stream);
+}
+
+size_t gs_ssim_workspace_bytes(int32_t n_planes, int32_t height, int32_t width) {
+    return ssim_workspace_bytes(n_planes, height, width);
+}
+
+gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_planes, int32_t height, int32_t width,
+                            int64_t n_norm, float lambda, float* dl_dimg, float* loss_accum, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (n_planes < 0 || n_planes > 65535)
+        return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: n_planes must be in [0, 65535]");
+    if (n_planes == 0) return GS_OK;
+    if (height < 1 || width < 1) return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: height and width must be >= 1");
+    if (n_norm < 1) return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: n_norm must be >= 1");
+    if (!(lambda >= 0.f && lambda <= 1.f))
+        return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: lambda must be in [0, 1]");
+    if (!img || !target || !dl_dimg) return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: NULL image pointer");
+    if (dl_dimg == img || dl_dimg == target)
+        return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: dl_dimg aliases an input image");
+    const size_t need = ssim_workspace_bytes(n_planes, height, width);
+    if (!ws || ws_bytes < need)
+        return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: workspace of %zu bytes needed, %zu given", need,
+                         ws ? ws_bytes : (size_t)0);
+    return launch_ssim_loss_grad(img, target, n_planes, height, width, n_norm, lambda, dl_dimg, loss_accum, ws,
+                                 (hipStream_t)stream);
 }
 
 gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_projected* proj, const gs_bins* bins,

@@ -256,6 +256,39 @@ def l1_loss_grad(rgb: torch.Tensor, target: torch.Tensor, dl_drgb: Optional[torc
     return loss, dl_drgb
 
 
+SSIM_LAMBDA = 0.2
+
+
+def ssim_workspace_bytes(n_planes: int, height: int, width: int) -> int:
+    return int(L.load().gs_ssim_workspace_bytes(n_planes, height, width))
+
+
+def ssim_loss_grad(img: torch.Tensor, target: torch.Tensor, dl_dimg: Optional[torch.Tensor] = None,
+                   loss: Optional[torch.Tensor] = None, lam: float = SSIM_LAMBDA, n_norm: Optional[int] = None,
+                   ws: Optional[torch.Tensor] = None):
+    """The Sec. 3.2 training loss (1 - lam) L2 + lam D-SSIM of img against target, both
+    [..., H, W] stacks of planes, and its gradient, on the device. n_norm is the element count
+    the means run over (img.numel() by default; the batch total when views of different
+    sizes are passed one call each). Returns (loss, dl_dimg); loss accumulates (+=)."""
+    _check_f32(img, "img")
+    _check_f32(target, "target")
+    if img.shape != target.shape or img.dim() < 2:
+        raise ValueError("img and target must be [..., H, W] stacks of the same shape")
+    h, w = int(img.shape[-2]), int(img.shape[-1])
+    planes = img.numel() // max(h * w, 1)
+    if dl_dimg is None:
+        dl_dimg = torch.empty_like(img)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=img.device)
+    need = ssim_workspace_bytes(planes, h, w)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=img.device)
+    n = img.numel() if n_norm is None else int(n_norm)
+    L.check(L.load().gs_ssim_loss_grad(_ptr(img), _ptr(target), planes, h, w, n, float(lam), _ptr(dl_dimg),
+                                       _ptr(loss), _ptr(ws), ws.numel(), _stream(img.device)))
+    return loss, dl_dimg
+
+
 def render(g: Gaussians, views: ViewBatch, params=None, subset=None, capacity=None):
     """Plain path: preprocess -> bin_sort (growing the pair buffer if needed) -> render_fwd."""
     proj = preprocess(g, views, params, subset=subset)

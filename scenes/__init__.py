@@ -29,6 +29,7 @@ SEED_GAUSSIANS = 0
 SEED_TARGETS = 1
 SEED_CAMERAS = 2
 SEED_KMEANS = 3
+SEED_IMAGES = 4
 
 
 @dataclass
@@ -212,6 +213,33 @@ def target_images(cams, seed=SEED_TARGETS) -> List[np.ndarray]:
     """U(0,1) target images, planar [3][H][W] float32 per view."""
     rng = np.random.default_rng(seed)
     return [_f32(rng.uniform(0.0, 1.0, (3, c.height, c.width))) for c in cams]
+
+
+def image_pair(n_planes, height, width, seed=SEED_IMAGES):
+    """Render-like image x and target y, [n_planes][height][width] float32 in [0, 1]: smooth
+    low-frequency content (a few random sinusoids), pixel noise, a flat patch (zero local
+    variance) and saturated regions at 0 and 1; y is x with a smooth shift, its own noise and a
+    flat patch of another value."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(height, dtype=np.float64)[:, None]
+    j = np.arange(width, dtype=np.float64)[None, :]
+
+    def smooth():
+        f = np.zeros((height, width))
+        for _ in range(4):
+            ky, kx = rng.uniform(0.01, 0.2, 2)
+            f += rng.uniform(0.1, 0.3) * np.sin(ky * i + kx * j + rng.uniform(0, 2 * np.pi))
+        return f
+
+    x = np.empty((n_planes, height, width))
+    y = np.empty_like(x)
+    for p in range(n_planes):
+        x[p] = 0.5 + smooth() + rng.normal(0.0, 0.05, (height, width))
+        y[p] = x[p] + 0.3 * smooth() + rng.normal(0.0, 0.05, (height, width))
+        h0, w0 = height // 3, width // 3
+        x[p, h0:h0 + max(1, height // 4), w0:w0 + max(1, width // 4)] = 0.25
+        y[p, h0:h0 + max(1, height // 5), w0:w0 + max(1, width // 5)] = 0.75
+    return _f32(np.clip(x, 0.0, 1.0)), _f32(np.clip(y, 0.0, 1.0))
 
 
 # ---------------------------------------------------------------------------------------------

@@ -557,3 +557,85 @@ def test_pruning_unseen_gaussians_keeps_renders_bitwise():
     a = gs.render(g, vb, P)
     b = gs.render(pg, vb, P)
     assert torch.equal(a["rgb"], b["rgb"]) and torch.equal(a["t_final"], b["t_final"])
+
+
+# ----------------------------------------------------------------------------------------------
+# Training loss (1 - lambda) L2 + lambda D-SSIM (Sec. 3.2) against the FP64 oracle.
+# Bars from the FP32 arithmetic: the loss is a sum of O(1) terms with FP32 tile partials, well
+# inside 1e-5 relative. The gradient combines window sums of the SSIM partials, which reach
+# 1 / C2 ~ 1e3 on flat patches, so FP32 cancellation leaves an absolute error that scales with
+# the largest gradient: each element must lie within 1e-3 relative plus 1e-4 of max |g|.
+# ----------------------------------------------------------------------------------------------
+from oracle import loss as OL  # noqa: E402
+
+TOL_LOSS = 1e-5
+
+
+def _grad_close(got, ref):
+    bound = 1e-3 * np.abs(ref) + 1e-4 * np.abs(ref).max()
+    bad = np.abs(got - ref) > bound
+    assert not bad.any(), f"{int(bad.sum())} elements off, worst {np.abs(got - ref).max():.3e}"
+
+
+def _ssim_gpu(x, y, lam=0.2, n_norm=None, loss=None, ws=None):
+    xt, yt = torch.as_tensor(x, device=DEV), torch.as_tensor(y, device=DEV)
+    l, d = gs.ssim_loss_grad(xt, yt, lam=lam, n_norm=n_norm, loss=loss, ws=ws)
+    torch.cuda.synchronize()
+    return l, d.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(3, 37, 150), (2, 16, 64), (1, 5, 7), (1, 1, 1), (3, 70, 9)])
+@pytest.mark.parametrize("lam", [0.2, 0.0, 1.0])
+def test_ssim_loss_matches_oracle(shape, lam):
+    x, y = scenes.image_pair(*shape, seed=sum(shape))
+    _say(f"ssim loss {shape} lam={lam}")
+    l, d = _ssim_gpu(x, y, lam)
+    ref = OL.loss(x, y, lam)
+    assert abs(l.item() - ref) <= TOL_LOSS * abs(ref) + 1e-7
+    _grad_close(d, OL.loss_grad(x, y, lam))
+
+
+def test_ssim_loss_identical_images():
+    x, _ = scenes.image_pair(3, 40, 70, seed=9)
+    _say("ssim loss of identical images")
+    l, d = _ssim_gpu(x, x)
+    assert abs(l.item()) < 1e-6
+    assert np.abs(d).max() < 1e-4 * 1.0 / x.size
+
+
+def test_ssim_loss_views_compose():
+    """A batch of views of different sizes: one call per view with the batch's element count
+    adds up to the oracle's loss of the whole batch; gradients are per view."""
+    a = scenes.image_pair(3, 33, 90, seed=11)
+    b = scenes.image_pair(3, 50, 41, seed=12)
+    n = a[0].size + b[0].size
+    loss = torch.zeros(1, device=DEV)
+    ws = torch.empty(gs.ssim_workspace_bytes(3, 50, 90), dtype=torch.uint8, device=DEV)
+    _say("ssim loss, two views composed")
+    _, da = _ssim_gpu(*a, n_norm=n, loss=loss, ws=ws)
+    _, db = _ssim_gpu(*b, n_norm=n, loss=loss, ws=ws)
+    ref = OL.loss(*a, n=n) + OL.loss(*b, n=n)
+    assert abs(loss.item() - ref) <= TOL_LOSS * ref
+    _grad_close(da, OL.loss_grad(*a, n=n))
+    _grad_close(db, OL.loss_grad(*b, n=n))
+
+
+def test_ssim_loss_full_view():
+    """A 1256 x 828 view (three planes), in the launch configuration the benchmark times: the
+    loss and every element of the gradient against the oracle (about 10 s of FP64 work)."""
+    x, y = scenes.image_pair(3, 828, 1256, seed=13)
+    _say("ssim loss full view")
+    l, d = _ssim_gpu(x, y)
+    ref = OL.loss(x, y)
+    assert abs(l.item() - ref) <= TOL_LOSS * ref
+    _grad_close(d, OL.loss_grad(x, y))
+
+
+def test_ssim_argument_errors():
+    x = torch.zeros((3, 8, 8), device=DEV)
+    with pytest.raises(ValueError):
+        gs.ssim_loss_grad(x, torch.zeros((3, 8, 9), device=DEV))
+    with pytest.raises(gs.GSError, match="lambda"):
+        gs.ssim_loss_grad(x, x.clone(), lam=1.5)
+    with pytest.raises(gs.GSError, match="alias"):
+        gs.ssim_loss_grad(x, x.clone(), dl_dimg=x)

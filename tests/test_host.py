@@ -147,6 +147,28 @@ def test_prune_argument_errors():
     assert lib.gs_prune_mask(None, 10, 0.01, ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
 
 
+def test_ssim_argument_errors():
+    """Argument checks of the loss entry point run on the host before any launch."""
+    lib = gs.load()
+    v = ctypes.c_void_p
+    x, y, d, loss, ws = v(16), v(32), v(48), v(64), v(80)
+    need = lib.gs_ssim_workspace_bytes(3, 20, 30)
+    assert need >= 3 * 3 * 20 * 30 * 4
+    assert lib.gs_ssim_workspace_bytes(0, 20, 30) == 0
+    assert lib.gs_ssim_loss_grad(x, y, 0, 0, 0, 1, 0.2, d, loss, None, 0, None) == L.GS_OK  # nothing to do
+    assert lib.gs_ssim_loss_grad(x, y, 3, 20, 30, 1800, 1.5, d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert b"lambda" in lib.gs_last_error()
+    assert lib.gs_ssim_loss_grad(x, y, 3, 20, 30, 1800, float("nan"), d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_ssim_loss_grad(x, y, 3, 20, 30, 0, 0.2, d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_ssim_loss_grad(x, y, 3, 0, 30, 1800, 0.2, d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_ssim_loss_grad(x, y, 70000, 20, 30, 1800, 0.2, d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_ssim_loss_grad(x, y, 3, 20, 30, 1800, 0.2, x, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+    assert b"alias" in lib.gs_last_error()
+    assert lib.gs_ssim_loss_grad(x, y, 3, 20, 30, 1800, 0.2, d, loss, ws, need - 1, None) == L.GS_ERR_INVALID_ARG
+    assert b"workspace" in lib.gs_last_error()
+    assert lib.gs_ssim_loss_grad(None, y, 3, 20, 30, 1800, 0.2, d, loss, ws, need, None) == L.GS_ERR_INVALID_ARG
+
+
 def test_kmeans_recovers_separated_groups():
     rng = np.random.default_rng(0)
     centres = np.array([[0, 0, 0], [10, 0, 0], [0, 10, 0], [0, 0, 10]], float)
