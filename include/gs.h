@@ -236,8 +236,9 @@ gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, floa
  *   dl_dimg     device [n_planes][height][width], written: dL/dx (must not alias img/target)
  *   loss_accum  device scalar or NULL: *loss_accum += this call's part of L
  *   ws          device workspace of at least gs_ssim_workspace_bytes(n_planes, height, width)
- * Errors: n_planes outside [0, 65535], a non-positive size or n_norm, lambda outside [0, 1],
- * NULL pointers or a short workspace return GS_ERR_INVALID_ARG before anything is enqueued. */
+ * Errors: n_planes outside [0, 65535], a non-positive size or n_norm, a plane of 2^31 pixels
+ * or more, lambda outside [0, 1], NULL pointers, dl_dimg aliasing an input or a short workspace
+ * return GS_ERR_INVALID_ARG before anything is enqueued. */
 size_t gs_ssim_workspace_bytes(int32_t n_planes, int32_t height, int32_t width);
 gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_planes, int32_t height, int32_t width,
                             int64_t n_norm, float lambda, float* dl_dimg, float* loss_accum, void* ws,

@@ -217,6 +217,8 @@ gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_pla
         return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: n_planes must be in [0, 65535]");
     if (n_planes == 0) return GS_OK;
     if (height < 1 || width < 1) return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: height and width must be >= 1");
+    if ((int64_t)height * width > INT32_MAX || width > (INT32_MAX - 128) / 32)
+        return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: a plane must hold fewer than 2^31 pixels");
     if (n_norm < 1) return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: n_norm must be >= 1");
     if (!(lambda >= 0.f && lambda <= 1.f))
         return set_error(GS_ERR_INVALID_ARG, "gs_ssim_loss_grad: lambda must be in [0, 1]");

@@ -16,6 +16,8 @@ namespace gs {
 // ---------------------------------------------------------------------------------------
 gs_status set_error(gs_status code, const char* fmt, ...);
 gs_status check_launch(const char* what);
+// workgroups of a persistent launch of fn: CUs x resident workgroups per CU, at most n_items
+int persistent_grid(const void* fn, int threads, int64_t n_items);
 
 // ---------------------------------------------------------------------------------------
 // wave64 primitives. Every helper must be called with all 64 lanes active.

@@ -46,6 +46,7 @@ struct SsimArgs {
     float* loss;
     int64_t plane;    // H * W
     int32_t h, w, tiles_x, n_tiles, n_planes;
+    int32_t vec;      // rows of 4 pixels are 16-byte aligned in x, y and dl (w % 4 == 0, aligned bases)
     float lam, inv_n;
     float g[ST];      // normalised 1D window
 };
@@ -66,210 +67,303 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(NTH) void k_ssim_stats(SsimArgs a) {
-    __shared__ __align__(16) float2 s_in[IY][IX];
-    __shared__ __align__(16) float s_h[5][IY][SX];
-    __shared__ float red[8];
-    const int tile = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-    const int x0 = (tile % a.tiles_x) * SX, y0 = (tile / a.tiles_x) * SY;
-    const float* __restrict__ xp = a.x + p * a.plane;
-    const float* __restrict__ yp = a.y + p * a.plane;
+// One job = one tile of one plane; jobs are numbered plane-major.
+struct Job {
+    int64_t p;
+    int tile, x0, y0;
+    bool interior;  // the whole input window lies inside the plane
+};
 
-    constexpr int NLD = (IY * IX + NTH - 1) / NTH;
-    float2 v[NLD];
-    float sx = 0.f, sy = 0.f;
+__device__ __forceinline__ Job job_of(const SsimArgs& a, int64_t j) {
+    Job jb;
+    jb.p = j / a.n_tiles;
+    jb.tile = (int)(j - jb.p * a.n_tiles);
+    jb.x0 = (jb.tile % a.tiles_x) * SX;
+    jb.y0 = (jb.tile / a.tiles_x) * SY;
+    jb.interior = jb.x0 >= SR && jb.x0 + SX + SR <= a.w && jb.y0 >= SR && jb.y0 + SY + SR <= a.h;
+    return jb;
+}
+
+constexpr int NLD = (IY * IX + NTH - 1) / NTH;  // window elements per thread
+constexpr int NV = 4 * IX;                       // vertical-pass items: 74 columns x 4 row groups
+constexpr int VX = 76;                           // row stride of the vertical sums in LDS
+
+// window element k of this thread: row r, column c of the IY x IX window
+__device__ __forceinline__ void elem(int k, int& r, int& c) {
+    const int i = threadIdx.x + k * NTH;
+    r = i / IX;
+    c = i - r * IX;
+}
+
+// x and y over a job's input window (zero outside the plane), into registers
+__device__ __forceinline__ void load_window(const SsimArgs& a, const Job& jb, float2 (&v)[NLD]) {
+    const int64_t base = jb.p * a.plane + (int64_t)(jb.y0 - SR) * a.w + (jb.x0 - SR);
+    const float* __restrict__ xp = a.x + base;
+    const float* __restrict__ yp = a.y + base;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-        const int i = tid + k * NTH;
-        const int r = i / IX, c = i - r * IX;
-        const int gy = y0 + r - SR, gx = x0 + c - SR;
+        int r, c;
+        elem(k, r, c);
+        const int o = r * a.w + c;
+        const bool in = (k + 1) * NTH <= IY * IX || r < IY;
         v[k] = make_float2(0.f, 0.f);
-        if (i < IY * IX && gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) {
-            const int64_t o = (int64_t)gy * a.w + gx;
+        if (jb.interior) {
+            if (in) v[k] = make_float2(xp[o], yp[o]);
+        } else if (in && (unsigned)(jb.y0 + r - SR) < (unsigned)a.h && (unsigned)(jb.x0 + c - SR) < (unsigned)a.w) {
             v[k] = make_float2(xp[o], yp[o]);
         }
-        sx += v[k].x, sy += v[k].y;
     }
-    const float2 cs = block_sum2(sx, sy, red);
-    const float cx = cs.x * (1.f / (IY * IX)), cy = cs.y * (1.f / (IY * IX));
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int i = tid + k * NTH;
-        if (i < IY * IX) {
-            const int r = i / IX, c = i - r * IX;
-            s_in[r][c] = make_float2(v[k].x - cx, v[k].y - cy);
-        }
-    }
-    if (tid == 0) a.shift[(int64_t)p * a.n_tiles + tile] = make_float2(cx, cy);
-    __syncthreads();
+}
 
-    // horizontal window sums of x, y, x^2, y^2, xy: four adjacent columns per item
-    for (int it = tid; it < IY * (SX / 4); it += NTH) {
-        const int r = it >> 4, c0 = (it & 15) * 4;
-        float vx[ST + 3], vy[ST + 3];
+// Persistent grid over the jobs; the next job's window is loaded into registers while the
+// current one is computed. Vertical sums first (over the window's 74 columns), then
+// horizontal sums (over the tile's 16 rows): the halo costs 74/64 of the first pass only.
+__global__ __launch_bounds__(NTH) void k_ssim_stats(SsimArgs a) {
+    __shared__ __align__(16) float2 s_in[IY][IX];
+    __shared__ __align__(16) float s_v[5][SY][VX];
+    __shared__ float red[8];
+    const int tid = threadIdx.x;
+    const int64_t n_jobs = (int64_t)a.n_planes * a.n_tiles;
+    const bool vec = a.vec;
+    float2 v[NLD];
+    int64_t j = blockIdx.x;
+    if (j < n_jobs) load_window(a, job_of(a, j), v);
+    for (; j < n_jobs; j += gridDim.x) {
+        const Job jb = job_of(a, j);
+        float sx = 0.f, sy = 0.f;
 #pragma unroll
-        for (int j = 0; j < (ST + 3) / 2; ++j) {
-            const float4 q = *reinterpret_cast<const float4*>(&s_in[r][c0 + 2 * j]);
-            vx[2 * j] = q.x, vy[2 * j] = q.y, vx[2 * j + 1] = q.z, vy[2 * j + 1] = q.w;
+        for (int k = 0; k < NLD; ++k) sx += v[k].x, sy += v[k].y;
+        const float2 cs = block_sum2(sx, sy, red);
+        const float cx = cs.x * (1.f / (IY * IX)), cy = cs.y * (1.f / (IY * IX));
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            int r, c;
+            elem(k, r, c);
+            if ((k + 1) * NTH <= IY * IX || r < IY) s_in[r][c] = make_float2(v[k].x - cx, v[k].y - cy);
         }
-        float o[5][4];
+        if (tid == 0) a.shift[j] = make_float2(cx, cy);
+        __syncthreads();
+        if (j + gridDim.x < n_jobs) load_window(a, job_of(a, j + gridDim.x), v);
+
+        // vertical window sums of x, y, x^2, y^2, xy: one column, four output rows per item
+        for (int it = tid; it < NV; it += NTH) {
+            const int g4 = it / IX, c = it - g4 * IX, r0 = 4 * g4;
+            float vx[ST + 3], vy[ST + 3], pxx[ST + 3], pyy[ST + 3], pxy[ST + 3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float sx = 0.f, sy = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
-#pragma unroll
-            for (int t = 0; t < ST; ++t) {
-                const float gx = a.g[t] * vx[k + t], gy = a.g[t] * vy[k + t];
-                sx += gx, sy += gy;
-                sxx = fmaf(gx, vx[k + t], sxx);
-                syy = fmaf(gy, vy[k + t], syy);
-                sxy = fmaf(gx, vy[k + t], sxy);
+            for (int q = 0; q < ST + 3; ++q) {
+                const float2 e = s_in[r0 + q][c];
+                vx[q] = e.x, vy[q] = e.y, pxx[q] = e.x * e.x, pyy[q] = e.y * e.y, pxy[q] = e.x * e.y;
             }
-            o[0][k] = sx, o[1][k] = sy, o[2][k] = sxx, o[3][k] = syy, o[4][k] = sxy;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float hx = 0.f, hy = 0.f, hxx = 0.f, hyy = 0.f, hxy = 0.f;
+#pragma unroll
+                for (int t = 0; t < ST; ++t) {
+                    hx = fmaf(a.g[t], vx[k + t], hx);
+                    hy = fmaf(a.g[t], vy[k + t], hy);
+                    hxx = fmaf(a.g[t], pxx[k + t], hxx);
+                    hyy = fmaf(a.g[t], pyy[k + t], hyy);
+                    hxy = fmaf(a.g[t], pxy[k + t], hxy);
+                }
+                s_v[0][r0 + k][c] = hx, s_v[1][r0 + k][c] = hy, s_v[2][r0 + k][c] = hxx;
+                s_v[3][r0 + k][c] = hyy, s_v[4][r0 + k][c] = hxy;
+            }
         }
-#pragma unroll
-        for (int m = 0; m < 5; ++m)
-            *reinterpret_cast<float4*>(&s_h[m][r][c0]) = make_float4(o[m][0], o[m][1], o[m][2], o[m][3]);
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // vertical window sums: one column, four rows per thread
-    const int c = tid & 63, r0 = (tid >> 6) * 4;
-    float mom[5][4];
+        // horizontal window sums: one row, four adjacent output columns per thread
+        const int r = tid >> 4, c0 = (tid & 15) * 4;
+        float mom[5][4];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        float v[ST + 3];
+        for (int m = 0; m < 5; ++m) {
+            float w[16];
 #pragma unroll
-        for (int j = 0; j < ST + 3; ++j) v[j] = s_h[m][r0 + j][c];
+            for (int u = 0; u < 4; ++u) {
+                const float4 f4 = *reinterpret_cast<const float4*>(&s_v[m][r][c0 + 4 * u]);
+                w[4 * u] = f4.x, w[4 * u + 1] = f4.y, w[4 * u + 2] = f4.z, w[4 * u + 3] = f4.w;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < ST; ++t) acc = fmaf(a.g[t], w[k + t], acc);
+                mom[m][k] = acc;
+            }
+        }
+
+        float part = 0.f;
+        float out[3][4];
+        const int gy = jb.y0 + r, gx0 = jb.x0 + c0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            float s = 0.f;
-#pragma unroll
-            for (int t = 0; t < ST; ++t) s = fmaf(a.g[t], v[k + t], s);
-            mom[m][k] = s;
-        }
-    }
-
-    float part = 0.f;
-    const int gx = x0 + c;
-    float* __restrict__ m0 = a.maps + p * a.plane;
-    float* __restrict__ m1 = m0 + a.n_planes * a.plane;
-    float* __restrict__ m2 = m1 + a.n_planes * a.plane;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int gy = y0 + r0 + k;
-        if (gx < a.w && gy < a.h) {
             const float ma = mom[0][k], mb = mom[1][k];  // shifted means mu_x - cx, mu_y - cy
             const float vx = mom[2][k] - ma * ma, vy = mom[3][k] - mb * mb, cxy = mom[4][k] - ma * mb;
             const float mx = ma + cx, my = mb + cy;
             const float a1 = 2.f * mx * my + kC1, a2 = 2.f * cxy + kC2;
             const float b1 = mx * mx + my * my + kC1, b2 = vx + vy + kC2;
-            const float rb = 1.f / (b1 * b2);
-            const float s = a1 * a2 * rb;
-            const float beta = -s * b1 * rb;   // -S / b2
+            const float rb = __builtin_amdgcn_rcpf(b1 * b2);
+            const float ss = a1 * a2 * rb;
+            const float beta = -ss * b1 * rb;  // -S / b2
             const float gamma = 2.f * a1 * rb;
             const float delta = 2.f * a2 * rb * (my - mx * a1 * b2 * rb);
-            const float alpha_c = delta - 2.f * ma * beta - mb * gamma;
-            const float2 xy = s_in[SR + r0 + k][SR + c];
-            const float d = (xy.x - xy.y) + (cx - cy);
-            part += (1.f - a.lam) * d * d + a.lam * (1.f - s);
-            const int64_t o = (int64_t)gy * a.w + gx;
-            m0[o] = alpha_c;
-            m1[o] = beta;
-            m2[o] = gamma;
+            out[0][k] = delta - 2.f * ma * beta - mb * gamma;  // alpha_c
+            out[1][k] = beta;
+            out[2][k] = gamma;
+            const float2 e = s_in[SR + r][SR + c0 + k];
+            const float d = (e.x - e.y) + (cx - cy);
+            if (gy < a.h && gx0 + k < a.w) part += (1.f - a.lam) * d * d + a.lam * (1.f - ss);
         }
+        if (gy < a.h) {
+            const int64_t o = jb.p * a.plane + (int64_t)gy * a.w + gx0;
+            const int64_t ms = a.n_planes * a.plane;
+            if (vec && gx0 + 4 <= a.w) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    *reinterpret_cast<float4*>(a.maps + m * ms + o) = make_float4(out[m][0], out[m][1], out[m][2], out[m][3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (gx0 + k < a.w) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) a.maps[m * ms + o + k] = out[m][k];
+                    }
+            }
+        }
+        const float tot = block_sum(part, red);
+        if (tid == 0) a.partial[j] = tot;
+        __syncthreads();  // s_in, s_v and red are rewritten by the next job
     }
-    const float tot = block_sum(part, red);
-    if (tid == 0) a.partial[(int64_t)p * a.n_tiles + tile] = tot;
 }
 
-__global__ __launch_bounds__(NTH) void k_ssim_grad(SsimArgs a) {
-    __shared__ __align__(16) float s_m[3][IY][MX];
-    __shared__ __align__(16) float s_h[3][IY][SX];
-    __shared__ float red[4];
-    const int tile = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-    const int x0 = (tile % a.tiles_x) * SX, y0 = (tile / a.tiles_x) * SY;
-    const int64_t maps_stride = a.n_planes * a.plane;
-    const float* __restrict__ mp = a.maps + p * a.plane;
-    const float2* __restrict__ sh = a.shift + (int64_t)p * a.n_tiles;
-    const float2 cb = sh[tile];
+// the three maps over a job's input window, and the shift of each element's own tile
+struct MapWindow {
+    float m[3][NLD];
+    float2 ca[NLD];
+};
 
-    for (int i = tid; i < IY * IX; i += NTH) {
-        const int r = i / IX, c = i - r * IX;
-        const int gy = y0 + r - SR, gx = x0 + c - SR;
-        float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-        if (gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) {
-            const int64_t o = (int64_t)gy * a.w + gx;
-            v0 = mp[o], v1 = mp[o + maps_stride], v2 = mp[o + 2 * maps_stride];
-            // alpha_c of a halo pixel is centred on its own tile's shift: move it to this tile's
-            const float2 ca = sh[(gy / SY) * a.tiles_x + gx / SX];
-            v0 = fmaf(2.f * (cb.x - ca.x), v1, fmaf(cb.y - ca.y, v2, v0));
+__device__ __forceinline__ void load_maps(const SsimArgs& a, const Job& jb, MapWindow& w) {
+    const int64_t stride = a.n_planes * a.plane;
+    const float* __restrict__ mp = a.maps + jb.p * a.plane + (int64_t)(jb.y0 - SR) * a.w + (jb.x0 - SR);
+    const float2* __restrict__ sh = a.shift + jb.p * a.n_tiles;
+    const float2 cb = sh[jb.tile];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        int r, c;
+        elem(k, r, c);
+        const int o = r * a.w + c;
+        const bool in = ((k + 1) * NTH <= IY * IX || r < IY) &&
+                        (jb.interior || ((unsigned)(jb.y0 + r - SR) < (unsigned)a.h &&
+                                         (unsigned)(jb.x0 + c - SR) < (unsigned)a.w));
+        w.m[0][k] = w.m[1][k] = w.m[2][k] = 0.f;
+        w.ca[k] = cb;
+        if (in) {
+            w.m[0][k] = mp[o], w.m[1][k] = mp[o + stride], w.m[2][k] = mp[o + 2 * stride];
+            // the tile of a halo element: one row / column of tiles away at most
+            const int dty = r < SR ? -1 : (r >= SY + SR ? 1 : 0);
+            const int dtx = c < SR ? -1 : (c >= SX + SR ? 1 : 0);
+            if (dty | dtx) w.ca[k] = sh[jb.tile + dty * a.tiles_x + dtx];
         }
-        s_m[0][r][c] = v0, s_m[1][r][c] = v1, s_m[2][r][c] = v2;
     }
-    __syncthreads();
+}
 
-    for (int it = tid; it < IY * (SX / 4); it += NTH) {
-        const int r = it >> 4, c0 = (it & 15) * 4;
+// LDS holds the maps window, then the vertical sums; the horizontal sums stay in registers.
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_ssim_grad(SsimArgs a) {
+    __shared__ float s_m[3][IY][IX];
+    __shared__ __align__(16) float s_v[3][SY][VX];
+    __shared__ float red[4];
+    const int tid = threadIdx.x;
+    const int64_t n_jobs = (int64_t)a.n_planes * a.n_tiles;
+    const bool vec = a.vec;
+    MapWindow w;
+    int64_t j = blockIdx.x;
+    if (j < n_jobs) load_maps(a, job_of(a, j), w);
+    for (; j < n_jobs; j += gridDim.x) {
+        const Job jb = job_of(a, j);
+        const float2 cb = a.shift[j];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            int r, c;
+            elem(k, r, c);
+            if ((k + 1) * NTH <= IY * IX || r < IY) {
+                // alpha_c of a halo element is centred on its own tile's shift: move it to this tile's
+                s_m[0][r][c] = fmaf(2.f * (cb.x - w.ca[k].x), w.m[1][k], fmaf(cb.y - w.ca[k].y, w.m[2][k], w.m[0][k]));
+                s_m[1][r][c] = w.m[1][k];
+                s_m[2][r][c] = w.m[2][k];
+            }
+        }
+        __syncthreads();
+        if (j + gridDim.x < n_jobs) load_maps(a, job_of(a, j + gridDim.x), w);
+
+        for (int it = tid; it < NV; it += NTH) {
+            const int g4 = it / IX, c = it - g4 * IX, r0 = 4 * g4;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                float vv[ST + 3];
+#pragma unroll
+                for (int q = 0; q < ST + 3; ++q) vv[q] = s_m[m][r0 + q][c];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int t = 0; t < ST; ++t) acc = fmaf(a.g[t], vv[k + t], acc);
+                    s_v[m][r0 + k][c] = acc;
+                }
+            }
+        }
+        __syncthreads();
+
+        const int r = tid >> 4, c0 = (tid & 15) * 4;
+        float w3[3][4];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            float v[16];
+            float vv[16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 q = *reinterpret_cast<const float4*>(&s_m[m][r][c0 + 4 * j]);
-                v[4 * j] = q.x, v[4 * j + 1] = q.y, v[4 * j + 2] = q.z, v[4 * j + 3] = q.w;
+            for (int u = 0; u < 4; ++u) {
+                const float4 f4 = *reinterpret_cast<const float4*>(&s_v[m][r][c0 + 4 * u]);
+                vv[4 * u] = f4.x, vv[4 * u + 1] = f4.y, vv[4 * u + 2] = f4.z, vv[4 * u + 3] = f4.w;
             }
-            float o[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                float s = 0.f;
+                float acc = 0.f;
 #pragma unroll
-                for (int t = 0; t < ST; ++t) s = fmaf(a.g[t], v[k + t], s);
-                o[k] = s;
+                for (int t = 0; t < ST; ++t) acc = fmaf(a.g[t], vv[k + t], acc);
+                w3[m][k] = acc;
             }
-            *reinterpret_cast<float4*>(&s_h[m][r][c0]) = make_float4(o[0], o[1], o[2], o[3]);
         }
-    }
-    __syncthreads();
 
-    const int c = tid & 63, r0 = (tid >> 6) * 4;
-    float w3[3][4];
+        const int gy = jb.y0 + r, gx0 = jb.x0 + c0;
+        const float c_l2 = 2.f * (1.f - a.lam) * a.inv_n, c_s = a.lam * a.inv_n;
+        if (gy < a.h) {
+            const int64_t o = jb.p * a.plane + (int64_t)gy * a.w + gx0;
+            if (vec && gx0 + 4 <= a.w) {
+                const float4 x4 = *reinterpret_cast<const float4*>(a.x + o);
+                const float4 y4 = *reinterpret_cast<const float4*>(a.y + o);
+                const float xv[4] = {x4.x, x4.y, x4.z, x4.w}, yv[4] = {y4.x, y4.y, y4.z, y4.w};
+                float dv[4];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        float v[ST + 3];
+                for (int k = 0; k < 4; ++k) {
+                    const float ds = fmaf(2.f * (xv[k] - cb.x), w3[1][k], fmaf(yv[k] - cb.y, w3[2][k], w3[0][k]));
+                    dv[k] = c_l2 * (xv[k] - yv[k]) - c_s * ds;
+                }
+                *reinterpret_cast<float4*>(a.dl + o) = make_float4(dv[0], dv[1], dv[2], dv[3]);
+            } else {
 #pragma unroll
-        for (int j = 0; j < ST + 3; ++j) v[j] = s_h[m][r0 + j][c];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float s = 0.f;
-#pragma unroll
-            for (int t = 0; t < ST; ++t) s = fmaf(a.g[t], v[k + t], s);
-            w3[m][k] = s;
+                for (int k = 0; k < 4; ++k)
+                    if (gx0 + k < a.w) {
+                        const float xv = a.x[o + k], yv = a.y[o + k];
+                        const float ds = fmaf(2.f * (xv - cb.x), w3[1][k], fmaf(yv - cb.y, w3[2][k], w3[0][k]));
+                        a.dl[o + k] = c_l2 * (xv - yv) - c_s * ds;
+                    }
+            }
         }
-    }
-
-    const int gx = x0 + c;
-    const float* __restrict__ xp = a.x + p * a.plane;
-    const float* __restrict__ yp = a.y + p * a.plane;
-    float* __restrict__ dp = a.dl + p * a.plane;
-    const float c_l2 = 2.f * (1.f - a.lam) * a.inv_n, c_s = a.lam * a.inv_n;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int gy = y0 + r0 + k;
-        if (gx < a.w && gy < a.h) {
-            const int64_t o = (int64_t)gy * a.w + gx;
-            const float xv = xp[o], yv = yp[o];
-            const float ds = fmaf(2.f * (xv - cb.x), w3[1][k], fmaf(yv - cb.y, w3[2][k], w3[0][k]));
-            dp[o] = c_l2 * (xv - yv) - c_s * ds;
-        }
+        __syncthreads();  // s_m and s_v are rewritten by the next job
     }
 
-    // workgroup (0, 0): the loss, from the first launch's tile partials in a fixed order
-    if (tile == 0 && p == 0 && a.loss) {
-        const int64_t n_part = (int64_t)a.n_planes * a.n_tiles;
-        float s = 0.f;
-        for (int64_t i = tid; i < n_part; i += NTH) s += a.partial[i];
-        __syncthreads();
-        const float tot = block_sum(s, red);
+    // workgroup 0: the loss, from the first launch's tile partials in a fixed order
+    if (blockIdx.x == 0 && a.loss) {
+        float acc = 0.f;
+        for (int64_t i = tid; i < n_jobs; i += NTH) acc += a.partial[i];
+        const float tot = block_sum(acc, red);
         if (tid == 0) atomicAdd(a.loss, tot * a.inv_n);
     }
 }
@@ -297,6 +391,8 @@ gs_status launch_ssim_loss_grad(const float* img, const float* target, int32_t n
     a.n_planes = n_planes;
     a.lam = lam;
     a.inv_n = (float)(1.0 / (double)n_norm);
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    a.vec = (w % 4 == 0) && al16(img) && al16(target) && al16(dl);
     const size_t maps = 3 * sizeof(float) * (size_t)n_planes * (size_t)a.plane;
     const size_t tiles = (size_t)a.n_tiles * (size_t)n_planes;
     a.maps = static_cast<float*>(ws);
@@ -309,11 +405,13 @@ gs_status launch_ssim_loss_grad(const float* img, const float* target, int32_t n
         sum += g[t];
     }
     for (int t = 0; t < ST; ++t) a.g[t] = (float)(g[t] / sum);
-    const dim3 grid((unsigned)a.n_tiles, (unsigned)n_planes);
-    hipLaunchKernelGGL(k_ssim_stats, grid, dim3(NTH), 0, s, a);
+    const int64_t n_jobs = (int64_t)a.n_tiles * n_planes;
+    const int grid_a = persistent_grid(reinterpret_cast<const void*>(k_ssim_stats), NTH, n_jobs);
+    const int grid_b = persistent_grid(reinterpret_cast<const void*>(k_ssim_grad), NTH, n_jobs);
+    hipLaunchKernelGGL(k_ssim_stats, dim3(grid_a), dim3(NTH), 0, s, a);
     gs_status st = check_launch("ssim_loss_grad (statistics)");
     if (st != GS_OK) return st;
-    hipLaunchKernelGGL(k_ssim_grad, grid, dim3(NTH), 0, s, a);
+    hipLaunchKernelGGL(k_ssim_grad, dim3(grid_b), dim3(NTH), 0, s, a);
     return check_launch("ssim_loss_grad (gradient)");
 }
 

@@ -532,7 +532,7 @@ gs_status launch_l1(const float* rgb, const float* tgt, int64_t n, float scale, 
 // workgroups of a persistent launch: CUs x resident workgroups of this kernel per CU. The
 // device queries run on the first launch of each kernel on each device and are cached, so
 // later launches (for instance inside a captured graph) make no runtime query.
-static int persistent_grid(const void* fn, int threads, int n_tiles) {
+int persistent_grid(const void* fn, int threads, int64_t n_tiles) {
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, int> cache;
     int dev = 0;
@@ -552,7 +552,7 @@ static int persistent_grid(const void* fn, int threads, int n_tiles) {
         std::lock_guard<std::mutex> lock(mu);
         cache[{fn, dev}] = slots;
     }
-    return std::max(1, std::min(n_tiles, slots));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, slots));
 }
 
 template <typename K>

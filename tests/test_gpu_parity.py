@@ -584,7 +584,7 @@ def _ssim_gpu(x, y, lam=0.2, n_norm=None, loss=None, ws=None):
     return l, d.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("shape", [(3, 37, 150), (2, 16, 64), (1, 5, 7), (1, 1, 1), (3, 70, 9)])
+@pytest.mark.parametrize("shape", [(3, 37, 150), (2, 16, 64), (1, 5, 7), (1, 1, 1), (3, 70, 9), (2, 53, 132)])
 @pytest.mark.parametrize("lam", [0.2, 0.0, 1.0])
 def test_ssim_loss_matches_oracle(shape, lam):
     x, y = scenes.image_pair(*shape, seed=sum(shape))
@@ -593,6 +593,24 @@ def test_ssim_loss_matches_oracle(shape, lam):
     ref = OL.loss(x, y, lam)
     assert abs(l.item() - ref) <= TOL_LOSS * abs(ref) + 1e-7
     _grad_close(d, OL.loss_grad(x, y, lam))
+
+
+def test_ssim_loss_unaligned_buffers():
+    """Width a multiple of 4 but buffers 4 bytes off a 16-byte boundary: the scalar path."""
+    x, y = scenes.image_pair(2, 40, 68, seed=15)
+    n = x.size
+    xb = torch.zeros(n + 1, device=DEV)
+    yb = torch.zeros(n + 1, device=DEV)
+    db = torch.zeros(n + 1, device=DEV)
+    xb[1:] = torch.as_tensor(x.reshape(-1), device=DEV)
+    yb[1:] = torch.as_tensor(y.reshape(-1), device=DEV)
+    xt, yt, dt = xb[1:].view(2, 40, 68), yb[1:].view(2, 40, 68), db[1:].view(2, 40, 68)
+    _say("ssim loss, unaligned buffers")
+    l, _ = gs.ssim_loss_grad(xt, yt, dl_dimg=dt)
+    torch.cuda.synchronize()
+    assert abs(l.item() - OL.loss(x, y)) <= TOL_LOSS * OL.loss(x, y)
+    _grad_close(dt.cpu().numpy().astype(np.float64), OL.loss_grad(x, y))
+    assert db[0].item() == 0.0
 
 
 def test_ssim_loss_identical_images():
