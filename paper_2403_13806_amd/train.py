@@ -1,5 +1,7 @@
-"""Batched training step (forward + L1 loss + backward over many views of uneven size) as
-one captured hipGraph, and the autotuner that picks its launch configuration.
+"""Batched training step (forward + loss + backward over many views of uneven size) as
+one captured hipGraph, and the autotuner that picks its launch configuration. The loss is
+L1 (loss="l1") or the Sec. 3.2 training loss 0.8 L2 + 0.2 D-SSIM (loss="l2_dssim", one
+gs_ssim_loss_grad call per view with the batch's element count, sharing one workspace).
 
   StepConfig      tile size, batch depth (records staged per lane) and persistent launch
   FwdBwdStep      preallocated buffers, an eager step, capture into a hipGraph, replay
@@ -21,7 +23,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from .splat import Gaussians, Renderer, ViewBatch, l1_loss_grad
+from .splat import SSIM_LAMBDA, Gaussians, Renderer, ViewBatch, l1_loss_grad, ssim_loss_grad, ssim_workspace_bytes
 
 
 @dataclass(frozen=True)
@@ -45,13 +47,19 @@ def zero_grads(g: Gaussians) -> Gaussians:
                      torch.zeros_like(g.opacity), torch.zeros_like(g.sh), g.sh_degree)
 
 
+LOSSES = ("l1", "l2_dssim")
+
+
 class FwdBwdStep:
-    """Forward, L1 loss against per-view targets, and backward for a batch of views."""
+    """Forward, loss against per-view targets, and backward for a batch of views."""
 
     def __init__(self, g: Gaussians, cams: Sequence, targets: Sequence, params=None, cfg: StepConfig = StepConfig(),
-                 capacity: Optional[int] = None, device=None):
+                 capacity: Optional[int] = None, device=None, loss: str = "l1"):
+        if loss not in LOSSES:
+            raise ValueError(f"loss must be one of {LOSSES}")
         dev = torch.device(device if device is not None else "cuda")
         self.cfg = cfg
+        self.loss_kind = loss
         self.views = ViewBatch(cams, cfg.tile, dev, cfg.batch_depth, cfg.persistent)
         self.r = Renderer(g, self.views, params, capacity)
         self.target = self.views.pack_images(targets)
@@ -60,13 +68,27 @@ class FwdBwdStep:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self._npx3 = self.target.numel()
+        self._planes = []
+        self.ws = None
+        if loss == "l2_dssim":
+            need = 1
+            for v, (w, h) in enumerate(self.views.sizes):
+                o = 3 * int(self.views.pixel_offset_host[v])
+                self._planes.append((o, o + 3 * w * h, (3, h, w)))
+                need = max(need, ssim_workspace_bytes(3, h, w))
+            self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
     def enqueue(self):
         """Enqueue one step on the current stream (no allocation, no host synchronisation)."""
         for t in (self.grad.mean, self.grad.scale, self.grad.quat, self.grad.opacity, self.grad.sh, self.loss):
             t.zero_()
         rgb = self.r.forward()
-        l1_loss_grad(rgb[:self._npx3], self.target, self.dl, self.loss)
+        if self.loss_kind == "l1":
+            l1_loss_grad(rgb[:self._npx3], self.target, self.dl, self.loss)
+        else:
+            for a, b, shape in self._planes:
+                ssim_loss_grad(rgb[a:b].view(shape), self.target[a:b].view(shape), self.dl[a:b].view(shape),
+                               self.loss, SSIM_LAMBDA, self._npx3, self.ws)
         self.r.backward(self.dl, self.grad)
 
     def capture(self, warmup: int = 2):

@@ -451,6 +451,47 @@ def test_graph_replay_matches_eager():
     assert step.ok()
 
 
+def test_training_step_with_paper_loss():
+    """The step with the Sec. 3.2 loss over views of uneven size: the loss word and dL/d(image)
+    match the oracle's loss of the whole batch on the step's own render, the Gaussian gradients
+    match a reverse call fed that same dL/d(image), and a captured graph replays it."""
+    from paper_2403_13806_amd.train import FwdBwdStep, StepConfig, zero_grads
+    sc = scenes.mixture_scene(20000, seed=9, sh_degree=3)
+    cams = scenes.uneven_views([(64, 48), (126, 83), (160, 106)])
+    tg = scenes.target_images(cams)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("training step, L2 + D-SSIM")
+    step = FwdBwdStep(g, cams, tg, P, StepConfig(16, 16, 1, False), device=DEV, loss="l2_dssim")
+    step.run()
+    torch.cuda.synchronize()
+    n = 3 * step.views.n_pixels
+    ref_loss, ref_dl = 0.0, []
+    for v, c in enumerate(cams):
+        img = step.views.image(step.r.rgb, v).cpu().numpy().astype(np.float64)
+        ref_loss += OL.loss(img, tg[v], n=n)
+        ref_dl.append(OL.loss_grad(img, tg[v], n=n))
+    assert abs(step.loss.item() - ref_loss) <= TOL_LOSS * ref_loss
+    for v in range(len(cams)):
+        _grad_close(step.views.image(step.dl, v).cpu().numpy().astype(np.float64), ref_dl[v])
+    grad = zero_grads(g)
+    step.r.backward(step.dl, grad)
+    torch.cuda.synchronize()
+    ref_g = [t.clone() for t in (grad.mean, grad.scale, grad.quat, grad.opacity, grad.sh)]
+    for a, b in zip((step.grad.mean, step.grad.scale, step.grad.quat, step.grad.opacity, step.grad.sh), ref_g):
+        assert torch.linalg.norm(a - b) <= 1e-5 * torch.linalg.norm(b) + 1e-12
+    ref_rgb, ref_l = step.r.rgb.clone(), float(step.loss.item())
+    cap = FwdBwdStep(g, cams, tg, P, StepConfig(16, 16, 1, False), device=DEV, loss="l2_dssim").capture()
+    for rep in range(3):
+        cap.run()
+        torch.cuda.synchronize()
+        assert torch.equal(cap.r.rgb, ref_rgb), rep
+        assert abs(float(cap.loss.item()) - ref_l) <= 1e-6 * ref_l, rep
+        for a, b in zip((cap.grad.mean, cap.grad.scale, cap.grad.quat, cap.grad.opacity, cap.grad.sh), ref_g):
+            assert torch.linalg.norm(a - b) <= 1e-5 * torch.linalg.norm(b) + 1e-12, rep
+        step.run()
+        torch.cuda.synchronize()
+
+
 def test_autotune_picks_a_valid_config(tmp_path, monkeypatch):
     from paper_2403_13806_amd.train import StepConfig, autotune
     monkeypatch.setenv("GS_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
