@@ -494,7 +494,8 @@ def importance_pass(torch, gs, scenes, P, dev, chunk=10):
 def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, extra=32):
     """Test-time visibility filtering at house scale: 5M Gaussians in 12 rooms, 640 training
     cameras at 1920x1080 clustered into 64 by k-means, per-cluster lists at h > t_cluster, a
-    300-frame 1920x1080 path rendered with and without the lists."""
+    300-frame 1920x1080 path rendered without the lists, with them (gathered by index), and
+    from the lists materialised as compact per-cluster copies (bitwise the same frames)."""
     from paper_2403_13806_amd.splat import PathRenderer
     log(f"house: {n} Gaussians, 640 training views + {extra} random views per cluster, k={k}, "
         f"t_cluster={t_cluster}")
@@ -511,15 +512,24 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
     sizes = np.array([int(x.shape[0]) for x in vf.lists])
     frame_lists = [vf.list_for(c) for c in path]
     pr = PathRenderer(g, path, P, device=dev, max_entries=g.n)
+    # the lists materialised as compact per-cluster copies (memory for coalesced loads)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vf.materialize()
+    torch.cuda.synchronize()
+    t_mat = time.perf_counter() - t0
+    frame_copies = [vf.copy_for(c) for c in path]
     # unfiltered and filtered frame rates over the whole path
     rates, imgs = {}, {}
-    for name, lists in (("unfiltered", [None] * len(path)), ("filtered", frame_lists)):
+    for name, lists, copies in (("unfiltered", [None] * len(path), [None] * len(path)),
+                                ("filtered", frame_lists, [None] * len(path)),
+                                ("filtered_materialized", [None] * len(path), frame_copies)):
         for f in range(3):
-            pr.frame(f, lists[f])
+            pr.frame(f, lists[f], copies[f])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for f in range(len(path)):
-            pr.frame(f, lists[f])
+            pr.frame(f, lists[f], copies[f])
         torch.cuda.synchronize()
         rates[name] = len(path) / (time.perf_counter() - t0)
     # validation pass (untimed): capacity, and filtered vs unfiltered image difference
@@ -529,6 +539,7 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
         assert pr.ok()
         b = pr.frame(f, frame_lists[f]).clone()
         assert pr.ok()
+        assert torch.equal(b, pr.frame(f, g=frame_copies[f])) and pr.ok()
         d = (a - b).abs()
         maxd = max(maxd, float(d.max()))
         mse = float((d * d).mean())
@@ -538,9 +549,13 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
            "list_size_mean": float(sizes.mean()), "list_size_max": int(sizes.max()),
            "unfiltered_fps": rates["unfiltered"], "filtered_fps": rates["filtered"],
            "speedup": rates["filtered"] / rates["unfiltered"],
+           "filtered_materialized_fps": rates["filtered_materialized"],
+           "speedup_materialized": rates["filtered_materialized"] / rates["unfiltered"],
+           "materialize_s": t_mat, "materialized_bytes": vf.copy_bytes(),
            "filtered_vs_unfiltered_max_abs": maxd, "filtered_vs_unfiltered_psnr_min": float(min(psnr))}
     log(f"  lists mean {sizes.mean():.0f}; unfiltered {rates['unfiltered']:.0f} fps, filtered "
-        f"{rates['filtered']:.0f} fps; max |diff| {maxd:.3g}, min PSNR {min(psnr):.1f} dB")
+        f"{rates['filtered']:.0f} fps, filtered from materialised copies {rates['filtered_materialized']:.0f} fps "
+        f"({vf.copy_bytes() / 1e9:.2f} GB, built in {t_mat:.2f} s); max |diff| {maxd:.3g}, min PSNR {min(psnr):.1f} dB")
     return out
 
 

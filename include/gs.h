@@ -290,6 +290,17 @@ gs_status gs_prune_mask(const float* h, int64_t n, float t_prune, uint8_t* mask,
 gs_status gs_prune(const float* h, int64_t n, float t_prune, const float* const* planes_in, float* const* planes_out,
                    int32_t n_planes, int32_t* kept, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream);
 
+/* Gather of per-Gaussian planes by an index list: planes_out[p][k] = planes_in[p][index[k]]
+ * for k < n_index (host arrays of n_planes device pointers; index is a device int32 list).
+ * It materialises a Gaussian subset, for example a camera cluster's visibility list
+ * (Sec. 3.4), as compact planes: a render of the compact copy reads coalesced rows instead of
+ * gathering, and when the list is increasing it keeps the subset's order, so the render is the
+ * same as that of the subset. Indices outside [0, n_src) read nothing and give 0. Output
+ * planes must hold n_index floats and must not alias an input plane. Errors: negative counts,
+ * NULL pointers, aliasing (GS_ERR_INVALID_ARG), n_index or n_src >= 2^31 (GS_ERR_UNSUPPORTED). */
+gs_status gs_gather(const int32_t* index, int64_t n_index, int64_t n_src, const float* const* planes_in,
+                    float* const* planes_out, int32_t n_planes, void* stream);
+
 /* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
  * iterations from a k-means++ seeding with the given seed, at most max_iter iterations
  * or until assignments stop changing; ties go to the lowest centre; an empty cluster is

@@ -40,6 +40,7 @@ size_t prune_workspace_bytes(int64_t n);
 gs_status launch_prune_mask(const float*, int64_t, float, uint8_t*, hipStream_t);
 gs_status launch_prune(const float*, int64_t, float, const float* const*, float* const*, int32_t, int32_t*, int64_t*,
                        void*, size_t, hipStream_t);
+gs_status launch_gather(const int32_t*, int64_t, int64_t, const float* const*, float* const*, int32_t, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
 gs_status launch_render_fwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*, float*,
                             uint32_t*, uint32_t*, hipStream_t);
@@ -319,6 +320,23 @@ gs_status gs_prune(const float* h, int64_t n, float t_prune, const float* const*
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
     return launch_prune(h, n, t_prune, planes_in, planes_out, n_planes, kept, n_kept, ws, prune_workspace_bytes(n),
                         (hipStream_t)stream);
+}
+
+gs_status gs_gather(const int32_t* index, int64_t n_index, int64_t n_src, const float* const* planes_in,
+                    float* const* planes_out, int32_t n_planes, void* stream) {
+    if (n_index < 0 || n_src < 0 || n_planes < 0 || (n_index > 0 && !index) ||
+        (n_planes > 0 && (!planes_in || !planes_out)))
+        return set_error(GS_ERR_INVALID_ARG, "gs_gather: bad arguments");
+    if (n_index >= ((int64_t)1 << 31) || n_src >= ((int64_t)1 << 31))
+        return set_error(GS_ERR_UNSUPPORTED, "gs_gather: at most 2^31-1 entries");
+    for (int p = 0; p < n_planes; ++p) {
+        if (n_index > 0 && (!planes_in[p] || !planes_out[p]))
+            return set_error(GS_ERR_INVALID_ARG, "gs_gather: plane %d is NULL", p);
+        for (int q = 0; q < n_planes; ++q)
+            if (n_index > 0 && planes_out[p] == planes_in[q])
+                return set_error(GS_ERR_INVALID_ARG, "gs_gather: output plane %d aliases input plane %d", p, q);
+    }
+    return launch_gather(index, n_index, n_src, planes_in, planes_out, n_planes, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------------------

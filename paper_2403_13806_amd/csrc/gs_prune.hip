@@ -8,6 +8,8 @@
 //   gather   one lane per kept Gaussian loads its index once and copies that Gaussian's value
 //            of up to 32 planes per launch; writes are coalesced, reads follow the increasing
 //            kept indices
+// The gather alone (gs_gather) also materialises a Gaussian subset, such as a camera cluster's
+// visibility list (Sec. 3.4), as compact planes, so renders of that subset read coalesced rows.
 #include <algorithm>
 
 #include "gs_device.hpp"
@@ -36,14 +38,39 @@ struct PlaneTable {
     int count;
 };
 
-__global__ __launch_bounds__(256) void k_gather_planes(PlaneTable tab, const int32_t* __restrict__ kept,
-                                                       const int64_t* n_kept, int64_t bound) {
+// out[p][k] = in[p][index[k]] for k < min(*n_index, bound) (n_index NULL: k < bound); an index
+// outside [0, n_src) reads nothing and writes 0
+__global__ __launch_bounds__(256) void k_gather_planes(PlaneTable tab, const int32_t* __restrict__ index,
+                                                       const int64_t* n_index, int64_t bound, int64_t n_src) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nk = min(*n_kept, bound);
+    const int64_t nk = n_index ? min(*n_index, bound) : bound;
     if (k >= nk) return;
-    const int64_t i = kept[k];
+    const int64_t i = index[k];
+    const bool ok = i >= 0 && i < n_src;
 #pragma unroll 4
-    for (int p = 0; p < tab.count; ++p) tab.out[p][k] = tab.in[p][i];
+    for (int p = 0; p < tab.count; ++p) tab.out[p][k] = ok ? tab.in[p][i] : 0.f;
+}
+
+static gs_status gather_launches(const float* const* planes_in, float* const* planes_out, int32_t n_planes,
+                                 const int32_t* index, const int64_t* n_index, int64_t bound, int64_t n_src,
+                                 hipStream_t stream) {
+    for (int p0 = 0; p0 < n_planes; p0 += PLANES_PER_LAUNCH) {
+        PlaneTable tab;
+        tab.count = std::min(PLANES_PER_LAUNCH, n_planes - p0);
+        for (int p = 0; p < PLANES_PER_LAUNCH; ++p) {
+            tab.in[p] = p < tab.count ? planes_in[p0 + p] : nullptr;
+            tab.out[p] = p < tab.count ? planes_out[p0 + p] : nullptr;
+        }
+        hipLaunchKernelGGL(k_gather_planes, dim3((unsigned)((bound + 255) / 256)), dim3(256), 0, stream, tab, index,
+                           n_index, bound, n_src);
+    }
+    return check_launch("gather");
+}
+
+gs_status launch_gather(const int32_t* index, int64_t n_index, int64_t n_src, const float* const* planes_in,
+                        float* const* planes_out, int32_t n_planes, hipStream_t stream) {
+    if (n_index == 0 || n_planes == 0) return GS_OK;
+    return gather_launches(planes_in, planes_out, n_planes, index, nullptr, n_index, n_src, stream);
 }
 
 size_t prune_workspace_bytes(int64_t n) {
@@ -60,17 +87,7 @@ gs_status launch_prune(const float* h, int64_t n, float t, const float* const* p
         hipLaunchKernelGGL(k_keep_bits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, h, n, t, bits);
     gs_status st = launch_bits_to_list(bits, n, kept, n_kept, (char*)ws + list_ws_offset, stream);
     if (st || n == 0) return st;
-    for (int p0 = 0; p0 < n_planes; p0 += PLANES_PER_LAUNCH) {
-        PlaneTable tab;
-        tab.count = std::min(PLANES_PER_LAUNCH, n_planes - p0);
-        for (int p = 0; p < PLANES_PER_LAUNCH; ++p) {
-            tab.in[p] = p < tab.count ? planes_in[p0 + p] : nullptr;
-            tab.out[p] = p < tab.count ? planes_out[p0 + p] : nullptr;
-        }
-        hipLaunchKernelGGL(k_gather_planes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, tab, kept, n_kept,
-                           n);
-    }
-    return check_launch("prune");
+    return gather_launches(planes_in, planes_out, n_planes, kept, n_kept, n, n, stream);
 }
 
 }  // namespace gs

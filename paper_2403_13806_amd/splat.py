@@ -358,6 +358,37 @@ def prune_gaussians(g: "Gaussians", h: torch.Tensor, t_prune: float, extra: Sequ
     return pg, kept, out[5:]
 
 
+def gather(index: torch.Tensor, planes: Sequence[torch.Tensor], n_src: Optional[int] = None):
+    """out[..., k] = plane[..., index[k]] for every per-Gaussian FP32 plane (last dimension n_src):
+    compact copies of a Gaussian subset, such as a visibility list (Sec. 3.4). No host
+    synchronisation."""
+    if not (index.is_cuda and index.dtype == torch.int32 and index.is_contiguous() and index.dim() == 1):
+        raise ValueError("index must be a contiguous 1D int32 device tensor")
+    m = index.numel()
+    n = planes[0].shape[-1] if n_src is None else int(n_src)
+    rows_in, outs = [], []
+    for t in planes:
+        _check_f32(t, "plane")
+        if t.shape[-1] != n:
+            raise ValueError(f"plane of shape {tuple(t.shape)} does not end in n = {n}")
+        r = t.reshape(-1, n)
+        rows_in.extend(r[k] for k in range(r.shape[0]))
+        outs.append(torch.empty((*t.shape[:-1], m), dtype=torch.float32, device=index.device))
+    rows_out = [r for o in outs for r in o.reshape(int(np.prod(o.shape[:-1], dtype=np.int64)), m)]
+    vp = ctypes.c_void_p * max(len(rows_in), 1)
+    L.check(L.load().gs_gather(_ptr(index), m, n, vp(*[r.data_ptr() for r in rows_in]),
+                               vp(*[r.data_ptr() for r in rows_out]), len(rows_in), _stream(index.device)))
+    return outs
+
+
+def gather_gaussians(g: "Gaussians", index: torch.Tensor, extra: Sequence[torch.Tensor] = ()):
+    """Compact copy of the Gaussians listed in index (and of any per-Gaussian state in extra).
+    With an increasing index list the copy keeps the subset's order, so its renders equal the
+    renders of the subset."""
+    out = gather(index, [g.mean, g.scale, g.quat, g.opacity, g.sh, *extra], g.n)
+    return Gaussians(out[0], out[1], out[2], out[3], out[4], g.sh_degree), out[5:]
+
+
 def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[int], k: int, t_cluster: float,
                        params=None, bits: Optional[torch.Tensor] = None, capacity=None) -> torch.Tensor:
     """OR into bits [k][ceil(n/32)] the per-cluster indicator lists (eq. importance-score-vis)."""
@@ -562,7 +593,8 @@ class VisibilityFilter:
 
     def __init__(self, g: Gaussians, train_cams: Sequence, k: int = 64, t_cluster: float = 0.001, params=None,
                  chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None,
-                 extra_per_cluster: int = 0, jitter: float = 1.0, max_pitch: float = np.deg2rad(30.0)):
+                 extra_per_cluster: int = 0, jitter: float = 1.0, max_pitch: float = np.deg2rad(30.0),
+                 materialize: bool = False):
         dev = _dev(device)
         self.g, self.k, self.t_cluster, self.params, self.tile, self.device = g, k, t_cluster, params, tile, dev
         pos = np.stack([c.position for c in train_cams])
@@ -589,6 +621,17 @@ class VisibilityFilter:
             vb = ViewBatch(views[c0:c0 + chunk], tile, dev)
             cluster_visibility(g, vb, owner[c0:c0 + chunk], k, t_cluster, params, bits=self.bits)
         self.lists = [bits_to_list(self.bits[c * words:(c + 1) * words], g.n) for c in range(k)]
+        # materialised lists: each cluster's Gaussians copied into compact planes (memory for
+        # coalesced loads: a filtered render then reads rows instead of gathering by index)
+        self.copies = [gather_gaussians(g, lst)[0] for lst in self.lists] if materialize else None
+
+    def materialize(self):
+        if self.copies is None:
+            self.copies = [gather_gaussians(self.g, lst)[0] for lst in self.lists]
+        return self
+
+    def copy_bytes(self) -> int:
+        return 0 if self.copies is None else sum(4 * (11 + c.sh.shape[0]) * c.n for c in self.copies)
 
     def cluster_of(self, cam) -> int:
         return nearest_centre(self.centres, cam.position)
@@ -596,8 +639,15 @@ class VisibilityFilter:
     def list_for(self, cam) -> torch.Tensor:
         return self.lists[self.cluster_of(cam)]
 
+    def copy_for(self, cam) -> "Gaussians":
+        if self.copies is None:
+            raise ValueError("the lists are not materialised (materialize=True or materialize())")
+        return self.copies[self.cluster_of(cam)]
+
     def render(self, cam, capacity=None):
         views = ViewBatch([cam], self.tile, self.device)
+        if self.copies is not None:
+            return render(self.copy_for(cam), views, self.params, capacity=capacity)
         return render(self.g, views, self.params, subset=self.list_for(cam), capacity=capacity)
 
 
@@ -637,17 +687,21 @@ class PathRenderer:
         self.proj.n = n
         return self.proj
 
-    def frame(self, f: int, subset: Optional[torch.Tensor] = None):
-        """Enqueue frame f (optionally with only the listed Gaussians); returns the rgb buffer."""
+    def frame(self, f: int, subset: Optional[torch.Tensor] = None, g: Optional["Gaussians"] = None):
+        """Enqueue frame f (optionally with only the listed Gaussians, or with another set of
+        Gaussians g such as a materialised visibility list); returns the rgb buffer."""
         lib = L.load()
-        n = self.g.n if subset is None else int(subset.shape[0])
+        if g is not None and subset is not None:
+            raise ValueError("pass a subset or a Gaussian set, not both")
+        src = self._sg if g is None else g.struct()
+        n = (self.g.n if g is None else g.n) if subset is None else int(subset.shape[0])
         if n > self.max_entries:
             raise ValueError("subset larger than max_entries")
         sv = self.views.struct()
         sv.cams = ctypes.c_void_p(self.cams_all.data_ptr() + ctypes.sizeof(L.gs_camera) * f)
         sp = self._proj_n(n).struct()
         s = _stream(self.device)
-        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(sv), ctypes.byref(self.p), _ptr(subset), n, 1,
+        L.check(lib.gs_preprocess(ctypes.byref(src), ctypes.byref(sv), ctypes.byref(self.p), _ptr(subset), n, 1,
                                   ctypes.byref(sp), s))
         L.check(lib.gs_bin_sort(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(self._sb), _ptr(self.ws),
                                 self.ws.numel(), s))

@@ -583,6 +583,48 @@ def test_prune_compaction_matches_numpy():
         assert pg.n == int(keep.sum())
 
 
+def test_gather_matches_numpy():
+    """gs_gather copies rows by index bit-exactly (unsorted, repeated, and out-of-range indices,
+    which give 0), for more planes than one launch takes."""
+    rng = np.random.default_rng(22)
+    n = 5003
+    planes = [rng.standard_normal((k, n)).astype(np.float32) for k in (3, 48, 1)]
+    idx = rng.integers(0, n, 2000).astype(np.int32)
+    idx[:5] = [0, n - 1, -1, n, 7]
+    _say("gather")
+    out = gs.gather(torch.as_tensor(idx, device=DEV), [torch.as_tensor(p, device=DEV) for p in planes])
+    ok = (idx >= 0) & (idx < n)
+    for o, p in zip(out, planes):
+        want = np.zeros((p.shape[0], idx.size), np.float32)
+        want[:, ok] = p[:, idx[ok]]
+        assert np.array_equal(o.cpu().numpy(), want)
+    empty = gs.gather(torch.zeros(0, dtype=torch.int32, device=DEV), [torch.as_tensor(planes[0], device=DEV)])
+    assert empty[0].shape == (3, 0)
+
+
+def test_materialized_visibility_lists_render_bitwise():
+    """A cluster's list materialised as compact planes (Sec. 3.4, memory for coalesced loads)
+    renders every path frame bitwise like the list used as a subset of the full set."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    sc = scenes.house_scene(30000, seed=5, sh_degree=3)
+    train = scenes.house_training_views(24, width=96, height=54)
+    path = scenes.house_test_path(12, width=96, height=54)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("materialised visibility lists")
+    vf = gs.VisibilityFilter(g, train, k=4, t_cluster=0.01, params=P, device=DEV, materialize=True)
+    assert vf.copy_bytes() == sum(4 * 59 * int(lst.numel()) for lst in vf.lists)
+    pr = PathRenderer(g, path, P, device=DEV, max_entries=g.n)
+    for f, cam in enumerate(path):
+        a = pr.frame(f, vf.list_for(cam)).clone()
+        assert pr.ok()
+        b = pr.frame(f, g=vf.copy_for(cam)).clone()
+        assert pr.ok()
+        assert torch.equal(a, b), f
+    img = vf.render(path[3])["rgb"]
+    ref = gs.render(g, gs.ViewBatch([path[3]], device=DEV), P, subset=vf.list_for(path[3]))["rgb"]
+    assert torch.equal(img, ref)
+
+
 def test_pruning_unseen_gaussians_keeps_renders_bitwise():
     """The Gaussians with h = 0 over a set of views are never composited in them, so
     removing them (compaction keeps index order, hence every tie-break) leaves each of

@@ -147,6 +147,18 @@ def test_prune_argument_errors():
     assert lib.gs_prune_mask(None, 10, 0.01, ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
 
 
+def test_gather_argument_errors():
+    lib = gs.load()
+    vp = ctypes.c_void_p * 2
+    pin = vp(16, 32)
+    assert lib.gs_gather(ctypes.c_void_p(64), 10, 100, pin, vp(48, 16), 2, None) == L.GS_ERR_INVALID_ARG
+    assert b"aliases" in lib.gs_last_error()
+    assert lib.gs_gather(None, 10, 100, pin, vp(48, 64), 2, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_gather(ctypes.c_void_p(64), -1, 100, pin, vp(48, 80), 2, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_gather(ctypes.c_void_p(64), 1 << 31, 100, pin, vp(48, 80), 2, None) == L.GS_ERR_UNSUPPORTED
+    assert lib.gs_gather(None, 0, 100, pin, vp(48, 80), 2, None) == L.GS_OK  # nothing to do
+
+
 def test_ssim_argument_errors():
     """Argument checks of the loss entry point run on the host before any launch."""
     lib = gs.load()
