@@ -16,7 +16,8 @@ computes and which passage of the paper it follows:
   pairs        the (tile, depth, index) key list the binning step must produce
 
 The training loss of Sec. 3.2 ((1 - lambda) L2 + lambda D-SSIM) and its gradient are in
-``oracle.loss`` (numpy, FP64).
+``oracle.loss`` (numpy, FP64); the initialisation of Sec. 3.2 (nearest-neighbour scales,
+opacity, rotation and DC colour of one Gaussian per point) is in ``oracle.init``.
 """
 from __future__ import annotations
 
