@@ -234,6 +234,7 @@ def main():
              "copy_256MiB_GBps": copy_gbps}
     extra["prune"] = prune_pass(torch, gs, g, h_buf, dev)
     extra["loss_l2_dssim"] = loss_pass(torch, gs, scenes, dev)
+    extra["init_1M_points"] = init_pass(torch, gs, scenes, dev)
 
     if not args.quick:
         extra.update(fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W))
@@ -334,6 +335,24 @@ def loss_pass(torch, gs, scenes, dev, reps=20):
     log(f"loss (L2 + D-SSIM): 3 x 828 x 1256, {ms:.4f} ms, {alg / ms / 1e6:.0f} GB/s algorithmic")
     return {"planes": 3, "height": 828, "width": 1256, "ms": ms, "alg_bytes": alg,
             "alg_GBps": alg / ms / 1e6, "hbm_frac": alg / ms / 1e-3 / PEAK_HBM}
+
+
+def init_pass(torch, gs, scenes, dev, reps=5):
+    """Initialisation of the point representation (Sec. 3.2) from 1M points (the means of the
+    house scene: mostly on walls and floors, storage order random): exact nearest-neighbour
+    scales on the cell grid plus the constant parameters."""
+    sc = scenes.house_scene(1_000_000, seed=6, sh_degree=0)
+    pts = torch.as_tensor(np.ascontiguousarray(sc.mean), device=dev)
+    col = torch.rand((3, pts.shape[1]), device=dev)
+    gs.init_gaussians(pts, col, 3)
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(reps):
+            g = gs.init_gaussians(pts, col, 3)
+    ms = tm.ms() / reps
+    log(f"init: 1M house points, {ms:.3f} ms (nearest-neighbour scales + constants)")
+    return {"points": int(pts.shape[1]), "ms": ms, "points_per_s": pts.shape[1] / ms * 1e3,
+            "median_scale": float(g.scale[0].median().item())}
 
 
 def calib_copy(torch, dev, nbytes=256 << 20, reps=5):

@@ -301,6 +301,31 @@ gs_status gs_prune(const float* h, int64_t n, float t_prune, const float* const*
 gs_status gs_gather(const int32_t* index, int64_t n_index, int64_t n_src, const float* const* planes_in,
                     float* const* planes_out, int32_t n_planes, void* stream);
 
+/* Initialisation of the point representation from a point set P (Sec. 3.2), whose points
+ * the caller provides (the paper draws them from a radiance field's median depths).
+ * gs_nn_distance: dist[i] = min over p in P, p != p_i of ||p_i - p||_2, the isotropic scale
+ * the paper gives each initial Gaussian. points is device [3][n] (the layout of
+ * gs_gaussians.mean). Coincident copies of p_i are not neighbours; with no point at another
+ * position dist[i] = +inf; a point with a non-finite coordinate gets NaN and is no one's
+ * neighbour. Exact: squared distances in FP64 from the FP32 coordinates, (dx^2 + dy^2) + dz^2
+ * without fused multiply-add, the square root rounded to FP32 once. Uniform cell grid
+ * (about one cell per point over the bounding box) searched in rings of cells around each
+ * point; the work grows with the distance to the nearest point in cells, so isolated points
+ * far from all others are slow.
+ *   ws  device workspace of at least gs_nn_workspace_bytes(n)
+ * gs_init_gaussians: the same distances as scale (s, s, s), mean = points, quat = (1, 0, 0, 0),
+ * opacity = 0.1, SH DC coefficient of channel c = (colour_c - 1/2) / Y_00 (so the colour
+ * model returns the given colour; colours device [3][n] or NULL for 1/2), all other SH 0.
+ * Outputs in the layout of gs_gaussians for sh_degree 0..3, written; they must not alias
+ * points or colours.
+ * Errors: n < 0, NULL pointers, aliasing, a short workspace (GS_ERR_INVALID_ARG),
+ * n >= 2^31 or sh_degree outside 0..3 (GS_ERR_UNSUPPORTED). */
+size_t gs_nn_workspace_bytes(int64_t n);
+gs_status gs_nn_distance(const float* points, int64_t n, float* dist, void* ws, size_t ws_bytes, void* stream);
+gs_status gs_init_gaussians(const float* points, const float* colours, int64_t n, int32_t sh_degree, float* mean,
+                            float* scale, float* quat, float* opacity, float* sh, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
  * iterations from a k-means++ seeding with the given seed, at most max_iter iterations
  * or until assignments stop changing; ties go to the lowest centre; an empty cluster is

@@ -65,7 +65,7 @@ SPLAT_BYTES = 64
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_nearest_centre",
            "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
-           "gs_gather", "gs_last_error"]
+           "gs_gather", "gs_nn_workspace_bytes", "gs_nn_distance", "gs_init_gaussians", "gs_last_error"]
 
 _lib = None
 
@@ -121,6 +121,13 @@ def load(path: str = LIB_PATH):
     L.gs_prune.restype = i32
     L.gs_gather.argtypes = [c_void_p, i64, i64, P(c_void_p), P(c_void_p), i32, c_void_p]
     L.gs_gather.restype = i32
+    L.gs_nn_workspace_bytes.argtypes = [i64]
+    L.gs_nn_workspace_bytes.restype = ctypes.c_size_t
+    L.gs_nn_distance.argtypes = [c_void_p, i64, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]
+    L.gs_nn_distance.restype = i32
+    L.gs_init_gaussians.argtypes = [c_void_p, c_void_p, i64, i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, ctypes.c_size_t, c_void_p]
+    L.gs_init_gaussians.restype = i32
     L.gs_kmeans.argtypes = [c_void_p, i32, i32, u64, i32, c_void_p, c_void_p]
     L.gs_kmeans.restype = i32
     L.gs_nearest_centre.argtypes = [c_void_p, i32, c_void_p]

@@ -42,6 +42,10 @@ gs_status launch_prune(const float*, int64_t, float, const float* const*, float*
                        void*, size_t, hipStream_t);
 gs_status launch_gather(const int32_t*, int64_t, int64_t, const float* const*, float* const*, int32_t, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
+size_t nn_workspace_bytes(int64_t);
+gs_status launch_nn_distance(const float*, int64_t, float*, void*, hipStream_t);
+gs_status launch_init_gaussians(const float*, const float*, int64_t, int32_t, float*, float*, float*, float*, float*,
+                                void*, hipStream_t);
 gs_status launch_render_fwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*, float*,
                             uint32_t*, uint32_t*, hipStream_t);
 gs_status launch_l1(const float*, const float*, int64_t, float, float*, float*, hipStream_t);
@@ -337,6 +341,39 @@ gs_status gs_gather(const int32_t* index, int64_t n_index, int64_t n_src, const 
                 return set_error(GS_ERR_INVALID_ARG, "gs_gather: output plane %d aliases input plane %d", p, q);
     }
     return launch_gather(index, n_index, n_src, planes_in, planes_out, n_planes, (hipStream_t)stream);
+}
+
+size_t gs_nn_workspace_bytes(int64_t n) { return nn_workspace_bytes(n); }
+
+static gs_status check_nn(const float* points, int64_t n, size_t ws_bytes, const void* ws, const char* who) {
+    if (n < 0 || (n > 0 && !points)) return set_error(GS_ERR_INVALID_ARG, "%s: bad arguments", who);
+    if (n >= ((int64_t)1 << 31)) return set_error(GS_ERR_UNSUPPORTED, "%s: at most 2^31-1 points", who);
+    const size_t need = nn_workspace_bytes(n);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "%s: workspace too small: %zu bytes, need %zu", who, ws_bytes, need);
+    return GS_OK;
+}
+
+gs_status gs_nn_distance(const float* points, int64_t n, float* dist, void* ws, size_t ws_bytes, void* stream) {
+    gs_status st = check_nn(points, n, ws_bytes, ws, "gs_nn_distance");
+    if (st) return st;
+    if (n > 0 && !dist) return set_error(GS_ERR_INVALID_ARG, "gs_nn_distance: dist is NULL");
+    return launch_nn_distance(points, n, dist, ws, (hipStream_t)stream);
+}
+
+gs_status gs_init_gaussians(const float* points, const float* colours, int64_t n, int32_t sh_degree, float* mean,
+                            float* scale, float* quat, float* opacity, float* sh, void* ws, size_t ws_bytes,
+                            void* stream) {
+    gs_status st = check_nn(points, n, ws_bytes, ws, "gs_init_gaussians");
+    if (st) return st;
+    if (sh_degree < 0 || sh_degree > 3)
+        return set_error(GS_ERR_UNSUPPORTED, "gs_init_gaussians: sh_degree must be 0..3");
+    if (n > 0 && (!mean || !scale || !quat || !opacity || !sh))
+        return set_error(GS_ERR_INVALID_ARG, "gs_init_gaussians: NULL output plane");
+    if (n > 0 && (mean == points || (colours && (sh == colours || mean == colours))))
+        return set_error(GS_ERR_INVALID_ARG, "gs_init_gaussians: an output aliases an input");
+    return launch_init_gaussians(points, colours, n, sh_degree, mean, scale, quat, opacity, sh, ws,
+                                 (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -389,6 +389,43 @@ def gather_gaussians(g: "Gaussians", index: torch.Tensor, extra: Sequence[torch.
     return Gaussians(out[0], out[1], out[2], out[3], out[4], g.sh_degree), out[5:]
 
 
+def nn_distance(points: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Distance from each point of points [3][n] to the nearest point at another position
+    (the initial isotropic scale of Sec. 3.2); +inf without such a point."""
+    _check_f32(points, "points")
+    if points.dim() != 2 or points.shape[0] != 3:
+        raise ValueError("points must be [3, n]")
+    n = int(points.shape[1])
+    dist = torch.empty(n, dtype=torch.float32, device=points.device)
+    need = int(L.load().gs_nn_workspace_bytes(n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=points.device)
+    L.check(L.load().gs_nn_distance(_ptr(points), n, _ptr(dist), _ptr(ws), ws.numel(), _stream(points.device)))
+    return dist
+
+
+def init_gaussians(points: torch.Tensor, colours: Optional[torch.Tensor] = None, sh_degree: int = 3) -> "Gaussians":
+    """Gaussians initialised from a point set (Sec. 3.2): mean = points, isotropic scale = the
+    nearest-neighbour distance, identity rotation, opacity 0.1, DC colour = colours [3][n]
+    (1/2 when None), higher SH 0."""
+    _check_f32(points, "points")
+    if points.dim() != 2 or points.shape[0] != 3:
+        raise ValueError("points must be [3, n]")
+    if colours is not None:
+        _check_f32(colours, "colours")
+        if colours.shape != points.shape:
+            raise ValueError("colours must be shaped like points")
+    n, dev = int(points.shape[1]), points.device
+    e = lambda r: torch.empty((r, n), dtype=torch.float32, device=dev)
+    g = Gaussians(e(3), e(3), e(4), torch.empty(n, dtype=torch.float32, device=dev), e((sh_degree + 1) ** 2 * 3),
+                  int(sh_degree))
+    need = int(L.load().gs_nn_workspace_bytes(n))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    L.check(L.load().gs_init_gaussians(_ptr(points), _ptr(colours), n, int(sh_degree), _ptr(g.mean), _ptr(g.scale),
+                                       _ptr(g.quat), _ptr(g.opacity), _ptr(g.sh), _ptr(ws), ws.numel(), _stream(dev)))
+    return g
+
+
 def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[int], k: int, t_cluster: float,
                        params=None, bits: Optional[torch.Tensor] = None, capacity=None) -> torch.Tensor:
     """OR into bits [k][ceil(n/32)] the per-cluster indicator lists (eq. importance-score-vis)."""

@@ -740,3 +740,74 @@ def test_ssim_argument_errors():
         gs.ssim_loss_grad(x, x.clone(), lam=1.5)
     with pytest.raises(gs.GSError, match="alias"):
         gs.ssim_loss_grad(x, x.clone(), dl_dimg=x)
+
+
+# ----------------------------------------------------------------------------------------------
+# Initialisation from a point set (Sec. 3.2): nearest-neighbour scales and constants, bit-exact
+# against the FP64 oracle (same FP64 formula, one rounding to FP32).
+# ----------------------------------------------------------------------------------------------
+from oracle import init as OI  # noqa: E402
+
+
+def _nn_cases():
+    rng = np.random.default_rng(31)
+    cases = {
+        "uniform": rng.uniform(-2, 2, (3, 3000)),
+        "plane": np.vstack([rng.uniform(-2, 2, (2, 2000)), np.zeros((1, 2000))]),
+        "line": np.vstack([rng.uniform(-2, 2, (1, 1000)), np.zeros((2, 1000))]),
+        "clusters": rng.normal(0, 0.05, (3, 2000)) + rng.integers(0, 4, (1, 2000)) * 3.0,
+        "duplicates": np.repeat(rng.uniform(0, 1, (3, 400)), 3, axis=1),
+        "lattice": np.stack(np.meshgrid(*[np.arange(9) * 0.375] * 3, indexing="ij")).reshape(3, -1),
+        "far_offset": rng.uniform(-1, 1, (3, 1500)) + 1000.0,
+        "one": np.zeros((3, 1)),
+        "coincident": np.ones((3, 9)),
+    }
+    return {k: v.astype(np.float32) for k, v in cases.items()}
+
+
+@pytest.mark.parametrize("name", list(_nn_cases()))
+def test_nn_distance_matches_oracle(name):
+    p = _nn_cases()[name]
+    _say(f"nn distance {name} n={p.shape[1]}")
+    got = gs.nn_distance(torch.as_tensor(p, device=DEV)).cpu().numpy()
+    assert np.array_equal(got, OI.nn_distance(p))
+
+
+def test_nn_distance_non_finite_points():
+    rng = np.random.default_rng(32)
+    p = rng.uniform(-1, 1, (3, 700)).astype(np.float32)
+    p[1, 7], p[0, 9], p[2, 11] = np.nan, np.inf, -np.inf
+    fin = np.all(np.isfinite(p), 0)
+    _say("nn distance with non-finite points")
+    got = gs.nn_distance(torch.as_tensor(p, device=DEV)).cpu().numpy()
+    assert np.all(np.isnan(got[~fin]))
+    assert np.array_equal(got[fin], OI.nn_distance(p[:, fin]))
+    assert gs.nn_distance(torch.zeros((3, 0), device=DEV)).numel() == 0
+
+
+def test_nn_distance_1M_surface_points_sampled():
+    """1M points of the house scene (mostly on walls and floors, storage order random): the
+    distances of 300 sampled points against the definition over all 1M points."""
+    sc = scenes.house_scene(1_000_000, seed=6, sh_degree=0)
+    p = np.ascontiguousarray(sc.mean)
+    _say("nn distance, 1M house points")
+    got = gs.nn_distance(torch.as_tensor(p, device=DEV)).cpu().numpy()
+    idx = np.random.default_rng(33).choice(p.shape[1], 300, replace=False)
+    assert np.array_equal(got[idx], OI.nn_distance_at(p, idx))
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+@pytest.mark.parametrize("deg,with_colour", [(3, True), (0, True), (1, False)])
+def test_init_gaussians_matches_oracle(deg, with_colour):
+    rng = np.random.default_rng(34)
+    p = rng.uniform(-3, 3, (3, 2500)).astype(np.float32)
+    c = rng.uniform(0, 1, (3, 2500)).astype(np.float32) if with_colour else None
+    _say(f"init gaussians deg={deg} colour={with_colour}")
+    g = gs.init_gaussians(torch.as_tensor(p, device=DEV), None if c is None else torch.as_tensor(c, device=DEV), deg)
+    want = OI.init_gaussians(p, c, deg)
+    for got, ref in zip((g.mean, g.scale, g.quat, g.opacity, g.sh), want):
+        assert np.array_equal(got.cpu().numpy(), ref)
+    # the initial Gaussians render (every one passes the culls of a view that sees them)
+    cam = scenes.look_at_camera(np.array([0.0, 0.0, -9.0]), np.zeros(3), 96, 64)
+    out = gs.render(g, gs.ViewBatch([cam], device=DEV), P)
+    assert torch.isfinite(out["rgb"]).all()

@@ -159,6 +159,23 @@ def test_gather_argument_errors():
     assert lib.gs_gather(None, 0, 100, pin, vp(48, 80), 2, None) == L.GS_OK  # nothing to do
 
 
+def test_init_argument_errors():
+    lib = gs.load()
+    v = ctypes.c_void_p
+    need = lib.gs_nn_workspace_bytes(1000)
+    assert need >= 16 * 1000 and lib.gs_nn_workspace_bytes(0) == 0
+    assert lib.gs_nn_distance(None, 1000, v(16), v(32), need, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_nn_distance(v(16), 1000, v(48), v(32), need - 1, None) == L.GS_ERR_INVALID_ARG
+    assert b"workspace" in lib.gs_last_error()
+    assert lib.gs_nn_distance(v(16), 1 << 31, v(48), v(32), 1 << 40, None) == L.GS_ERR_UNSUPPORTED
+    assert lib.gs_nn_distance(None, 0, None, None, 0, None) == L.GS_OK
+    outs = [v(64), v(80), v(96), v(112), v(128)]
+    assert lib.gs_init_gaussians(v(16), None, 1000, 4, *outs, v(32), need, None) == L.GS_ERR_UNSUPPORTED
+    assert lib.gs_init_gaussians(v(16), None, 1000, 3, v(16), *outs[1:], v(32), need, None) == L.GS_ERR_INVALID_ARG
+    assert b"alias" in lib.gs_last_error()
+    assert lib.gs_init_gaussians(v(16), None, 1000, 3, None, *outs[1:], v(32), need, None) == L.GS_ERR_INVALID_ARG
+
+
 def test_ssim_argument_errors():
     """Argument checks of the loss entry point run on the host before any launch."""
     lib = gs.load()
