@@ -242,6 +242,7 @@ def main():
         del rs
         extra["importance_150_views"] = importance_pass(torch, gs, scenes, P, dev)
         extra["house_filtering"] = filtered_pass(torch, gs, scenes, P, dev)
+        extra["training_loop"] = trainer_pass(torch, gs, scenes, P, dev, g, cams)
 
     cpu = None
     if not args.no_cpu:
@@ -353,6 +354,48 @@ def init_pass(torch, gs, scenes, dev, reps=5):
     log(f"init: 1M house points, {ms:.3f} ms (nearest-neighbour scales + constants)")
     return {"points": int(pts.shape[1]), "ms": ms, "points_per_s": pts.shape[1] / ms * 1e3,
             "median_scale": float(g.scale[0].median().item())}
+
+
+def trainer_pass(torch, gs, scenes, P, dev, g, cams, steps=20):
+    """The optimisation loop on the 1M-Gaussian scene and its eight 1256x828 views: one drawn
+    view per step, the Sec. 3.2 loss, the fused Adam step over all parameter groups, and one
+    pruning event (importance over the eight views, compaction of parameters and both Adam
+    moments). The Adam step moves 32 bytes per element (parameter, gradient and both moments
+    read; parameter, moments and the cleared gradient written)."""
+    from paper_2403_13806_amd.train import TrainConfig, Trainer
+    g0 = gs.Gaussians(g.mean.clone(), g.scale.clone(), g.quat.clone(), g.opacity.clone(), g.sh.clone(), g.sh_degree)
+    tg = scenes.target_images(cams)
+    cfg = TrainConfig(steps=30000, prune_steps=(), t_prune=0.01)
+    tr = Trainer(g0, cams, tg, P, cfg, device=dev)
+    for _ in range(3):
+        tr.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) / steps * 1e3
+    with Timer(torch) as tm:
+        gs.adam_step(tr.groups(), tr.it + 1, cfg.betas, cfg.eps)
+    adam_ms = tm.ms()
+    n_elem = sum(t[0].numel() for t in tr.groups())
+    t0 = time.perf_counter()
+    tr.prune(0.01)
+    torch.cuda.synchronize()
+    prune_s = time.perf_counter() - t0
+    before, after = tr.history[-1]["before"], tr.history[-1]["after"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    step_ms_after = (time.perf_counter() - t0) / steps * 1e3
+    assert tr.ok()
+    log(f"training loop: {step_ms:.3f} ms/step ({1e3 / step_ms:.0f} steps/s) at {before} Gaussians, Adam "
+        f"{adam_ms:.3f} ms ({32 * n_elem / adam_ms / 1e6:.0f} GB/s over {n_elem} elements); pruning to {after} "
+        f"in {prune_s:.3f} s; then {step_ms_after:.3f} ms/step")
+    return {"gaussians": before, "steps_per_s": 1e3 / step_ms, "ms_per_step": step_ms, "adam_ms": adam_ms,
+            "adam_GBps": 32 * n_elem / adam_ms / 1e6, "adam_hbm_frac": 32 * n_elem / adam_ms / 1e-3 / PEAK_HBM,
+            "prune_event_s": prune_s, "kept": after, "steps_per_s_after_prune": 1e3 / step_ms_after}
 
 
 def calib_copy(torch, dev, nbytes=256 << 20, reps=5):

@@ -326,6 +326,34 @@ gs_status gs_init_gaussians(const float* points, const float* colours, int64_t n
                             float* scale, float* quat, float* opacity, float* sh, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* One Adam step over parameter groups (the optimisation of phi in Sec. 3.2; the paper takes
+ * its optimiser from 3D Gaussian splatting without restating it). Per element of each group,
+ * in the group's parametrisation u of the stored value x:
+ *   GS_ADAM_LINEAR  u = x
+ *   GS_ADAM_LOG     u = log x (x > 0), du = dx * x
+ *   GS_ADAM_LOGIT   u = log(x / (1 - x)), x first clamped to [1e-6, 1 - 1e-6], du = dx x (1 - x)
+ *   m = b1 m + (1 - b1) du,  v = b2 v + (1 - b2) du^2,
+ *   u -= lr (m / (1 - b1^step)) / (sqrt(v) / sqrt(1 - b2^step) + eps),  x = u mapped back;
+ * then grad = 0 when zero_grad is set. The moments and the step are FP32; 1 - b1, 1 - b2 and the
+ * bias corrections are formed in FP64 from the FP64 arguments and rounded once (so b2 = 0.999
+ * does not turn into 1 - fl32(0.999)). param, grad, m and v are device arrays of count floats
+ * each (distinct buffers); step counts from 1. Groups with count 0 are skipped.
+ * Errors: NULL pointers, step < 1, a negative count or an unknown mode (GS_ERR_INVALID_ARG). */
+#define GS_ADAM_LINEAR 0
+#define GS_ADAM_LOG 1
+#define GS_ADAM_LOGIT 2
+typedef struct gs_adam_group {
+    float* param;
+    float* grad;
+    float* m;
+    float* v;
+    int64_t count;
+    float lr;
+    int32_t mode;
+} gs_adam_group;
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, double beta1, double beta2, double eps,
+                       int64_t step, int32_t zero_grad, void* stream);
+
 /* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
  * iterations from a k-means++ seeding with the given seed, at most max_iter iterations
  * or until assignments stop changing; ties go to the lowest centre; an empty cluster is

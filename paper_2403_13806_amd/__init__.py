@@ -5,7 +5,7 @@ this package only marshals PyTorch device buffers into those calls.
 """
 from ._lib import GSError, load  # noqa: F401
 from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, VisibilityFilter,  # noqa: F401
-                    alloc_workspace,
+                    adam_step, alloc_workspace,
                     bin_sort, bits_to_list, cluster_visibility, gather, gather_gaussians, importance, kmeans,
                     init_gaussians, l1_loss_grad, make_params, nearest_centre, nn_distance,
                     preprocess, prune, prune_gaussians, prune_mask, render, render_bwd, render_fwd,

@@ -59,13 +59,21 @@ class gs_bins(ctypes.Structure):
                 ("n_pairs", c_void_p), ("overflow", c_void_p), ("queue", c_void_p)]
 
 
+class gs_adam_group(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p), ("count", i64),
+                ("lr", f32), ("mode", i32)]
+
+
+GS_ADAM_LINEAR, GS_ADAM_LOG, GS_ADAM_LOGIT = 0, 1, 2
+
 assert ctypes.sizeof(gs_camera) == 80
 SPLAT_BYTES = 64
 
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_nearest_centre",
            "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
-           "gs_gather", "gs_nn_workspace_bytes", "gs_nn_distance", "gs_init_gaussians", "gs_last_error"]
+           "gs_gather", "gs_nn_workspace_bytes", "gs_nn_distance", "gs_init_gaussians",
+           "gs_adam_step", "gs_last_error"]
 
 _lib = None
 
@@ -128,6 +136,9 @@ def load(path: str = LIB_PATH):
     L.gs_init_gaussians.argtypes = [c_void_p, c_void_p, i64, i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p, ctypes.c_size_t, c_void_p]
     L.gs_init_gaussians.restype = i32
+    L.gs_adam_step.argtypes = [P(gs_adam_group), i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, i32,
+                               c_void_p]
+    L.gs_adam_step.restype = i32
     L.gs_kmeans.argtypes = [c_void_p, i32, i32, u64, i32, c_void_p, c_void_p]
     L.gs_kmeans.restype = i32
     L.gs_nearest_centre.argtypes = [c_void_p, i32, c_void_p]

@@ -43,6 +43,7 @@ gs_status launch_prune(const float*, int64_t, float, const float* const*, float*
 gs_status launch_gather(const int32_t*, int64_t, int64_t, const float* const*, float* const*, int32_t, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
 size_t nn_workspace_bytes(int64_t);
+gs_status launch_adam(const gs_adam_group*, int32_t, double, double, double, int64_t, int32_t, hipStream_t);
 gs_status launch_nn_distance(const float*, int64_t, float*, void*, hipStream_t);
 gs_status launch_init_gaussians(const float*, const float*, int64_t, int32_t, float*, float*, float*, float*, float*,
                                 void*, hipStream_t);
@@ -374,6 +375,25 @@ gs_status gs_init_gaussians(const float* points, const float* colours, int64_t n
         return set_error(GS_ERR_INVALID_ARG, "gs_init_gaussians: an output aliases an input");
     return launch_init_gaussians(points, colours, n, sh_degree, mean, scale, quat, opacity, sh, ws,
                                  (hipStream_t)stream);
+}
+
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, double beta1, double beta2, double eps,
+                       int64_t step, int32_t zero_grad, void* stream) {
+    if (n_groups < 0 || (n_groups > 0 && !groups) || step < 1)
+        return set_error(GS_ERR_INVALID_ARG, "gs_adam_step: bad arguments");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0))
+        return set_error(GS_ERR_INVALID_ARG, "gs_adam_step: betas must be in [0, 1), eps >= 0");
+    for (int k = 0; k < n_groups; ++k) {
+        const gs_adam_group& g = groups[k];
+        if (g.count < 0 || (g.count > 0 && (!g.param || !g.grad || !g.m || !g.v)))
+            return set_error(GS_ERR_INVALID_ARG, "gs_adam_step: group %d has a NULL buffer or negative count", k);
+        if (g.mode != GS_ADAM_LINEAR && g.mode != GS_ADAM_LOG && g.mode != GS_ADAM_LOGIT)
+            return set_error(GS_ERR_INVALID_ARG, "gs_adam_step: group %d has unknown mode %d", k, g.mode);
+        if (g.count > 0 && (g.param == g.grad || g.param == g.m || g.param == g.v || g.grad == g.m ||
+                            g.grad == g.v || g.m == g.v))
+            return set_error(GS_ERR_INVALID_ARG, "gs_adam_step: group %d buffers alias", k);
+    }
+    return launch_adam(groups, n_groups, beta1, beta2, eps, step, zero_grad, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------------------

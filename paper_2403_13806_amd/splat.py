@@ -426,6 +426,29 @@ def init_gaussians(points: torch.Tensor, colours: Optional[torch.Tensor] = None,
     return g
 
 
+ADAM_MODES = {"linear": L.GS_ADAM_LINEAR, "log": L.GS_ADAM_LOG, "logit": L.GS_ADAM_LOGIT}
+
+
+def adam_step(groups: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor, float, str]], step: int,
+              betas: Tuple[float, float] = (0.9, 0.999), eps: float = 1e-15, zero_grad: bool = True):
+    """One fused Adam step (gs_adam_step) over groups (param, grad, m, v, lr, mode) of
+    contiguous FP32 device tensors; mode is "linear", "log" or "logit". Clears the gradients
+    when zero_grad is set. No allocation on the device, no host synchronisation."""
+    arr = (L.gs_adam_group * max(len(groups), 1))()
+    dev = None
+    for k, (x, g, m, v, lr, mode) in enumerate(groups):
+        for t in (x, g, m, v):
+            _check_f32(t, "Adam buffer")
+        if not (x.numel() == g.numel() == m.numel() == v.numel()):
+            raise ValueError("param, grad and moments must have the same number of elements")
+        arr[k] = L.gs_adam_group(_ptr(x), _ptr(g), _ptr(m), _ptr(v), x.numel(), float(lr), ADAM_MODES[mode])
+        dev = x.device
+    if not groups:
+        return
+    L.check(L.load().gs_adam_step(arr, len(groups), float(betas[0]), float(betas[1]), float(eps), int(step),
+                                  int(bool(zero_grad)), _stream(dev)))
+
+
 def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[int], k: int, t_cluster: float,
                        params=None, bits: Optional[torch.Tensor] = None, capacity=None) -> torch.Tensor:
     """OR into bits [k][ceil(n/32)] the per-cluster indicator lists (eq. importance-score-vis)."""

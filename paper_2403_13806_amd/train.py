@@ -8,12 +8,15 @@ gs_ssim_loss_grad call per view with the batch's element count, sharing one work
   autotune        times every candidate configuration on the actual scene and views and
                   keeps the fastest; results are cached as JSON keyed by device, scene size
                   and the set of view resolutions
+  Trainer         the optimisation loop: one drawn view per step, the Sec. 3.2 loss, a fused
+                  Adam step, pruning of parameters and Adam moments at the scheduled steps
 
 The step enqueues only calls of the C ABI plus zero fills of the accumulating outputs; it
 allocates nothing and never synchronises with the host, so it can be captured and replayed.
 """
 from __future__ import annotations
 
+import ctypes
 import json
 import os
 import time
@@ -176,3 +179,150 @@ def autotune(g: Gaussians, cams: Sequence, targets: Sequence, params=None, candi
         except OSError:
             pass
     return best
+
+
+# ---------------------------------------------------------------------------------------------
+# Optimisation with pruning (Sec. 3.2, Sec. 3.3)
+# ---------------------------------------------------------------------------------------------
+
+@dataclass
+class TrainConfig:
+    """Schedule and optimiser settings. The paper gives the loss (lambda = 0.2), the pruning
+    rule and when it is applied (twice during optimisation; t_prune 0.01 for the default model,
+    0.25 for the light one); the optimiser and its learning rates are those of 3D Gaussian
+    splatting: Adam, positions at 1.6e-4 x the camera extent decaying exponentially to 1.6e-6 x
+    over the run, SH DC 2.5e-3, higher SH bands 2.5e-3 / 20 enabled one band every 1000 steps,
+    opacity 0.05 in logit space, scales 5e-3 in log space, rotations 1e-3."""
+    steps: int = 30000
+    prune_steps: Tuple[int, ...] = (16000, 24000)
+    t_prune: float = 0.01
+    lam: float = 0.2
+    lr_mean: float = 1.6e-4
+    lr_mean_final: float = 1.6e-6
+    lr_sh_dc: float = 2.5e-3
+    lr_sh_rest: float = 2.5e-3 / 20
+    lr_opacity: float = 0.05
+    lr_scale: float = 5e-3
+    lr_quat: float = 1e-3
+    sh_band_every: int = 1000
+    betas: Tuple[float, float] = (0.9, 0.999)
+    eps: float = 1e-15
+    seed: int = 0
+    headroom: float = 2.0
+
+
+def camera_extent(cams: Sequence) -> float:
+    """1.1 x the largest distance of a camera centre from the centroid of the centres."""
+    pos = np.stack([np.asarray(c.position, np.float64) for c in cams])
+    return float(1.1 * np.max(np.linalg.norm(pos - pos.mean(0), axis=1))) or 1.0
+
+
+class Trainer:
+    """Optimises Gaussians against per-view targets (the radiance field's renders in the
+    paper) with the Sec. 3.2 loss, one uniformly drawn training view per step, a fused Adam
+    step on the device, and pruning at cfg.prune_steps: the importance of every Gaussian over
+    all training views (eq. importance-score), then the Gaussians with h < t_prune removed
+    from the parameters and from both Adam moments by one compaction (Sec. 3.3).
+
+    All training views share one resolution. Nothing is allocated per step; a step does not
+    synchronise with the host (pruning does, to size the new arrays)."""
+
+    def __init__(self, g: Gaussians, cams: Sequence, targets: Sequence, params=None,
+                 cfg: TrainConfig = TrainConfig(), tile=None, device=None):
+        from .splat import DEFAULT_TILE, camera_struct
+        from . import _lib as L
+        dev = torch.device(device if device is not None else "cuda")
+        if any((c.width, c.height) != (cams[0].width, cams[0].height) for c in cams):
+            raise ValueError("every training view must have the same resolution")
+        self.cfg, self.params, self.device = cfg, params, dev
+        self.cams = list(cams)
+        self.tile = DEFAULT_TILE if tile is None else tile
+        self.extent = camera_extent(self.cams)
+        arr = (L.gs_camera * len(cams))(*[camera_struct(c) for c in cams])
+        self.cams_all = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(dev)
+        self._cam_bytes = ctypes.sizeof(L.gs_camera)
+        w, h = cams[0].width, cams[0].height
+        self.targets = torch.stack([torch.as_tensor(np.asarray(t, np.float32).reshape(3, h, w)) for t in targets]).to(dev)
+        self.dl = torch.empty((3, h, w), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.ws_loss = torch.empty(max(ssim_workspace_bytes(3, h, w), 1), dtype=torch.uint8, device=dev)
+        self.rng = np.random.default_rng(cfg.seed)
+        self.it = 0
+        self.history: List[dict] = []
+        self._set_gaussians(g, zero_grads(g), zero_grads(g))
+
+    def _set_gaussians(self, g: Gaussians, m: Gaussians, v: Gaussians):
+        self.g, self.m, self.v = g, m, v
+        self.grad = zero_grads(g)
+        self.view = ViewBatch([self.cams[0]], self.tile, self.device)
+        self.r = Renderer(g, self.view, self.params, capacity=self._capacity(g))
+
+    def _capacity(self, g: Gaussians) -> int:
+        """Pairs of the most demanding training view times the headroom."""
+        from .splat import bin_sort, preprocess
+        most = 0
+        for cam in self.cams:
+            one = ViewBatch([cam], self.tile, self.device)
+            most = max(most, int(bin_sort(preprocess(g, one, self.params), one).n_pairs.item()))
+        return int(most * self.cfg.headroom) + 4096
+
+    def lr_mean(self) -> float:
+        c = self.cfg
+        t = min(self.it / max(c.steps, 1), 1.0)
+        return self.extent * float(np.exp((1 - t) * np.log(c.lr_mean) + t * np.log(c.lr_mean_final)))
+
+    def groups(self):
+        c, g, gr, m, v = self.cfg, self.g, self.grad, self.m, self.v
+        out = [(g.mean, gr.mean, m.mean, v.mean, self.lr_mean(), "linear"),
+               (g.scale, gr.scale, m.scale, v.scale, c.lr_scale, "log"),
+               (g.quat, gr.quat, m.quat, v.quat, c.lr_quat, "linear"),
+               (g.opacity, gr.opacity, m.opacity, v.opacity, c.lr_opacity, "logit"),
+               (g.sh[0:3], gr.sh[0:3], m.sh[0:3], v.sh[0:3], c.lr_sh_dc, "linear")]
+        for band in range(1, g.sh_degree + 1):
+            rows = slice(3 * band * band, 3 * (band + 1) * (band + 1))
+            lr = c.lr_sh_rest if self.it >= band * c.sh_band_every else 0.0
+            out.append((g.sh[rows], gr.sh[rows], m.sh[rows], v.sh[rows], lr, "linear"))
+        return out
+
+    def step(self):
+        """One optimisation step on a uniformly drawn training view; pruning when due."""
+        from .splat import adam_step
+        i = int(self.rng.integers(len(self.cams)))
+        self.r._sv.cams = ctypes.c_void_p(self.cams_all.data_ptr() + self._cam_bytes * i)
+        rgb = self.r.forward()
+        self.loss.zero_()
+        shape = self.dl.shape
+        ssim_loss_grad(rgb[:self.dl.numel()].view(shape), self.targets[i], self.dl, self.loss, self.cfg.lam, None,
+                       self.ws_loss)
+        self.r.backward(self.dl.view(-1), self.grad)
+        self.it += 1
+        adam_step(self.groups(), self.it, self.cfg.betas, self.cfg.eps, zero_grad=True)
+        if self.it in self.cfg.prune_steps:
+            self.prune()
+        return i
+
+    def importance(self) -> torch.Tensor:
+        from .splat import importance
+        h = torch.zeros(max(self.g.n, 1), dtype=torch.float32, device=self.device)
+        for c0 in range(0, len(self.cams), 8):
+            importance(self.g, ViewBatch(self.cams[c0:c0 + 8], self.tile, self.device), self.params, h=h)
+        return h
+
+    def prune(self, t_prune: Optional[float] = None):
+        """Remove the Gaussians with h < t_prune from the parameters and the Adam moments."""
+        from .splat import prune_gaussians
+        t = self.cfg.t_prune if t_prune is None else t_prune
+        h = self.importance()
+        m, v = self.m, self.v
+        before = self.g.n
+        pg, kept, rest = prune_gaussians(self.g, h, t, [m.mean, m.scale, m.quat, m.opacity, m.sh,
+                                                         v.mean, v.scale, v.quat, v.opacity, v.sh])
+        deg = self.g.sh_degree
+        pm = Gaussians(rest[0], rest[1], rest[2], rest[3], rest[4], deg)
+        pv = Gaussians(rest[5], rest[6], rest[7], rest[8], rest[9], deg)
+        self._set_gaussians(pg, pm, pv)
+        self.history.append({"step": self.it, "t_prune": t, "before": before, "after": pg.n})
+        return kept
+
+    def ok(self) -> bool:
+        return not self.r.check()[0]

@@ -811,3 +811,80 @@ def test_init_gaussians_matches_oracle(deg, with_colour):
     cam = scenes.look_at_camera(np.array([0.0, 0.0, -9.0]), np.zeros(3), 96, 64)
     out = gs.render(g, gs.ViewBatch([cam], device=DEV), P)
     assert torch.isfinite(out["rgb"]).all()
+
+
+# ----------------------------------------------------------------------------------------------
+# Adam step and the optimisation loop with pruning (Sec. 3.2, Sec. 3.3)
+# ----------------------------------------------------------------------------------------------
+from oracle import optim as OO  # noqa: E402
+
+
+def test_adam_step_matches_oracle():
+    """Three fused steps over groups in the three parametrisations against the FP64 oracle.
+    FP32 bars: moments within 1e-6 relative plus 1e-6 of the largest moment (a moment is a sum
+    of two rounded products that can nearly cancel), parameters within 1e-5 relative (log/exp
+    and the logistic map in FP32); gradients cleared."""
+    rng = np.random.default_rng(41)
+    specs = [(1000, "linear", 0.01, rng.standard_normal), (777, "log", 0.005, lambda n: rng.uniform(0.01, 2.0, n)),
+             (513, "logit", 0.05, lambda n: rng.uniform(0.02, 0.98, n)), (64, "linear", 0.0, rng.standard_normal)]
+    mode_id = {"linear": OO.LINEAR, "log": OO.LOG, "logit": OO.LOGIT}
+    xs = [f(n).astype(np.float32) for n, _, _, f in specs]
+    dev = [[torch.as_tensor(x, device=DEV), torch.zeros(len(x), device=DEV), torch.zeros(len(x), device=DEV),
+            torch.zeros(len(x), device=DEV)] for x in xs]
+    ref = [(x.astype(np.float64), np.zeros(len(x)), np.zeros(len(x))) for x in xs]
+    _say("adam step")
+    for t in range(1, 4):
+        grads = [rng.standard_normal(len(x)).astype(np.float32) for x in xs]
+        for d, gr in zip(dev, grads):
+            d[1].copy_(torch.as_tensor(gr, device=DEV))
+        gs.adam_step([(d[0], d[1], d[2], d[3], lr, mode) for d, (_, mode, lr, _) in zip(dev, specs)], t)
+        ref = [OO.adam_step(x, gr.astype(np.float64), m, v, lr, mode_id[mode], t)
+               for (x, m, v), gr, (_, mode, lr, _) in zip(ref, grads, specs)]
+        torch.cuda.synchronize()
+        for d, (x, m, v) in zip(dev, ref):
+            np.testing.assert_allclose(d[0].cpu().numpy(), x, rtol=1e-5, atol=1e-7)
+            np.testing.assert_allclose(d[2].cpu().numpy(), m, rtol=1e-6, atol=1e-6 * np.abs(m).max())
+            np.testing.assert_allclose(d[3].cpu().numpy(), v, rtol=1e-6, atol=1e-6 * np.abs(v).max())
+            assert not d[1].any()
+    with pytest.raises(gs.GSError):
+        gs.adam_step([(dev[0][0], dev[0][1], dev[0][2], dev[0][3], 0.1, "linear")], 0)
+
+
+def test_trainer_fits_and_prunes_with_moments():
+    """The optimisation loop fits a perturbed copy of a scene to that scene's renders (loss goes
+    down), prunes at its scheduled steps, and compacts both Adam moments with exactly the kept
+    Gaussians' values."""
+    from paper_2403_13806_amd.train import TrainConfig, Trainer
+    sc = scenes.mixture_scene(4000, seed=12, sh_degree=1, radius=2.0)
+    cams = scenes.orbit_views(6, 96, 64, radius=6.0)
+    teacher = gs.Gaussians.from_scene(sc, DEV)
+    targets = [gs.render(teacher, gs.ViewBatch([c], device=DEV), P)["rgb"].cpu().numpy() for c in cams]
+    rng = np.random.default_rng(42)
+    # the student: perturbed colours, opacities and scales, plus 300 Gaussians no view composites
+    # (opacity below alpha_min)
+    far = np.tile(np.array([[500.0], [500.0], [500.0]], np.float32), (1, 300))
+    student = gs.Gaussians.from_arrays(np.concatenate([sc.mean, far], 1),
+                                       np.concatenate([sc.scale * 1.3, np.full((3, 300), 0.05, np.float32)], 1),
+                                       np.concatenate([sc.quat, np.tile(sc.quat[:, :1], (1, 300))], 1),
+                                       np.concatenate([np.clip(sc.opacity * 0.7, 0.01, 1.0), np.full(300, 0.002)]),
+                                       np.concatenate([sc.sh + rng.normal(0, 0.3, sc.sh.shape), np.zeros((12, 300))],
+                                                      1).astype(np.float32), 1, DEV)
+    cfg = TrainConfig(steps=60, prune_steps=(30, 45), t_prune=0.005, lr_mean=1e-5, lr_mean_final=1e-6, seed=3)
+    tr = Trainer(student, cams, targets, P, cfg, device=DEV)
+    _say("trainer")
+    losses = []
+    for _ in range(60):
+        tr.step()
+        losses.append(float(tr.loss.item()))
+    assert tr.ok()
+    assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:10]), (losses[:10], losses[-10:])
+    assert [h["step"] for h in tr.history] == [30, 45]
+    assert tr.history[0]["before"] == 4300 and tr.history[0]["after"] <= 4000
+    assert tr.g.n == tr.history[-1]["after"]
+    # a further pruning: the moments follow the kept indices exactly
+    m_before = [t.clone() for t in (tr.m.mean, tr.m.sh, tr.v.scale, tr.v.opacity)]
+    kept = tr.prune(0.05).long()
+    for a, b in zip((tr.m.mean, tr.m.sh, tr.v.scale, tr.v.opacity), m_before):
+        assert torch.equal(a, b[..., kept])
+    tr.step()
+    assert tr.ok() and np.isfinite(tr.loss.item())

@@ -176,6 +176,23 @@ def test_init_argument_errors():
     assert lib.gs_init_gaussians(v(16), None, 1000, 3, None, *outs[1:], v(32), need, None) == L.GS_ERR_INVALID_ARG
 
 
+def test_adam_argument_errors():
+    lib = gs.load()
+    v = ctypes.c_void_p
+    grp = (L.gs_adam_group * 1)(L.gs_adam_group(v(16), v(32), v(48), v(64), 10, 0.1, L.GS_ADAM_LINEAR))
+    assert lib.gs_adam_step(grp, 1, 0.9, 0.999, 1e-15, 0, 1, None) == L.GS_ERR_INVALID_ARG  # step from 1
+    assert lib.gs_adam_step(grp, 1, 1.0, 0.999, 1e-15, 1, 1, None) == L.GS_ERR_INVALID_ARG
+    grp[0].mode = 7
+    assert lib.gs_adam_step(grp, 1, 0.9, 0.999, 1e-15, 1, 1, None) == L.GS_ERR_INVALID_ARG
+    assert b"mode" in lib.gs_last_error()
+    grp[0].mode, grp[0].m = L.GS_ADAM_LOG, 32
+    assert lib.gs_adam_step(grp, 1, 0.9, 0.999, 1e-15, 1, 1, None) == L.GS_ERR_INVALID_ARG
+    assert b"alias" in lib.gs_last_error()
+    grp[0].m, grp[0].v = 48, None
+    assert lib.gs_adam_step(grp, 1, 0.9, 0.999, 1e-15, 1, 1, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_adam_step(None, 0, 0.9, 0.999, 1e-15, 1, 1, None) == L.GS_OK
+
+
 def test_ssim_argument_errors():
     """Argument checks of the loss entry point run on the host before any launch."""
     lib = gs.load()
