@@ -18,49 +18,70 @@ namespace {
 
 constexpr int GROUPS_PER_LAUNCH = 16;
 constexpr int NT = 256;
+constexpr int PER_THREAD = 4;
+constexpr int CHUNK = NT * PER_THREAD;  // elements per workgroup, all of one group
 
 struct AdamTable {
     float* p[GROUPS_PER_LAUNCH];
     float* g[GROUPS_PER_LAUNCH];
     float* m[GROUPS_PER_LAUNCH];
     float* v[GROUPS_PER_LAUNCH];
-    int64_t end[GROUPS_PER_LAUNCH];  // prefix sums of the group sizes
+    int64_t count[GROUPS_PER_LAUNCH];
+    int64_t blk[GROUPS_PER_LAUNCH + 1];  // first workgroup of each group
     float lr[GROUPS_PER_LAUNCH];
     int32_t mode[GROUPS_PER_LAUNCH];
-    int32_t count;
+    int32_t count_groups;
     int32_t zero_grad;
     float b1, b2, omb1, omb2, eps, inv_bc1, inv_sqrt_bc2;  // omb = 1 - b, formed in FP64
 };
 
+// one workgroup = CHUNK consecutive elements of one group (group, pointers and mode are
+// uniform); each lane loads its PER_THREAD elements (NT apart, coalesced) before computing
 __global__ __launch_bounds__(NT) void k_adam(AdamTable t) {
-    const int64_t total = t.end[t.count - 1];
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
-        int k = 0;
-        while (i >= t.end[k]) ++k;
-        const int64_t j = i - (k ? t.end[k - 1] : 0);
-        float x = t.p[k][j], dx = t.g[k][j];
-        float u = x, du = dx;
-        if (t.mode[k] == GS_ADAM_LOG) {
-            u = logf(x);
-            du = dx * x;
-        } else if (t.mode[k] == GS_ADAM_LOGIT) {
-            x = fminf(fmaxf(x, 1e-6f), 1.f - 1e-6f);
-            u = logf(x / (1.f - x));
-            du = dx * x * (1.f - x);
+    const int64_t b = blockIdx.x;
+    int k = 0;
+    while (b >= t.blk[k + 1]) ++k;
+    const int64_t base = (b - t.blk[k]) * CHUNK + threadIdx.x;
+    const int64_t n = t.count[k];
+    float* __restrict__ P = t.p[k];
+    float* __restrict__ G = t.g[k];
+    float* __restrict__ M = t.m[k];
+    float* __restrict__ V = t.v[k];
+    const int mode = t.mode[k];
+    const float lr = t.lr[k];
+    float x[PER_THREAD], dx[PER_THREAD], m0[PER_THREAD], v0[PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < PER_THREAD; ++u) {
+        const int64_t j = base + u * NT;
+        x[u] = dx[u] = m0[u] = v0[u] = 0.f;
+        if (j < n) x[u] = P[j], dx[u] = G[j], m0[u] = M[j], v0[u] = V[j];
+    }
+#pragma unroll
+    for (int u = 0; u < PER_THREAD; ++u) {
+        const int64_t j = base + u * NT;
+        if (j >= n) continue;
+        float xv = x[u], uu = xv, du = dx[u];
+        if (mode == GS_ADAM_LOG) {
+            uu = logf(xv);
+            du = dx[u] * xv;
+        } else if (mode == GS_ADAM_LOGIT) {
+            xv = fminf(fmaxf(xv, 1e-6f), 1.f - 1e-6f);
+            uu = logf(xv / (1.f - xv));
+            du = dx[u] * xv * (1.f - xv);
         }
-        const float m = t.b1 * t.m[k][j] + t.omb1 * du;
-        const float v = t.b2 * t.v[k][j] + t.omb2 * du * du;
-        u -= t.lr[k] * (m * t.inv_bc1) / (sqrtf(v) * t.inv_sqrt_bc2 + t.eps);
-        if (t.mode[k] == GS_ADAM_LOG)
-            x = expf(u);
-        else if (t.mode[k] == GS_ADAM_LOGIT)
-            x = 1.f / (1.f + expf(-u));
+        const float m = t.b1 * m0[u] + t.omb1 * du;
+        const float v = t.b2 * v0[u] + t.omb2 * du * du;
+        uu -= lr * (m * t.inv_bc1) / (sqrtf(v) * t.inv_sqrt_bc2 + t.eps);
+        if (mode == GS_ADAM_LOG)
+            xv = expf(uu);
+        else if (mode == GS_ADAM_LOGIT)
+            xv = 1.f / (1.f + expf(-uu));
         else
-            x = u;
-        t.p[k][j] = x;
-        t.m[k][j] = m;
-        t.v[k][j] = v;
-        if (t.zero_grad) t.g[k][j] = 0.f;
+            xv = uu;
+        P[j] = xv;
+        M[j] = m;
+        V[j] = v;
+        if (t.zero_grad) G[j] = 0.f;
     }
 }
 
@@ -70,29 +91,28 @@ gs_status launch_adam(const gs_adam_group* groups, int32_t n_groups, double b1, 
                       int32_t zero_grad, hipStream_t s) {
     const double bc1 = 1.0 - std::pow(b1, (double)step), bc2 = 1.0 - std::pow(b2, (double)step);
     AdamTable t{};
-    int64_t acc = 0;
     auto flush = [&]() -> gs_status {
-        if (t.count == 0) return GS_OK;
+        if (t.count_groups == 0) return GS_OK;
         t.zero_grad = zero_grad;
         t.b1 = (float)b1, t.b2 = (float)b2, t.eps = (float)eps;
         t.omb1 = (float)(1.0 - b1), t.omb2 = (float)(1.0 - b2);
         t.inv_bc1 = (float)(1.0 / bc1);
         t.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
-        const int64_t blocks = std::min<int64_t>((acc + NT - 1) / NT, 8192);
+        for (int c = t.count_groups + 1; c <= GROUPS_PER_LAUNCH; ++c) t.blk[c] = t.blk[t.count_groups];
+        const int64_t blocks = t.blk[t.count_groups];
         hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(NT), 0, s, t);
         t = AdamTable{};
-        acc = 0;
         return check_launch("adam_step");
     };
     for (int k = 0; k < n_groups; ++k) {
         if (groups[k].count == 0) continue;
-        const int c = t.count++;
+        const int c = t.count_groups++;
         t.p[c] = groups[k].param, t.g[c] = groups[k].grad, t.m[c] = groups[k].m, t.v[c] = groups[k].v;
-        acc += groups[k].count;
-        t.end[c] = acc;
+        t.count[c] = groups[k].count;
+        t.blk[c + 1] = t.blk[c] + (groups[k].count + CHUNK - 1) / CHUNK;
         t.lr[c] = groups[k].lr;
         t.mode[c] = groups[k].mode;
-        if (t.count == GROUPS_PER_LAUNCH) {
+        if (t.count_groups == GROUPS_PER_LAUNCH) {
             gs_status st = flush();
             if (st != GS_OK) return st;
         }
