@@ -210,6 +210,11 @@ class TrainConfig:
     seed: int = 0
     headroom: float = 2.0
 
+    @classmethod
+    def light(cls, **kw) -> "TrainConfig":
+        """The lightweight variant: t_prune = 0.25 (the default model uses 0.01)."""
+        return cls(t_prune=0.25, **kw)
+
 
 def camera_extent(cams: Sequence) -> float:
     """1.1 x the largest distance of a camera centre from the centroid of the centres."""
