@@ -3,8 +3,8 @@
 // opacity 0.1, identity rotation, DC colour from a given per-point colour, higher SH 0.
 //
 // Exact nearest-neighbour distances on a uniform cell grid:
-//   k_nn_setup   clears the bounding box words
-//   k_bbox       bounding box of the finite points (ordered-integer atomics)
+//   k_bbox       bounding box of the finite points: per-workgroup partials (ordered-integer
+//                min/max), combined by k_bbox_final
 //   k_grid       one thread: cell size h with at most `cap` cells (about one point per cell over
 //                the box), grid dimensions
 //   k_cell_count cell of every point, its rank inside the cell (atomic counter per cell)
@@ -13,8 +13,8 @@
 //   k_nn         one lane per stored point, neighbouring lanes in the same or nearby cells:
 //                Chebyshev rings of cells around the point's cell, nearest squared distance
 //                over points at another position, stopping after ring r once that distance is
-//                at most r h (less a rounding margin): every point not yet visited lies in a
-//                cell at least r + 1 rings away, hence at least r h away
+//                at most the distance to the nearest face of the searched block of cells (less a
+//                rounding margin): every point not yet visited lies beyond one of those faces
 // Squared distances are FP64 from the FP32 coordinates, (dx dx + dy dy) + dz dz without fused
 // multiply-add, and the distance is rounded to FP32 once, so the minimum does not depend on the
 // visiting order.
@@ -27,6 +27,7 @@ namespace gs {
 namespace {
 
 constexpr int NB = 256;
+constexpr int BBOX_BLOCKS = 256;  // workgroups of the bounding-box pass
 constexpr int SCAN_T = 1024, SCAN_IPT = 4, SCAN_ITEMS = SCAN_T * SCAN_IPT;
 constexpr double kY00 = 0.28209479177387814;  // 1 / (2 sqrt(pi))
 
@@ -49,6 +50,7 @@ __device__ __forceinline__ float o2f(uint32_t o) {
 
 struct NnLayout {
     GridCtrl* ctrl;
+    uint32_t* bbox;    // [BBOX_BLOCKS][7] per-workgroup bounds and counts
     uint32_t* cell;    // [n] cell of each point (0xffffffff: non-finite)
     uint32_t* rank;    // [n]
     uint32_t* start;   // [cap + 1] counts, then exclusive starts
@@ -71,6 +73,8 @@ static NnLayout nn_layout(void* ws, int64_t n) {
     char* p = static_cast<char*>(ws);
     L.ctrl = reinterpret_cast<GridCtrl*>(p);
     p += a256(sizeof(GridCtrl));
+    L.bbox = reinterpret_cast<uint32_t*>(p);
+    p += a256(sizeof(uint32_t) * 7 * BBOX_BLOCKS);
     L.cell = reinterpret_cast<uint32_t*>(p);
     p += a256(sizeof(uint32_t) * (size_t)n);
     L.rank = reinterpret_cast<uint32_t*>(p);
@@ -83,16 +87,13 @@ static NnLayout nn_layout(void* ws, int64_t n) {
     return L;
 }
 
-__global__ void k_nn_setup(GridCtrl* c) {
-    for (int a = 0; a < 3; ++a) c->lo[a] = 0xffffffffu, c->hi[a] = 0u;
-    c->n_finite = 0;
-}
-
 __device__ __forceinline__ bool finite3(float x, float y, float z) {
     return isfinite(x) && isfinite(y) && isfinite(z);
 }
 
-__global__ __launch_bounds__(NB) void k_bbox(const float* __restrict__ pts, int64_t n, GridCtrl* c) {
+// per-workgroup bounds of the finite points and their count: partial[b] = (lo[3], hi[3], count)
+__global__ __launch_bounds__(NB) void k_bbox(const float* __restrict__ pts, int64_t n, uint32_t* __restrict__ partial) {
+    __shared__ uint32_t red[NB / 64][7];
     uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u}, cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * NB + threadIdx.x; i < n; i += (int64_t)gridDim.x * NB) {
         const float x = pts[i], y = pts[n + i], z = pts[2 * n + i];
@@ -110,10 +111,44 @@ __global__ __launch_bounds__(NB) void k_bbox(const float* __restrict__ pts, int6
         }
     }
     for (int s = 32; s >= 1; s >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, s);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) red[w][a] = lo[a], red[w][3 + a] = hi[a];
+        red[w][6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int f = threadIdx.x;
+        uint32_t v = red[0][f];
+        for (int k = 1; k < NB / 64; ++k) v = f < 3 ? min(v, red[k][f]) : (f < 6 ? max(v, red[k][f]) : v + red[k][f]);
+        partial[blockIdx.x * 7 + f] = v;
+    }
+}
+
+// one workgroup: the partial bounds combined into the control block
+__global__ __launch_bounds__(NB) void k_bbox_final(const uint32_t* __restrict__ partial, int nb, GridCtrl* c) {
+    __shared__ uint32_t red[NB / 64][7];
+    const int t = threadIdx.x, w = t >> 6;
+    uint32_t v[7] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
+    if (t < nb) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) atomicMin(&c->lo[a], lo[a]), atomicMax(&c->hi[a], hi[a]);
-        atomicAdd(&c->n_finite, cnt);
+        for (int f = 0; f < 7; ++f) v[f] = partial[t * 7 + f];
+    }
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+        for (int s = 32; s >= 1; s >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v[f], s);
+            v[f] = f < 3 ? min(v[f], o) : (f < 6 ? max(v[f], o) : v[f] + o);
+        }
+    if ((t & 63) == 0)
+        for (int f = 0; f < 7; ++f) red[w][f] = v[f];
+    __syncthreads();
+    if (t < 7) {
+        uint32_t x = red[0][t];
+        for (int k = 1; k < NB / 64; ++k) x = t < 3 ? min(x, red[k][t]) : (t < 6 ? max(x, red[k][t]) : x + red[k][t]);
+        if (t < 3) c->lo[t] = x;
+        else if (t < 6) c->hi[t - 3] = x;
+        else c->n_finite = x;
     }
 }
 
@@ -257,9 +292,10 @@ __device__ __forceinline__ double dist2(float4 p, double qx, double qy, double q
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-__device__ __forceinline__ void scan_cell(const uint32_t* __restrict__ start, const float4* __restrict__ sorted,
-                                          int64_t id, double qx, double qy, double qz, double& best) {
-    const uint32_t b = start[id], e = start[id + 1];
+// the points of cells [id0, id1] of one grid row: contiguous in the cell-ordered copy
+__device__ __forceinline__ void scan_cells(const uint32_t* __restrict__ start, const float4* __restrict__ sorted,
+                                           int64_t id0, int64_t id1, double qx, double qy, double qz, double& best) {
+    const uint32_t b = start[id0], e = start[id1 + 1];
     for (uint32_t j = b; j < e; ++j) {
         const double d = dist2(sorted[j], qx, qy, qz);
         if (d > 0.0 && d < best) best = d;
@@ -280,7 +316,10 @@ __global__ __launch_bounds__(NB) void k_nn(const GridCtrl* __restrict__ c, const
     const int cz = cell_axis(qz, c->org[2], c->inv_h, G2);
     const int rmax = max(G0, max(G1, G2));
     double best = INFINITY;
-    for (int r = 0; r <= rmax; ++r) {
+    // ring 0 alone can never end the search (its bound is 0), so the first step covers rings
+    // 0 and 1 together: every row of the 3 x 3 x 3 block as one contiguous range
+    for (int r = 1; r <= max(rmax, 1); ++r) {
+        const bool block = r == 1;
         for (int dz = -r; dz <= r; ++dz) {
             const int z = cz + dz;
             if (z < 0 || z >= G2) continue;
@@ -288,16 +327,25 @@ __global__ __launch_bounds__(NB) void k_nn(const GridCtrl* __restrict__ c, const
                 const int y = cy + dy;
                 if (y < 0 || y >= G1) continue;
                 const int64_t row = ((int64_t)z * G1 + y) * G0;
-                if (dz == -r || dz == r || dy == -r || dy == r) {
-                    const int x0 = max(cx - r, 0), x1 = min(cx + r, G0 - 1);
-                    for (int x = x0; x <= x1; ++x) scan_cell(start, sorted, row + x, qx, qy, qz, best);
+                if (block || dz == -r || dz == r || dy == -r || dy == r) {
+                    scan_cells(start, sorted, row + max(cx - r, 0), row + min(cx + r, G0 - 1), qx, qy, qz, best);
                 } else {
-                    if (cx - r >= 0) scan_cell(start, sorted, row + cx - r, qx, qy, qz, best);
-                    if (r > 0 && cx + r < G0) scan_cell(start, sorted, row + cx + r, qx, qy, qz, best);
+                    if (cx - r >= 0) scan_cells(start, sorted, row + cx - r, row + cx - r, qx, qy, qz, best);
+                    if (r > 0 && cx + r < G0) scan_cells(start, sorted, row + cx + r, row + cx + r, qx, qy, qz, best);
                 }
             }
         }
-        const double reach = (double)r * h - eps;  // every unvisited point is at least this far
+        // every unvisited point lies in a cell at least r + 1 rings away, beyond one of the six
+        // faces of the searched block (a face on the grid's border has nothing beyond it)
+        double reach = INFINITY;
+        const int cc[3] = {cx, cy, cz}, gd[3] = {G0, G1, G2};
+        const double qq[3] = {qx, qy, qz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (cc[a] - r > 0) reach = fmin(reach, qq[a] - (c->org[a] + (double)(cc[a] - r) * h));
+            if (cc[a] + r < gd[a] - 1) reach = fmin(reach, (c->org[a] + (double)(cc[a] + r + 1) * h) - qq[a]);
+        }
+        reach -= eps;
         if (reach > 0.0 && best <= reach * reach) break;
     }
     const int i = __float_as_int(q.w);
@@ -328,7 +376,7 @@ __global__ __launch_bounds__(NB) void k_init_params(const float* __restrict__ pt
 size_t nn_workspace_bytes(int64_t n) {
     if (n <= 0) return 0;
     const int64_t cap = cell_cap(n);
-    return a256(sizeof(GridCtrl)) + 2 * a256(sizeof(uint32_t) * (size_t)n) +
+    return a256(sizeof(GridCtrl)) + a256(sizeof(uint32_t) * 7 * BBOX_BLOCKS) + 2 * a256(sizeof(uint32_t) * (size_t)n) +
            a256(sizeof(uint32_t) * (size_t)(cap + 1)) + a256(sizeof(uint32_t) * (size_t)scan_blocks(cap + 1)) +
            sizeof(float4) * (size_t)n;
 }
@@ -338,8 +386,9 @@ gs_status launch_nn_distance(const float* pts, int64_t n, float* dist, void* ws,
     const NnLayout L = nn_layout(ws, n);
     const unsigned g = (unsigned)((n + NB - 1) / NB);
     const int64_t m = L.cap + 1, nb = scan_blocks(m);
-    hipLaunchKernelGGL(k_nn_setup, dim3(1), dim3(1), 0, s, L.ctrl);
-    hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(g, 1024)), dim3(NB), 0, s, pts, n, L.ctrl);
+    const unsigned nbb = std::min<unsigned>(g, BBOX_BLOCKS);
+    hipLaunchKernelGGL(k_bbox, dim3(nbb), dim3(NB), 0, s, pts, n, L.bbox);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(NB), 0, s, L.bbox, (int)nbb, L.ctrl);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(1), 0, s, L.ctrl, L.cap);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((m + NB - 1) / NB)), dim3(NB), 0, s, L.start, m, 0u);
     hipLaunchKernelGGL(k_cell_count, dim3(g), dim3(NB), 0, s, pts, n, L.ctrl, L.cell, L.rank, L.start, dist);

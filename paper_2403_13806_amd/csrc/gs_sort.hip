@@ -1,9 +1,8 @@
 // Tile binning and the (tile, depth, index) order that gives every tile its front-to-back
 // list ("correctly-sorted points", eq. render-gs):
-//   scan     exclusive prefix sum of the per-(view, Gaussian) tile counts in one pass:
-//            4096 items per block, wave DPP scan -> block scan -> decoupled look-back
-//            across blocks in launch-ticket order; the last block writes the pair total
-//            and the capacity check
+//   offsets  exclusive prefix sum of the per-(view, Gaussian) tile counts in two levels:
+//            sums of 256-entry blocks, one workgroup scanning those (it writes the pair
+//            total and the capacity check), and the scan inside each block during emission
 //   emit     load-balanced: the pairs of a wave's 64 Gaussians are contiguous in the
 //            output, so lanes walk that range 64 pairs at a time and find their Gaussian
 //            by a 6-step binary search over the wave's offsets in LDS; each pair is the
@@ -216,9 +215,75 @@ gs_status launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* ct
 // ---------------------------------------------------------------------------------------
 // Pair emission
 // ---------------------------------------------------------------------------------------
+// Pair offsets in entry order (view-major, then Gaussian) come in two levels: the tile counts
+// of every 256-entry emission block are summed (k_count_bsums), one workgroup scans those block
+// sums (k_scan_bsums: the block prefixes, the pair total and the capacity check), and each
+// emission block scans its own 256 counts. No chain of waits between blocks.
+constexpr int SB_T = 1024;  // threads of the block-sum scan
+
+__global__ __launch_bounds__(256) void k_count_bsums(const uint32_t* __restrict__ count, int64_t n, int64_t nbv,
+                                                     uint32_t* __restrict__ bsum) {
+    const int v = blockIdx.y, w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint32_t* cv = count + (int64_t)v * n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t bx = (int64_t)blockIdx.x * 16 + w * 4 + q;  // emission block of this wave
+        if (bx >= nbv) break;                                     // the same for the whole wave
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j = bx * 256 + k * 64 + l;
+            sum += j < n ? cv[j] : 0u;
+        }
+        sum = wave_read(wave_incl_scan(sum), 63);
+        if (l == 0) bsum[(int64_t)v * nbv + bx] = sum;
+    }
+}
+
+__global__ __launch_bounds__(SB_T) void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t m, uint64_t* total_out,
+                                                     uint32_t* flags, uint64_t capacity) {
+    __shared__ uint64_t part[SB_T / 64 + 1];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int64_t per = (m + SB_T - 1) / SB_T;
+    const int64_t b0 = (int64_t)t * per, b1 = min(m, b0 + per);
+    uint64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += bsum[i];
+    // inclusive scan of the per-thread u64 sums over the wave
+    uint64_t incl = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = (uint64_t)__shfl_up((long long)incl, d);
+        if (l >= d) incl += y;
+    }
+    if (l == 63) part[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+        uint64_t run = 0;
+        for (int k = 0; k < SB_T / 64; ++k) {
+            const uint64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        part[SB_T / 64] = run;
+    }
+    __syncthreads();
+    uint64_t pre = part[w] + incl - s;
+    // offsets past 2^32 only occur when the capacity check below has failed
+    for (int64_t i = b0; i < b1; ++i) {
+        const uint32_t x = bsum[i];
+        bsum[i] = (uint32_t)pre;
+        pre += x;
+    }
+    if (t == 0) {
+        const uint64_t total = part[SB_T / 64];
+        if (total_out) *total_out = total;
+        if (flags && total > capacity) atomicOr(flags, 1u);
+    }
+}
+
 struct EmitArgs {
     const uint32_t* count;
-    const uint32_t* offs;  // exclusive pair offsets in entry order
+    const uint32_t* bpre;  // exclusive pair offset of each 256-entry emission block
     const uint64_t* rect;
     const float* depth;
     const gs_camera* cams;
@@ -231,7 +296,7 @@ struct EmitArgs {
 };
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
-    __shared__ uint32_t s_off[256], s_db[256];
+    __shared__ uint32_t s_off[256], s_db[256], s_wsum[4];
     __shared__ uint64_t s_rect[256];
     __shared__ double s_inv[256];  // 1 / rectangle width
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
@@ -242,13 +307,15 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     uint32_t c = 0, off = 0xffffffffu, db = 0;
     uint64_t r = 0;
     if (j < a.n) {
-        off = a.offs[o];
         c = a.count[o];
         if (c) {
             r = a.rect[o];
             db = __float_as_uint(a.depth[o]);
         }
     }
+    uint32_t btot;
+    const uint32_t ex = block_excl_scan(c, btot, s_wsum);
+    if (j < a.n) off = a.bpre[(int64_t)v * gridDim.x + blockIdx.x] + ex;
     s_off[t] = off;
     s_db[t] = db;
     s_rect[t] = r;
@@ -866,15 +933,17 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     if ((st = launch_zero4(f, stream))) return st;
     if (vn == 0 || views->n_tiles == 0) return launch_lpt(views, bins, nullptr, stream);
 
-    // 1. pair offsets in entry order, pair total, capacity check
-    if ((st = launch_scan(proj->count, U32(L.offs), vn, U64(L.scan), bins->n_pairs, bins->overflow, bins->capacity,
-                          stream)))
-        return st;
+    // 1. pair offsets of the emission blocks, pair total, capacity check
+    const int64_t nbv = (n + 255) / 256;
+    hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0, stream,
+                       proj->count, n, nbv, U32(L.offs));
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views, bins->n_pairs,
+                       bins->overflow, bins->capacity);
     if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
     // 2. pairs (tile; depth bits, index)
     EmitArgs e;
     e.count = proj->count;
-    e.offs = U32(L.offs);
+    e.bpre = U32(L.offs);
     e.rect = proj->rect;
     e.depth = proj->depth;
     e.cams = views->cams;
