@@ -369,17 +369,40 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
     const int64_t VN = (int64_t)a.n_views * a.n;
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
     bool any = false;
+    // where the first view composited this Gaussian, its 2D gradients, its parameters and the
+    // gradients accumulated so far are requested together, in one round of loads
+    const uint32_t cnt0 = a.count[i];
+    const bool pre = cnt0 != 0;
+    float g20[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, old[11];
+    Geom gm{};
+    if (pre) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g20[k] = a.g2[k * VN + i];
+        gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n, i);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) old[k] = a.gmean[k * a.n + i], old[3 + k] = a.gscale[k * a.n + i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) old[6 + k] = a.gquat[k * a.n + i];
+        old[10] = a.gopac[i];
+    }
+    bool have_geom = pre;
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t o = (int64_t)v * a.n + i;
-        if (a.count[o] == 0) continue;
-        const float gu = a.g2[0 * VN + o], gv = a.g2[1 * VN + o], gA = a.g2[2 * VN + o], gB = a.g2[3 * VN + o],
-                    gC = a.g2[4 * VN + o], gO = a.g2[5 * VN + o];
+        if ((v == 0 ? cnt0 : a.count[o]) == 0) continue;
+        float g6[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g6[k] = v == 0 ? g20[k] : a.g2[k * VN + o];
+        const float gu = g6[0], gv = g6[1], gA = g6[2], gB = g6[3], gC = g6[4], gO = g6[5];
         if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) continue;
         any = true;
+        if (!have_geom) {
+            gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n, i);
+            have_geom = true;
+        }
         const gs_camera cam = a.cams[v];
         Proj P;
         double op;
-        if (!project_one(cam, a.p, a.mean, a.scale, a.quat, a.opac, a.n, i, P, op)) continue;
+        if (!project_vals(cam, a.p, gm, P, op)) continue;
         go += gO;
         const double idet = 1.0 / P.det;
         const double ca = P.syy * idet, cb = -P.sxy * idet, cc = P.sxx * idet;
@@ -430,7 +453,7 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) gp[k] += Rc[k] * gc[0] + Rc[3 + k] * gc[1] + Rc[6 + k] * gc[2];
         // Sigma = M M^T with M = Rq diag(s): dL/dM = 2 GS M
-        const double s[3] = {a.scale[i], a.scale[a.n + i], a.scale[2 * a.n + i]};
+        const double s[3] = {gm.s[0], gm.s[1], gm.s[2]};
         double GR[3][3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -457,14 +480,21 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         gq[3] += (gz - zq * dot) * iqn;
     }
     if (!any) return;
+    if (!pre) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a.gmean[k * a.n + i] += (float)gp[k];
-        a.gscale[k * a.n + i] += (float)gs[k];
+        for (int k = 0; k < 3; ++k) old[k] = a.gmean[k * a.n + i], old[3 + k] = a.gscale[k * a.n + i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) old[6 + k] = a.gquat[k * a.n + i];
+        old[10] = a.gopac[i];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] += (float)gq[k];
-    a.gopac[i] += (float)go;
+    for (int k = 0; k < 3; ++k) {
+        a.gmean[k * a.n + i] = old[k] + (float)gp[k];
+        a.gscale[k * a.n + i] = old[3 + k] + (float)gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] = old[6 + k] + (float)gq[k];
+    a.gopac[i] = old[10] + (float)go;
 }
 
 // Colour part of the reverse mode: SH coefficient gradients and the mean gradient through
@@ -488,17 +518,28 @@ __global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
         gsh[k] = 0.f;
     }
     float px = 0.f, py = 0.f, pz = 0.f;
+    // the first view's count and colour gradient are requested together with the parameters
+    uint32_t cnt0 = 0;
+    float gc0 = 0.f;
     if (valid) {
         px = a.mean[i];
         py = a.mean[a.n + i];
         pz = a.mean[2 * a.n + i];
+        cnt0 = a.count[i];
+        gc0 = a.g2[(6 + c) * VN + i];
     }
+    // the accumulated SH gradient is read early where the first view composited this Gaussian
+    float old[NB];
+    const bool pre = valid && cnt0 != 0 && gc0 != 0.f;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) old[k] = pre ? a.gsh[(int64_t)(k * 3 + c) * a.n + i] : 0.f;
     double gp[3] = {0, 0, 0};
     bool any = false;
     for (int v = 0; valid && v < a.n_views; ++v) {
         const int64_t o = (int64_t)v * a.n + i;
-        if (a.count[o] == 0) continue;
-        const float gc = a.g2[(6 + c) * VN + o];
+        const uint32_t cnt = v == 0 ? cnt0 : a.count[o];
+        if (cnt == 0) continue;
+        const float gc = v == 0 ? gc0 : a.g2[(6 + c) * VN + o];
         if (gc == 0.f) continue;
         any = true;
         const gs_camera cam = a.cams[v];
@@ -524,7 +565,10 @@ __global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
     s_any[c][l] = any ? 1u : 0u;
     if (any) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) a.gsh[(int64_t)(k * 3 + c) * a.n + i] += gsh[k];
+        for (int k = 0; k < NB; ++k) {
+            const int64_t q = (int64_t)(k * 3 + c) * a.n + i;
+            a.gsh[q] = (pre ? old[k] : a.gsh[q]) + gsh[k];
+        }
     }
     __syncthreads();
     if (c == 0 && valid && (s_any[0][l] | s_any[1][l] | s_any[2][l])) {
