@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="headline only")
-    ap.add_argument("--only", choices=["batched", "importance", "house"], default=None,
+    ap.add_argument("--only", choices=["batched", "importance", "house", "training"], default=None,
                     help="run one secondary workload alone (for profiling) and print its numbers")
     return ap.parse_args()
 
@@ -96,6 +96,10 @@ def main():
             res = fwd_bwd_and_batched(torch, gs, scenes, P, dev, g, sc, K, W, tune=False)
         elif args.only == "importance":
             res = importance_pass(torch, gs, scenes, P, dev)
+        elif args.only == "training":
+            sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+            g = gs.Gaussians.from_scene(sc, dev)
+            res = trainer_pass(torch, gs, scenes, P, dev, g, scenes.orbit_views(8), steps=K)
         else:
             res = filtered_pass(torch, gs, scenes, P, dev)
         print(json.dumps({"only": args.only, **res}), flush=True)

@@ -98,4 +98,14 @@ __device__ __forceinline__ int view_of_tile(const int32_t* __restrict__ tile_off
 
 __host__ __device__ __forceinline__ int div_up(int a, int b) { return (a + b - 1) / b; }
 
+// position of workgroup b in an order where each of the 8 XCDs (workgroups are dispatched to
+// them round-robin, each XCD has its own L2) takes one contiguous range of [0, n): work on
+// neighbouring tiles then shares an L2. Worth it where neighbours share data and costs are even
+// (the loss windows); the compositing tiles keep the plain order, which spreads the expensive
+// centre of a view over all XCDs.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n) {
+    const int64_t q = n / 8, rem = n % 8, x = b % 8, s = b / 8;
+    return x * q + (x < rem ? x : rem) + s;
+}
+
 }  // namespace gs

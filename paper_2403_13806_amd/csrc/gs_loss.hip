@@ -115,8 +115,9 @@ __device__ __forceinline__ void load_window(const SsimArgs& a, const Job& jb, fl
     }
 }
 
-// Persistent grid over the jobs; the next job's window is loaded into registers while the
-// current one is computed. Vertical sums first (over the window's 74 columns), then
+// Persistent grid over the jobs (round k of workgroup b takes job k G + xcd_order(b, G), so
+// each XCD works on a band of neighbouring tiles); the next job's window is loaded into
+// registers while the current one is computed. Vertical sums first (over the window's 74 columns), then
 // horizontal sums (over the tile's 16 rows): the halo costs 74/64 of the first pass only.
 __global__ __launch_bounds__(NTH) void k_ssim_stats(SsimArgs a) {
     __shared__ __align__(16) float2 s_in[IY][IX];
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(NTH) void k_ssim_stats(SsimArgs a) {
     const int64_t n_jobs = (int64_t)a.n_planes * a.n_tiles;
     const bool vec = a.vec;
     float2 v[NLD];
-    int64_t j = blockIdx.x;
+    int64_t j = xcd_order(blockIdx.x, gridDim.x);  // halos of neighbouring tiles share an L2
     if (j < n_jobs) load_window(a, job_of(a, j), v);
     for (; j < n_jobs; j += gridDim.x) {
         const Job jb = job_of(a, j);
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int64_t n_jobs = (int64_t)a.n_planes * a.n_tiles;
     const bool vec = a.vec;
     MapWindow w;
-    int64_t j = blockIdx.x;
+    int64_t j = xcd_order(blockIdx.x, gridDim.x);  // halos of neighbouring tiles share an L2
     if (j < n_jobs) load_maps(a, job_of(a, j), w);
     for (; j < n_jobs; j += gridDim.x) {
         const Job jb = job_of(a, j);
