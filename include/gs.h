@@ -8,7 +8,11 @@
  * (eq. importance-score, Sec. 3.3), the per-camera-cluster visibility indicator
  * lists used for test-time filtering (eq. importance-score-vis, Sec. 3.4), and the
  * gradient of a rendered image with respect to every Gaussian parameter (the
- * optimisation of phi in Sec. 3.2).
+ * optimisation of phi in Sec. 3.2). Around that path: the training loss of Sec. 3.2
+ * ((1 - lambda) L2 + lambda D-SSIM) and its gradient, pruning (stream compaction of
+ * every per-Gaussian array, Sec. 3.3), gathering a Gaussian subset into compact planes
+ * (materialised visibility lists), the initialisation of Sec. 3.2 (nearest-neighbour
+ * scales), and the Adam step that optimises phi.
  *
  * Model (the paper inherits it from 3D Gaussian splatting and leaves these
  * constants open; the values are the defaults of gs_params):
