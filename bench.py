@@ -625,7 +625,7 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
     return out
 
 
-def cpu_baseline(sc, cam, P, m=1024):
+def cpu_baseline(sc, cam, P, m=24576):
     """The FP64 oracle on the host: projection of all Gaussians for one view plus m random
     pixels; the frame time is extrapolated linearly in the pixel count."""
     import oracle
