@@ -207,13 +207,13 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
     const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
     const float amax = a.p.alpha_max, tmin = a.p.t_min;
     const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    bool done = !g.inside;
+    // T < t_min marks a finished ray; pixels outside the view start finished (T = -1, t_min >= 0)
+    float T = g.inside ? 1.f : -1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     uint32_t last = start, ncomp = 0;
     int cluster = 0;
     if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
     for (uint32_t base = start; base < end; base += BD) {
-        if (__syncthreads_and(done)) break;
+        if (__syncthreads_and(!(T >= tmin))) break;
         const uint32_t cnt = min((uint32_t)BD, end - base);
         stage<TW, TH, DEPTH>(sm, a, sp, base, cnt, g);
         if (MODE != MODE_FWD) {
@@ -234,7 +234,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                 // opacity and colour are requested together with the geometry
                 asm volatile("" ::"v"(s.opacity), "v"(s.rgb[0]), "v"(s.rgb[1]), "v"(s.rgb[2]));
                 const double q = quad(s, xc - s.u, yc - s.v);
-                const bool in = (q <= s.qmax) & !done;
+                const bool in = (q <= s.qmax) & (T >= tmin);
                 if (ballot(in) == 0) continue;
                 const float al = in ? clamp_alpha(s.opacity * falloff(q), amax) : 0.f;
                 const float wgt = al * T;
@@ -246,7 +246,6 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                 T = T * (1.f - al);
                 last = in ? base + j + 1 : last;
                 ncomp += in ? 1u : 0u;
-                done = done | (T < tmin);
                 // per staged record, combined over the workgroup's waves in LDS
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
@@ -258,7 +257,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                     if (ballot(wgt > a.t_cluster) != 0 && l == 0) atomicOr(&sm.hacc[j], 1u);
                 }
             }
-            if (ballot(!done) == 0) break;
+            if (ballot(T >= tmin) == 0) break;
         }
         if (MODE != MODE_FWD) {
             // one device-wide atomic per (tile, record) at most, and none when the value held
