@@ -25,7 +25,10 @@
 
 namespace gs {
 
-enum { MODE_FWD = 0, MODE_IMPORTANCE = 1, MODE_VISIBILITY = 2 };
+// MODE_FWD_COUNT is the forward pass that also counts the entries composited into each pixel
+// (gs_render_fwd with n_contrib); the count costs two VALU instructions per hit, so the plain
+// forward leaves it out
+enum { MODE_FWD = 0, MODE_IMPORTANCE = 1, MODE_VISIBILITY = 2, MODE_FWD_COUNT = 3 };
 
 struct RenderArgs {
     const gs_splat* splat;
@@ -216,7 +219,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
         if (__syncthreads_and(!(T >= tmin))) break;
         const uint32_t cnt = min((uint32_t)BD, end - base);
         stage<TW, TH, DEPTH>(sm, a, sp, base, cnt, g);
-        if (MODE != MODE_FWD) {
+        if (MODE == MODE_IMPORTANCE || MODE == MODE_VISIBILITY) {
 #pragma unroll
             for (int d = 0; d < DEPTH; ++d) sm.hacc[threadIdx.x + d * TW * TH] = 0u;
         }
@@ -238,14 +241,14 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
                 if (ballot(in) == 0) continue;
                 const float al = in ? clamp_alpha(s.opacity * falloff(q), amax) : 0.f;
                 const float wgt = al * T;
-                if (MODE == MODE_FWD) {  // colours are finite, so wgt = 0 adds exactly nothing
+                if (MODE == MODE_FWD || MODE == MODE_FWD_COUNT) {  // colours are finite: wgt = 0 adds nothing
                     C0 = fmaf(wgt, s.rgb[0], C0);
                     C1 = fmaf(wgt, s.rgb[1], C1);
                     C2 = fmaf(wgt, s.rgb[2], C2);
                 }
                 T = T * (1.f - al);
                 last = in ? base + j + 1 : last;
-                ncomp += in ? 1u : 0u;
+                if (MODE == MODE_FWD_COUNT) ncomp += in ? 1u : 0u;
                 // per staged record, combined over the workgroup's waves in LDS
                 if (MODE == MODE_IMPORTANCE) {
                     if (ballot(wgt > 0.f)) {
@@ -259,7 +262,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
             }
             if (ballot(T >= tmin) == 0) break;
         }
-        if (MODE != MODE_FWD) {
+        if (MODE == MODE_IMPORTANCE || MODE == MODE_VISIBILITY) {
             // one device-wide atomic per (tile, record) at most, and none when the value held
             // already covers it (a stale read can only cause a redundant atomic)
             __syncthreads();
@@ -282,7 +285,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
         }
     }
     __syncthreads();  // the staging area is reused by the next tile of a persistent workgroup
-    if (MODE == MODE_FWD && g.inside) {
+    if ((MODE == MODE_FWD || MODE == MODE_FWD_COUNT) && g.inside) {
         const int64_t plane = (int64_t)g.W * g.H;
         float* out = a.rgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
         out[0] = C0 + T * a.p.bg[0];
@@ -290,7 +293,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
         out[2 * plane] = C2 + T * a.p.bg[2];
         a.t_final[g.pix] = T;
         a.n_last[g.pix] = last;
-        if (a.n_contrib) a.n_contrib[g.pix] = ncomp;
+        if (MODE == MODE_FWD_COUNT) a.n_contrib[g.pix] = ncomp;
     }
 }
 
@@ -629,8 +632,11 @@ gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, con
     a.t_final = t_final;
     a.n_last = n_last;
     a.n_contrib = n_contrib;
-    return finish(launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s),
-                  "render_fwd");
+    const bool ok = n_contrib ? launch_mode<MODE_FWD_COUNT>(a, views->tile_w, views->tile_h, views->batch_depth,
+                                                            views->n_tiles, s)
+                              : launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->batch_depth,
+                                                      views->n_tiles, s);
+    return finish(ok, "render_fwd");
 }
 
 gs_status launch_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
