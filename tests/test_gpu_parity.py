@@ -888,3 +888,34 @@ def test_trainer_fits_and_prunes_with_moments():
         assert torch.equal(a, b[..., kept])
     tr.step()
     assert tr.ok() and np.isfinite(tr.loss.item())
+
+
+def test_session_initialise_train_prune_filter_render():
+    """The calls of a whole session chained at a small size: initialisation from points and
+    colours, the optimisation loop with one pruning, importance, materialised visibility lists
+    and a filtered frame equal to the subset render of the same list."""
+    from paper_2403_13806_amd import train
+    sc = scenes.mixture_scene(3000, seed=14, sh_degree=3, radius=2.0)
+    cams = scenes.orbit_views(6, 80, 60, radius=6.0)
+    teacher = gs.Gaussians.from_scene(sc, DEV)
+    targets = [gs.render(teacher, gs.ViewBatch([c], device=DEV), P)["rgb"].cpu().numpy() for c in cams]
+    rng = np.random.default_rng(15)
+    pts = torch.as_tensor(sc.mean, device=DEV)
+    cols = torch.as_tensor(rng.uniform(0, 1, (3, sc.mean.shape[1])).astype(np.float32), device=DEV)
+    _say("session")
+    g = gs.init_gaussians(pts, cols, 3)
+    assert torch.isfinite(g.scale).all() and (g.scale > 0).all()
+    tr = train.Trainer(g, cams, targets, P, train.TrainConfig(steps=40, prune_steps=(25,), t_prune=0.002), device=DEV)
+    losses = []
+    for _ in range(40):
+        tr.step()
+        losses.append(float(tr.loss.item()))
+    assert tr.ok() and np.mean(losses[-8:]) < np.mean(losses[:8])
+    assert len(tr.history) == 1 and tr.g.n == tr.history[0]["after"] <= 3000
+    h = gs.importance(tr.g, gs.ViewBatch(cams, device=DEV), P)
+    assert h.shape[0] == tr.g.n and float(h.max()) > 0
+    vf = gs.VisibilityFilter(tr.g, cams, k=2, t_cluster=0.01, params=P, device=DEV, materialize=True)
+    test_cam = scenes.orbit_views(1, 80, 60, radius=6.5, seed=99)[0]
+    frame = vf.render(test_cam)["rgb"]
+    ref = gs.render(tr.g, gs.ViewBatch([test_cam], device=DEV), P, subset=vf.list_for(test_cam))["rgb"]
+    assert torch.equal(frame, ref)
