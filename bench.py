@@ -234,7 +234,26 @@ def main():
                 "per_unit": f"{OPS_PER_COMPOSITE} lane-ops per composited (pixel, Gaussian)",
                 "units_per_launch": mc, "avg_launch_ms": avg["render_fwd"]}
 
+    # the same frames with two buffer sets on two streams (PathRenderer(pipeline=2)): the
+    # projection and binning of one frame overlap the compositing of the previous one
+    from paper_2403_13806_amd.splat import PathRenderer
+    pipe = PathRenderer(g, cams, P, device=dev, pipeline=2)
+    for k in range(W):
+        pipe.frame(k % len(cams))
+    pipe.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        pipe.frame(k % len(cams))
+    pipe.sync()
+    torch.cuda.synchronize()
+    pipelined_fps = K / (time.perf_counter() - t0)
+    assert pipe.ok()
+    del pipe
+    log(f"pipelined (2 streams, 2 buffer sets): {pipelined_fps:.1f} frames/s")
+
     extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3,
+             "pipelined_2_streams_frames_per_s": pipelined_fps,
              "copy_256MiB_GBps": copy_gbps}
     extra["prune"] = prune_pass(torch, gs, g, h_buf, dev)
     extra["loss_l2_dssim"] = loss_pass(torch, gs, scenes, dev)

@@ -712,14 +712,19 @@ class VisibilityFilter:
 
 
 class PathRenderer:
-    """Frames of a camera path (all of one resolution) rendered with one set of buffers and no
+    """Frames of a camera path (all of one resolution) rendered with persistent buffers and no
     host synchronisation per frame: the cameras of every frame are uploaded once and each
     frame points the view batch at its own camera. A frame may render only a subset of the
-    Gaussians (a visibility list). The pair capacity is fixed; ok() reports overflows."""
+    Gaussians (a visibility list). The pair capacity is fixed; ok() reports overflows.
+
+    pipeline = k > 1 keeps k buffer sets and k streams (default priority): frame f runs on
+    stream f mod k, so the projection and binning of one frame overlap the compositing of the
+    previous one. Its result stays valid until frame f + k is enqueued; call sync() before
+    reading it on the current stream."""
 
     def __init__(self, g: Gaussians, cams: Sequence, params=None, tile: Tuple[int, int] = DEFAULT_TILE,
                  capacity: Optional[int] = None, max_entries: Optional[int] = None, device=None,
-                 persistent: bool = False, batch_depth: int = 1):
+                 persistent: bool = False, batch_depth: int = 1, pipeline: int = 1):
         dev = _dev(device)
         self.g, self.params, self.device = g, params, dev
         self.p = make_params(params)
@@ -742,10 +747,25 @@ class PathRenderer:
         self.n_last = torch.empty(self.views.n_pixels, dtype=torch.int32, device=dev)
         self._sg = g.struct()
         self._sb = self.bins.struct()
+        self._sets = [(self.proj, self.bins, self._sb, self.ws, self.rgb, self.t_final, self.n_last)]
+        for _ in range(1, max(1, int(pipeline))):
+            bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.persistent)
+            self._sets.append((Projected(self.max_entries, 1, dev), bins, bins.struct(),
+                               alloc_workspace(self.max_entries, 1, capacity, self.views.n_tiles, dev),
+                               torch.empty_like(self.rgb), torch.empty_like(self.t_final),
+                               torch.empty_like(self.n_last)))
+        self.streams = [torch.cuda.Stream(device=dev) for _ in self._sets] if len(self._sets) > 1 else None
 
     def _proj_n(self, n):
         self.proj.n = n
         return self.proj
+
+    def sync(self):
+        """Make the current stream wait for every frame enqueued so far."""
+        if self.streams:
+            cur = torch.cuda.current_stream(self.device)
+            for st in self.streams:
+                cur.wait_stream(st)
 
     def frame(self, f: int, subset: Optional[torch.Tensor] = None, g: Optional["Gaussians"] = None):
         """Enqueue frame f (optionally with only the listed Gaussians, or with another set of
@@ -759,16 +779,25 @@ class PathRenderer:
             raise ValueError("subset larger than max_entries")
         sv = self.views.struct()
         sv.cams = ctypes.c_void_p(self.cams_all.data_ptr() + ctypes.sizeof(L.gs_camera) * f)
-        sp = self._proj_n(n).struct()
-        s = _stream(self.device)
+        k = f % len(self._sets)
+        proj, _, sb, ws, rgb, t_final, n_last = self._sets[k]
+        proj.n = n
+        sp = proj.struct()
+        if self.streams:
+            st = self.streams[k]
+            st.wait_stream(torch.cuda.current_stream(self.device))  # inputs made on the caller's stream
+            s = ctypes.c_void_p(st.cuda_stream)
+        else:
+            s = _stream(self.device)
         L.check(lib.gs_preprocess(ctypes.byref(src), ctypes.byref(sv), ctypes.byref(self.p), _ptr(subset), n, 1,
                                   ctypes.byref(sp), s))
-        L.check(lib.gs_bin_sort(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(self._sb), _ptr(self.ws),
-                                self.ws.numel(), s))
-        L.check(lib.gs_render_fwd(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(self._sb), ctypes.byref(self.p),
-                                  _ptr(self.rgb), _ptr(self.t_final), _ptr(self.n_last), None, s))
-        return self.rgb
+        L.check(lib.gs_bin_sort(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(sb), _ptr(ws), ws.numel(), s))
+        L.check(lib.gs_render_fwd(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(sb), ctypes.byref(self.p),
+                                  _ptr(rgb), _ptr(t_final), _ptr(n_last), None, s))
+        return rgb
 
     def ok(self) -> bool:
-        """True when the last frame fit the pair buffer (synchronises)."""
-        return int(self.bins.overflow.item()) == 0
+        """True when no frame of any buffer set overflowed its pair buffer since the last frame
+        enqueued on that set (synchronises)."""
+        self.sync()
+        return all(int(b.overflow.item()) == 0 for _, b, *_ in self._sets)

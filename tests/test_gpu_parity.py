@@ -919,3 +919,24 @@ def test_session_initialise_train_prune_filter_render():
     frame = vf.render(test_cam)["rgb"]
     ref = gs.render(tr.g, gs.ViewBatch([test_cam], device=DEV), P, subset=vf.list_for(test_cam))["rgb"]
     assert torch.equal(frame, ref)
+
+
+def test_path_renderer_pipeline_matches_single_stream():
+    """Two buffer sets on two streams: every frame equals the single-stream frame bitwise."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    sc = scenes.mixture_scene(30000, seed=16, sh_degree=3)
+    cams = scenes.orbit_views(5, 160, 106)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("pipelined path renderer")
+    p1 = PathRenderer(g, cams, P, device=DEV)
+    p2 = PathRenderer(g, cams, P, device=DEV, pipeline=2, capacity=p1.bins.capacity)
+    outs = []
+    for f in range(len(cams)):
+        outs.append(p2.frame(f))
+        if f % 2 == 1 or f == len(cams) - 1:  # read a pair of frames before their buffers are reused
+            p2.sync()
+            for k in range(len(outs)):
+                ref = p1.frame(f - len(outs) + 1 + k).clone()
+                assert torch.equal(outs[k], ref), f - len(outs) + 1 + k
+            outs = []
+    assert p1.ok() and p2.ok()
