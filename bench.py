@@ -617,6 +617,20 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
             pr.frame(f, lists[f], copies[f])
         torch.cuda.synchronize()
         rates[name] = len(path) / (time.perf_counter() - t0)
+    # the materialised frames pipelined over two streams
+    pr2 = PathRenderer(g, path, P, device=dev, max_entries=g.n, pipeline=2, capacity=pr.bins.capacity)
+    for f in range(3):
+        pr2.frame(f, None, frame_copies[f])
+    pr2.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(len(path)):
+        pr2.frame(f, None, frame_copies[f])
+    pr2.sync()
+    torch.cuda.synchronize()
+    rates["filtered_materialized_pipelined"] = len(path) / (time.perf_counter() - t0)
+    assert pr2.ok()
+    del pr2
     # validation pass (untimed): capacity, and filtered vs unfiltered image difference
     maxd, psnr = 0.0, []
     for f in range(0, len(path), 25):
@@ -635,11 +649,13 @@ def filtered_pass(torch, gs, scenes, P, dev, n=5_000_000, k=64, t_cluster=0.01, 
            "unfiltered_fps": rates["unfiltered"], "filtered_fps": rates["filtered"],
            "speedup": rates["filtered"] / rates["unfiltered"],
            "filtered_materialized_fps": rates["filtered_materialized"],
+           "filtered_materialized_pipelined_fps": rates["filtered_materialized_pipelined"],
            "speedup_materialized": rates["filtered_materialized"] / rates["unfiltered"],
            "materialize_s": t_mat, "materialized_bytes": vf.copy_bytes(),
            "filtered_vs_unfiltered_max_abs": maxd, "filtered_vs_unfiltered_psnr_min": float(min(psnr))}
     log(f"  lists mean {sizes.mean():.0f}; unfiltered {rates['unfiltered']:.0f} fps, filtered "
         f"{rates['filtered']:.0f} fps, filtered from materialised copies {rates['filtered_materialized']:.0f} fps "
+        f"({rates['filtered_materialized_pipelined']:.0f} pipelined over two streams) "
         f"({vf.copy_bytes() / 1e9:.2f} GB, built in {t_mat:.2f} s); max |diff| {maxd:.3g}, min PSNR {min(psnr):.1f} dB")
     return out
 
