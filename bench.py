@@ -235,22 +235,11 @@ def main():
                 "units_per_launch": mc, "avg_launch_ms": avg["render_fwd"]}
 
     # the same frames with two buffer sets on two streams (PathRenderer(pipeline=2)): the
-    # projection and binning of one frame overlap the compositing of the previous one
-    from paper_2403_13806_amd.splat import PathRenderer
-    pipe = PathRenderer(g, cams, P, device=dev, pipeline=2)
-    for k in range(W):
-        pipe.frame(k % len(cams))
-    pipe.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
-        pipe.frame(k % len(cams))
-    pipe.sync()
-    torch.cuda.synchronize()
-    pipelined_fps = K / (time.perf_counter() - t0)
-    assert pipe.ok()
-    del pipe
-    log(f"pipelined (2 streams, 2 buffer sets): {pipelined_fps:.1f} frames/s")
+    # projection and binning of one frame overlap the compositing of the previous one. Not in
+    # the quick run, whose kernel trace must time single-stream launches only
+    pipelined_fps = None
+    if not args.quick:
+        pipelined_fps = pipelined_frames(torch, gs, P, dev, g, cams, K, W)
 
     extra = {"stages": stage_rows, "work": work, "events_frames_per_s": K / ev_ms * 1e3,
              "pipelined_2_streams_frames_per_s": pipelined_fps,
@@ -337,6 +326,25 @@ def prune_pass(torch, gs, g, h, dev, t_prune=0.01, reps=5):
     return {"planes": len(rows_in), "gaussians": n, "kept": nk, "t_prune": t_prune, "ms": ms,
             "alg_GBps": alg / ms / 1e6, "hbm_frac": alg / ms / 1e-3 / PEAK_HBM,
             "stream_GBps": stream / ms / 1e6, "stream_hbm_frac": stream / ms / 1e-3 / PEAK_HBM}
+
+
+def pipelined_frames(torch, gs, P, dev, g, cams, K, W):
+    """The headline frames rendered by PathRenderer(pipeline=2)."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    pipe = PathRenderer(g, cams, P, device=dev, pipeline=2)
+    for k in range(W):
+        pipe.frame(k % len(cams))
+    pipe.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        pipe.frame(k % len(cams))
+    pipe.sync()
+    torch.cuda.synchronize()
+    fps = K / (time.perf_counter() - t0)
+    assert pipe.ok()
+    log(f"pipelined (2 streams, 2 buffer sets): {fps:.1f} frames/s")
+    return fps
 
 
 def loss_pass(torch, gs, scenes, dev, reps=20):
