@@ -383,8 +383,7 @@ def init_pass(torch, gs, scenes, dev, reps=5):
             g = gs.init_gaussians(pts, col, 3)
     ms = tm.ms() / reps
     log(f"init: 1M house points, {ms:.3f} ms (nearest-neighbour scales + constants)")
-    return {"points": int(pts.shape[1]), "ms": ms, "points_per_s": pts.shape[1] / ms * 1e3,
-            "median_scale": float(g.scale[0].median().item())}
+    return {"points": int(pts.shape[1]), "ms": ms, "points_per_s": pts.shape[1] / ms * 1e3}
 
 
 def trainer_pass(torch, gs, scenes, P, dev, g, cams, steps=20):
