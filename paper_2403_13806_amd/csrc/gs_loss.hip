@@ -33,7 +33,6 @@ namespace {
 
 constexpr int SX = 64, SY = 16, SR = 5, ST = 2 * SR + 1;
 constexpr int IX = SX + 2 * SR, IY = SY + 2 * SR;  // 74 x 26 input window of a tile
-constexpr int MX = 76;                              // map row stride in LDS (16-byte rows)
 constexpr int NTH = 256;
 
 struct SsimArgs {
