@@ -240,44 +240,57 @@ __global__ __launch_bounds__(256) void k_count_bsums(const uint32_t* __restrict_
     }
 }
 
+// one workgroup scans the block sums in chunks of SB_T * 4 (coalesced loads, the next chunk
+// requested before the current one is scanned) with a running carry
 __global__ __launch_bounds__(SB_T) void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t m, uint64_t* total_out,
                                                      uint32_t* flags, uint64_t capacity) {
+    constexpr int CH = SB_T * 4;
     __shared__ uint64_t part[SB_T / 64 + 1];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int64_t per = (m + SB_T - 1) / SB_T;
-    const int64_t b0 = (int64_t)t * per, b1 = min(m, b0 + per);
-    uint64_t s = 0;
-    for (int64_t i = b0; i < b1; ++i) s += bsum[i];
-    // inclusive scan of the per-thread u64 sums over the wave
-    uint64_t incl = s;
+    uint64_t carry = 0;
+    uint32_t nx[4];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = (uint64_t)__shfl_up((long long)incl, d);
-        if (l >= d) incl += y;
-    }
-    if (l == 63) part[w] = incl;
-    __syncthreads();
-    if (t == 0) {
-        uint64_t run = 0;
-        for (int k = 0; k < SB_T / 64; ++k) {
-            const uint64_t v = part[k];
-            part[k] = run;
-            run += v;
+    for (int k = 0; k < 4; ++k) nx[k] = (int64_t)4 * t + k < m ? bsum[4 * t + k] : 0u;
+    for (int64_t base = 0; base < m; base += CH) {
+        uint32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = nx[k];
+        const int64_t nb = base + CH;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nx[k] = nb + 4 * t + k < m ? bsum[nb + 4 * t + k] : 0u;
+        const uint64_t s = (uint64_t)x[0] + x[1] + x[2] + x[3];
+        // inclusive scan of the per-thread sums over the wave, then over the waves
+        uint64_t incl = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = (uint64_t)__shfl_up((long long)incl, d);
+            if (l >= d) incl += y;
         }
-        part[SB_T / 64] = run;
-    }
-    __syncthreads();
-    uint64_t pre = part[w] + incl - s;
-    // offsets past 2^32 only occur when the capacity check below has failed
-    for (int64_t i = b0; i < b1; ++i) {
-        const uint32_t x = bsum[i];
-        bsum[i] = (uint32_t)pre;
-        pre += x;
+        if (l == 63) part[w] = incl;
+        __syncthreads();
+        if (t == 0) {
+            uint64_t run = 0;
+            for (int k = 0; k < SB_T / 64; ++k) {
+                const uint64_t v = part[k];
+                part[k] = run;
+                run += v;
+            }
+            part[SB_T / 64] = run;
+        }
+        __syncthreads();
+        // offsets past 2^32 only occur when the capacity check below has failed
+        uint64_t pre = carry + part[w] + incl - s;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (base + 4 * t + k < m) bsum[base + 4 * t + k] = (uint32_t)pre;
+            pre += x[k];
+        }
+        carry += part[SB_T / 64];
+        __syncthreads();  // part is rewritten by the next chunk
     }
     if (t == 0) {
-        const uint64_t total = part[SB_T / 64];
-        if (total_out) *total_out = total;
-        if (flags && total > capacity) atomicOr(flags, 1u);
+        if (total_out) *total_out = carry;
+        if (flags && carry > capacity) atomicOr(flags, 1u);
     }
 }
 
