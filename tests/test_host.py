@@ -258,3 +258,21 @@ def test_generators_shapes_and_determinism():
     o = scenes.orbit_camera(0.0, 0.0, 4.0, 128, 96, fx=100.0)
     pv = scenes.plain_view()
     assert np.allclose(o.R, pv.R, atol=1e-7) and np.allclose(o.t, pv.t, atol=1e-6)
+
+
+def test_training_config_and_helpers():
+    """Host-side pieces of the optimisation loop: the paper's schedule and thresholds, the
+    light variant, the camera extent that scales the position learning rate, and the check
+    that every training view shares one resolution (raised before any device work)."""
+    from paper_2403_13806_amd import train
+    c = train.TrainConfig()
+    assert c.prune_steps == (16000, 24000) and c.t_prune == 0.01 and c.lam == 0.2
+    assert train.TrainConfig.light().t_prune == 0.25
+    cams = scenes.orbit_views(6, 64, 48, radius=4.0)
+    ext = train.camera_extent(cams)
+    assert abs(ext - 1.1 * 4.0) < 0.5  # centres on a sphere of radius 4 around the origin
+    odd = [cams[0], scenes.orbit_views(1, 80, 48)[0]]
+    with pytest.raises(ValueError, match="resolution"):
+        train.Trainer(None, odd, [None, None], device="cpu")
+    with pytest.raises(ValueError):
+        train.FwdBwdStep(None, cams, [], loss="l3")
