@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="headline only")
-    ap.add_argument("--only", choices=["batched", "importance", "house", "training"], default=None,
+    ap.add_argument("--only", choices=["batched", "importance", "house", "training", "kmeans"], default=None,
                     help="run one secondary workload alone (for profiling) and print its numbers")
     return ap.parse_args()
 
@@ -100,6 +100,8 @@ def main():
             sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
             g = gs.Gaussians.from_scene(sc, dev)
             res = trainer_pass(torch, gs, scenes, P, dev, g, scenes.orbit_views(8), steps=K)
+        elif args.only == "kmeans":
+            res = kmeans_pass(torch, gs, scenes, dev)
         else:
             res = filtered_pass(torch, gs, scenes, P, dev)
         print(json.dumps({"only": args.only, **res}), flush=True)
@@ -255,6 +257,7 @@ def main():
         extra["importance_150_views"] = importance_pass(torch, gs, scenes, P, dev)
         extra["house_filtering"] = filtered_pass(torch, gs, scenes, P, dev)
         extra["training_loop"] = trainer_pass(torch, gs, scenes, P, dev, g, cams)
+        extra["kmeans_131072_cameras"] = kmeans_pass(torch, gs, scenes, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -384,6 +387,35 @@ def init_pass(torch, gs, scenes, dev, reps=5):
     ms = tm.ms() / reps
     log(f"init: 1M house points, {ms:.3f} ms (nearest-neighbour scales + constants)")
     return {"points": int(pts.shape[1]), "ms": ms, "points_per_s": pts.shape[1] / ms * 1e3}
+
+
+def kmeans_pass(torch, gs, scenes, dev, reps=3):
+    """Camera clustering (Sec. 3.4) of a large camera set: 131072 camera centres drawn over the
+    12 house rooms, 64 clusters, at most 100 Lloyd iterations on the device from the host
+    k-means++ seeding; the host FP64 k-means on the same set timed once beside it."""
+    pos = scenes.house_camera_positions(131072)
+    t0 = time.perf_counter()
+    init = gs.kmeans_seed(pos, 64, seed=3)
+    seed_ms = (time.perf_counter() - t0) * 1e3
+    pos_d = torch.as_tensor(pos, device=dev)
+    init_d = torch.as_tensor(init, device=dev)
+    cen = init_d.clone()
+    ws = torch.empty(int(gs.load().gs_kmeans_workspace_bytes(131072, 64, 100)), dtype=torch.uint8, device=dev)
+    gs.kmeans_lloyd(pos_d, cen, 100, ws)
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(reps):
+            cen.copy_(init_d)
+            _, iters = gs.kmeans_lloyd(pos_d, cen, 100, ws)
+    ms = tm.ms() / reps
+    it = int(iters.item())
+    t0 = time.perf_counter()
+    gs.kmeans(pos, 64, seed=3)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    log(f"kmeans: 131072 cameras, 64 clusters, {it} iterations: device Lloyd {ms:.3f} ms, host seeding "
+        f"{seed_ms:.1f} ms, host k-means {host_ms:.1f} ms")
+    return {"cameras": 131072, "clusters": 64, "iterations": it, "device_lloyd_ms": ms, "host_seed_ms": seed_ms,
+            "host_kmeans_ms": host_ms}
 
 
 def trainer_pass(torch, gs, scenes, P, dev, g, cams, steps=20):

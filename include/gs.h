@@ -361,10 +361,37 @@ gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, double bet
 /* Host: k-means on camera positions (Sec. 3.4, input camera clustering), FP64 Lloyd
  * iterations from a k-means++ seeding with the given seed, at most max_iter iterations
  * or until assignments stop changing; ties go to the lowest centre; an empty cluster is
- * re-seeded at the point farthest from its centre. pos: host [m][3]; centres: host
+ * re-seeded at the point farthest from its centre in that iteration's assignment (ties to
+ * the lowest index); sums run in index order. pos: host [m][3]; centres: host
  * [k][3]; assign: host [m]. */
 gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int32_t max_iter, double* centres,
                     int32_t* assign);
+
+/* Host: the k-means++ seeding of gs_kmeans alone (Sec. 3.4, input camera clustering): the
+ * same splitmix64 stream from the seed, so gs_kmeans_lloyd from these centres follows
+ * gs_kmeans. pos: host [m][3]; centres: host [k][3], written. Needs 1 <= k <= m. */
+gs_status gs_kmeans_seed(const double* pos, int32_t m, int32_t k, uint64_t seed, double* centres);
+
+/* Workspace of gs_kmeans_lloyd in bytes (0 for invalid sizes). */
+size_t gs_kmeans_workspace_bytes(int64_t m, int32_t k, int32_t max_iter);
+
+/* Device: FP64 Lloyd iterations of k-means on camera positions (Sec. 3.4, input camera
+ * clustering), for camera sets too large for the host loop. From the centres given, each
+ * iteration assigns every point to its nearest centre (squared distance formed as
+ * (dx dx + dy dy) + dz dz without fused multiply-add; ties to the lowest centre) and stops
+ * if, after the first iteration, no assignment changed; otherwise each centre moves to the
+ * mean of its points and a centre without points moves to the point farthest from its
+ * centre in that assignment (ties to the lowest index). After max_iter updates the points
+ * are assigned once more. Sums run in a fixed order, so results repeat from run to run and
+ * differ from a sequential sum in the last bits only.
+ * pos: device [m][3] FP64, finite; centres: device [k][3], initial centres in, final out;
+ * assign: device [m] int32 out; iterations: device int32 out (centre updates made), or NULL;
+ * ws: device workspace of gs_kmeans_workspace_bytes(m, k, max_iter). Needs 1 <= k <= m,
+ * k <= 2048, 1 <= max_iter <= 10^6, m < 2^31; pos, centres and assign must not overlap.
+ * Asynchronous on the stream: 3 max_iter + 2 launches, those after convergence return at
+ * once. Cost per iteration O(m k). */
+gs_status gs_kmeans_lloyd(const double* pos, int64_t m, int32_t k, int32_t max_iter, double* centres,
+                          int32_t* assign, int32_t* iterations, void* ws, size_t ws_bytes, void* stream);
 
 /* Host: index of the centre nearest to x (squared distance, ties to the lowest index),
  * the cluster whose list renders a test view (Sec. 3.4). */

@@ -22,6 +22,6 @@ from ._lib import GSError, load  # noqa: F401
 from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, VisibilityFilter,  # noqa: F401
                     adam_step, alloc_workspace,
                     bin_sort, bits_to_list, cluster_visibility, gather, gather_gaussians, importance, kmeans,
-                    init_gaussians, l1_loss_grad, make_params, nearest_centre, nn_distance,
+                    kmeans_lloyd, kmeans_seed, init_gaussians, l1_loss_grad, make_params, nearest_centre, nn_distance,
                     preprocess, prune, prune_gaussians, prune_mask, render, render_bwd, render_fwd,
                     ssim_loss_grad, ssim_workspace_bytes, workspace_bytes)

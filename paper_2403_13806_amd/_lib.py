@@ -70,7 +70,8 @@ assert ctypes.sizeof(gs_camera) == 80
 SPLAT_BYTES = 64
 
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_nearest_centre",
+           "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_kmeans_seed",
+           "gs_kmeans_workspace_bytes", "gs_kmeans_lloyd", "gs_nearest_centre",
            "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
            "gs_gather", "gs_nn_workspace_bytes", "gs_nn_distance", "gs_init_gaussians",
            "gs_adam_step", "gs_last_error"]
@@ -141,6 +142,13 @@ def load(path: str = LIB_PATH):
     L.gs_adam_step.restype = i32
     L.gs_kmeans.argtypes = [c_void_p, i32, i32, u64, i32, c_void_p, c_void_p]
     L.gs_kmeans.restype = i32
+    L.gs_kmeans_seed.argtypes = [c_void_p, i32, i32, u64, c_void_p]
+    L.gs_kmeans_seed.restype = i32
+    L.gs_kmeans_workspace_bytes.argtypes = [i64, i32, i32]
+    L.gs_kmeans_workspace_bytes.restype = ctypes.c_size_t
+    L.gs_kmeans_lloyd.argtypes = [c_void_p, i64, i32, i32, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_size_t,
+                                  c_void_p]
+    L.gs_kmeans_lloyd.restype = i32
     L.gs_nearest_centre.argtypes = [c_void_p, i32, c_void_p]
     L.gs_nearest_centre.restype = i32
     L.gs_last_error.argtypes = []

@@ -43,6 +43,10 @@ gs_status launch_prune(const float*, int64_t, float, const float* const*, float*
 gs_status launch_gather(const int32_t*, int64_t, int64_t, const float* const*, float* const*, int32_t, hipStream_t);
 gs_status launch_fill_f32(float*, int64_t, float, hipStream_t);
 size_t nn_workspace_bytes(int64_t);
+int32_t kmeans_max_centres();
+size_t kmeans_workspace_bytes(int64_t, int32_t, int32_t);
+gs_status launch_kmeans_lloyd(const double*, int64_t, int32_t, int32_t, double*, int32_t*, int32_t*, void*,
+                              hipStream_t);
 gs_status launch_adam(const gs_adam_group*, int32_t, double, double, double, int64_t, int32_t, hipStream_t);
 gs_status launch_nn_distance(const float*, int64_t, float*, void*, hipStream_t);
 gs_status launch_init_gaussians(const float*, const float*, int64_t, int32_t, float*, float*, float*, float*, float*,
@@ -377,6 +381,30 @@ gs_status gs_init_gaussians(const float* points, const float* colours, int64_t n
                                  (hipStream_t)stream);
 }
 
+size_t gs_kmeans_workspace_bytes(int64_t m, int32_t k, int32_t max_iter) {
+    return kmeans_workspace_bytes(m, k, max_iter);
+}
+
+gs_status gs_kmeans_lloyd(const double* pos, int64_t m, int32_t k, int32_t max_iter, double* centres,
+                          int32_t* assign, int32_t* iterations, void* ws, size_t ws_bytes, void* stream) {
+    if (!pos || !centres || !assign || m < 1 || k < 1 || k > m || max_iter < 1)
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans_lloyd: need 1 <= k <= m, max_iter >= 1 and non-NULL buffers");
+    if (m >= ((int64_t)1 << 31)) return set_error(GS_ERR_UNSUPPORTED, "gs_kmeans_lloyd: at most 2^31-1 points");
+    if (k > kmeans_max_centres())
+        return set_error(GS_ERR_UNSUPPORTED, "gs_kmeans_lloyd: at most %d centres (got %d)", kmeans_max_centres(), k);
+    if (max_iter > 1000000) return set_error(GS_ERR_UNSUPPORTED, "gs_kmeans_lloyd: at most 10^6 iterations");
+    const size_t need = kmeans_workspace_bytes(m, k, max_iter);
+    if (ws_bytes < need || !ws)
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans_lloyd: workspace too small: %zu bytes, need %zu", ws_bytes,
+                         need);
+    const char *p0 = (const char*)pos, *p1 = p0 + 24 * m, *c0 = (const char*)centres, *c1 = c0 + 24 * (int64_t)k,
+               *a0 = (const char*)assign, *a1 = a0 + 4 * m;
+    auto overlap = [](const char* b0, const char* e0, const char* b1, const char* e1) { return b0 < e1 && b1 < e0; };
+    if (overlap(p0, p1, c0, c1) || overlap(p0, p1, a0, a1) || overlap(c0, c1, a0, a1))
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans_lloyd: pos, centres and assign must not overlap");
+    return launch_kmeans_lloyd(pos, m, k, max_iter, centres, assign, iterations, ws, (hipStream_t)stream);
+}
+
 gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, double beta1, double beta2, double eps,
                        int64_t step, int32_t zero_grad, void* stream) {
     if (n_groups < 0 || (n_groups > 0 && !groups) || step < 1)
@@ -409,6 +437,7 @@ static uint64_t splitmix64(uint64_t& s) {
 static double uniform01(uint64_t& s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
 
 static double d2(const double* a, const double* b) {
+#pragma clang fp contract(off)
     const double x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
     return x * x + y * y + z * z;
 }
@@ -427,10 +456,7 @@ int32_t gs_nearest_centre(const double* centres, int32_t k, const double* x) {
     return best;
 }
 
-gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int32_t max_iter, double* centres,
-                    int32_t* assign) {
-    if (!pos || !centres || !assign || m < 1 || k < 1 || k > m || max_iter < 0)
-        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans: need 1 <= k <= m and non-NULL buffers");
+static void kmeans_seed(const double* pos, int32_t m, int32_t k, uint64_t seed, double* centres) {
     uint64_t s = seed;
     // k-means++ seeding
     std::vector<double> dist(m);
@@ -457,6 +483,20 @@ gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int3
         for (int e = 0; e < 3; ++e) centres[3 * c + e] = pos[3 * pick + e];
         for (int32_t i = 0; i < m; ++i) dist[i] = std::min(dist[i], d2(pos + 3 * i, centres + 3 * c));
     }
+}
+
+gs_status gs_kmeans_seed(const double* pos, int32_t m, int32_t k, uint64_t seed, double* centres) {
+    if (!pos || !centres || m < 1 || k < 1 || k > m)
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans_seed: need 1 <= k <= m and non-NULL buffers");
+    kmeans_seed(pos, m, k, seed, centres);
+    return GS_OK;
+}
+
+gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int32_t max_iter, double* centres,
+                    int32_t* assign) {
+    if (!pos || !centres || !assign || m < 1 || k < 1 || k > m || max_iter < 0)
+        return set_error(GS_ERR_INVALID_ARG, "gs_kmeans: need 1 <= k <= m and non-NULL buffers");
+    kmeans_seed(pos, m, k, seed, centres);
     // Lloyd iterations
     for (int32_t i = 0; i < m; ++i) assign[i] = -1;
     std::vector<double> sum(3 * (size_t)k);
@@ -478,12 +518,11 @@ gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int3
             for (int e = 0; e < 3; ++e) sum[3 * c + e] += pos[3 * i + e];
             cnt[c]++;
         }
-        for (int32_t c = 0; c < k; ++c) {
-            if (cnt[c] > 0) {
-                for (int e = 0; e < 3; ++e) centres[3 * c + e] = sum[3 * c + e] / cnt[c];
-            } else {
-                // empty cluster: re-seed at the point farthest from its assigned centre
-                int32_t far = 0;
+        // an empty cluster is re-seeded at the point farthest from its assigned centre (the
+        // centres of this assignment, before any of them moves; ties to the lowest index)
+        int32_t far = -1;
+        for (int32_t c = 0; c < k && far < 0; ++c)
+            if (cnt[c] == 0) {
                 double fd = -1;
                 for (int32_t i = 0; i < m; ++i) {
                     const double d = d2(pos + 3 * i, centres + 3 * assign[i]);
@@ -492,6 +531,11 @@ gs_status gs_kmeans(const double* pos, int32_t m, int32_t k, uint64_t seed, int3
                         far = i;
                     }
                 }
+            }
+        for (int32_t c = 0; c < k; ++c) {
+            if (cnt[c] > 0) {
+                for (int e = 0; e < 3; ++e) centres[3 * c + e] = sum[3 * c + e] / cnt[c];
+            } else {
                 for (int e = 0; e < 3; ++e) centres[3 * c + e] = pos[3 * far + e];
             }
         }

@@ -8,7 +8,8 @@ streams), every computation is a call into libgs_hip.so (include/gs.h).
   Renderer                      persistent buffers for repeated frames (fixed capacity,
                                 no host synchronisation per frame)
   GSRender                      torch.autograd.Function over render_fwd / render_bwd
-  kmeans / nearest_centre       host camera clustering (Sec. 3.4)
+  kmeans / nearest_centre       camera clustering (Sec. 3.4): host, or host seeding + device Lloyd
+  kmeans_seed / kmeans_lloyd    the two halves of the device clustering
 """
 from __future__ import annotations
 
@@ -517,8 +518,15 @@ class GSRender(torch.autograd.Function):
         return grad.mean, grad.scale, grad.quat, grad.opacity, grad.sh, None, None, None
 
 
-def kmeans(pos: np.ndarray, k: int, seed: int = 3, max_iter: int = 100):
-    """FP64 k-means on camera positions [m][3] -> (centres [k][3], assignment [m])."""
+def kmeans(pos: np.ndarray, k: int, seed: int = 3, max_iter: int = 100, device=None):
+    """FP64 k-means on camera positions [m][3] -> (centres [k][3], assignment [m]), host arrays.
+    With a device, the seeding runs on the host and the Lloyd iterations on that GPU
+    (kmeans_lloyd): the same clustering up to the last bits of the centres."""
+    if device is not None:
+        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+        cen = torch.as_tensor(kmeans_seed(pos, k, seed), device=device)
+        asg, _ = kmeans_lloyd(torch.as_tensor(pos, device=device), cen, max(1, int(max_iter)))
+        return cen.cpu().numpy(), asg.cpu().numpy()
     lib = L.load()
     pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
     m = pos.shape[0]
@@ -527,6 +535,41 @@ def kmeans(pos: np.ndarray, k: int, seed: int = 3, max_iter: int = 100):
     L.check(lib.gs_kmeans(pos.ctypes.data_as(ctypes.c_void_p), m, int(k), int(seed), int(max_iter),
                           cen.ctypes.data_as(ctypes.c_void_p), asg.ctypes.data_as(ctypes.c_void_p)))
     return cen, asg
+
+
+def kmeans_seed(pos: np.ndarray, k: int, seed: int = 3) -> np.ndarray:
+    """The k-means++ seeding of kmeans() alone: initial centres [k][3] (host, FP64)."""
+    lib = L.load()
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    cen = np.zeros((k, 3), np.float64)
+    L.check(lib.gs_kmeans_seed(pos.ctypes.data_as(ctypes.c_void_p), pos.shape[0], int(k), int(seed),
+                               cen.ctypes.data_as(ctypes.c_void_p)))
+    return cen
+
+
+def kmeans_lloyd(pos: torch.Tensor, centres: torch.Tensor, max_iter: int = 100,
+                 ws: Optional[torch.Tensor] = None):
+    """Device FP64 Lloyd iterations from the given centres (Sec. 3.4 camera clustering, for large
+    camera sets). pos: device [m][3] float64; centres: device [k][3] float64, updated in place.
+    Returns (assignment [m] int32, iterations [1] int32), both on the device; nothing waits."""
+    if pos.dtype != torch.float64 or centres.dtype != torch.float64:
+        raise TypeError("pos and centres must be float64")
+    if pos.device.type != "cuda" or centres.device != pos.device:
+        raise ValueError("pos and centres must be on the same GPU")
+    if pos.dim() != 2 or pos.shape[1] != 3 or centres.dim() != 2 or centres.shape[1] != 3:
+        raise ValueError("pos must be [m, 3] and centres [k, 3]")
+    if not (pos.is_contiguous() and centres.is_contiguous()):
+        raise ValueError("pos and centres must be contiguous")
+    m, k = int(pos.shape[0]), int(centres.shape[0])
+    lib = L.load()
+    assign = torch.empty(m, dtype=torch.int32, device=pos.device)
+    iters = torch.zeros(1, dtype=torch.int32, device=pos.device)
+    need = int(lib.gs_kmeans_workspace_bytes(m, k, int(max_iter)))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=pos.device)
+    L.check(lib.gs_kmeans_lloyd(_ptr(pos), m, k, int(max_iter), _ptr(centres), _ptr(assign), _ptr(iters), _ptr(ws),
+                                ws.numel(), _stream(pos.device)))
+    return assign, iters
 
 
 def nearest_centre(centres: np.ndarray, x) -> int:

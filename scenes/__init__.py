@@ -357,6 +357,17 @@ def house_training_views(n_views=640, width=1920, height=1080, seed=SEED_CAMERAS
     return cams
 
 
+def house_camera_positions(m, seed=SEED_CAMERAS) -> np.ndarray:
+    """[m][3] float64 camera centres drawn like house_training_views (room k mod 12, uniform in
+    the room inset by 1 m, eye height floor + U(1.2, 1.8) m), for camera sets too large to
+    build views for, such as the frames of a long capture."""
+    rng = np.random.default_rng(seed)
+    rooms = np.array([_room_origin(f, rx, rz) for f in range(2) for rx in range(3) for rz in range(2)])
+    o = rooms[np.arange(m) % len(rooms)]
+    off = np.stack([rng.uniform(1, ROOM - 1, m), -rng.uniform(1.2, 1.8, m), rng.uniform(1, ROOM - 1, m)], 1)
+    return np.ascontiguousarray(o + off, np.float64)
+
+
 def house_test_path(n_frames=300, width=1920, height=1080) -> List[Camera]:
     """Closed path per floor through the room centres and doorways at eye height 1.6 m, looking
     along the direction of travel; half the frames on each floor."""

@@ -941,3 +941,107 @@ def test_path_renderer_pipeline_matches_single_stream():
                 assert torch.equal(outs[k], ref), f - len(outs) + 1 + k
             outs = []
     assert p1.ok() and p2.ok()
+
+
+# ---- device Lloyd k-means (Sec. 3.4 camera clustering) against the FP64 oracle ----
+# Bars: assignments and the iteration count exact (both sides take each decision from the same
+# FP64 distance); centres within 1e-12 of the point-set extent (sums in another order).
+
+def _blobs(m, k_true, seed, spread=0.4):
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(-10, 10, (k_true, 3))
+    lab = rng.integers(0, k_true, m)
+    return np.ascontiguousarray(cen[lab] + rng.normal(0, spread, (m, 3)), np.float64)
+
+
+def _lloyd_gpu(pos, init, max_iter):
+    c = torch.as_tensor(np.ascontiguousarray(init, np.float64), device=DEV)
+    a, it = gs.kmeans_lloyd(torch.as_tensor(pos, device=DEV), c, max_iter)
+    torch.cuda.synchronize()
+    return c.cpu().numpy(), a.cpu().numpy(), int(it.item())
+
+
+def _check_lloyd(pos, init, max_iter):
+    from oracle import kmeans as OK
+    c, a, it = _lloyd_gpu(pos, init, max_iter)
+    rc, ra, rit = OK.lloyd(pos, init, max_iter)
+    assert np.array_equal(a, ra), f"{int((a != ra).sum())} assignments differ"
+    assert it == rit
+    ext = float(np.abs(pos).max())
+    assert np.abs(c - rc).max() <= 1e-12 * ext
+    return c, a, it
+
+
+@pytest.mark.parametrize("m,k,max_iter,seed", [(640, 64, 100, 0), (5000, 7, 3, 1), (9000, 100, 100, 2),
+                                               (4096, 13, 100, 3), (4097, 13, 100, 4), (50, 50, 10, 5),
+                                               (300, 1, 10, 6), (1, 1, 5, 7)])
+def test_kmeans_lloyd_matches_oracle(m, k, max_iter, seed):
+    _say(f"kmeans m={m} k={k} max_iter={max_iter}")
+    pos = _blobs(m, 12, seed)
+    init = gs.kmeans_seed(pos, k, seed=3)
+    _check_lloyd(pos, init, max_iter)
+
+
+def test_kmeans_lloyd_house_cameras_and_host_kmeans():
+    """640 house training cameras in 64 clusters (the visibility filter's setting): device and
+    oracle agree, and kmeans(device=...) is the host kmeans up to the last bits."""
+    pos = scenes.house_camera_positions(640)
+    _say("kmeans house 640")
+    init = gs.kmeans_seed(pos, 64, seed=3)
+    c, a, _ = _check_lloyd(pos, init, 100)
+    hc, ha = gs.kmeans(pos, 64, seed=3)
+    dc, da = gs.kmeans(pos, 64, seed=3, device=DEV)
+    assert np.array_equal(ha, a) and np.array_equal(da, a)
+    assert np.abs(hc - c).max() <= 1e-12 * 30 and np.array_equal(dc, c)
+
+
+def test_kmeans_lloyd_empty_cluster_and_ties():
+    # centre 3 starts far from every point: empty in the first assignment, it moves to the point
+    # farthest from its centre
+    pos = _blobs(3000, 3, 8)
+    init = np.concatenate([pos[[0, 1000, 2000]], [[500.0, 500.0, 500.0]]])
+    _check_lloyd(pos, init, 50)
+    # lattice points with exact distance ties: the lower centre wins
+    g = np.arange(-4, 5, dtype=np.float64)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).copy()
+    init = np.array([[-1.0, 0, 0], [1.0, 0, 0], [0, 0, 3.0]])
+    _check_lloyd(pos, init, 1)
+    _check_lloyd(pos, init, 30)
+    # duplicate points: zero distances, k equal to the number of distinct points
+    pos = np.repeat(np.array([[0.0, 0, 0], [1.0, 2, 3], [5.0, 5, 5]]), 40, axis=0)
+    _check_lloyd(pos, pos[[0, 40, 80]], 10)
+
+
+def test_kmeans_lloyd_large_camera_set_properties():
+    """131072 house camera positions, 64 clusters, at most 100 iterations (the timed case):
+    repeatable bit for bit; once converged, every sampled point sits at its nearest centre (ties
+    to the lowest) and each centre is the mean of its points."""
+    pos = scenes.house_camera_positions(131072)
+    _say("kmeans 131072 x 64")
+    init = gs.kmeans_seed(pos, 64, seed=3)
+    c, a, it = _lloyd_gpu(pos, init, 100)
+    c2, a2, it2 = _lloyd_gpu(pos, init, 100)
+    assert np.array_equal(c, c2) and np.array_equal(a, a2) and it == it2
+    from oracle import kmeans as OK
+    idx = np.random.default_rng(0).choice(pos.shape[0], 4096, replace=False)
+    d = OK._d2(pos[idx], c)
+    assert np.array_equal(a[idx], np.argmin(d, axis=1))
+    if it < 100:  # converged: the last update left the assignment unchanged
+        for j in range(64):
+            mem = pos[a == j]
+            assert len(mem) > 0
+            # both sums carry at most n eps |x| of rounding (|x| <= 30 m)
+            assert np.abs(mem.mean(0) - c[j]).max() <= 2 * len(mem) * 1.2e-16 * 30
+
+
+def test_kmeans_lloyd_argument_errors():
+    pos = torch.zeros((10, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(gs.GSError):
+        gs.kmeans_lloyd(pos, torch.zeros((11, 3), dtype=torch.float64, device=DEV))
+    with pytest.raises(gs.GSError):
+        gs.kmeans_lloyd(pos, torch.zeros((2, 3), dtype=torch.float64, device=DEV), max_iter=0)
+    with pytest.raises(TypeError):
+        gs.kmeans_lloyd(pos.float(), torch.zeros((2, 3), device=DEV))
+    big = torch.zeros((3000, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(gs.GSError):
+        gs.kmeans_lloyd(big, torch.zeros((2049, 3), dtype=torch.float64, device=DEV))

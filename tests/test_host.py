@@ -245,6 +245,49 @@ def test_kmeans_k1_and_k_equals_m():
         gs.kmeans(pos, 8)
 
 
+def test_host_kmeans_follows_lloyd_oracle():
+    """The host k-means is the oracle's Lloyd iterations from its own k-means++ seeding, on the
+    640 house cameras (64 clusters) and on blobs with an empty cluster forced by the seeding."""
+    from oracle import kmeans as OK
+    for pos, k in ((scenes.house_camera_positions(640), 64),
+                   (np.random.default_rng(4).normal(size=(400, 3)) * [1, 1, 5], 9)):
+        init = gs.kmeans_seed(pos, k, seed=3)
+        # seeding: k distinct input points, repeatable
+        assert len({tuple(c) for c in init}) == k
+        assert all((pos == c).all(1).any() for c in init)
+        assert np.array_equal(init, gs.kmeans_seed(pos, k, seed=3))
+        rc, ra, _ = OK.lloyd(pos, init, 100)
+        hc, ha = gs.kmeans(pos, k, seed=3)
+        assert np.array_equal(ha, ra)
+        assert np.abs(hc - rc).max() <= 1e-12 * np.abs(pos).max()
+
+
+def test_kmeans_lloyd_argument_errors():
+    lib = gs.load()
+    f = ctypes.c_void_p
+    pos, cen, asg, ws = f(1 << 20), f(1 << 30), f(1 << 32), f(1 << 34)
+    need = lib.gs_kmeans_workspace_bytes(1000, 64, 100)
+    assert need >= 100 * 4 + 64 * 32
+    assert lib.gs_kmeans_workspace_bytes(0, 64, 100) == 0
+
+    def call(pos=pos, m=1000, k=64, it=100, cen=cen, asg=asg, ws=ws, wsb=need):
+        return lib.gs_kmeans_lloyd(pos, m, k, it, cen, asg, None, ws, wsb, None)
+
+    assert call(k=0) == L.GS_ERR_INVALID_ARG
+    assert call(k=1001) == L.GS_ERR_INVALID_ARG
+    assert call(it=0) == L.GS_ERR_INVALID_ARG
+    assert call(cen=None) == L.GS_ERR_INVALID_ARG
+    assert call(m=3000, k=2049, wsb=lib.gs_kmeans_workspace_bytes(3000, 2049, 100)) == L.GS_ERR_UNSUPPORTED
+    assert b"2048" in lib.gs_last_error()
+    assert call(wsb=need - 1) == L.GS_ERR_INVALID_ARG
+    assert b"workspace" in lib.gs_last_error()
+    assert call(cen=f((1 << 20) + 24 * 999)) == L.GS_ERR_INVALID_ARG
+    assert b"overlap" in lib.gs_last_error()
+    assert call(m=1 << 31, wsb=1 << 40) == L.GS_ERR_UNSUPPORTED
+    with pytest.raises(gs.GSError):
+        gs.kmeans_seed(np.zeros((3, 3)), 4)
+
+
 def test_generators_shapes_and_determinism():
     a = scenes.mixture_scene(5000, seed=1)
     b = scenes.mixture_scene(5000, seed=1)
