@@ -692,16 +692,23 @@ class VisibilityFilter:
     extra_per_cluster random cameras are added to every cluster's views, as the method does
     for robustness to test views: each sits at a random member camera's position moved by a
     uniform offset in a ball of radius `jitter`, looks in a random direction (yaw uniform,
-    pitch uniform in +-max_pitch) and copies that member's intrinsics."""
+    pitch uniform in +-max_pitch) and copies that member's intrinsics.
+
+    The Lloyd iterations run on the GPU from DEVICE_KMEANS_CAMERAS cameras on (device_kmeans=None),
+    or as asked; the host and device clusterings follow the same steps."""
+
+    DEVICE_KMEANS_CAMERAS = 4096
 
     def __init__(self, g: Gaussians, train_cams: Sequence, k: int = 64, t_cluster: float = 0.001, params=None,
                  chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None,
                  extra_per_cluster: int = 0, jitter: float = 1.0, max_pitch: float = np.deg2rad(30.0),
-                 materialize: bool = False):
+                 materialize: bool = False, device_kmeans: Optional[bool] = None):
         dev = _dev(device)
         self.g, self.k, self.t_cluster, self.params, self.tile, self.device = g, k, t_cluster, params, tile, dev
         pos = np.stack([c.position for c in train_cams])
-        self.centres, self.assign = kmeans(pos, k, seed=seed)
+        if device_kmeans is None:
+            device_kmeans = len(train_cams) >= self.DEVICE_KMEANS_CAMERAS
+        self.centres, self.assign = kmeans(pos, k, seed=seed, device=dev if device_kmeans else None)
         views, owner = list(train_cams), list(self.assign)
         if extra_per_cluster > 0:
             rng = np.random.default_rng(seed)

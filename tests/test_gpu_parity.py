@@ -1045,3 +1045,18 @@ def test_kmeans_lloyd_argument_errors():
     big = torch.zeros((3000, 3), dtype=torch.float64, device=DEV)
     with pytest.raises(gs.GSError):
         gs.kmeans_lloyd(big, torch.zeros((2049, 3), dtype=torch.float64, device=DEV))
+
+
+def test_visibility_filter_device_kmeans_same_lists():
+    """The filter's clustering on the device gives the host clustering's assignment, hence the
+    same per-cluster lists."""
+    sc = scenes.house_scene(6000, seed=4, sh_degree=0)
+    train = scenes.house_training_views(24, width=64, height=36)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("visibility filter, device k-means")
+    a = gs.VisibilityFilter(g, train, k=4, t_cluster=0.01, params=P, device=DEV, device_kmeans=False)
+    b = gs.VisibilityFilter(g, train, k=4, t_cluster=0.01, params=P, device=DEV, device_kmeans=True)
+    assert np.array_equal(a.assign, b.assign)
+    assert np.abs(a.centres - b.centres).max() <= 1e-12 * 30
+    for c in range(4):
+        assert torch.equal(a.lists[c], b.lists[c])
