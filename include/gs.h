@@ -388,7 +388,7 @@ size_t gs_kmeans_workspace_bytes(int64_t m, int32_t k, int32_t max_iter);
  * assign: device [m] int32 out; iterations: device int32 out (centre updates made), or NULL;
  * ws: device workspace of gs_kmeans_workspace_bytes(m, k, max_iter). Needs 1 <= k <= m,
  * k <= 2048, 1 <= max_iter <= 10^6, m < 2^31; pos, centres and assign must not overlap.
- * Asynchronous on the stream: 3 max_iter + 2 launches, those after convergence return at
+ * Asynchronous on the stream: 2 max_iter + 2 launches, those after convergence return at
  * once. Cost per iteration O(m k). */
 gs_status gs_kmeans_lloyd(const double* pos, int64_t m, int32_t k, int32_t max_iter, double* centres,
                           int32_t* assign, int32_t* iterations, void* ws, size_t ws_bytes, void* stream);
