@@ -397,6 +397,103 @@ def test_full_size_sampled_pixels():
     check_band(mism, band, "full-size sampled pixels")
 
 
+def test_full_size_backward_sampled_pixels():
+    """200k Gaussians, one 1256x828 view, 16x16 tiles through a Renderer (the single-view
+    forward + backward benchmark's launch): the gradient of sum(w * image), w non-zero on 256
+    sampled pixels, against the oracle's gradient over those pixels; the image at them too."""
+    from paper_2403_13806_amd.train import zero_grads
+    sc = scenes.mixture_scene(200_000, seed=0, sh_degree=3, log_scale_mu=-4.0)
+    cam = scenes.orbit_camera(0.0, np.deg2rad(15.0), 4.0, 1256, 828)
+    _say("full size backward 200k x 1256x828, sampled pixels")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    r = gs.Renderer(g, views, P)
+    rgb = r.forward()
+    rng = np.random.default_rng(3)
+    flat = rng.choice(cam.width * cam.height, 256, replace=False)
+    px, py = (flat % cam.width).astype(np.int32), (flat // cam.width).astype(np.int32)
+    _, runs = band_runs(sc, cam, P, pixels=(px, py))
+    keep = ~image_band(runs)  # a pixel in the threshold band composites another set
+    _say(f"  {int((~keep).sum())} sampled pixels in the band dropped")
+    img = views.image(rgb, 0).cpu().numpy().astype(np.float64)
+    assert np.abs(img[:, py, px].T - runs[0]["rgb"])[keep].max() <= TOL_IMAGE
+    px, py = px[keep], py[keep]
+    wv = rng.uniform(-1, 1, (px.size, 3)).astype(np.float32)
+    w = np.zeros((3, cam.height, cam.width), np.float32)
+    w[:, py, px] = wv.T
+    grad = zero_grads(g)
+    r.backward(torch.as_tensor(w.reshape(-1), device=DEV), grad)
+    torch.cuda.synchronize()
+    assert r.check()[0] is False
+    ref = oracle.render_bwd(sc, cam, P, wv.astype(np.float64), pixels=(px, py))
+    for name in ("mean", "scale", "quat", "opacity", "sh"):
+        rel, _ = _grad_check(getattr(grad, name).cpu().numpy(), ref[name], name)
+        assert rel <= TOL_GRAD, name
+
+
+def test_full_size_importance_150_views():
+    """500k Gaussians, 150 orbit views at 1256x828 in chunks of 10 with the persistent launch at
+    16x32 (the importance benchmark's launch): equal bit for bit to the maximum of 150 single-view
+    passes at 16x16 (the maximum is exact in any order), and never below the oracle's maximum over
+    sampled pixels of three views (a maximum over fewer rays), beyond the importance tolerance."""
+    sc = scenes.mixture_scene(500_000, seed=0, sh_degree=3)
+    cams = scenes.orbit_views(150)
+    _say("full size importance 500k x 150 views")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    h = torch.zeros(g.n, device=DEV)
+    for i in range(0, 150, 10):
+        r = gs.Renderer(g, gs.ViewBatch(cams[i:i + 10], (16, 32), DEV, persistent=True), P, want_color=False)
+        r.importance(h)
+        assert r.check()[0] is False
+    hv = torch.zeros(g.n, device=DEV)
+    for c in cams:
+        hv = torch.maximum(hv, gs.importance(g, gs.ViewBatch([c], (16, 16), DEV), P))
+    torch.cuda.synchronize()
+    assert torch.equal(h, hv)
+    hh = h.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    for v in (0, 50, 100):
+        c = cams[v]
+        flat = rng.choice(c.width * c.height, 128, replace=False)
+        pix = ((flat % c.width).astype(np.int32), (flat // c.width).astype(np.int32))
+        _, runs = band_runs(sc, c, P, pixels=pix, want_h=True)
+        lo = np.min([rr["h"] for rr in runs], axis=0)  # the smallest of the threshold-shifted runs
+        assert np.all(hh >= lo - TOL_H), f"view {v}: {int((hh < lo - TOL_H).sum())} Gaussians below"
+        assert (lo > 0).sum() > 100
+
+
+def test_full_size_batched_fwd_bwd_8_uneven_views():
+    """1M Gaussians, 8 views from 640x480 to 1920x1080 in one batched step (16x16, the batched
+    benchmark's default launch) against 8 single-view launches: images bitwise equal, and the
+    batched gradient equal to the sum of the single-view gradients fed the same image
+    gradient (FP32 sums in another order: 1e-5 relative per parameter group)."""
+    from paper_2403_13806_amd.train import FwdBwdStep, StepConfig, zero_grads
+    sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+    cams = scenes.uneven_views()
+    tg = scenes.target_images(cams)
+    _say("full size batched fwd+bwd 1M x 8 uneven views")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    step = FwdBwdStep(g, cams, tg, P, StepConfig(16, 16, 1, False), device=DEV)
+    step.run()
+    torch.cuda.synchronize()
+    assert step.ok()
+    total = zero_grads(g)
+    for v, c in enumerate(cams):
+        one = gs.ViewBatch([c], (16, 16), DEV)
+        r = gs.Renderer(g, one, P)
+        rgb = r.forward()
+        assert torch.equal(one.image(rgb, 0), step.views.image(step.r.rgb, v)), v
+        r.backward(step.views.image(step.dl, v).contiguous().reshape(-1), total)
+        assert r.check()[0] is False
+    torch.cuda.synchronize()
+    for name in ("mean", "scale", "quat", "opacity", "sh"):
+        a = getattr(step.grad, name).double()
+        b = getattr(total, name).double()
+        rel = float((a - b).norm() / b.norm().clamp_min(1e-30))
+        _say(f"  {name}: rel {rel:.2e}")
+        assert rel <= 1e-5, name
+
+
 @pytest.mark.parametrize("tile,depth,persistent", [((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 2, False),
                                                    ((16, 8), 1, True), ((32, 16), 2, True), ((32, 32), 1, True)])
 def test_launch_forms_bitwise(tile, depth, persistent):
