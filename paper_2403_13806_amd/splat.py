@@ -724,6 +724,7 @@ class VisibilityFilter:
                                             rng.uniform(-max_pitch, max_pitch), m))
                     owner.append(c)
         self.views_used = len(views)
+        self.cluster_views, self.view_owner = views, np.asarray(owner, np.int32)  # every view and its cluster
         words = (g.n + 31) // 32
         self.bits = torch.zeros(max(k * words, 1), dtype=torch.int32, device=dev)
         owner = np.asarray(owner, np.int32)

@@ -494,6 +494,53 @@ def test_full_size_batched_fwd_bwd_8_uneven_views():
         assert rel <= 1e-5, name
 
 
+def test_full_size_house_filtering():
+    """5M Gaussians over the 12 house rooms, 640 training cameras at 1920x1080 in 64 clusters with
+    32 extra cameras per cluster, t_cluster 0.01, lists materialised (the house benchmark's
+    set-up). Every list is exactly the set of Gaussians whose importance over the cluster's views
+    exceeds t_cluster (the same FP32 weights, whatever the launch); no list misses a Gaussian the
+    oracle puts above t_cluster on sampled pixels of a member view; path frames rendered from the
+    copies equal the renders of the lists bit for bit."""
+    from paper_2403_13806_amd.splat import PathRenderer
+    t = 0.01
+    sc = scenes.house_scene(5_000_000)
+    train = scenes.house_training_views(640)
+    path = scenes.house_test_path(300)
+    _say("full size house filtering 5M x 640 views")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    vf = gs.VisibilityFilter(g, train, k=64, t_cluster=t, params=P, chunk=8, device=DEV, extra_per_cluster=32)
+    assert vf.views_used == 640 + 64 * 32
+    for c in range(64):
+        members = [vf.cluster_views[v] for v in np.nonzero(vf.view_owner == c)[0]]
+        hc = torch.zeros(g.n, device=DEV)
+        for i in range(0, len(members), 8):
+            r = gs.Renderer(g, gs.ViewBatch(members[i:i + 8], (16, 16), DEV), P, want_color=False)
+            r.importance(hc)
+            assert r.check()[0] is False
+        want = torch.nonzero(hc > t).flatten().to(torch.int32)
+        assert torch.equal(vf.lists[c], want), c
+    # the oracle on sampled pixels of two training views
+    rng = np.random.default_rng(6)
+    for v in (0, 333):
+        cam = train[v]
+        flat = rng.choice(cam.width * cam.height, 24, replace=False)
+        pix = ((flat % cam.width).astype(np.int32), (flat // cam.width).astype(np.int32))
+        _, runs = band_runs(sc, cam, P, pixels=pix, want_h=True)
+        lo = np.min([rr["h"] for rr in runs], axis=0)
+        need = np.nonzero(lo > t + TOL_H)[0]
+        got = np.zeros(sc.n, bool)
+        got[vf.lists[int(vf.assign[v])].cpu().numpy()] = True
+        _say(f"  view {v}: {need.size} Gaussians above t_cluster on the sampled pixels")
+        assert need.size > 0 and got[need].all()
+    vf.materialize()
+    pr = PathRenderer(g, path, P, device=DEV, max_entries=g.n)
+    for f in range(0, 300, 25):
+        a = pr.frame(f, None, vf.copy_for(path[f])).clone()
+        assert pr.ok()
+        b = gs.render(g, gs.ViewBatch([path[f]], device=DEV), P, subset=vf.list_for(path[f]))["rgb"]
+        assert torch.equal(a, b), f
+
+
 @pytest.mark.parametrize("tile,depth,persistent", [((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 2, False),
                                                    ((16, 8), 1, True), ((32, 16), 2, True), ((32, 32), 1, True)])
 def test_launch_forms_bitwise(tile, depth, persistent):
