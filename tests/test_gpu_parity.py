@@ -995,6 +995,50 @@ def test_adam_step_matches_oracle():
         gs.adam_step([(dev[0][0], dev[0][1], dev[0][2], dev[0][3], 0.1, "linear")], 0)
 
 
+def test_full_size_adam_sampled():
+    """The optimisation loop's step at 1M Gaussians (SH degree 3, eight groups in the loop's
+    parametrisations and learning rates, 59M elements, one launch) from non-zero moments at step
+    5000, against the FP64 oracle on 4096 sampled elements of every group (the step is
+    elementwise, so a sample is checked exactly); bars as in the small test."""
+    from paper_2403_13806_amd.train import TrainConfig
+    n = 1_000_000
+    cfg = TrainConfig()
+    rng = np.random.default_rng(43)
+    specs = [(3, "linear", 1.6e-4 * 5.0, lambda k: rng.normal(0, 3, k)),
+             (3, "log", cfg.lr_scale, lambda k: rng.uniform(0.005, 0.5, k)),
+             (4, "linear", cfg.lr_quat, lambda k: rng.normal(0, 1, k)),
+             (1, "logit", cfg.lr_opacity, lambda k: rng.uniform(0.01, 0.99, k)),
+             (3, "linear", cfg.lr_sh_dc, lambda k: rng.normal(0, 0.5, k)),
+             (9, "linear", cfg.lr_sh_rest, lambda k: rng.normal(0, 0.2, k)),
+             (15, "linear", cfg.lr_sh_rest, lambda k: rng.normal(0, 0.2, k)),
+             (21, "linear", cfg.lr_sh_rest, lambda k: rng.normal(0, 0.2, k))]
+    mode_id = {"linear": OO.LINEAR, "log": OO.LOG, "logit": OO.LOGIT}
+    _say("full size adam 1M Gaussians, 59M elements")
+    host, dev = [], []
+    for rows, mode, lr, f in specs:
+        k = rows * n
+        x = f(k).astype(np.float32)
+        gr = rng.normal(0, 1e-3, k).astype(np.float32)
+        m = rng.normal(0, 1e-4, k).astype(np.float32)
+        v = (rng.uniform(0, 1e-6, k)).astype(np.float32)
+        host.append((x, gr, m, v))
+        dev.append([torch.as_tensor(a, device=DEV) for a in (x, gr, m, v)])
+    assert sum(x.size for x, *_ in host) == 59 * n
+    step = 5000
+    gs.adam_step([(d[0], d[1], d[2], d[3], lr, mode) for d, (_, mode, lr, _) in zip(dev, specs)], step,
+                 cfg.betas, cfg.eps)
+    torch.cuda.synchronize()
+    for (x, gr, m, v), d, (_, mode, lr, _) in zip(host, dev, specs):
+        idx = rng.choice(x.size, 4096, replace=False)
+        rx, rm, rv = OO.adam_step(x[idx], gr[idx].astype(np.float64), m[idx], v[idx], lr, mode_id[mode], step,
+                                  cfg.betas[0], cfg.betas[1], cfg.eps)
+        ti = torch.as_tensor(idx, device=DEV)
+        np.testing.assert_allclose(d[0][ti].cpu().numpy(), rx, rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(d[2][ti].cpu().numpy(), rm, rtol=1e-6, atol=1e-6 * np.abs(rm).max())
+        np.testing.assert_allclose(d[3][ti].cpu().numpy(), rv, rtol=1e-6, atol=1e-6 * np.abs(rv).max())
+        assert not d[1].any()
+
+
 def test_trainer_fits_and_prunes_with_moments():
     """The optimisation loop fits a perturbed copy of a scene to that scene's renders (loss goes
     down), prunes at its scheduled steps, and compacts both Adam moments with exactly the kept
