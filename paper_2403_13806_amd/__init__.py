@@ -23,5 +23,6 @@ from .splat import (Bins, Gaussians, GSRender, Projected, Renderer, ViewBatch, V
                     adam_step, alloc_workspace,
                     bin_sort, bits_to_list, cluster_visibility, gather, gather_gaussians, importance, kmeans,
                     kmeans_lloyd, kmeans_seed, init_gaussians, l1_loss_grad, make_params, nearest_centre, nn_distance,
-                    preprocess, prune, prune_gaussians, prune_mask, render, render_bwd, render_fwd,
+                    preprocess, prune, prune_gaussians, prune_mask, render, render_batch, render_bwd, render_filtered,
+                    render_fwd,
                     ssim_loss_grad, ssim_workspace_bytes, workspace_bytes)

@@ -5,6 +5,8 @@ streams), every computation is a call into libgs_hip.so (include/gs.h).
   preprocess / bin_sort /       the C-ABI calls, one to one
   render_fwd / render_bwd /
   importance / cluster_visibility / bits_to_list
+  render / render_batch         the plain path for one view batch (images per view)
+  render_filtered               a test view with its nearest cluster's visibility list
   Renderer                      persistent buffers for repeated frames (fixed capacity,
                                 no host synchronisation per frame)
   GSRender                      torch.autograd.Function over render_fwd / render_bwd
@@ -296,6 +298,24 @@ def render(g: Gaussians, views: ViewBatch, params=None, subset=None, capacity=No
     bins = bin_sort(proj, views, capacity)
     rgb, t, last = render_fwd(proj, views, bins, params)
     return {"rgb": rgb, "t_final": t, "n_last": last, "proj": proj, "bins": bins}
+
+
+def render_batch(g: Gaussians, cams: Sequence, params=None, tile: Tuple[int, int] = DEFAULT_TILE,
+                 batch_depth: int = 1, persistent: bool = False, device=None) -> List[torch.Tensor]:
+    """Every view of cams in one launch per stage (views of uneven size share one global tile
+    space); returns each view's planar [3][H][W] image, a view of the batch's rgb buffer."""
+    views = ViewBatch(cams, tile, _dev(device), batch_depth, persistent)
+    out = render(g, views, params)
+    return [views.image(out["rgb"], v) for v in range(len(cams))]
+
+
+def render_filtered(g: Gaussians, cam, lists: Sequence[torch.Tensor], centres: np.ndarray, params=None,
+                    tile: Tuple[int, int] = DEFAULT_TILE, device=None) -> torch.Tensor:
+    """A test view rendered with the visibility list of the cluster centre nearest to its camera
+    centre (Sec. 3.4; ties to the lowest centre): planar [3][H][W] image."""
+    c = nearest_centre(centres, cam.position)
+    views = ViewBatch([cam], tile, _dev(device))
+    return views.image(render(g, views, params, subset=lists[c])["rgb"], 0)
 
 
 def importance(g: Gaussians, views: ViewBatch, params=None, h: Optional[torch.Tensor] = None, capacity=None):

@@ -686,6 +686,25 @@ def test_visibility_filter_and_path_renderer():
         assert torch.equal(a0, b0), f
 
 
+def test_render_batch_and_render_filtered():
+    """The Python-level names of the batch and filtered renders: per-view images of one batched
+    launch equal single-view renders; a filtered render uses the nearest centre's list."""
+    sc = scenes.house_scene(8000, seed=4, sh_degree=1)
+    train = scenes.house_training_views(12, width=96, height=54)
+    g = gs.Gaussians.from_scene(sc, DEV)
+    _say("render_batch / render_filtered")
+    imgs = gs.render_batch(g, train[:5], P)
+    for v in range(5):
+        one = gs.ViewBatch([train[v]], device=DEV)
+        assert torch.equal(imgs[v], one.image(gs.render(g, one, P)["rgb"], 0)), v
+    vf = gs.VisibilityFilter(g, train, k=3, t_cluster=0.01, params=P, device=DEV)
+    for cam in scenes.house_test_path(4, width=96, height=54):
+        got = gs.render_filtered(g, cam, vf.lists, vf.centres, P)
+        c = int(np.argmin(((vf.centres - cam.position) ** 2).sum(1)))
+        one = gs.ViewBatch([cam], device=DEV)
+        assert torch.equal(got, one.image(gs.render(g, one, P, subset=vf.lists[c])["rgb"], 0))
+
+
 def test_visibility_filter_extra_cameras_only_add():
     """Extra random cameras per cluster (Sec. 3.4) only add views to a cluster, so each
     cluster's list can only grow (the per-cluster max is monotone in the view set)."""
