@@ -464,7 +464,8 @@ def test_full_size_importance_150_views():
 
 def test_full_size_batched_fwd_bwd_8_uneven_views():
     """1M Gaussians, 8 views from 640x480 to 1920x1080 in one batched step (16x16, the batched
-    benchmark's default launch) against 8 single-view launches: images bitwise equal, and the
+    benchmark's default launch) against 8 single-view launches: images bitwise equal (and the
+    1920x1080 view against the oracle on sampled pixels), and the
     batched gradient equal to the sum of the single-view gradients fed the same image
     gradient (FP32 sums in another order: 1e-5 relative per parameter group)."""
     from paper_2403_13806_amd.train import FwdBwdStep, StepConfig, zero_grads
@@ -486,6 +487,15 @@ def test_full_size_batched_fwd_bwd_8_uneven_views():
         r.backward(step.views.image(step.dl, v).contiguous().reshape(-1), total)
         assert r.check()[0] is False
     torch.cuda.synchronize()
+    # the largest view (1920x1080) on 96 sampled pixels against the oracle
+    v = 7
+    c = cams[v]
+    rng = np.random.default_rng(8)
+    flat = rng.choice(c.width * c.height, 96, replace=False)
+    px, py = (flat % c.width).astype(np.int32), (flat // c.width).astype(np.int32)
+    _, runs = band_runs(sc, c, P, pixels=(px, py))
+    img = step.views.image(step.r.rgb, v).cpu().numpy().astype(np.float64)
+    check_band(np.abs(img[:, py, px].T - runs[0]["rgb"]).max(1) > TOL_IMAGE, image_band(runs), "1920x1080 view")
     for name in ("mean", "scale", "quat", "opacity", "sh"):
         a = getattr(step.grad, name).double()
         b = getattr(total, name).double()
