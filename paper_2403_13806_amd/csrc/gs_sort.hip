@@ -221,8 +221,17 @@ gs_status launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* ct
 // emission block scans its own 256 counts. No chain of waits between blocks.
 constexpr int SB_T = 1024;  // threads of the block-sum scan
 
+// It also clears the frame's state first (the job of k_zero4 when there is no pair to bin):
+// no later kernel of the frame runs before it ends.
 __global__ __launch_bounds__(256) void k_count_bsums(const uint32_t* __restrict__ count, int64_t n, int64_t nbv,
-                                                     uint32_t* __restrict__ bsum) {
+                                                     uint32_t* __restrict__ bsum, Fill4 clear) {
+    {
+        const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+        const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            for (int64_t i = tid; i < clear.n[b]; i += nth) clear.p[b][i] = 0u;
+    }
     const int v = blockIdx.y, w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const uint32_t* cv = count + (int64_t)v * n;
 #pragma unroll
@@ -943,13 +952,16 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     f.n[2] = 2;
     f.p[3] = U32(L.ctrl);
     f.n[3] = vn == 0 ? 0 : (int64_t)((L.ctrl_end - L.ctrl) / 4);
-    if ((st = launch_zero4(f, stream))) return st;
-    if (vn == 0 || views->n_tiles == 0) return launch_lpt(views, bins, nullptr, stream);
+    if (vn == 0 || views->n_tiles == 0) {
+        if ((st = launch_zero4(f, stream))) return st;
+        return launch_lpt(views, bins, nullptr, stream);
+    }
 
-    // 1. pair offsets of the emission blocks, pair total, capacity check
+    // 1. pair offsets of the emission blocks (clearing the state above first), pair total,
+    // capacity check
     const int64_t nbv = (n + 255) / 256;
     hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0, stream,
-                       proj->count, n, nbv, U32(L.offs));
+                       proj->count, n, nbv, U32(L.offs), f);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views, bins->n_pairs,
                        bins->overflow, bins->capacity);
     if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
