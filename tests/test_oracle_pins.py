@@ -330,6 +330,214 @@ def test_tile_lists_cover_every_support(tile):
         assert (t[a], d[a], vals[a]) < (t[a + 1], d[a + 1], vals[a + 1])
 
 
+# ----------------------------------------------------------------------------------------------
+# Tile rectangle (Sec. 3.2 bins each projected Gaussian into screen tiles; the rule is a reading:
+# the support's exact bounding box, hx = sqrt(q_max Sigma'_xx), hy = sqrt(q_max Sigma'_yy),
+# widened by 2^-16 px, floored to tiles and clamped to the grid). Each case below computes the
+# half-extents and the rectangle in closed form from the scene's numbers, not from the oracle.
+# ----------------------------------------------------------------------------------------------
+
+EPS_RECT = 2.0 ** -16
+LOWPASS = np.float64(np.float32(0.3))
+A_MIN = np.float64(np.float32(1 / 255))
+
+
+def _axis_aligned_extent(world, s, opac, cam):
+    """Closed form for R = I, t = (0, 0, 4) and an identity rotation: Sigma = diag(s^2),
+    J = [[f/z, 0, -f x/z^2], [0, f/z, -f y/z^2]] at camera-space (x, y, z) = world + t."""
+    x, y, z = (np.float64(np.float32(world[0])), np.float64(np.float32(world[1])),
+               np.float64(np.float32(world[2])) + 4.0)
+    a, b, c = np.float64(np.float32(s[0])) ** 2, np.float64(np.float32(s[1])) ** 2, np.float64(np.float32(s[2])) ** 2
+    f = 100.0
+    sxx = (f / z) ** 2 * a + (f * x / z ** 2) ** 2 * c + LOWPASS
+    syy = (f / z) ** 2 * b + (f * y / z ** 2) ** 2 * c + LOWPASS
+    qmax = min(9.0, 2.0 * np.log(np.float64(np.float32(opac)) / A_MIN))
+    u, v = f * x / z + cam.cx, f * y / z + cam.cy
+    return u, v, np.sqrt(qmax * sxx), np.sqrt(qmax * syy), qmax
+
+
+def _rect(u, v, hx, hy, cam, tile):
+    tw, th = tile
+    nx, ny = -(-cam.width // tw), -(-cam.height // th)
+    tx0 = max(0, int(np.floor((u - hx - EPS_RECT) / tw)))
+    tx1 = min(nx - 1, int(np.floor((u + hx + EPS_RECT) / tw)))
+    ty0 = max(0, int(np.floor((v - hy - EPS_RECT) / th)))
+    ty1 = min(ny - 1, int(np.floor((v + hy + EPS_RECT) / th)))
+    count = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) if (tx1 >= tx0 and ty1 >= ty0) else 0
+    return (tx0, ty0, tx1, ty1), count
+
+
+def _check_rect(pr, u, v, hx, hy, qmax, cam, tile):
+    assert pr[F["vis"]] == 1
+    assert abs(pr[F["u"]] - u) < 1e-12 * max(1.0, abs(u)) and abs(pr[F["v"]] - v) < 1e-12 * max(1.0, abs(v))
+    assert abs(pr[F["qmax"]] - qmax) < 1e-12 * qmax
+    assert abs(pr[F["hx"]] - hx) < 1e-12 * hx and abs(pr[F["hy"]] - hy) < 1e-12 * hy
+    rect, count = _rect(u, v, hx, hy, cam, tile)
+    if count:
+        got = tuple(int(pr[F[k]]) for k in ("tx0", "ty0", "tx1", "ty1"))
+        assert got == rect, (got, rect)
+    assert int(pr[F["count"]]) == count
+    return rect, count
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_tile_rect_axis_aligned_closed_form(tile):
+    # q_max = kappa^2 = 9 (opacity 0.8); Sigma'_xy != 0 off the axes does not enter hx, hy
+    cam = scenes.plain_view()
+    counts = []
+    for world, s in [((0.3, -0.2, 0.5), (0.28, 0.15, 0.1)), ((-0.45, 0.3, -1.0), (0.02, 0.31, 0.04)),
+                     ((0.0, 0.0, 0.0), (0.05, 0.02, 0.07))]:
+        u, v, hx, hy, qm = _axis_aligned_extent(world, s, 0.8, cam)
+        assert qm == 9.0
+        pr = oracle.project(_one([world], [s], [1, 0, 0, 0], [0.8]), cam, P, tile=tile)[0]
+        counts.append(_check_rect(pr, u, v, hx, hy, qm, cam, tile)[1])
+    assert max(counts) > 2
+
+
+def test_tile_rect_low_opacity_radius():
+    # opacity 0.02: q_max = 2 ln(o / alpha_min) = 2 ln(5.1) ~ 3.26 < 9 shrinks the box
+    cam = scenes.plain_view()
+    world, s = (0.1, 0.05, 0.2), (0.09, 0.06, 0.05)
+    u, v, hx, hy, qm = _axis_aligned_extent(world, s, 0.02, cam)
+    assert 3.2 < qm < 3.3
+    pr = oracle.project(_one([world], [s], [1, 0, 0, 0], [0.02]), cam, P)[0]
+    _check_rect(pr, u, v, hx, hy, qm, cam, (16, 16))
+    # the same Gaussian at full opacity covers a wider box
+    pr9 = oracle.project(_one([world], [s], [1, 0, 0, 0], [0.8]), cam, P)[0]
+    assert abs(pr9[F["hx"]] / pr[F["hx"]] - np.sqrt(9.0 / qm)) < 1e-12
+
+
+def test_tile_rect_clamped_to_the_grid():
+    # 128 x 96 view, 16 x 16 tiles: 8 x 6 tiles. Means near (and past) the image border but
+    # inside the 1.3x guard window keep their projection; the box is clamped to the grid.
+    cam = scenes.plain_view()
+    tile = (16, 16)
+    z = 4.0
+    cases = {
+        "left_top": ((2.0 - 64.0) * z / 100.0, (3.0 - 48.0) * z / 100.0),        # u = 2, v = 3
+        "right_bottom": ((125.0 - 64.0) * z / 100.0, (94.0 - 48.0) * z / 100.0),  # u = 125, v = 94
+        "past_left": ((-12.0 - 64.0) * z / 100.0, 0.0),                           # u = -12, outside the image
+    }
+    got = {}
+    for name, (wx, wy) in cases.items():
+        world, s = (wx, wy, 0.0), (0.3, 0.3, 0.05)
+        u, v, hx, hy, qm = _axis_aligned_extent(world, s, 0.8, cam)
+        pr = oracle.project(_one([world], [s], [1, 0, 0, 0], [0.8]), cam, P, tile=tile)[0]
+        got[name] = _check_rect(pr, u, v, hx, hy, qm, cam, tile)
+    assert got["left_top"][0][:2] == (0, 0) and got["right_bottom"][0][2:] == (7, 5)
+    # u - hx < 0 < u + hx for the first, u + hx > 128 for the second: the clamp did act
+    assert got["past_left"][0][0] == 0 and got["past_left"][1] > 0
+    # a box entirely left of the image: visible per the culls, but no tile
+    world, s = ((-18.0 - 64.0) * z / 100.0, 0.0, 0.0), (0.02, 0.02, 0.02)
+    u, v, hx, hy, qm = _axis_aligned_extent(world, s, 0.8, cam)
+    assert u + hx < 0
+    pr = oracle.project(_one([world], [s], [1, 0, 0, 0], [0.8]), cam, P, tile=tile)[0]
+    assert pr[F["vis"]] == 1 and pr[F["count"]] == 0
+
+
+def _scale_for_right_edge(target, world, cam):
+    """FP32 x-scale for which u + hx lies just below `target`, by bisection on the closed form."""
+    lo, hi = np.float32(1e-3), np.float32(0.5)
+    for _ in range(200):
+        mid = np.float32((np.float64(lo) + np.float64(hi)) / 2)
+        if mid in (lo, hi):
+            break
+        u, _, hx, _, _ = _axis_aligned_extent(world, (mid, 0.03, 0.03), 0.8, cam)
+        if u + hx < target:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+@pytest.mark.parametrize("gap", [2.0 ** -18, 2.0 ** -14])
+def test_tile_rect_widening_at_a_tile_boundary(gap):
+    # The right edge of the support's box placed just below the boundary x = 64 of tiles 3 and 4
+    # (16-px tiles): within the 2^-16 widening (gap 2^-18) the box reaches tile 4; beyond it
+    # (gap 2^-14) it stops at tile 3.
+    cam = scenes.plain_view()
+    world = (-0.4, 0.0, 0.0)  # u = 64 - 10 = 54
+    target = 64.0 - gap
+    sx = _scale_for_right_edge(target, world, cam)
+    u, v, hx, hy, qm = _axis_aligned_extent(world, (sx, 0.03, 0.03), 0.8, cam)
+    edge = u + hx
+    # FP32 steps of the scale move the edge by ~1e-6 px: the bisection lands within 2^-19 of it
+    assert target - 2.0 ** -19 < edge < target + 1e-9 and edge < 64.0
+    pr = oracle.project(_one([world], [(sx, 0.03, 0.03)], [1, 0, 0, 0], [0.8]), cam, P)[0]
+    rect, _ = _check_rect(pr, u, v, hx, hy, qm, cam, (16, 16))
+    assert rect[2] == (4 if gap < EPS_RECT else 3)
+
+
+def test_tile_rect_rotated_with_scipy():
+    # Sigma = Rq diag(s^2) Rq^T with Rq from scipy's quaternion rotation, Sigma' from the
+    # numerical Jacobian of the perspective map of a rotated camera; hx, hy and the rectangle
+    # follow from Sigma'_xx, Sigma'_yy and q_max alone.
+    rng = np.random.default_rng(17)
+    cam = scenes.orbit_camera(0.9, 0.35, 4.0, 320, 240)
+    Rc, tc = cam.R.astype(np.float64), cam.t.astype(np.float64)
+
+    def proj(x):
+        pc = Rc @ x + tc
+        return np.array([cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy])
+
+    checked = 0
+    for trial in range(60):
+        p = rng.uniform(-0.8, 0.8, 3).astype(np.float32)
+        s = np.exp(rng.normal(-2.5, 0.6, 3)).astype(np.float32)
+        q = rng.standard_normal(4).astype(np.float32)
+        o = np.float32(rng.choice([0.8, 0.03]))
+        for tile in [(16, 16), (8, 32)]:
+            pr = oracle.project(_one(p, s, q, [o]), cam, P, tile=tile)[0]
+            if pr[F["vis"]] == 0:
+                continue
+            qd = q.astype(np.float64)
+            Rq = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+            Sig = Rq @ np.diag(s.astype(np.float64) ** 2) @ Rq.T
+            pd = p.astype(np.float64)
+            Jp = np.zeros((2, 3))
+            for k in range(3):
+                e = np.zeros(3)
+                e[k] = 1e-6
+                Jp[:, k] = (proj(pd + e) - proj(pd - e)) / 2e-6
+            Sp = Jp @ Sig @ Jp.T + LOWPASS * np.eye(2)
+            qm = min(9.0, 2.0 * np.log(np.float64(o) / A_MIN))
+            hx, hy = np.sqrt(qm * Sp[0, 0]), np.sqrt(qm * Sp[1, 1])
+            u, v = proj(pd)
+            assert abs(pr[F["hx"]] - hx) < 1e-7 * hx and abs(pr[F["hy"]] - hy) < 1e-7 * hy
+            # rectangle from the reference box, unless an edge lies within 1e-5 px of a tile line
+            edges = np.array([(u - hx - EPS_RECT) / tile[0], (u + hx + EPS_RECT) / tile[0],
+                              (v - hy - EPS_RECT) / tile[1], (v + hy + EPS_RECT) / tile[1]])
+            if np.any(np.abs(edges - np.round(edges)) * min(tile) < 1e-5):
+                continue
+            rect, count = _rect(u, v, hx, hy, cam, tile)
+            assert int(pr[F["count"]]) == count
+            if count:
+                assert tuple(int(pr[F[k]]) for k in ("tx0", "ty0", "tx1", "ty1")) == rect
+            checked += 1
+    assert checked > 60
+
+
+def test_half_extents_bound_the_support_ellipse():
+    # hx, hy are the exact half-widths of {d : d^T conic d <= q_max}: the boundary points
+    # sqrt(q_max) V diag(lambda^-1/2) (cos t, sin t) (numpy's eigen-decomposition of the
+    # oracle's conic) reach +-hx in x and +-hy in y and never beyond.
+    sc = scenes.mixture_scene(3000, seed=5)
+    cam = scenes.orbit_camera(0.2, 0.1, 4.0, 320, 240)
+    pr = oracle.project(sc, cam, P)
+    vis = np.nonzero(pr[:, F["vis"]] == 1)[0]
+    assert len(vis) > 200
+    t = np.linspace(0, 2 * np.pi, 20001)
+    circle = np.stack([np.cos(t), np.sin(t)])
+    for i in vis[:200]:
+        C = np.array([[pr[i, F["ca"]], pr[i, F["cb"]]], [pr[i, F["cb"]], pr[i, F["cc"]]]])
+        lam, V = np.linalg.eigh(C)
+        d = np.sqrt(pr[i, F["qmax"]]) * (V @ (circle / np.sqrt(lam)[:, None]))
+        ex, ey = np.abs(d[0]).max(), np.abs(d[1]).max()
+        # dense sampling reaches the extreme to second order in the angle step
+        assert ex <= pr[i, F["hx"]] * (1 + 1e-9) and ex >= pr[i, F["hx"]] * (1 - 1e-7)
+        assert ey <= pr[i, F["hy"]] * (1 + 1e-9) and ey >= pr[i, F["hy"]] * (1 - 1e-7)
+
+
 def test_pairs_brute_force_per_tile():
     sc = scenes.uniform_cube_scene(150, seed=9)
     cams = [scenes.plain_view(), scenes.orbit_camera(0.4, 0.2, 4.0, 70, 50, fx=60.0)]
