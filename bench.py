@@ -113,7 +113,8 @@ def main():
     sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
     cams = scenes.orbit_views(8)
     g = gs.Gaussians.from_scene(sc, dev)
-    rs = [gs.Renderer(g, gs.ViewBatch([c], TILE, dev), P) for c in cams]
+    # forward-only frames: the pairs' emission slots (the backward's input) are not kept
+    rs = [gs.Renderer(g, gs.ViewBatch([c], TILE, dev), P, backward=False) for c in cams]
     torch.cuda.synchronize()
 
     # ---------------- headline: plain forward frames/s ----------------
@@ -151,8 +152,11 @@ def main():
                              g.n, g.sh_degree)
     dl_buf = torch.full((3 * rs[0].views.n_pixels,), 1e-6, dtype=torch.float32, device=dev)
     reps = max(3, K // 8)
-    for r in rs:
+    for r, cam0 in zip(rs, cams):
         s = _stream(dev)
+        # the reverse call runs on a renderer that keeps the emission slots, after its forward
+        rb = gs.Renderer(g, gs.ViewBatch([cam0], TILE, dev), P, capacity=r.bins.capacity)
+        rb.forward()
         for _ in range(reps):
             with Timer(torch) as a:
                 L.check(lib.gs_preprocess(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r.p), None, r.g.n, 1,
@@ -170,9 +174,9 @@ def main():
                 L.check(lib.gs_cluster_visibility(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
                                                   ctypes.byref(r.p), _ptr(one_cluster), 1, 0.01, _ptr(bits_buf), s))
             with Timer(torch) as f:
-                L.check(lib.gs_render_bwd(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r._sp),
-                                          ctypes.byref(r._sb), ctypes.byref(r.p), _ptr(r.t_final), _ptr(r.n_last),
-                                          _ptr(dl_buf), ctypes.byref(gg), _ptr(r.ws), r.ws.numel(), s))
+                L.check(lib.gs_render_bwd(ctypes.byref(rb._sg), ctypes.byref(rb._sv), ctypes.byref(rb._sp),
+                                          ctypes.byref(rb._sb), ctypes.byref(rb.p), _ptr(rb.t_final), _ptr(rb.n_last),
+                                          _ptr(dl_buf), ctypes.byref(gg), _ptr(rb.ws), rb.ws.numel(), s))
             stages["preprocess"].append(a.ms())
             stages["bin_sort"].append(b.ms())
             stages["render_fwd"].append(c.ms())
@@ -552,7 +556,7 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W, tune=True):
     torch.cuda.synchronize()
     out["fwd_bwd_1M_8uneven_batched_graph_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
     out["fwd_bwd_1M_8uneven_batched_graph_config"] = {"tile": list(cfg.tile), "batch_depth": cfg.batch_depth,
-                                                      "persistent": cfg.persistent}
+                                                      "lpt": cfg.lpt}
     log(f"  batched, {cfg}, hipGraph: {out['fwd_bwd_1M_8uneven_batched_graph_views_per_s']:.1f} views/s")
     assert step.ok()
     del step
@@ -585,13 +589,14 @@ def importance_rate(torch, gs, rs, n, dev, K):
 
 def importance_pass(torch, gs, scenes, P, dev, chunk=10):
     """Pruning score over all training rays: 500k Gaussians (mixture, SH-3), 150 orbit views
-    at 1256x828 in batches of `chunk` views, persistent longest-first launch; h = max over all
+    at 1256x828 in batches of `chunk` views, longest-first tile order; h = max over all
     pixels of all views of alpha*T, mask h < 0.01."""
     log("importance: 500k Gaussians, 150 views at 1256x828")
     sc = scenes.mixture_scene(500_000, seed=0, sh_degree=3)
     cams = scenes.orbit_views(150)
     g = gs.Gaussians.from_scene(sc, dev)
-    rs = [gs.Renderer(g, gs.ViewBatch(cams[i:i + chunk], TILE, dev, persistent=True), P, want_color=False)
+    rs = [gs.Renderer(g, gs.ViewBatch(cams[i:i + chunk], TILE, dev, lpt=True), P, want_color=False,
+                      backward=False)
           for i in range(0, len(cams), chunk)]
     h = torch.zeros(g.n, device=dev)
     for r in rs:

@@ -148,7 +148,8 @@ typedef struct gs_views {
     int64_t n_pixels;
     int32_t batch_depth;         /* list records staged per lane per batch in compositing: 1 or 2
                                     (2 only for tiles of at most 512 pixels) */
-    int32_t persistent;          /* 1: compositing runs as a persistent grid over bins->queue */
+    int32_t lpt;                 /* 1: the traversals take tiles longest list first (bins->queue);
+                                    0: in tile order */
 } gs_views;
 
 /* Per-(view, Gaussian) outputs of gs_preprocess, [n_views][n] each:
@@ -169,10 +170,18 @@ typedef struct gs_projected {
  *   vals    [capacity] index of the Gaussian within its view (0 .. n-1)
  *   ranges  [n_tiles][2] [start, end) of each tile in keys/vals
  *   n_pairs device scalar: pairs required
- *   overflow device scalar: 0 when the bins are valid (see the conventions above)
+ *   overflow device scalar: 0 when the bins are valid (see the conventions above); cleared
+ *           by every gs_bin_sort
  *   queue   [n_tiles] or NULL: when set, gs_bin_sort also writes every tile id ordered by
  *           decreasing list length (by powers of two; order within a power is unspecified),
- *           the work order of the persistent compositing launch */
+ *           the work order of the traversals when views->lpt is set
+ *   entry_offset  [n_views * n] or NULL: when set, gs_bin_sort writes the emission slot of
+ *           each (view, entry): the exclusive prefix sum of the tile counts in (view, entry)
+ *           order, so entry o owns the slots [entry_offset[o], entry_offset[o] + count[o]), one
+ *           per tile of its rectangle in row-major order. gs_render_bwd needs it.
+ *   overflow_sticky  device scalar or NULL: when set, every gs_bin_sort ORs its overflow word
+ *           into it; the library never clears it, so it reports an overflow in any frame since
+ *           the caller last cleared it */
 typedef struct gs_bins {
     uint64_t* keys;
     uint32_t* vals;
@@ -181,6 +190,8 @@ typedef struct gs_bins {
     uint64_t* n_pairs;
     uint32_t* overflow;
     uint32_t* queue;
+    uint32_t* entry_offset;
+    uint32_t* overflow_sticky;
 } gs_bins;
 
 /* Host helper: fill tile_offset[n_views+1] and pixel_offset[n_views+1] (HOST arrays)
@@ -190,7 +201,8 @@ gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w,
                          int32_t* tile_offset, int64_t* pixel_offset);
 
 /* Device workspace bytes needed by gs_bin_sort / gs_render_bwd / gs_bits_to_list / gs_prune for n
- * entries per view, n_views views, a pair capacity and n_tiles tiles. */
+ * entries per view, n_views views, a pair capacity and n_tiles tiles (gs_render_bwd keeps nine
+ * FP32 partial gradients per pair: 36 bytes x capacity). */
 size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 
 /* Project every Gaussian (or the listed subset) into every view of `views` (Sec. 3.2:
@@ -248,10 +260,16 @@ gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_pla
                             int64_t n_norm, float lambda, float* dl_dimg, float* loss_accum, void* ws,
                             size_t ws_bytes, void* stream);
 
-/* Gradient of L with respect to the Gaussian parameters given dL/d(rgb) (layout of
- * rgb), accumulated (+=) into grad. Reverse traversal per pixel from n_last; the
- * transmittance before each entry is recovered from t_final by division. proj must
- * come from gs_preprocess with want_color = 1 and no subset. ws as for gs_bin_sort. */
+/* Reverse mode of the render (the optimisation of the point representation phi, Sec. 3.2:
+ * the Gaussians' positions, scales, rotations, opacities and SH coefficients are fitted by
+ * gradient descent through the compositing of eq. render-gs). Given dL/d(rgb) (layout of rgb)
+ * it adds dL/d(parameters) into grad (+=). Reverse traversal per pixel from n_last, the
+ * transmittance before each entry recovered from t_final by division; every pair's nine 2D
+ * partial sums (u, v, conic, opacity, colour) go to the pair's own slot (no atomics), and each
+ * Gaussian's slots are summed in a fixed order, so the gradients repeat bit for bit from run
+ * to run. proj must come from gs_preprocess with want_color = 1 and no subset; bins from
+ * gs_bin_sort with entry_offset set; ws as for gs_bin_sort (gs_workspace_bytes with the
+ * bins' capacity). After a pair overflow (bins->overflow != 0) nothing is added. */
 gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_projected* proj,
                         const gs_bins* bins, const gs_params* p, const float* t_final, const uint32_t* n_last,
                         const float* dl_drgb, gs_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream);
@@ -267,7 +285,8 @@ gs_status gs_importance(const gs_projected* proj, const gs_views* views, const g
  * c = view_cluster[v] (device [n_views], 0 <= c < k), set bit i of row c of bits_accum
  * (device [k][ceil(n/32)] uint32, bit i%32 of word i/32) when Gaussian i is composited
  * with weight alpha*T > t_cluster in some pixel of v (that is, the per-cluster max
- * exceeds t_cluster). Bits are OR-ed into the buffer. */
+ * exceeds t_cluster). Bits are OR-ed into the buffer. A view whose cluster id lies outside
+ * [0, k) sets no bit (the ids are device data, so the library cannot check them on the host). */
 gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
                                 const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
                                 uint32_t* bits_accum, void* stream);

@@ -47,7 +47,7 @@ class gs_gaussians_grad(ctypes.Structure):
 class gs_views(ctypes.Structure):
     _fields_ = [("cams", c_void_p), ("tile_offset", c_void_p), ("pixel_offset", c_void_p), ("n_views", i32),
                 ("tile_w", i32), ("tile_h", i32), ("n_tiles", i32), ("n_pixels", i64), ("batch_depth", i32),
-                ("persistent", i32)]
+                ("lpt", i32)]
 
 
 class gs_projected(ctypes.Structure):
@@ -56,7 +56,8 @@ class gs_projected(ctypes.Structure):
 
 class gs_bins(ctypes.Structure):
     _fields_ = [("keys", c_void_p), ("vals", c_void_p), ("ranges", c_void_p), ("capacity", u64),
-                ("n_pairs", c_void_p), ("overflow", c_void_p), ("queue", c_void_p)]
+                ("n_pairs", c_void_p), ("overflow", c_void_p), ("queue", c_void_p), ("entry_offset", c_void_p),
+                ("overflow_sticky", c_void_p)]
 
 
 class gs_adam_group(ctypes.Structure):

@@ -31,7 +31,7 @@ gs_status check_launch(const char* what) {
 gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_params*, const int32_t*, int64_t, int,
                             gs_projected*, hipStream_t);
 gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
-                                const float*, gs_gaussians_grad*, hipStream_t);
+                                const gs_bins*, const float*, gs_gaussians_grad*, hipStream_t);
 gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t);
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
@@ -60,12 +60,14 @@ gs_status launch_ssim_loss_grad(const float*, const float*, int32_t, int32_t, in
 gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
                             hipStream_t);
 gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
-                            float, uint32_t*, hipStream_t);
+                            int32_t, float, uint32_t*, hipStream_t);
 gs_status launch_render_bwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const float*,
-                            const uint32_t*, const float*, float*, hipStream_t);
+                            const uint32_t*, const float*, float*, float*, hipStream_t);
 
-static size_t bwd_workspace_bytes(int64_t n, int32_t n_views) {
-    return sizeof(float) * 9 * (size_t)n * (size_t)n_views;
+// nine FP32 partial gradients per pair slot, then their nine sums per (view, entry)
+static size_t bwd_slots_bytes(uint64_t capacity) { return (sizeof(float) * 9 * (size_t)capacity + 255) & ~(size_t)255; }
+static size_t bwd_workspace_bytes(uint64_t capacity, int64_t n, int32_t n_views) {
+    return bwd_slots_bytes(capacity) + sizeof(float) * 9 * (size_t)n * (size_t)n_views;
 }
 
 static bool tile_ok(int tw, int th) {
@@ -86,14 +88,13 @@ static gs_status check_views(const gs_views* v) {
         return set_error(GS_ERR_UNSUPPORTED, "batch_depth must be 1 or 2 (got %d)", v->batch_depth);
     if (v->batch_depth == 2 && v->tile_w * v->tile_h > 512)
         return set_error(GS_ERR_UNSUPPORTED, "batch_depth 2 needs a tile of at most 512 pixels (LDS)");
-    if (v->persistent != 0 && v->persistent != 1)
-        return set_error(GS_ERR_INVALID_ARG, "persistent must be 0 or 1 (got %d)", v->persistent);
+    if (v->lpt != 0 && v->lpt != 1) return set_error(GS_ERR_INVALID_ARG, "lpt must be 0 or 1 (got %d)", v->lpt);
     return GS_OK;
 }
 
 static gs_status check_queue(const gs_views* v, const gs_bins* b) {
-    if (v->persistent && !b->queue)
-        return set_error(GS_ERR_INVALID_ARG, "persistent compositing needs bins->queue (built by gs_bin_sort)");
+    if (v->lpt && !b->queue)
+        return set_error(GS_ERR_INVALID_ARG, "the longest-first order needs bins->queue (built by gs_bin_sort)");
     return GS_OK;
 }
 
@@ -165,7 +166,7 @@ gs_status gs_view_layout(const gs_camera* cams, int32_t n_views, int32_t tile_w,
 size_t gs_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
     if (n < 0 || n_views < 0) return 0;
     size_t b = sort_workspace_bytes(n, n_views, capacity, n_tiles);
-    b = std::max(b, bwd_workspace_bytes(n, n_views));
+    b = std::max(b, bwd_workspace_bytes(capacity, n, n_views));
     b = std::max(b, list_workspace_bytes(n));
     b = std::max(b, prune_workspace_bytes(n) + list_workspace_bytes(n));
     return b;
@@ -259,14 +260,16 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_p
     if ((st = check_queue(views, bins))) return st;
     if (views->n_pixels > 0 && (!t_final || !n_last || !dl_drgb))
         return set_error(GS_ERR_INVALID_ARG, "t_final, n_last or dl_drgb is NULL");
-    const size_t need = bwd_workspace_bytes(g->n, views->n_views);
+    if (g->n > 0 && !bins->entry_offset)
+        return set_error(GS_ERR_INVALID_ARG, "the backward needs bins->entry_offset (written by gs_bin_sort)");
+    const size_t need = bwd_workspace_bytes(bins->capacity, g->n, views->n_views);
     if (ws_bytes < need || (need > 0 && !ws))
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
-    float* g2 = (float*)ws;
-    if ((st = launch_fill_f32(g2, 9 * g->n * (int64_t)views->n_views, 0.f, s))) return st;
-    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, g2, s))) return st;
-    return launch_preprocess_bwd(g, views, p, proj, g2, grad, s);
+    float* slots = (float*)ws;
+    float* g2 = (float*)((char*)ws + bwd_slots_bytes(bins->capacity));
+    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, slots, g2, s))) return st;
+    return launch_preprocess_bwd(g, views, p, proj, bins, g2, grad, s);
 }
 
 gs_status gs_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -292,7 +295,7 @@ gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views,
         return set_error(GS_ERR_INVALID_ARG, "view_cluster or bits_accum is NULL");
     if (!(t_cluster >= 0.f)) return set_error(GS_ERR_INVALID_ARG, "t_cluster must be >= 0");
     if ((st = check_queue(views, bins))) return st;
-    return launch_visibility(proj, views, bins, p, view_cluster, t_cluster, bits_accum, (hipStream_t)stream);
+    return launch_visibility(proj, views, bins, p, view_cluster, k, t_cluster, bits_accum, (hipStream_t)stream);
 }
 
 gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, int64_t* count, void* ws,

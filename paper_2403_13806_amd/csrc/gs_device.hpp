@@ -81,6 +81,13 @@ __device__ __forceinline__ float wave_sum(float x) {
     return a + b;
 }
 
+// the LDS writes of this wave are visible to its later LDS reads (no other wave involved)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------------------
 // View lookup for a global tile id: largest v with tile_offset[v] <= tile.
 // ---------------------------------------------------------------------------------------

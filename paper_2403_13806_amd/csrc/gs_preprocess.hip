@@ -338,8 +338,9 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 
 // ---------------------------------------------------------------------------------------
 // Reverse mode: chain per-(view, Gaussian) gradients of the 2D quantities (u, v, conic
-// a, b, c, opacity, rgb) to the parameters. One thread per Gaussian, looping over the
-// views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
+// a, b, c, opacity, rgb) to the parameters (the per-entry sums over the entry's pairs, formed
+// in a fixed order by the reverse traversal's last step). One thread per Gaussian, looping
+// over the views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
 // This kernel covers position (through u, v and J), scale, rotation and opacity; the
 // colour part follows in k_preprocess_bwd_sh.
 // ---------------------------------------------------------------------------------------
@@ -355,7 +356,8 @@ struct PreBwdArgs {
     int n_views;
     gs_params p;
     const uint32_t* count;   // [V][n]
-    const float* g2;         // [9][V*n]
+    const float* g2;         // [9][V*n], read where count > 0
+    const uint32_t* overflow;  // nothing is added after a pair overflow
     float* gmean;
     float* gscale;
     float* gquat;
@@ -365,7 +367,7 @@ struct PreBwdArgs {
 
 __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
     const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
-    if (i >= a.n) return;
+    if (i >= a.n || *a.overflow) return;
     const int64_t VN = (int64_t)a.n_views * a.n;
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
     bool any = false;
@@ -509,6 +511,7 @@ __global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
     __shared__ uint32_t s_any[3][64];
     const int c = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 64 + l;
+    if (*a.overflow) return;  // the same for the whole workgroup
     const bool valid = i < a.n;
     const int64_t VN = (int64_t)a.n_views * a.n;
     float shv[NB], gsh[NB];
@@ -618,8 +621,8 @@ gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const 
 }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, const gs_params* p,
-                                const gs_projected* proj, const float* g2, gs_gaussians_grad* grad,
-                                hipStream_t stream) {
+                                const gs_projected* proj, const gs_bins* bins, const float* g2,
+                                gs_gaussians_grad* grad, hipStream_t stream) {
     if (g->n == 0) return GS_OK;
     PreBwdArgs a;
     a.mean = g->mean;
@@ -634,6 +637,7 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.p = *p;
     a.count = proj->count;
     a.g2 = g2;
+    a.overflow = bins->overflow;
     a.gmean = grad->mean;
     a.gscale = grad->scale;
     a.gquat = grad->quat;

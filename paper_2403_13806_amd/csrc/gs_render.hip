@@ -11,10 +11,10 @@
 // support test d^T conic d <= q_max runs in FP64 -- same issue rate as FP32 on CDNA4 -- so
 // it agrees with an FP64 evaluation; the exponential and the transmittance are FP32.
 //
-// Launch forms: one workgroup per tile, or persistent -- a grid of (CUs x occupancy)
-// workgroups walking a list of tiles ordered longest-first (LPT), workgroup b taking
-// entries b, 2G-1-b, 2G+b, ... (boustrophedon), so no shared counter has to be reset
-// between launches and a captured graph can replay the launch as is.
+// One workgroup per tile. Workgroup b takes tile b, or, in the longest-first (LPT) order,
+// the b-th entry of a list of tiles sorted by decreasing list length: workgroups are
+// dispatched in increasing b as resources free up, so the dispatcher itself hands out the
+// longest tiles first, with no queue counter to reset between launches or graph replays.
 #include <math.h>
 
 #include <algorithm>
@@ -49,14 +49,17 @@ struct RenderArgs {
     const int32_t* view_cluster;
     int64_t words;
     float t_cluster;
+    int k_clusters;  // rows of bits; views with a cluster id outside [0, k) set nothing
     // backward
     const float* dl_drgb;
     const float* t_in;
     const uint32_t* last_in;
-    float* g2;  // [9][n_views * n]
-    // persistent form
-    const uint32_t* queue;  // tiles, longest list first
-    int n_tiles;
+    const uint64_t* rect;          // [n_views * n] tile rectangles
+    const uint32_t* entry_offset;  // [n_views * n] first emission slot of each entry
+    uint64_t capacity;             // slots
+    float* slots;                  // [capacity][9] per-pair partial gradients
+    // longest-first order
+    const uint32_t* queue;  // tiles, longest list first, or NULL
 };
 
 // bit w set when the support ellipse d^T conic d <= q_max meets the rectangle spanned by
@@ -94,7 +97,7 @@ __device__ __forceinline__ uint64_t wave_hits(const gs_splat& s, double ox, doub
 }
 
 struct TileGeom {
-    int view, W, H, px, py, wave;
+    int view, W, H, tx, ty, px, py, wave;
     bool inside;
     double ox, oy;   // centre of the tile's first pixel
     int64_t pix;     // global pixel index
@@ -110,6 +113,8 @@ __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     const int tiles_x = div_up(g.W, TW);
     const int local = tile - a.tile_offset[g.view];
     const int tx = local % tiles_x, ty = local / tiles_x;
+    g.tx = tx;
+    g.ty = ty;
     const int t = threadIdx.x, l = t & 63;
     g.wave = t >> 6;
     const int bx = (g.wave % (TW / 8)) * 8, by = (g.wave / (TW / 8)) * 8;
@@ -154,11 +159,22 @@ struct Smem {
     uint32_t top;
 };
 
-// the backward also accumulates, per staged record, the nine 2D-gradient sums of all waves
-template <int TW, int TH, int DEPTH>
-struct SmemBwd : Smem<TW, TH, DEPTH> {
-    float acc[Smem<TW, TH, DEPTH>::BD * 9];
-    uint64_t hitq[Smem<TW, TH, DEPTH>::BD];  // quarter masks, bit 4 w + quarter
+// The reverse traversal stages BB records per batch and keeps, per wave and staged record,
+// the nine 2D-gradient sums of that wave's pixels: the waves' sums are combined in wave
+// order when the batch is flushed, so every per-pair sum is formed in a fixed order.
+template <int TW, int TH>
+struct BwdShape {
+    static constexpr int NT = TW * TH, NW = NT / 64, BB = NT < 128 ? NT : 128;
+};
+
+template <int TW, int TH>
+struct SmemBwd {
+    using S = BwdShape<TW, TH>;
+    gs_splat rec[S::BB];
+    uint64_t hitq[S::BB];  // quarter masks, bit 4 w + quarter
+    uint32_t gid[S::BB];
+    float acc[S::NW * S::BB * 9];  // [wave][record][field]
+    uint32_t top;
 };
 
 // stage records [base, base + cnt) of the tile's list; mark the wave blocks each one meets
@@ -181,24 +197,29 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
     }
 }
 
-// the backward's staging: quarter masks
-template <int TW, int TH, int DEPTH>
-__device__ __forceinline__ void stage_q(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, const gs_splat* sp,
+// the backward's staging: records [base, base + cnt) with their quarter masks
+template <int TW, int TH>
+__device__ __forceinline__ void stage_q(SmemBwd<TW, TH>& sm, const RenderArgs& a, const gs_splat* sp,
                                         uint32_t base, uint32_t cnt, const TileGeom& g) {
-    constexpr int NT = TW * TH;
-#pragma unroll
-    for (int d = 0; d < DEPTH; ++d) {
-        const uint32_t q = threadIdx.x + d * NT;
-        uint64_t hm = 0;
-        const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
-        if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
-            const gs_splat s = sp[id];
-            sm.rec[q] = s;
-            sm.gid[q] = id;
-            hm = wave_hits<TW, TH, true>(s, g.ox, g.oy);
-        }
-        sm.hitq[q] = hm;
+    const uint32_t q = threadIdx.x;
+    if (q >= (uint32_t)BwdShape<TW, TH>::BB) return;
+    uint64_t hm = 0;
+    const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
+    if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
+        const gs_splat s = sp[id];
+        sm.rec[q] = s;
+        hm = wave_hits<TW, TH, true>(s, g.ox, g.oy);
     }
+    sm.gid[q] = (int64_t)id < a.n ? id : 0xffffffffu;
+    sm.hitq[q] = hm;
+}
+
+// emission slot of the pair (tile (tx, ty) of its view, entry o): entry o's pairs are
+// numbered from entry_offset[o] over the tiles of its rectangle in row-major order
+__device__ __forceinline__ uint64_t pair_slot(const RenderArgs& a, int64_t o, int tx, int ty) {
+    const uint64_t r = a.rect[o];
+    const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff;
+    return (uint64_t)a.entry_offset[o] + (uint64_t)((uint32_t)ty - y0) * (x1 - x0 + 1u) + ((uint32_t)tx - x0);
 }
 
 template <int TW, int TH, int DEPTH, int MODE>
@@ -214,7 +235,11 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
     float T = g.inside ? 1.f : -1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     uint32_t last = start, ncomp = 0;
     int cluster = 0;
-    if (MODE == MODE_VISIBILITY) cluster = a.view_cluster[g.view];
+    bool cluster_ok = true;
+    if (MODE == MODE_VISIBILITY) {
+        cluster = a.view_cluster[g.view];
+        cluster_ok = (unsigned)cluster < (unsigned)a.k_clusters;
+    }
     for (uint32_t base = start; base < end; base += BD) {
         if (__syncthreads_and(!(T >= tmin))) break;
         const uint32_t cnt = min((uint32_t)BD, end - base);
@@ -270,7 +295,7 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
             for (int d = 0; d < DEPTH; ++d) {
                 const uint32_t q = threadIdx.x + d * TW * TH;
                 const uint32_t v = sm.hacc[q];
-                if (q < cnt && v != 0u) {
+                if (q < cnt && v != 0u && cluster_ok) {
                     const uint32_t id = sm.gid[q];
                     if (MODE == MODE_IMPORTANCE) {
                         unsigned int* hp = reinterpret_cast<unsigned int*>(a.h) + id;
@@ -284,7 +309,6 @@ __device__ void fwd_tile(Smem<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile)
             }
         }
     }
-    __syncthreads();  // the staging area is reused by the next tile of a persistent workgroup
     if ((MODE == MODE_FWD || MODE == MODE_FWD_COUNT) && g.inside) {
         const int64_t plane = (int64_t)g.W * g.H;
         float* out = a.rgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
@@ -348,12 +372,14 @@ __device__ __forceinline__ float row_sum9(const float (&v)[9], int lane) {
 // then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
 // dx = xc - u. Each row of 16 lanes holds a 4x4 quarter of the wave's block and walks only
 // the entries that meet its quarter, so one iteration serves up to four entries; the nine
-// per-entry sums are reduced over the row into the entry's LDS accumulator, and one global
-// atomic per (tile, entry, field) adds the workgroup's sums into g2[field][view * n + index].
-template <int TW, int TH, int DEPTH>
-__device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int tile) {
-    constexpr int NT = TW * TH;
-    constexpr int BD = NT * DEPTH;
+// per-entry sums are reduced over the row and added into the wave's own LDS accumulator of
+// the entry. When a batch is done, its records' wave sums are added in wave order and
+// stored (plain stores) into each pair's emission slot; pairs behind every pixel's last
+// entry get zeros. Each Gaussian's slots are then summed by the parameter chains.
+template <int TW, int TH>
+__device__ void bwd_tile(SmemBwd<TW, TH>& sm, const RenderArgs& a, int tile) {
+    using S = BwdShape<TW, TH>;
+    constexpr int NT = S::NT, BB = S::BB, NW = S::NW;
     const TileGeom g = tile_geom<TW, TH, true>(a, tile);
     const int t = threadIdx.x, l = t & 63, w = g.wave;
     const int fld = row_sum9_field(l);
@@ -381,23 +407,32 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
     if (g.inside && last > start) atomicMax(&sm.top, last);
     __syncthreads();
     const uint32_t top = sm.top;
-    const int64_t VN = (int64_t)a.n_views * a.n;
+    // the quarter's last composited entry (max over its 16 pixels): entries behind it are skipped
+    int ql = (int)last;
+    ql = max(ql, dpp<0xB1>(ql));
+    ql = max(ql, dpp<0x4E>(ql));
+    ql = max(ql, dpp<0x141>(ql));
+    ql = max(ql, dpp<0x140>(ql));
+    const uint32_t qlast = (uint32_t)ql;
     const int64_t vbase = (int64_t)g.view * a.n;
-    for (int q = t; q < BD * 9; q += NT) sm.acc[q] = 0.f;
+    float* accw = sm.acc + w * (BB * 9);
+    for (int q = t; q < NW * BB * 9; q += NT) sm.acc[q] = 0.f;
     for (uint32_t hi = top; hi > start;) {
-        const uint32_t lo = (hi - start > (uint32_t)BD) ? hi - BD : start;
+        const uint32_t lo = (hi - start > (uint32_t)BB) ? hi - BB : start;
         __syncthreads();
-        stage_q<TW, TH, DEPTH>(sm, a, sp, lo, hi - lo, g);
+        stage_q<TW, TH>(sm, a, sp, lo, hi - lo, g);
         __syncthreads();
         // entries that meet this wave's block, back to front
 #pragma unroll 1
-        for (int c = BD / 64 - 1; c >= 0; --c) {
+        for (int c = BB / 64 - 1; c >= 0; --c) {
             // each quarter (one row of 16 lanes) walks the entries that meet its 4x4 pixels
             const uint32_t hq = (uint32_t)(sm.hitq[c * 64 + l] >> (4 * w));
             const uint64_t m0 = ballot(hq & 1u), m1 = ballot((hq >> 1) & 1u), m2 = ballot((hq >> 2) & 1u),
                            m3 = ballot((hq >> 3) & 1u);
             const int qd = l >> 4;
             uint64_t m = qd == 0 ? m0 : qd == 1 ? m1 : qd == 2 ? m2 : m3;  // the same in a quarter
+            const int64_t lim = (int64_t)qlast - (int64_t)(lo + c * 64);
+            m = lim <= 0 ? 0ull : (lim >= 64 ? m : m & ((1ull << lim) - 1ull));
             while (ballot(m != 0)) {
                 const bool act = m != 0;
                 const int b = act ? 63 - (int)__builtin_clzll(m) : 0;
@@ -437,48 +472,135 @@ __device__ void bwd_tile(SmemBwd<TW, TH, DEPTH>& sm, const RenderArgs& a, int ti
                 v[6] = contrib ? dC0 * wt : 0.f;
                 v[7] = contrib ? dC1 * wt : 0.f;
                 v[8] = contrib ? dC2 * wt : 0.f;
-                // per-quarter sums, one field per lane, added into that quarter's entry
+                // per-quarter sums, one field per lane, added into this wave's sums of that
+                // entry (lanes of one instruction that meet at one address are applied in a
+                // fixed order, so the result does not depend on timing)
                 const float z = row_sum9(v, l);
-                if (act & (fld < 9)) atomicAdd(&sm.acc[j * 9 + fld], z);
+                if (act & (fld < 9)) atomicAdd(&accw[j * 9 + fld], z);
             }
         }
         __syncthreads();
-        // one global atomic per (tile, record, field) for the whole workgroup; the sums of
-        // dq dx and dq dy become dL/du = -2 (a sx + b sy), dL/dv = -2 (b sx + c sy)
+        // one slot per (tile, record): each (record, field) sum of the waves is formed in wave
+        // order (into wave 0's accumulator), then each record's nine sums are stored with plain
+        // stores; the sums of dq dx and dq dy become dL/du = -2 (a sx + b sy), dL/dv = -2 (b sx + c sy)
+        for (int q = t; q < BB * 9; q += NT) {
+            float sum = sm.acc[q];
+#pragma unroll 1
+            for (int ww = 1; ww < NW; ++ww) {
+                sum += sm.acc[ww * BB * 9 + q];
+                sm.acc[ww * BB * 9 + q] = 0.f;
+            }
+            sm.acc[q] = sum;
+        }
+        __syncthreads();
         const uint32_t cnt = hi - lo;
-        for (int j = t; j < BD; j += NT) {
+        if (t < BB) {
             float f9[9];
 #pragma unroll
             for (int f = 0; f < 9; ++f) {
-                f9[f] = sm.acc[j * 9 + f];
-                sm.acc[j * 9 + f] = 0.f;
+                f9[f] = sm.acc[t * 9 + f];
+                sm.acc[t * 9 + f] = 0.f;
             }
-            if ((uint32_t)j >= cnt) continue;
-            const float sx = f9[0], sy = f9[1];
-            f9[0] = -2.f * ((float)sm.rec[j].ca * sx + (float)sm.rec[j].cb * sy);
-            f9[1] = -2.f * ((float)sm.rec[j].cb * sx + (float)sm.rec[j].cc * sy);
-            const int64_t gi = vbase + sm.gid[j];
+            const uint32_t id = sm.gid[t];
+            if ((uint32_t)t < cnt && id != 0xffffffffu) {
+                const float sx = f9[0], sy = f9[1];
+                f9[0] = -2.f * ((float)sm.rec[t].ca * sx + (float)sm.rec[t].cb * sy);
+                f9[1] = -2.f * ((float)sm.rec[t].cb * sx + (float)sm.rec[t].cc * sy);
+                const uint64_t slot = pair_slot(a, vbase + id, g.tx, g.ty);
+                if (slot < a.capacity) {
+                    float* dst = a.slots + slot * 9;
 #pragma unroll
-            for (int f = 0; f < 9; ++f)
-                if (f9[f] != 0.f) atomicAdd(a.g2 + f * VN + gi, f9[f]);
+                    for (int f = 0; f < 9; ++f) dst[f] = f9[f];
+                }
+            }
         }
         hi = lo;
     }
-    __syncthreads();
+    // pairs behind every pixel's last composited entry contribute nothing
+    for (uint32_t pos = top + t; pos < end; pos += NT) {
+        const uint32_t id = a.vals[pos];
+        if ((int64_t)id >= a.n) continue;
+        const uint64_t slot = pair_slot(a, vbase + id, g.tx, g.ty);
+        if (slot < a.capacity) {
+            float* dst = a.slots + slot * 9;
+#pragma unroll
+            for (int f = 0; f < 9; ++f) dst[f] = 0.f;
+        }
+    }
 }
 
-// tile of the i-th work item of workgroup b in the persistent form (boustrophedon rounds)
-__device__ __forceinline__ int persistent_item(int r, int b, int G) {
-    return r * G + ((r & 1) ? G - 1 - b : b);
+// Per-entry sums of the pair slots: entry o owns the slots [entry_offset[o], entry_offset[o] +
+// count[o]) and consecutive entries own consecutive runs, so the runs of a wave's 64 entries
+// form one range, read 64 slots at a time (coalesced). In each chunk a segmented inclusive
+// scan over the lanes (lanes of one entry are contiguous) sums every entry's slots in the
+// chunk, and the last lane of each run hands the sum to the entry's own lane through LDS; the
+// entry's lane adds the chunks in order. Every sum is formed in the same order on every run.
+// Writes g2[f][o] (f < 9) for the entries with count > 0.
+__global__ __launch_bounds__(256) void k_pair_sums(const uint32_t* __restrict__ count,
+                                                   const uint32_t* __restrict__ eoff, int64_t vn,
+                                                   const float* __restrict__ slots, uint64_t capacity,
+                                                   const uint32_t* overflow, float* __restrict__ g2) {
+    __shared__ uint32_t s_beg[4][64];
+    __shared__ float s_part[4][64 * 9];
+    if (*overflow) return;  // the slots are incomplete; nothing is added downstream either
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t o0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    if (o0 >= vn) return;  // the whole wave (no workgroup barrier below)
+    const int64_t o = o0 + l;
+    const bool valid = o < vn;
+    const uint32_t c = valid ? count[o] : 0u;
+    const uint32_t e = valid ? eoff[o] : 0u;
+    const int last = (int)min((int64_t)63, vn - 1 - o0);
+    const uint32_t S0 = wave_read(e, 0), S1 = wave_read(e + c, last);
+    s_beg[w][l] = e;
+    wave_sync();
+    float acc[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) acc[f] = 0.f;
+    for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
+        const uint32_t sl = base + l;
+        const bool in = sl < S1 && (uint64_t)sl < capacity;
+        // owner: the largest lane whose run starts at or before sl (lanes with no pairs share
+        // the next lane's start, so the largest such lane is the one with pairs)
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (L + step <= last && s_beg[w][L + step] <= sl) L += step;
+        if (!in) L = -1 - l;  // unique: never merged with another lane
+        float x[9];
+#pragma unroll
+        for (int f = 0; f < 9; ++f) x[f] = in ? slots[(uint64_t)sl * 9 + f] : 0.f;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int Ld = __shfl_up(L, d);
+            const bool merge = l >= d && Ld == L;
+#pragma unroll
+            for (int f = 0; f < 9; ++f) {
+                const float y = __shfl_up(x[f], d);
+                x[f] = merge ? x[f] + y : x[f];
+            }
+        }
+        const int Ln = __shfl_down(L, 1);
+        if (in && (l == 63 || Ln != L)) {
+#pragma unroll
+            for (int f = 0; f < 9; ++f) s_part[w][L * 9 + f] = x[f];
+        }
+        wave_sync();
+        if (c > 0 && e < base + 64 && e + c > base) {
+#pragma unroll
+            for (int f = 0; f < 9; ++f) acc[f] += s_part[w][l * 9 + f];
+        }
+        wave_sync();
+    }
+    if (c > 0) {
+#pragma unroll
+        for (int f = 0; f < 9; ++f) g2[f * vn + o] = acc[f];
+    }
 }
 
-// tile of round r of workgroup b: the workgroup's own tile in the one-per-tile form, the
-// r-th boustrophedon item of the longest-first list in the persistent form; -1 when done
-__device__ __forceinline__ int tile_of_round(const RenderArgs& a, int r) {
-    const int b = blockIdx.x;
-    if (a.queue == nullptr) return r == 0 ? b : -1;
-    const int item = persistent_item(r, b, gridDim.x);
-    return item < a.n_tiles ? (int)a.queue[item] : -1;
+// tile of this workgroup: its own, or the entry of the longest-first list at its position
+__device__ __forceinline__ int tile_of_block(const RenderArgs& a) {
+    return a.queue ? (int)a.queue[blockIdx.x] : (int)blockIdx.x;
 }
 
 // single-depth batches: at most 64 VGPRs, so that eight waves fit on each SIMD
@@ -486,21 +608,13 @@ template <int TW, int TH, int DEPTH, int MODE>
 __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(DEPTH == 1 ? 8 : 1, 8))) void k_render(
     RenderArgs a) {
     __shared__ Smem<TW, TH, DEPTH> sm;
-    for (int r = 0;; ++r) {
-        const int tile = tile_of_round(a, r);
-        if (tile < 0) break;
-        fwd_tile<TW, TH, DEPTH, MODE>(sm, a, tile);
-    }
+    fwd_tile<TW, TH, DEPTH, MODE>(sm, a, tile_of_block(a));
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
-    __shared__ SmemBwd<TW, TH, DEPTH> sm;
-    for (int r = 0;; ++r) {
-        const int tile = tile_of_round(a, r);
-        if (tile < 0) break;
-        bwd_tile<TW, TH, DEPTH>(sm, a, tile);
-    }
+    __shared__ SmemBwd<TW, TH> sm;
+    bwd_tile<TW, TH>(sm, a, tile_of_block(a));
 }
 
 // L1 loss and its gradient: grid-stride over the elements, one atomic per workgroup for
@@ -559,8 +673,7 @@ int persistent_grid(const void* fn, int threads, int64_t n_tiles) {
 
 template <typename K>
 static void launch_tiles(K kernel, const RenderArgs& a, int threads, int n_tiles, hipStream_t s) {
-    const int grid = a.queue ? persistent_grid(reinterpret_cast<const void*>(kernel), threads, n_tiles) : n_tiles;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(threads), 0, s, a);
 }
 
 template <int MODE>
@@ -583,21 +696,14 @@ static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int n_ti
     return false;
 }
 
-static bool launch_bwd(const RenderArgs& a, int tw, int th, int depth, int n_tiles, hipStream_t s) {
-#define GS_CASE(W_, H_, D_)                                                                      \
-    if (tw == W_ && th == H_ && depth == D_) {                                                   \
-        launch_tiles(k_render_bwd<W_, H_, D_>, a, W_ * H_, n_tiles, s);                          \
+static bool launch_bwd(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
+#define GS_CASE(W_, H_)                                                                          \
+    if (tw == W_ && th == H_) {                                                                  \
+        launch_tiles(k_render_bwd<W_, H_>, a, W_ * H_, n_tiles, s);                              \
         return true;                                                                             \
     }
-    GS_CASE(8, 8, 1) GS_CASE(8, 8, 2)
-    GS_CASE(16, 8, 1) GS_CASE(16, 8, 2)
-    GS_CASE(8, 16, 1) GS_CASE(8, 16, 2)
-    GS_CASE(16, 16, 1) GS_CASE(16, 16, 2)
-    GS_CASE(32, 8, 1) GS_CASE(32, 8, 2)
-    GS_CASE(8, 32, 1) GS_CASE(8, 32, 2)
-    GS_CASE(32, 16, 1) GS_CASE(32, 16, 2)
-    GS_CASE(16, 32, 1) GS_CASE(16, 32, 2)
-    GS_CASE(32, 32, 1)
+    GS_CASE(8, 8) GS_CASE(16, 8) GS_CASE(8, 16) GS_CASE(16, 16) GS_CASE(32, 8) GS_CASE(8, 32)
+    GS_CASE(32, 16) GS_CASE(16, 32) GS_CASE(32, 32)
 #undef GS_CASE
     return false;
 }
@@ -614,8 +720,7 @@ static RenderArgs base_args(const gs_projected* proj, const gs_views* views, con
     a.n_views = views->n_views;
     a.n = proj->n;
     a.p = *p;
-    a.queue = views->persistent ? bins->queue : nullptr;
-    a.n_tiles = views->n_tiles;
+    a.queue = views->lpt ? bins->queue : nullptr;
     return a;
 }
 
@@ -650,11 +755,12 @@ gs_status launch_importance(const gs_projected* proj, const gs_views* views, con
 }
 
 gs_status launch_visibility(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
-                            const int32_t* view_cluster, float t_cluster, uint32_t* bits, hipStream_t s) {
+                            const int32_t* view_cluster, int32_t k, float t_cluster, uint32_t* bits, hipStream_t s) {
     if (views->n_tiles == 0) return GS_OK;
     RenderArgs a = base_args(proj, views, bins, p);
     a.bits = bits;
     a.view_cluster = view_cluster;
+    a.k_clusters = k;
     a.words = (proj->n + 31) / 32;
     a.t_cluster = t_cluster;
     return finish(
@@ -663,15 +769,23 @@ gs_status launch_visibility(const gs_projected* proj, const gs_views* views, con
 }
 
 gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
-                            const float* t_final, const uint32_t* n_last, const float* dl_drgb, float* g2,
-                            hipStream_t s) {
+                            const float* t_final, const uint32_t* n_last, const float* dl_drgb, float* slots,
+                            float* g2, hipStream_t s) {
     if (views->n_tiles == 0) return GS_OK;
+    const int64_t vn = proj->n * (int64_t)views->n_views;
     RenderArgs a = base_args(proj, views, bins, p);
     a.t_in = t_final;
     a.last_in = n_last;
     a.dl_drgb = dl_drgb;
-    a.g2 = g2;
-    return finish(launch_bwd(a, views->tile_w, views->tile_h, views->batch_depth, views->n_tiles, s), "render_bwd");
+    a.rect = proj->rect;
+    a.entry_offset = bins->entry_offset;
+    a.capacity = bins->capacity;
+    a.slots = slots;
+    if (!launch_bwd(a, views->tile_w, views->tile_h, views->n_tiles, s)) return finish(false, "render_bwd");
+    if (vn > 0)
+        hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj->count,
+                           bins->entry_offset, vn, slots, bins->capacity, bins->overflow, g2);
+    return check_launch("render_bwd");
 }
 
 }  // namespace gs

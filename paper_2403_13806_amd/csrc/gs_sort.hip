@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_count_bsums(const uint32_t* __restrict_
 // one workgroup scans the block sums in chunks of SB_T * 4 (coalesced loads, the next chunk
 // requested before the current one is scanned) with a running carry
 __global__ __launch_bounds__(SB_T) void k_scan_bsums(uint32_t* __restrict__ bsum, int64_t m, uint64_t* total_out,
-                                                     uint32_t* flags, uint64_t capacity) {
+                                                     uint32_t* flags, uint64_t capacity, uint32_t* sticky) {
     constexpr int CH = SB_T * 4;
     __shared__ uint64_t part[SB_T / 64 + 1];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
@@ -299,7 +299,10 @@ __global__ __launch_bounds__(SB_T) void k_scan_bsums(uint32_t* __restrict__ bsum
     }
     if (t == 0) {
         if (total_out) *total_out = carry;
-        if (flags && carry > capacity) atomicOr(flags, 1u);
+        if (flags && carry > capacity) {
+            atomicOr(flags, 1u);
+            if (sticky) atomicOr(sticky, 1u);
+        }
     }
 }
 
@@ -315,6 +318,7 @@ struct EmitArgs {
     const uint32_t* overflow;
     uint32_t* tkey;        // global tile of each pair
     uint64_t* tval;        // FP32 depth bits << 32 | Gaussian index
+    uint32_t* eoff;        // [n_views * n] first pair of each entry, or NULL
 };
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
@@ -337,7 +341,10 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     }
     uint32_t btot;
     const uint32_t ex = block_excl_scan(c, btot, s_wsum);
-    if (j < a.n) off = a.bpre[(int64_t)v * gridDim.x + blockIdx.x] + ex;
+    if (j < a.n) {
+        off = a.bpre[(int64_t)v * gridDim.x + blockIdx.x] + ex;
+        if (a.eoff) a.eoff[o] = off;
+    }
     s_off[t] = off;
     s_db[t] = db;
     s_rect[t] = r;
@@ -570,14 +577,8 @@ struct TileSortArgs {
     uint32_t* vals;
     uint32_t* n_deferred;  // number of deferred tiles (zero on entry)
     uint32_t* deferred;    // [n_tiles] their ids
+    uint32_t* sticky;      // OR-ed with the overflow word, or NULL
 };
-
-// the LDS writes of this wave are visible to its later LDS reads (no other wave involved)
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Ascending bitonic sort of s[0, N) by a 256-thread workgroup (N a power of two >= 2).
 // Pair i of a stage goes to thread i mod 256, so in a stage of stride j <= 64 the pairs of
@@ -752,6 +753,11 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
 // deferred (long) lists; a grid-stride loop over them
 __global__ __launch_bounds__(256) void k_tile_sort_large(TileSortArgs a) {
     __shared__ uint64_t s[LARGE_LIST];
+    // the last launch of the binning: every flag of this frame is set by now
+    if (a.sticky && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t o = *a.overflow;
+        if (o) atomicOr(a.sticky, o);
+    }
     if (*a.overflow) return;
     const uint32_t nd = min(*a.n_deferred, (uint32_t)a.n_tiles);
     for (uint32_t it = blockIdx.x; it < nd; it += gridDim.x) {
@@ -803,7 +809,7 @@ __global__ void k_iota(uint32_t* __restrict__ p, int n) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Longest-first tile order for the persistent compositing launch: tiles are bucketed by
+// Longest-first tile order of the traversals (views->lpt): tiles are bucketed by
 // bit length of their list size (33 buckets) and laid out from the longest bucket down.
 // ---------------------------------------------------------------------------------------
 constexpr int LPT_B = 33;
@@ -963,7 +969,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0, stream,
                        proj->count, n, nbv, U32(L.offs), f);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views, bins->n_pairs,
-                       bins->overflow, bins->capacity);
+                       bins->overflow, bins->capacity, bins->overflow_sticky);
     if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
     // 2. pairs (tile; depth bits, index)
     EmitArgs e;
@@ -978,6 +984,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     e.overflow = bins->overflow;
     e.tkey = U32(L.tk0);
     e.tval = U64(L.tv0);
+    e.eoff = bins->entry_offset;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
     // 3. grouped by tile
     const int np = L.passes;
@@ -1021,6 +1028,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ta.vals = bins->vals;
     ta.n_deferred = U32(L.n_deferred);
     ta.deferred = U32(L.deferred);
+    ta.sticky = bins->overflow_sticky;
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)views->n_tiles), dim3(256), 0, stream, ta);
     hipLaunchKernelGGL(k_tile_sort_large, dim3((unsigned)std::min(views->n_tiles, 512)), dim3(256), 0, stream, ta);
     return launch_lpt(views, bins, U32(L.lpt), stream);

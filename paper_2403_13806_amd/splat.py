@@ -104,13 +104,13 @@ class ViewBatch:
     """Views rendered in one call: cameras, tile size and the global tile/pixel layout."""
 
     def __init__(self, cams: Sequence, tile: Tuple[int, int] = DEFAULT_TILE, device=None, batch_depth: int = 1,
-                 persistent: bool = False):
+                 lpt: bool = False):
         lib = L.load()
         self.cams = list(cams)
         self.n_views = len(self.cams)
         self.tile = (int(tile[0]), int(tile[1]))
         self.batch_depth = int(batch_depth)
-        self.persistent = bool(persistent)
+        self.lpt = bool(lpt)  # traversals take tiles longest list first
         self.device = _dev(device)
         arr = (L.gs_camera * self.n_views)(*[camera_struct(c) for c in self.cams])
         toff = (ctypes.c_int32 * (self.n_views + 1))()
@@ -129,7 +129,7 @@ class ViewBatch:
     def struct(self) -> L.gs_views:
         return L.gs_views(_ptr(self.cams_dev), _ptr(self.tile_offset), _ptr(self.pixel_offset), self.n_views,
                           self.tile[0], self.tile[1], self.n_tiles, self.n_pixels, self.batch_depth,
-                          int(self.persistent))
+                          int(self.lpt))
 
     def image(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
         """View v's planar [3][H][W] image inside a global rgb buffer."""
@@ -167,10 +167,12 @@ class Projected:
 
 
 class Bins:
-    """Sorted pairs and tile ranges; `queue` (the longest-first tile order) is only built
-    when asked for: persistent compositing launches need it."""
+    """Sorted pairs and tile ranges. `queue` (the longest-first tile order) is only built
+    when asked for (views with lpt need it); `entry_offset` (the emission slot of every
+    (view, entry), which the backward needs) only when entries > 0. `overflow_sticky`
+    collects the overflow word of every bin_sort since construction (or the last clear)."""
 
-    def __init__(self, capacity: int, n_tiles: int, device, queue: bool = True):
+    def __init__(self, capacity: int, n_tiles: int, device, queue: bool = True, entries: int = 0):
         self.capacity = int(capacity)
         cap = max(self.capacity, 1)
         self.keys = torch.empty(cap, dtype=torch.int64, device=device)
@@ -178,11 +180,15 @@ class Bins:
         self.ranges = torch.empty(max(2 * n_tiles, 2), dtype=torch.int32, device=device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        self.overflow_sticky = torch.zeros(1, dtype=torch.int32, device=device)
         self.queue = torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device) if queue else None
+        self.entries = int(entries)
+        self.entry_offset = (torch.empty(self.entries, dtype=torch.int32, device=device) if self.entries > 0
+                             else None)
 
     def struct(self) -> L.gs_bins:
         return L.gs_bins(_ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), self.capacity, _ptr(self.n_pairs),
-                         _ptr(self.overflow), _ptr(self.queue))
+                         _ptr(self.overflow), _ptr(self.queue), _ptr(self.entry_offset), _ptr(self.overflow_sticky))
 
 
 def workspace_bytes(n: int, n_views: int, capacity: int, n_tiles: int) -> int:
@@ -208,14 +214,16 @@ def preprocess(g: Gaussians, views: ViewBatch, params=None, subset: Optional[tor
 
 
 def bin_sort(proj: Projected, views: ViewBatch, capacity: Optional[int] = None, bins: Optional[Bins] = None,
-             ws: Optional[torch.Tensor] = None, grow: bool = True) -> Bins:
+             ws: Optional[torch.Tensor] = None, grow: bool = True, backward: bool = False) -> Bins:
     """Bin and sort. With grow=True the pair count is read back (one host sync) and the call
-    is repeated with a larger buffer when the capacity was too small."""
+    is repeated with a larger buffer when the capacity was too small. backward=True keeps the
+    entries' emission slots, which render_bwd needs."""
     lib = L.load()
+    entries = proj.n * views.n_views if backward else 0
     if bins is None:
         if capacity is None:
             capacity = max(1 << 16, 4 * proj.n * views.n_views)
-        bins = Bins(capacity, views.n_tiles, views.device, queue=views.persistent)
+        bins = Bins(capacity, views.n_tiles, views.device, queue=views.lpt, entries=entries)
     for _ in range(3):
         need = workspace_bytes(proj.n, views.n_views, bins.capacity, views.n_tiles)
         if ws is None or ws.numel() < need:
@@ -227,7 +235,8 @@ def bin_sort(proj: Projected, views: ViewBatch, capacity: Optional[int] = None, 
         if int(bins.overflow.item()) == 0:
             return bins
         need_pairs = int(bins.n_pairs.item())
-        bins = Bins(int(need_pairs * 1.125) + 4096, views.n_tiles, views.device, queue=bins.queue is not None)
+        bins = Bins(int(need_pairs * 1.125) + 4096, views.n_tiles, views.device, queue=bins.queue is not None,
+                    entries=bins.entries)
     raise RuntimeError("bin_sort: capacity growth did not converge")
 
 
@@ -292,20 +301,21 @@ def ssim_loss_grad(img: torch.Tensor, target: torch.Tensor, dl_dimg: Optional[to
     return loss, dl_dimg
 
 
-def render(g: Gaussians, views: ViewBatch, params=None, subset=None, capacity=None):
-    """Plain path: preprocess -> bin_sort (growing the pair buffer if needed) -> render_fwd."""
+def render(g: Gaussians, views: ViewBatch, params=None, subset=None, capacity=None, backward: bool = True):
+    """Plain path: preprocess -> bin_sort (growing the pair buffer if needed) -> render_fwd.
+    backward=True keeps what render_bwd needs (the emission slots of the pairs)."""
     proj = preprocess(g, views, params, subset=subset)
-    bins = bin_sort(proj, views, capacity)
+    bins = bin_sort(proj, views, capacity, backward=backward and subset is None)
     rgb, t, last = render_fwd(proj, views, bins, params)
     return {"rgb": rgb, "t_final": t, "n_last": last, "proj": proj, "bins": bins}
 
 
 def render_batch(g: Gaussians, cams: Sequence, params=None, tile: Tuple[int, int] = DEFAULT_TILE,
-                 batch_depth: int = 1, persistent: bool = False, device=None) -> List[torch.Tensor]:
+                 batch_depth: int = 1, lpt: bool = False, device=None) -> List[torch.Tensor]:
     """Every view of cams in one launch per stage (views of uneven size share one global tile
     space); returns each view's planar [3][H][W] image, a view of the batch's rgb buffer."""
-    views = ViewBatch(cams, tile, _dev(device), batch_depth, persistent)
-    out = render(g, views, params)
+    views = ViewBatch(cams, tile, _dev(device), batch_depth, lpt)
+    out = render(g, views, params, backward=False)
     return [views.image(out["rgb"], v) for v in range(len(cams))]
 
 
@@ -475,9 +485,14 @@ def cluster_visibility(g: Gaussians, views: ViewBatch, view_cluster: Sequence[in
     """OR into bits [k][ceil(n/32)] the per-cluster indicator lists (eq. importance-score-vis)."""
     lib = L.load()
     words = (g.n + 31) // 32
+    ids = np.asarray(view_cluster, np.int64).reshape(-1)
+    if k < 1 or ids.shape[0] != views.n_views or (ids.size and (ids.min() < 0 or ids.max() >= k)):
+        raise ValueError(f"view_cluster must hold one id in [0, {k}) per view")
     if bits is None:
         bits = torch.zeros(max(k * words, 1), dtype=torch.int32, device=views.device)
-    vc = torch.as_tensor(np.asarray(view_cluster, np.int32), device=views.device)
+    elif bits.dtype != torch.int32 or not bits.is_cuda or bits.numel() < k * words:
+        raise ValueError(f"bits must be an int32 device tensor of at least k * ceil(n / 32) = {k * words} words")
+    vc = torch.as_tensor(ids.astype(np.int32), device=views.device)
     proj = preprocess(g, views, params, want_color=False)
     bins = bin_sort(proj, views, capacity)
     p = make_params(params)
@@ -506,7 +521,9 @@ def render_bwd(g: Gaussians, views: ViewBatch, proj: Projected, bins: Bins, t_fi
     if grad is None:
         grad = Gaussians(torch.zeros_like(g.mean), torch.zeros_like(g.scale), torch.zeros_like(g.quat),
                          torch.zeros_like(g.opacity), torch.zeros_like(g.sh), g.sh_degree)
-    need = workspace_bytes(g.n, views.n_views, 0, views.n_tiles)
+    if bins.entry_offset is None:
+        raise ValueError("render_bwd needs bins made with backward=True (the pairs' emission slots)")
+    need = workspace_bytes(g.n, views.n_views, bins.capacity, views.n_tiles)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity), _ptr(grad.sh),
@@ -602,10 +619,13 @@ def nearest_centre(centres: np.ndarray, x) -> int:
 class Renderer:
     """Repeated frames of one view batch with persistent buffers: no allocation and no host
     synchronisation per frame. The pair capacity is fixed at construction (from a first
-    sized run); check() reports whether any frame since construction overflowed it."""
+    sized run); check() reports whether any frame since construction (or the last
+    clear_overflow()) overflowed it. backward=False leaves out the pairs' emission slots,
+    which only backward() reads."""
 
     def __init__(self, g: Gaussians, views: ViewBatch, params=None, capacity: Optional[int] = None,
-                 want_color: bool = True, headroom: float = 1.25, subset: Optional[torch.Tensor] = None):
+                 want_color: bool = True, headroom: float = 1.25, subset: Optional[torch.Tensor] = None,
+                 backward: bool = True):
         self.g, self.views, self.params = g, views, params
         self.p = make_params(params)
         dev = views.device
@@ -616,7 +636,9 @@ class Renderer:
         if capacity is None:
             b = bin_sort(self.proj, views)
             capacity = int(int(b.n_pairs.item()) * headroom) + 4096
-        self.bins = Bins(capacity, views.n_tiles, dev, queue=views.persistent)
+        self.backward_ok = bool(backward) and subset is None
+        self.bins = Bins(capacity, views.n_tiles, dev, queue=views.lpt,
+                         entries=self.n_entries * views.n_views if self.backward_ok else 0)
         self.ws = alloc_workspace(self.n_entries, views.n_views, capacity, views.n_tiles, dev)
         self.rgb = torch.empty(3 * max(views.n_pixels, 1), dtype=torch.float32, device=dev)
         self.t_final = torch.empty(max(views.n_pixels, 1), dtype=torch.float32, device=dev)
@@ -626,7 +648,6 @@ class Renderer:
         self._sv = views.struct()
         self._sp = self.proj.struct()
         self._sb = self.bins.struct()
-        self.overflowed = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def _pre(self, stream):
         lib = L.load()
@@ -657,8 +678,8 @@ class Renderer:
         return h
 
     def backward(self, dl_drgb: torch.Tensor, grad: Gaussians):
-        if self.subset is not None:
-            raise ValueError("the backward needs a projection of every Gaussian (no subset)")
+        if not self.backward_ok:
+            raise ValueError("this Renderer was built without the backward (a subset, or backward=False)")
         s = _stream(self.views.device)
         gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity),
                                  _ptr(grad.sh), self.g.n, self.g.sh_degree)
@@ -669,8 +690,12 @@ class Renderer:
         return grad
 
     def check(self) -> Tuple[bool, int]:
-        """(overflowed, pairs of the last frame); synchronises."""
-        return bool(int(self.bins.overflow.item())), int(self.bins.n_pairs.item())
+        """(some frame since construction or the last clear_overflow() overflowed the pair
+        capacity, pairs of the last frame); synchronises."""
+        return bool(int(self.bins.overflow_sticky.item())), int(self.bins.n_pairs.item())
+
+    def clear_overflow(self):
+        self.bins.overflow_sticky.zero_()
 
 
 @dataclass
@@ -795,11 +820,11 @@ class PathRenderer:
 
     def __init__(self, g: Gaussians, cams: Sequence, params=None, tile: Tuple[int, int] = DEFAULT_TILE,
                  capacity: Optional[int] = None, max_entries: Optional[int] = None, device=None,
-                 persistent: bool = False, batch_depth: int = 1, pipeline: int = 1):
+                 lpt: bool = False, batch_depth: int = 1, pipeline: int = 1):
         dev = _dev(device)
         self.g, self.params, self.device = g, params, dev
         self.p = make_params(params)
-        self.views = ViewBatch([cams[0]], tile, dev, batch_depth, persistent)
+        self.views = ViewBatch([cams[0]], tile, dev, batch_depth, lpt)
         if any((c.width, c.height) != (cams[0].width, cams[0].height) for c in cams):
             raise ValueError("every frame of a path must have the same resolution")
         arr = (L.gs_camera * len(cams))(*[camera_struct(c) for c in cams])
@@ -811,7 +836,7 @@ class PathRenderer:
             preprocess(g, self.views, params, out=self._proj_n(g.n))
             b = bin_sort(self._proj_n(g.n), self.views)
             capacity = int(int(b.n_pairs.item()) * 2.0) + 65536
-        self.bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.persistent)
+        self.bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.lpt)
         self.ws = alloc_workspace(self.max_entries, 1, capacity, self.views.n_tiles, dev)
         self.rgb = torch.empty(3 * self.views.n_pixels, dtype=torch.float32, device=dev)
         self.t_final = torch.empty(self.views.n_pixels, dtype=torch.float32, device=dev)
@@ -820,7 +845,7 @@ class PathRenderer:
         self._sb = self.bins.struct()
         self._sets = [(self.proj, self.bins, self._sb, self.ws, self.rgb, self.t_final, self.n_last)]
         for _ in range(1, max(1, int(pipeline))):
-            bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.persistent)
+            bins = Bins(capacity, self.views.n_tiles, dev, queue=self.views.lpt)
             self._sets.append((Projected(self.max_entries, 1, dev), bins, bins.struct(),
                                alloc_workspace(self.max_entries, 1, capacity, self.views.n_tiles, dev),
                                torch.empty_like(self.rgb), torch.empty_like(self.t_final),
@@ -868,7 +893,6 @@ class PathRenderer:
         return rgb
 
     def ok(self) -> bool:
-        """True when no frame of any buffer set overflowed its pair buffer since the last frame
-        enqueued on that set (synchronises)."""
+        """True when no frame since construction overflowed its pair buffer (synchronises)."""
         self.sync()
-        return all(int(b.overflow.item()) == 0 for _, b, *_ in self._sets)
+        return all(int(b.overflow_sticky.item()) == 0 for _, b, *_ in self._sets)

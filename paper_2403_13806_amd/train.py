@@ -3,7 +3,8 @@ one captured hipGraph, and the autotuner that picks its launch configuration. Th
 L1 (loss="l1") or the Sec. 3.2 training loss 0.8 L2 + 0.2 D-SSIM (loss="l2_dssim", one
 gs_ssim_loss_grad call per view with the batch's element count, sharing one workspace).
 
-  StepConfig      tile size, batch depth (records staged per lane) and persistent launch
+  StepConfig      tile size, batch depth (records staged per lane) and tile order (longest
+                  list first, or tile order)
   FwdBwdStep      preallocated buffers, an eager step, capture into a hipGraph, replay
   autotune        times every candidate configuration on the actual scene and views and
                   keeps the fastest; results are cached as JSON keyed by device, scene size
@@ -34,7 +35,7 @@ class StepConfig:
     tile_w: int = 16
     tile_h: int = 16
     batch_depth: int = 1
-    persistent: bool = False
+    lpt: bool = False
 
     @property
     def tile(self):
@@ -63,7 +64,7 @@ class FwdBwdStep:
         dev = torch.device(device if device is not None else "cuda")
         self.cfg = cfg
         self.loss_kind = loss
-        self.views = ViewBatch(cams, cfg.tile, dev, cfg.batch_depth, cfg.persistent)
+        self.views = ViewBatch(cams, cfg.tile, dev, cfg.batch_depth, cfg.lpt)
         self.r = Renderer(g, self.views, params, capacity)
         self.target = self.views.pack_images(targets)
         self.grad = zero_grads(g)
@@ -115,7 +116,7 @@ class FwdBwdStep:
             self.enqueue()
 
     def ok(self) -> bool:
-        """True when no frame since construction overflowed the pair buffer (synchronises)."""
+        """True when no step since construction overflowed the pair buffer (synchronises)."""
         return not self.r.check()[0]
 
 
@@ -209,6 +210,7 @@ class TrainConfig:
     eps: float = 1e-15
     seed: int = 0
     headroom: float = 2.0
+    check_every: int = 1000
 
     @classmethod
     def light(cls, **kw) -> "TrainConfig":
@@ -230,7 +232,11 @@ class Trainer:
     from the parameters and from both Adam moments by one compaction (Sec. 3.3).
 
     All training views share one resolution. Nothing is allocated per step; a step does not
-    synchronise with the host (pruning does, to size the new arrays)."""
+    synchronise with the host (pruning does, to size the new arrays). The pair capacity is
+    sized from the most demanding training view times cfg.headroom; a step that overflows it
+    renders nothing and takes an Adam step without Gaussian gradients, so the overflow flag
+    (sticky over steps) is read before every pruning and every cfg.check_every steps, and an
+    overflow raises."""
 
     def __init__(self, g: Gaussians, cams: Sequence, targets: Sequence, params=None,
                  cfg: TrainConfig = TrainConfig(), tile=None, device=None):
@@ -304,7 +310,15 @@ class Trainer:
         adam_step(self.groups(), self.it, self.cfg.betas, self.cfg.eps, zero_grad=True)
         if self.it in self.cfg.prune_steps:
             self.prune()
+        elif self.cfg.check_every > 0 and self.it % self.cfg.check_every == 0:
+            self.check_capacity()
         return i
+
+    def check_capacity(self):
+        """Raise if some step since the last check overflowed the pair capacity (synchronises)."""
+        if not self.ok():
+            raise RuntimeError(f"a training step before step {self.it} overflowed the pair capacity "
+                               f"({self.r.bins.capacity} pairs); use a larger TrainConfig.headroom")
 
     def importance(self) -> torch.Tensor:
         from .splat import importance
@@ -317,6 +331,7 @@ class Trainer:
         """Remove the Gaussians with h < t_prune from the parameters and the Adam moments."""
         from .splat import prune_gaussians
         t = self.cfg.t_prune if t_prune is None else t_prune
+        self.check_capacity()
         h = self.importance()
         m, v = self.m, self.v
         before = self.g.n
@@ -330,4 +345,5 @@ class Trainer:
         return kept
 
     def ok(self) -> bool:
+        """True when no step on the current Gaussians overflowed the pair capacity (synchronises)."""
         return not self.r.check()[0]

@@ -34,7 +34,7 @@ def test_struct_layout_sizes():
     assert ctypes.sizeof(L.gs_camera) == 80
     assert ctypes.sizeof(L.gs_params) == 36
     assert ctypes.sizeof(L.gs_views) == 56
-    assert ctypes.sizeof(L.gs_bins) == 56
+    assert ctypes.sizeof(L.gs_bins) == 72
 
 
 def test_view_layout():
@@ -62,15 +62,15 @@ def test_workspace_bytes_grows_with_inputs():
     assert lib.gs_workspace_bytes(2000, 1, 10000, 100) >= a
     assert lib.gs_workspace_bytes(1000, 1, 20000, 100) > a
     assert lib.gs_workspace_bytes(1000, 2, 10000, 100) >= a
-    # the backward's 2D gradients: 9 floats per (view, Gaussian)
-    assert lib.gs_workspace_bytes(10 ** 6, 4, 0, 1) >= 36 * 4 * 10 ** 6
+    # the backward's partial 2D gradients: 9 floats per pair slot
+    assert lib.gs_workspace_bytes(10, 1, 4 * 10 ** 6, 1) >= 36 * 4 * 10 ** 6
 
 
 def _dummy_views(tile=(16, 16)):
     v = L.gs_views()
     v.cams = v.tile_offset = v.pixel_offset = ctypes.c_void_p(16)
     v.n_views, v.tile_w, v.tile_h, v.n_tiles, v.n_pixels = 1, tile[0], tile[1], 48, 12288
-    v.batch_depth, v.persistent = 1, 0
+    v.batch_depth, v.lpt = 1, 0
     return v
 
 
@@ -101,7 +101,7 @@ def test_argument_errors_are_reported_before_launch():
     g.n = 10
     # capacity must stay below 2^32; the workspace must be large enough
     b = L.gs_bins(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 32, ctypes.c_void_p(16),
-                  ctypes.c_void_p(16), None)
+                  ctypes.c_void_p(16), None, None, None)
     assert lib.gs_bin_sort(R(out), R(v), R(b), ctypes.c_void_p(16), 1 << 40, None) == L.GS_ERR_UNSUPPORTED
     b.capacity = 1000
     assert lib.gs_bin_sort(R(out), R(v), R(b), ctypes.c_void_p(16), 10, None) == L.GS_ERR_INVALID_ARG
@@ -116,8 +116,17 @@ def test_argument_errors_are_reported_before_launch():
                              ctypes.c_void_p(16), 11, 3)
     assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
+    # ... and the pairs' emission slots, and a workspace of 36 bytes per pair slot
+    gg.n = 10
+    assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
+    assert b"entry_offset" in lib.gs_last_error()
+    b.entry_offset = ctypes.c_void_p(16)
+    assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 36 * 1000 - 1, None) == L.GS_ERR_INVALID_ARG
+    assert b"workspace" in lib.gs_last_error()
     assert lib.gs_bits_to_list(None, 10, None, None, None, 0, None) == L.GS_ERR_INVALID_ARG
-    # batch depth and the persistent form
+    # batch depth and the longest-first order
     v3 = _dummy_views()
     v3.batch_depth = 3
     assert lib.gs_preprocess(R(g), R(v3), R(p), None, 0, 1, R(out), None) == L.GS_ERR_UNSUPPORTED
@@ -126,7 +135,7 @@ def test_argument_errors_are_reported_before_launch():
     assert lib.gs_preprocess(R(g), R(v5), R(p), None, 0, 1, R(out), None) == L.GS_ERR_UNSUPPORTED
     assert b"512" in lib.gs_last_error()
     v4 = _dummy_views()
-    v4.persistent = 1  # bins has no queue
+    v4.lpt = 1  # bins has no queue
     assert lib.gs_importance(R(out), R(v4), R(b), R(p), ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
     assert b"queue" in lib.gs_last_error()
 
@@ -319,3 +328,17 @@ def test_training_config_and_helpers():
         train.Trainer(None, odd, [None, None], device="cpu")
     with pytest.raises(ValueError):
         train.FwdBwdStep(None, cams, [], loss="l3")
+
+
+def test_cluster_ids_are_checked_on_the_host():
+    # the kernel skips ids outside [0, k) (they are device data); the binding rejects them first
+    sc = scenes.uniform_cube_scene(50, seed=1)
+    g = gs.Gaussians.from_scene(sc, "cpu")
+    views = gs.ViewBatch([scenes.plain_view(), scenes.plain_view()], (16, 16), "cpu")
+    for ids, k in [([0, 4], 4), ([-1, 0], 4), ([0], 4), ([0, 0], 0)]:
+        with pytest.raises(ValueError):
+            gs.cluster_visibility(g, views, ids, k, 0.01)
+    import torch
+    short = torch.zeros(4 * 2 - 1, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        gs.cluster_visibility(g, views, [0, 3], 4, 0.01, bits=short)
