@@ -89,6 +89,12 @@ static gs_status check_views(const gs_views* v) {
     if (v->batch_depth == 2 && v->tile_w * v->tile_h > 512)
         return set_error(GS_ERR_UNSUPPORTED, "batch_depth 2 needs a tile of at most 512 pixels (LDS)");
     if (v->lpt != 0 && v->lpt != 1) return set_error(GS_ERR_INVALID_ARG, "lpt must be 0 or 1 (got %d)", v->lpt);
+    const int ppl = v->pixels_per_lane;
+    if (ppl != 0 && ppl != 1 && ppl != 2 && ppl != 4)
+        return set_error(GS_ERR_UNSUPPORTED, "pixels_per_lane must be 0, 1, 2 or 4 (got %d)", ppl);
+    if ((ppl >= 2 && v->tile_w < 16) || (ppl == 4 && v->tile_h < 16))
+        return set_error(GS_ERR_UNSUPPORTED, "pixels_per_lane %d needs a tile of at least %dx%d", ppl, 16,
+                         ppl == 4 ? 16 : 8);
     return GS_OK;
 }
 

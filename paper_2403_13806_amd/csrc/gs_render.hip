@@ -75,23 +75,28 @@ struct RenderArgs {
 // that holds a covered pixel centre is always marked.
 // QUARTERS: test the four 4x4 quarters of every wave block instead (bit 4 w + quarter,
 // quarters numbered row-major inside the block).
-template <int TW, int TH, bool QUARTERS = false>
+// the support test over the rectangle [x0, x1] x [y0, y1] of pixel-centre offsets from the
+// mean (see above); kx = -b/c, ky = -b/a, lim = q_max with the rounding margins
+__device__ __forceinline__ bool rect_hit(const gs_splat& s, double x0, double x1, double y0, double y1, double kx,
+                                         double ky, double lim) {
+    const double ex = fmin(fmax(0.0, x0), x1), ey = fmin(fmax(0.0, y0), y1);
+    const double fy = fmin(fmax(kx * ex, y0), y1), fx = fmin(fmax(ky * ey, x0), x1);
+    const double q1 = s.ca * ex * ex + 2.0 * s.cb * ex * fy + s.cc * fy * fy;
+    const double q2 = s.ca * fx * fx + 2.0 * s.cb * fx * ey + s.cc * ey * ey;
+    return fmin(q1, q2) <= lim;
+}
+
+template <int TW, int TH>
 __device__ __forceinline__ uint64_t wave_hits(const gs_splat& s, double ox, double oy) {
-    constexpr int NB = (TW / 8) * (TH / 8) * (QUARTERS ? 4 : 1);
-    constexpr double SIDE = QUARTERS ? 3.0 : 7.0;
+    constexpr int NB = (TW / 8) * (TH / 8);
     const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
     const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
     uint64_t m = 0;
 #pragma unroll 1
-    for (int bit = 0; bit < NB; ++bit) {
-        const int w = QUARTERS ? bit >> 2 : bit, qd = QUARTERS ? bit & 3 : 0;
-        const double x0 = ox + (double)((w % (TW / 8)) * 8 + (qd & 1) * 4) - s.u, x1 = x0 + SIDE;
-        const double y0 = oy + (double)((w / (TW / 8)) * 8 + (qd >> 1) * 4) - s.v, y1 = y0 + SIDE;
-        const double ex = fmin(fmax(0.0, x0), x1), ey = fmin(fmax(0.0, y0), y1);
-        const double fy = fmin(fmax(kx * ex, y0), y1), fx = fmin(fmax(ky * ey, x0), x1);
-        const double q1 = s.ca * ex * ex + 2.0 * s.cb * ex * fy + s.cc * fy * fy;
-        const double q2 = s.ca * fx * fx + 2.0 * s.cb * fx * ey + s.cc * ey * ey;
-        if (fmin(q1, q2) <= lim) m |= 1ull << bit;
+    for (int w = 0; w < NB; ++w) {
+        const double x0 = ox + (double)((w % (TW / 8)) * 8) - s.u;
+        const double y0 = oy + (double)((w / (TW / 8)) * 8) - s.v;
+        if (rect_hit(s, x0, x0 + 7.0, y0, y0 + 7.0, kx, ky, lim)) m |= 1ull << w;
     }
     return m;
 }
@@ -103,8 +108,7 @@ struct TileGeom {
     int64_t pix;     // global pixel index
 };
 
-// QUARTERS: lanes 16 q .. 16 q + 15 of a wave hold quarter q (4x4, row-major) of its block
-template <int TW, int TH, bool QUARTERS = false>
+template <int TW, int TH>
 __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     TileGeom g;
     g.view = view_of_tile(a.tile_offset, a.n_views, tile);
@@ -118,14 +122,8 @@ __device__ __forceinline__ TileGeom tile_geom(const RenderArgs& a, int tile) {
     const int t = threadIdx.x, l = t & 63;
     g.wave = t >> 6;
     const int bx = (g.wave % (TW / 8)) * 8, by = (g.wave / (TW / 8)) * 8;
-    if (QUARTERS) {
-        const int qd = l >> 4, sl = l & 15;
-        g.px = tx * TW + bx + (qd & 1) * 4 + (sl & 3);
-        g.py = ty * TH + by + (qd >> 1) * 4 + (sl >> 2);
-    } else {
-        g.px = tx * TW + bx + (l & 7);
-        g.py = ty * TH + by + (l >> 3);
-    }
+    g.px = tx * TW + bx + (l & 7);
+    g.py = ty * TH + by + (l >> 3);
     g.inside = g.px < g.W && g.py < g.H;
     g.ox = (double)(tx * TW) + 0.5;
     g.oy = (double)(ty * TH) + 0.5;
@@ -159,17 +157,26 @@ struct Smem {
     uint32_t top;
 };
 
-// The reverse traversal stages BB records per batch and keeps, per wave and staged record,
-// the nine 2D-gradient sums of that wave's pixels: the waves' sums are combined in wave
-// order when the batch is flushed, so every per-pair sum is formed in a fixed order.
-template <int TW, int TH>
+// The reverse traversal: each lane holds a cluster of PXW x PXH neighbouring pixels, a wave an
+// (8 PXW) x (8 PXH) block of the tile, and each row of 16 lanes (a quarter of the wave) a
+// (4 PXW) x (4 PXH) part of it. It stages BB records per batch and keeps, per wave and staged
+// record, the nine 2D-gradient sums of that wave's pixels: the waves' sums are combined in
+// wave order when the batch is flushed, so every per-pair sum is formed in a fixed order.
+template <int TW, int TH, int PXW, int PXH>
 struct BwdShape {
-    static constexpr int NT = TW * TH, NW = NT / 64, BB = NT < 128 ? NT : 128;
+    static constexpr int P = PXW * PXH;           // pixels per lane
+    static constexpr int NT = TW * TH / P;        // threads
+    static constexpr int NW = NT / 64;            // waves
+    static constexpr int BW = 8 * PXW, BH = 8 * PXH;  // wave block
+    static constexpr int WPR = TW / BW;           // waves per row of blocks
+    static constexpr int BB = NT < 128 ? NT : 128;  // records per batch
+    static_assert(TW % BW == 0 && TH % BH == 0 && NW >= 1, "tile not a whole number of wave blocks");
+    static_assert(NW * 4 <= 64, "quarter masks hold 64 bits");
 };
 
-template <int TW, int TH>
+template <int TW, int TH, int PXW, int PXH>
 struct SmemBwd {
-    using S = BwdShape<TW, TH>;
+    using S = BwdShape<TW, TH, PXW, PXH>;
     gs_splat rec[S::BB];
     uint64_t hitq[S::BB];  // quarter masks, bit 4 w + quarter
     uint32_t gid[S::BB];
@@ -198,17 +205,26 @@ __device__ __forceinline__ void stage(Smem<TW, TH, DEPTH>& sm, const RenderArgs&
 }
 
 // the backward's staging: records [base, base + cnt) with their quarter masks
-template <int TW, int TH>
-__device__ __forceinline__ void stage_q(SmemBwd<TW, TH>& sm, const RenderArgs& a, const gs_splat* sp,
-                                        uint32_t base, uint32_t cnt, const TileGeom& g) {
+template <int TW, int TH, int PXW, int PXH>
+__device__ __forceinline__ void stage_q(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, const gs_splat* sp,
+                                        uint32_t base, uint32_t cnt, double ox, double oy) {
+    using S = BwdShape<TW, TH, PXW, PXH>;
     const uint32_t q = threadIdx.x;
-    if (q >= (uint32_t)BwdShape<TW, TH>::BB) return;
+    if (q >= (uint32_t)S::BB) return;
     uint64_t hm = 0;
     const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
     if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
         const gs_splat s = sp[id];
         sm.rec[q] = s;
-        hm = wave_hits<TW, TH, true>(s, g.ox, g.oy);
+        const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
+        const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
+#pragma unroll 1
+        for (int bit = 0; bit < 4 * S::NW; ++bit) {
+            const int w = bit >> 2, qd = bit & 3;
+            const double x0 = ox + (double)((w % S::WPR) * S::BW + (qd & 1) * 4 * PXW) - s.u;
+            const double y0 = oy + (double)((w / S::WPR) * S::BH + (qd >> 1) * 4 * PXH) - s.v;
+            if (rect_hit(s, x0, x0 + (4 * PXW - 1), y0, y0 + (4 * PXH - 1), kx, ky, lim)) hm |= 1ull << bit;
+        }
     }
     sm.gid[q] = (int64_t)id < a.n ? id : 0xffffffffu;
     sm.hitq[q] = hm;
@@ -376,60 +392,87 @@ __device__ __forceinline__ float row_sum9(const float (&v)[9], int lane) {
 // the entry. When a batch is done, its records' wave sums are added in wave order and
 // stored (plain stores) into each pair's emission slot; pairs behind every pixel's last
 // entry get zeros. Each Gaussian's slots are then summed by the parameter chains.
-template <int TW, int TH>
-__device__ void bwd_tile(SmemBwd<TW, TH>& sm, const RenderArgs& a, int tile) {
-    using S = BwdShape<TW, TH>;
-    constexpr int NT = S::NT, BB = S::BB, NW = S::NW;
-    const TileGeom g = tile_geom<TW, TH, true>(a, tile);
-    const int t = threadIdx.x, l = t & 63, w = g.wave;
+template <int TW, int TH, int PXW, int PXH>
+__device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int tile) {
+    using S = BwdShape<TW, TH, PXW, PXH>;
+    constexpr int NT = S::NT, BB = S::BB, NW = S::NW, P = S::P;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int fld = row_sum9_field(l);
+    const int view = view_of_tile(a.tile_offset, a.n_views, tile);
+    const int W = a.cams[view].width, H = a.cams[view].height;
+    const int tiles_x = div_up(W, TW);
+    const int local = tile - a.tile_offset[view];
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    // lane (lx, ly) of the wave's 8 x 8 lane grid: quarter qd = l / 16 (row-major 2 x 2), 4 x 4
+    // lanes each; its pixels are the PXW x PXH cluster at (px0, py0)
+    const int qd = l >> 4, sl = l & 15;
+    const int lx = (qd & 1) * 4 + (sl & 3), ly = (qd >> 1) * 4 + (sl >> 2);
+    const int px0 = tx * TW + (w % S::WPR) * S::BW + lx * PXW;
+    const int py0 = ty * TH + (w / S::WPR) * S::BH + ly * PXH;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const double xc = (double)g.px + 0.5, yc = (double)g.py + 0.5;
     const float amax = a.p.alpha_max;
-    const gs_splat* sp = a.splat + (int64_t)g.view * a.n;
-    float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f;
-    uint32_t last = start;
-    if (g.inside) {
-        T = a.t_in[g.pix];
-        last = a.last_in[g.pix];
-        const int64_t plane = (int64_t)g.W * g.H;
-        const float* d = a.dl_drgb + 3 * a.pixel_offset[g.view] + (int64_t)g.py * g.W + g.px;
-        dC0 = d[0];
-        dC1 = d[plane];
-        dC2 = d[2 * plane];
-        S0 = T * a.p.bg[0];
-        S1 = T * a.p.bg[1];
-        S2 = T * a.p.bg[2];
+    const gs_splat* sp = a.splat + (int64_t)view * a.n;
+    const int64_t plane = (int64_t)W * H, poff = a.pixel_offset[view];
+    double xc[PXW], yc[PXH];
+#pragma unroll
+    for (int i = 0; i < PXW; ++i) xc[i] = (double)(px0 + i) + 0.5;
+#pragma unroll
+    for (int j = 0; j < PXH; ++j) yc[j] = (double)(py0 + j) + 0.5;
+    float T[P], dC[P][3], Sc[P][3];
+    uint32_t last[P];
+    bool inside[P];
+    uint32_t lmax = start;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int px = px0 + p % PXW, py = py0 + p / PXW;
+        inside[p] = px < W && py < H;
+        T[p] = 1.f;
+        last[p] = start;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dC[p][c] = Sc[p][c] = 0.f;
+        if (inside[p]) {
+            const int64_t pix = poff + (int64_t)py * W + px;
+            T[p] = a.t_in[pix];
+            last[p] = a.last_in[pix];
+            const float* d = a.dl_drgb + 3 * poff + (int64_t)py * W + px;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dC[p][c] = d[c * plane];
+                Sc[p][c] = T[p] * a.p.bg[c];
+            }
+        }
+        // never read outside the tile's list, whatever n_last holds
+        last[p] = min(max(last[p], start), end);
+        lmax = max(lmax, inside[p] ? last[p] : start);
     }
-    last = min(max(last, start), end);  // never read outside the tile's list, whatever n_last holds
     if (t == 0) sm.top = start;
     __syncthreads();
-    if (g.inside && last > start) atomicMax(&sm.top, last);
+    if (lmax > start) atomicMax(&sm.top, lmax);
     __syncthreads();
     const uint32_t top = sm.top;
-    // the quarter's last composited entry (max over its 16 pixels): entries behind it are skipped
-    int ql = (int)last;
+    // the quarter's last composited entry (max over its pixels): entries behind it are skipped
+    int ql = (int)lmax;
     ql = max(ql, dpp<0xB1>(ql));
     ql = max(ql, dpp<0x4E>(ql));
     ql = max(ql, dpp<0x141>(ql));
     ql = max(ql, dpp<0x140>(ql));
     const uint32_t qlast = (uint32_t)ql;
-    const int64_t vbase = (int64_t)g.view * a.n;
+    const int64_t vbase = (int64_t)view * a.n;
+    const double ox = (double)(tx * TW) + 0.5, oy = (double)(ty * TH) + 0.5;
     float* accw = sm.acc + w * (BB * 9);
     for (int q = t; q < NW * BB * 9; q += NT) sm.acc[q] = 0.f;
     for (uint32_t hi = top; hi > start;) {
         const uint32_t lo = (hi - start > (uint32_t)BB) ? hi - BB : start;
         __syncthreads();
-        stage_q<TW, TH>(sm, a, sp, lo, hi - lo, g);
+        stage_q<TW, TH, PXW, PXH>(sm, a, sp, lo, hi - lo, ox, oy);
         __syncthreads();
         // entries that meet this wave's block, back to front
 #pragma unroll 1
         for (int c = BB / 64 - 1; c >= 0; --c) {
-            // each quarter (one row of 16 lanes) walks the entries that meet its 4x4 pixels
+            // each quarter (one row of 16 lanes) walks the entries that meet its pixels
             const uint32_t hq = (uint32_t)(sm.hitq[c * 64 + l] >> (4 * w));
             const uint64_t m0 = ballot(hq & 1u), m1 = ballot((hq >> 1) & 1u), m2 = ballot((hq >> 2) & 1u),
                            m3 = ballot((hq >> 3) & 1u);
-            const int qd = l >> 4;
             uint64_t m = qd == 0 ? m0 : qd == 1 ? m1 : qd == 2 ? m2 : m3;  // the same in a quarter
             const int64_t lim = (int64_t)qlast - (int64_t)(lo + c * 64);
             m = lim <= 0 ? 0ull : (lim >= 64 ? m : m & ((1ull << lim) - 1ull));
@@ -442,36 +485,49 @@ __device__ void bwd_tile(SmemBwd<TW, TH>& sm, const RenderArgs& a, int tile) {
                 // whole record up front; branch-free body apart from the wave-uniform skip
                 const gs_splat s = sm.rec[j];
                 asm volatile("" ::"v"(s.opacity), "v"(s.rgb[0]), "v"(s.rgb[1]), "v"(s.rgb[2]));
-                const double ddx = xc - s.u, ddy = yc - s.v;
-                const double q = quad(s, ddx, ddy);
-                const bool contrib = act & (q <= s.qmax) & g.inside & (pos < last);
-                if (ballot(contrib) == 0) continue;
-                const float G = falloff(q);
-                const float og = s.opacity * G;
-                const float al = contrib ? clamp_alpha(og, amax) : 0.f;
-                const float r = __builtin_amdgcn_rcpf(1.f - al);
-                T = contrib ? T * r : T;
-                const float wt = al * T;
-                const float dA = dC0 * (T * s.rgb[0] - S0 * r) + dC1 * (T * s.rgb[1] - S1 * r) +
-                                 dC2 * (T * s.rgb[2] - S2 * r);
-                S0 = fmaf(wt, s.rgb[0], S0);  // wt = 0 where the entry does not contribute
-                S1 = fmaf(wt, s.rgb[1], S1);
-                S2 = fmaf(wt, s.rgb[2], S2);
-                // dq dx, dq dy (turned into the u, v gradients with the conic once per record
-                // in the flush), a b c o r g b; the geometric terms vanish where alpha is clamped
-                const bool free_a = contrib & (og < amax);
-                const float dx = (float)ddx, dy = (float)ddy;
-                const float dq = free_a ? -0.5f * al * dA : 0.f;
+                double q[P];
+                bool con[P];
+                bool any = false;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    q[p] = quad(s, xc[p % PXW] - s.u, yc[p / PXW] - s.v);
+                    con[p] = act & (q[p] <= s.qmax) & inside[p] & (pos < last[p]);
+                    any |= con[p];
+                }
+                if (ballot(any) == 0) continue;
                 float v[9];
-                v[0] = dq * dx;
-                v[1] = dq * dy;
-                v[2] = v[0] * dx;
-                v[3] = 2.f * v[0] * dy;
-                v[4] = v[1] * dy;
-                v[5] = free_a ? dA * G : 0.f;
-                v[6] = contrib ? dC0 * wt : 0.f;
-                v[7] = contrib ? dC1 * wt : 0.f;
-                v[8] = contrib ? dC2 * wt : 0.f;
+#pragma unroll
+                for (int f = 0; f < 9; ++f) v[f] = 0.f;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float G = falloff(q[p]);
+                    const float og = s.opacity * G;
+                    const float al = con[p] ? clamp_alpha(og, amax) : 0.f;
+                    const float r = __builtin_amdgcn_rcpf(1.f - al);
+                    T[p] = con[p] ? T[p] * r : T[p];
+                    const float wt = al * T[p];
+                    const float dA = dC[p][0] * (T[p] * s.rgb[0] - Sc[p][0] * r) +
+                                     dC[p][1] * (T[p] * s.rgb[1] - Sc[p][1] * r) +
+                                     dC[p][2] * (T[p] * s.rgb[2] - Sc[p][2] * r);
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        Sc[p][cc] = fmaf(wt, s.rgb[cc], Sc[p][cc]);  // wt = 0 where p does not contribute
+                    // dq dx, dq dy (turned into the u, v gradients with the conic once per record
+                    // in the flush), a b c o r g b; the geometric terms vanish where alpha is clamped
+                    const bool free_a = con[p] & (og < amax);
+                    const float dx = (float)(xc[p % PXW] - s.u), dy = (float)(yc[p / PXW] - s.v);
+                    const float dq = free_a ? -0.5f * al * dA : 0.f;
+                    const float a0 = dq * dx, a1 = dq * dy;
+                    v[0] += a0;
+                    v[1] += a1;
+                    v[2] += a0 * dx;
+                    v[3] += 2.f * a0 * dy;
+                    v[4] += a1 * dy;
+                    v[5] += free_a ? dA * G : 0.f;
+                    v[6] += con[p] ? dC[p][0] * wt : 0.f;
+                    v[7] += con[p] ? dC[p][1] * wt : 0.f;
+                    v[8] += con[p] ? dC[p][2] * wt : 0.f;
+                }
                 // per-quarter sums, one field per lane, added into this wave's sums of that
                 // entry (lanes of one instruction that meet at one address are applied in a
                 // fixed order, so the result does not depend on timing)
@@ -506,7 +562,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH>& sm, const RenderArgs& a, int tile) {
                 const float sx = f9[0], sy = f9[1];
                 f9[0] = -2.f * ((float)sm.rec[t].ca * sx + (float)sm.rec[t].cb * sy);
                 f9[1] = -2.f * ((float)sm.rec[t].cb * sx + (float)sm.rec[t].cc * sy);
-                const uint64_t slot = pair_slot(a, vbase + id, g.tx, g.ty);
+                const uint64_t slot = pair_slot(a, vbase + id, tx, ty);
                 if (slot < a.capacity) {
                     float* dst = a.slots + slot * 9;
 #pragma unroll
@@ -520,7 +576,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH>& sm, const RenderArgs& a, int tile) {
     for (uint32_t pos = top + t; pos < end; pos += NT) {
         const uint32_t id = a.vals[pos];
         if ((int64_t)id >= a.n) continue;
-        const uint64_t slot = pair_slot(a, vbase + id, g.tx, g.ty);
+        const uint64_t slot = pair_slot(a, vbase + id, tx, ty);
         if (slot < a.capacity) {
             float* dst = a.slots + slot * 9;
 #pragma unroll
@@ -611,10 +667,10 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(DEPTH ==
     fwd_tile<TW, TH, DEPTH, MODE>(sm, a, tile_of_block(a));
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(RenderArgs a) {
-    __shared__ SmemBwd<TW, TH> sm;
-    bwd_tile<TW, TH>(sm, a, tile_of_block(a));
+template <int TW, int TH, int PXW, int PXH>
+__global__ __launch_bounds__(TW* TH / (PXW * PXH)) void k_render_bwd(RenderArgs a) {
+    __shared__ SmemBwd<TW, TH, PXW, PXH> sm;
+    bwd_tile<TW, TH, PXW, PXH>(sm, a, tile_of_block(a));
 }
 
 // L1 loss and its gradient: grid-stride over the elements, one atomic per workgroup for
@@ -696,14 +752,25 @@ static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int n_ti
     return false;
 }
 
-static bool launch_bwd(const RenderArgs& a, int tw, int th, int n_tiles, hipStream_t s) {
-#define GS_CASE(W_, H_)                                                                          \
-    if (tw == W_ && th == H_) {                                                                  \
-        launch_tiles(k_render_bwd<W_, H_>, a, W_ * H_, n_tiles, s);                              \
+// pixels per lane of the reverse traversal: as asked, else 2 where the tile is at least 16 wide
+static int bwd_pixels_per_lane(const gs_views* v) {
+    if (v->pixels_per_lane) return v->pixels_per_lane;
+    return v->tile_w >= 16 ? 2 : 1;
+}
+
+// pixels per lane of the reverse traversal: 1 (1 x 1), 2 (2 x 1) or 4 (2 x 2); a tile must hold
+// whole wave blocks of 8 x 8 lanes
+static bool launch_bwd(const RenderArgs& a, int tw, int th, int px, int n_tiles, hipStream_t s) {
+#define GS_CASE(W_, H_, PW_, PH_)                                                                \
+    if (tw == W_ && th == H_ && px == PW_ * PH_) {                                               \
+        launch_tiles(k_render_bwd<W_, H_, PW_, PH_>, a, W_ * H_ / (PW_ * PH_), n_tiles, s);      \
         return true;                                                                             \
     }
-    GS_CASE(8, 8) GS_CASE(16, 8) GS_CASE(8, 16) GS_CASE(16, 16) GS_CASE(32, 8) GS_CASE(8, 32)
-    GS_CASE(32, 16) GS_CASE(16, 32) GS_CASE(32, 32)
+    GS_CASE(8, 8, 1, 1) GS_CASE(16, 8, 1, 1) GS_CASE(8, 16, 1, 1) GS_CASE(16, 16, 1, 1) GS_CASE(32, 8, 1, 1)
+    GS_CASE(8, 32, 1, 1) GS_CASE(32, 16, 1, 1) GS_CASE(16, 32, 1, 1) GS_CASE(32, 32, 1, 1)
+    GS_CASE(16, 8, 2, 1) GS_CASE(16, 16, 2, 1) GS_CASE(32, 8, 2, 1) GS_CASE(32, 16, 2, 1) GS_CASE(16, 32, 2, 1)
+    GS_CASE(32, 32, 2, 1)
+    GS_CASE(16, 16, 2, 2) GS_CASE(32, 16, 2, 2) GS_CASE(16, 32, 2, 2) GS_CASE(32, 32, 2, 2)
 #undef GS_CASE
     return false;
 }
@@ -781,7 +848,8 @@ gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, con
     a.entry_offset = bins->entry_offset;
     a.capacity = bins->capacity;
     a.slots = slots;
-    if (!launch_bwd(a, views->tile_w, views->tile_h, views->n_tiles, s)) return finish(false, "render_bwd");
+    if (!launch_bwd(a, views->tile_w, views->tile_h, bwd_pixels_per_lane(views), views->n_tiles, s))
+        return finish(false, "render_bwd");
     if (vn > 0)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj->count,
                            bins->entry_offset, vn, slots, bins->capacity, bins->overflow, g2);

@@ -104,13 +104,14 @@ class ViewBatch:
     """Views rendered in one call: cameras, tile size and the global tile/pixel layout."""
 
     def __init__(self, cams: Sequence, tile: Tuple[int, int] = DEFAULT_TILE, device=None, batch_depth: int = 1,
-                 lpt: bool = False):
+                 lpt: bool = False, pixels_per_lane: int = 0):
         lib = L.load()
         self.cams = list(cams)
         self.n_views = len(self.cams)
         self.tile = (int(tile[0]), int(tile[1]))
         self.batch_depth = int(batch_depth)
         self.lpt = bool(lpt)  # traversals take tiles longest list first
+        self.pixels_per_lane = int(pixels_per_lane)  # reverse traversal; 0 = the library's default
         self.device = _dev(device)
         arr = (L.gs_camera * self.n_views)(*[camera_struct(c) for c in self.cams])
         toff = (ctypes.c_int32 * (self.n_views + 1))()
@@ -129,7 +130,7 @@ class ViewBatch:
     def struct(self) -> L.gs_views:
         return L.gs_views(_ptr(self.cams_dev), _ptr(self.tile_offset), _ptr(self.pixel_offset), self.n_views,
                           self.tile[0], self.tile[1], self.n_tiles, self.n_pixels, self.batch_depth,
-                          int(self.lpt))
+                          int(self.lpt), self.pixels_per_lane, 0)
 
     def image(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
         """View v's planar [3][H][W] image inside a global rgb buffer."""

@@ -298,16 +298,19 @@ def test_backward_matches_oracle(case):
             assert elem.mean() >= 0.999, name
 
 
-@pytest.mark.parametrize("tile,depth", [((8, 8), 1), ((32, 16), 2), ((16, 32), 1), ((32, 32), 1)])
-def test_backward_tile_shapes(tile, depth):
-    """The reverse traversal at other tile shapes and batch depths (one to sixteen waves per
-    workgroup, quarter lists of up to 64 bits) against the oracle gradient."""
+@pytest.mark.parametrize("tile,depth,ppl", [((8, 8), 1, 1), ((32, 16), 2, 1), ((16, 32), 1, 1), ((32, 32), 1, 1),
+                                            ((16, 8), 1, 2), ((16, 16), 1, 2), ((32, 32), 1, 2), ((16, 16), 2, 4),
+                                            ((16, 32), 1, 4), ((32, 32), 1, 4)])
+def test_backward_tile_shapes(tile, depth, ppl):
+    """The reverse traversal at other tile shapes, batch depths and pixels per lane (one to
+    sixteen waves per workgroup, quarter lists of up to 64 bits, 1 x 1, 2 x 1 and 2 x 2 pixel
+    clusters per lane) against the oracle gradient."""
     sc, cam = _case("plain")
     rng = np.random.default_rng(12)
     w = rng.uniform(-1, 1, (3, cam.height, cam.width)).astype(np.float32)
-    _say(f"backward tile={tile} depth={depth}")
+    _say(f"backward tile={tile} depth={depth} pixels per lane={ppl}")
     g = gs.Gaussians.from_scene(sc, DEV)
-    views = gs.ViewBatch([cam], tile, DEV, batch_depth=depth)
+    views = gs.ViewBatch([cam], tile, DEV, batch_depth=depth, pixels_per_lane=ppl)
     out = gs.render(g, views, P)
     grad = gs.render_bwd(g, views, out["proj"], out["bins"], out["t_final"], out["n_last"],
                          torch.as_tensor(w.reshape(-1), device=DEV), P)

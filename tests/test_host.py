@@ -33,7 +33,7 @@ def test_library_exports_every_declared_entry_point():
 def test_struct_layout_sizes():
     assert ctypes.sizeof(L.gs_camera) == 80
     assert ctypes.sizeof(L.gs_params) == 36
-    assert ctypes.sizeof(L.gs_views) == 56
+    assert ctypes.sizeof(L.gs_views) == 64
     assert ctypes.sizeof(L.gs_bins) == 72
 
 
