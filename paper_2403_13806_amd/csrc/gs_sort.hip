@@ -902,8 +902,8 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.status = p;
     p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
     L.ctrl_end = p;
-    L.offs = p;
-    p = align256(p + sizeof(uint32_t) * (size_t)vn);
+    L.offs = p;  // pair offsets of the 256-entry emission blocks of every view
+    p = align256(p + sizeof(uint32_t) * (size_t)((n + 255) / 256) * (size_t)std::max(n_views, 0));
     L.deferred = p;
     p = align256(p + sizeof(uint32_t) * nt);
     const size_t k4 = sizeof(uint32_t) * (size_t)capacity, v8 = sizeof(uint64_t) * (size_t)capacity;
