@@ -227,6 +227,19 @@ gs_status gs_preprocess(const gs_gaussians* g, const gs_views* views, const gs_p
 gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* gs_bin_sort without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments and results as gs_bin_sort; the scratch is a static device array of
+ * GS_BIN_SORT_NOALLOC_BYTES (64 MiB) that each GPU the library runs on holds until the
+ * process ends (its address is looked up once per device, on the first call). The call
+ * allocates nothing. A frame whose scratch need (the gs_bin_sort workspace, about 25 bytes per
+ * pair of capacity plus 2 KB per 256 entries) exceeds it returns GS_ERR_UNSUPPORTED before
+ * anything is enqueued. Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents (each call clears what it needs itself): calls that overlap on one GPU
+ * (other streams, other threads) race, so serialise them. */
+#define GS_BIN_SORT_NOALLOC_BYTES (64u << 20)
+gs_status gs_bin_sort_noalloc(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* stream);
+
 /* Front-to-back compositing of every pixel of every view (eq. render-gs). Writes rgb
  * [3 * n_pixels], t_final [n_pixels] (transmittance after the last composited entry)
  * and n_last [n_pixels] (1 + position in keys/vals of the pixel's last composited

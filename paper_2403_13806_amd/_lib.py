@@ -70,7 +70,8 @@ GS_ADAM_LINEAR, GS_ADAM_LOG, GS_ADAM_LOGIT = 0, 1, 2
 assert ctypes.sizeof(gs_camera) == 80
 SPLAT_BYTES = 64
 
-EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
+EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_bin_sort_noalloc",
+           "gs_render_fwd", "gs_render_bwd",
            "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_kmeans_seed",
            "gs_kmeans_workspace_bytes", "gs_kmeans_lloyd", "gs_nearest_centre",
            "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.gs_preprocess.restype = i32
     L.gs_bin_sort.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), c_void_p, ctypes.c_size_t, c_void_p]
     L.gs_bin_sort.restype = i32
+    L.gs_bin_sort_noalloc.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), c_void_p]
+    L.gs_bin_sort_noalloc.restype = i32
     L.gs_render_fwd.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), P(gs_params), c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p]
     L.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, i64, f32, c_void_p, c_void_p, c_void_p]

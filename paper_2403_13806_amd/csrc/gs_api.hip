@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "gs_device.hpp"
@@ -140,6 +142,31 @@ static gs_status check_bins(const gs_bins* b) {
     return GS_OK;
 }
 
+// Scratch of gs_bin_sort_noalloc: one copy per GPU the library runs on, held until the process
+// ends. In host code `scratch` names a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, on the first call made with that device current.
+static __device__ __align__(256) unsigned char scratch[GS_BIN_SORT_NOALLOC_BYTES];
+
+static gs_status noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> ptrs;
+    int dev = 0;
+    const hipError_t e0 = hipGetDevice(&dev);
+    if (e0 != hipSuccess) return set_error(GS_ERR_HIP, "gs_bin_sort_noalloc: hipGetDevice: %s", hipGetErrorString(e0));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = ptrs.find(dev);
+    if (it == ptrs.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return set_error(GS_ERR_HIP, "gs_bin_sort_noalloc: hipGetSymbolAddress of the scratch on device %d: %s",
+                             dev, hipGetErrorString(e));
+        it = ptrs.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return GS_OK;
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -201,6 +228,19 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* 
     const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
     if (ws_bytes < need || (need > 0 && !ws))
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort_noalloc(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, false)) || (st = check_views(views)) || (st = check_bins(bins))) return st;
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
+    if (need > (size_t)GS_BIN_SORT_NOALLOC_BYTES)
+        return set_error(GS_ERR_UNSUPPORTED,
+                         "gs_bin_sort_noalloc: this call needs %zu bytes of scratch, the static scratch holds %zu "
+                         "(use gs_bin_sort with a workspace)", need, (size_t)GS_BIN_SORT_NOALLOC_BYTES);
+    void* ws = nullptr;
+    if ((st = noalloc_scratch(&ws))) return st;
     return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);
 }
 
