@@ -1354,3 +1354,147 @@ def test_visibility_filter_device_kmeans_same_lists():
     assert np.abs(a.centres - b.centres).max() <= 1e-12 * 30
     for c in range(4):
         assert torch.equal(a.lists[c], b.lists[c])
+
+
+# ----------------------------------------------------------------------------------------------
+# Crop views of the full-size scenes: a crop is the full view's camera with the principal point
+# moved by the crop origin and a 128 x 128 image, so the oracle renders every pixel of it while
+# the GPU's tiles hold the full scenes' long lists. The guard window is widened for both sides
+# (a parameter), so a crop keeps every Gaussian whose support meets it. The oracle renders the
+# Gaussians whose tile rectangle meets the crop (the others cover no pixel of it), in index
+# order, so every per-pixel order is the full scene's.
+# ----------------------------------------------------------------------------------------------
+
+CROP_P = scenes.Params(guard=30.0)
+
+
+def _crop(cam, ox, oy, w=128, h=128):
+    return scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - ox, cam.cy - oy, w, h)
+
+
+def _oracle_crops(sc, crops, want_h=False):
+    """Indices of the Gaussians whose rectangle meets some crop, and the oracle's threshold-band
+    runs of every crop over that subset."""
+    keep = np.zeros(sc.n, bool)
+    for c in crops:
+        pr = oracle.project(sc, c, CROP_P)
+        keep |= (pr[:, F["vis"]] == 1) & (pr[:, F["count"]] > 0)
+        del pr
+    idx = np.nonzero(keep)[0]
+    sub = sc.subset(idx)
+    return idx, [band_runs(sub, c, CROP_P, want_h=want_h)[1] for c in crops]
+
+
+def _check_crop_images(views, out, ncontrib, runs_per_crop, what):
+    for v, runs in enumerate(runs_per_crop):
+        img = views.image(out[0], v).cpu().numpy().astype(np.float64)
+        T = views.plane(out[1], v).cpu().numpy().astype(np.float64)
+        nc = views.plane(ncontrib, v).cpu().numpy().astype(np.int64)
+        band = image_band(runs)
+        mism = (np.abs(img - runs[0]["rgb"]).max(0) > TOL_IMAGE) | (np.abs(T - runs[0]["T"]) > TOL_IMAGE)
+        check_band(mism, band, f"{what} crop {v} image and T")
+        nband = band.copy()
+        for r in runs[1:]:
+            nband |= r["ncomp"] != runs[0]["ncomp"]
+        check_band(nc != runs[0]["ncomp"], nband, f"{what} crop {v} composited count")
+        _say(f"  crop {v}: {int(runs[0]['ncomp'].sum())} composited, max per pixel {int(runs[0]['ncomp'].max())}")
+
+
+def _gpu_crops(g, crops, tile, lpt=False):
+    views = gs.ViewBatch(crops, tile, DEV, lpt=lpt)
+    proj = gs.preprocess(g, views, CROP_P)
+    bins = gs.bin_sort(proj, views)
+    ncontrib = torch.zeros(views.n_pixels, dtype=torch.int32, device=DEV)
+    out = gs.render_fwd(proj, views, bins, CROP_P, n_contrib=ncontrib)
+    torch.cuda.synchronize()
+    rg = bins.ranges[:2 * views.n_tiles].view(-1, 2).long()
+    _say(f"  longest tile list {int((rg[:, 1] - rg[:, 0]).max())} entries")
+    return views, out, ncontrib
+
+
+def test_crops_of_the_full_size_frame():
+    """1M Gaussians, the benchmark's 1256x828 view at 16x32 tiles: three 128x128 crops (centre,
+    top-left, bottom-right) in one batch, every pixel's colour and T within 1e-4 and its
+    composited count exact outside the threshold band; the importance over the crops within
+    1e-5 of the oracle's, two-sided."""
+    sc = scenes.mixture_scene(1_000_000, seed=0, sh_degree=3)
+    cam = scenes.orbit_views(8)[0]
+    crops = [_crop(cam, 564, 350), _crop(cam, 0, 0), _crop(cam, 1128, 700)]
+    _say("crops of the 1M x 1256x828 frame")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views, out, ncontrib = _gpu_crops(g, crops, (16, 32))
+    idx, runs = _oracle_crops(sc, crops, want_h=True)
+    _check_crop_images(views, out, ncontrib, runs, "frame")
+    h = gs.importance(g, views, CROP_P).cpu().numpy().astype(np.float64)
+    h_ref = np.max([r[0]["h"] for r in runs], axis=0)
+    band = np.zeros(idx.size, bool)
+    for r in runs:
+        band |= h_band(r)
+    check_band(np.abs(h[idx] - h_ref) > TOL_H, band, "frame crops importance")
+    rest = np.ones(sc.n, bool)
+    rest[idx] = False
+    assert np.all(h[rest] == 0)
+
+
+def test_crops_importance_500k_150_views():
+    """500k Gaussians of the 150-view importance workload: 128x128 crops of views 0, 50 and 100
+    in one batch in longest-first order at 16x32 (the importance benchmark's launch form). The
+    importance within 1e-5 of the oracle's maximum over the crops, two-sided, the prune mask at
+    0.01 equal outside the band, and the images, T and composited counts of the crops."""
+    sc = scenes.mixture_scene(500_000, seed=0, sh_degree=3)
+    cams = scenes.orbit_views(150)
+    crops = [_crop(cams[0], 564, 350), _crop(cams[50], 400, 300), _crop(cams[100], 700, 400)]
+    _say("crops of the 500k x 150-view importance workload")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views, out, ncontrib = _gpu_crops(g, crops, (16, 32), lpt=True)
+    idx, runs = _oracle_crops(sc, crops, want_h=True)
+    _check_crop_images(views, out, ncontrib, runs, "importance workload")
+    h = torch.zeros(g.n, device=DEV)
+    r = gs.Renderer(g, views, CROP_P, want_color=False, backward=False)
+    r.importance(h)
+    assert r.check()[0] is False
+    h = h.cpu().numpy().astype(np.float64)
+    h_ref = np.max([rr[0]["h"] for rr in runs], axis=0)
+    band = np.zeros(idx.size, bool)
+    for rr in runs:
+        band |= h_band(rr)
+    check_band(np.abs(h[idx] - h_ref) > TOL_H, band, "importance crops")
+    rest = np.ones(sc.n, bool)
+    rest[idx] = False
+    assert np.all(h[rest] == 0)
+    t = 0.01
+    mask = gs.prune_mask(torch.as_tensor(h.astype(np.float32), device=DEV), t).cpu().numpy().astype(bool)
+    check_band(mask[idx] != (h_ref < t), band | (np.abs(h_ref - t) <= TOL_H), "prune mask on the crops")
+    _say(f"  {int((h_ref > 0).sum())} Gaussians composited in the crops, {int((h_ref >= t).sum())} kept")
+
+
+def test_crops_house_cluster_bits():
+    """5M Gaussians of the house scene: 128x128 crops of three training views at 1920x1080,
+    assigned to two clusters. Images, T and composited counts of the crops, and the cluster
+    bits at t_cluster 0.01 equal to the oracle's outside the band, two-sided (no missing and
+    no spurious member)."""
+    sc = scenes.house_scene(5_000_000)
+    train = scenes.house_training_views(640)
+    crops = [_crop(train[0], 896, 476), _crop(train[333], 896, 476), _crop(train[100], 600, 300)]
+    assign, k, t = [0, 1, 1], 2, 0.01
+    _say("crops of the 5M house scene")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views, out, ncontrib = _gpu_crops(g, crops, (16, 16))
+    idx, runs = _oracle_crops(sc, crops, want_h=True)
+    _check_crop_images(views, out, ncontrib, runs, "house")
+    bits = gs.cluster_visibility(g, views, assign, k, t, CROP_P)
+    torch.cuda.synchronize()
+    words = (sc.n + 31) // 32
+    b = bits.cpu().numpy().view(np.uint32).reshape(k, words)
+    got = np.unpackbits(b.view(np.uint8).reshape(k, -1), axis=1, bitorder="little")[:, :sc.n].astype(bool)
+    hc = np.zeros((k, idx.size))
+    band = np.zeros((k, idx.size), bool)
+    for v, rr in enumerate(runs):
+        hc[assign[v]] = np.maximum(hc[assign[v]], rr[0]["h"])
+        band[assign[v]] |= h_band(rr)
+    band |= np.abs(hc - t) <= TOL_H
+    check_band(got[:, idx] != (hc > t), band, "house crops cluster bits")
+    rest = np.ones(sc.n, bool)
+    rest[idx] = False
+    assert not got[:, rest].any()
+    _say(f"  cluster members: {got.sum(1).tolist()}")
