@@ -54,9 +54,12 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_SO)
+        path = os.environ.get("GS_ORACLE_LIB")  # another build of gs_oracle.c (the sanitizer run's)
+        if not path:
+            path = _SO
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build()
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         lp = ctypes.POINTER(ctypes.c_int64)

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgs_hip.so")
+# GS_HIP_LIB names another build of the same library (the sanitizer run loads a host-only
+# build with address and undefined-behaviour checks)
+LIB_PATH = os.environ.get("GS_HIP_LIB") or os.path.join(_HERE, "libgs_hip.so")
 
 c_void_p = ctypes.c_void_p
 i32 = ctypes.c_int32
