@@ -561,6 +561,210 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* n_p
 }
 
 // ---------------------------------------------------------------------------------------
+// Grouping by tile in one stable counting pass, for batches of at most 4096 tiles: the tile
+// histogram of every block of TILE_ITEMS pairs, the exclusive prefix of each tile's counts over
+// the blocks (column scans, which also give every tile's total and so its range), then one
+// scatter pass that ranks each block's pairs by tile (12 ballots per pair, index order kept)
+// and writes them at tile start + earlier blocks' count + rank. No block waits on another.
+// ---------------------------------------------------------------------------------------
+constexpr int G12 = 4096;           // tiles (digit values)
+constexpr int G12_MAX_ROWS = 2048;  // blocks: the column scan holds 16 columns of every block in LDS
+
+__global__ __launch_bounds__(BLK) void k_g12_hist(const uint32_t* __restrict__ keys, const uint64_t* n_items,
+                                                  uint64_t bound, const uint32_t* overflow,
+                                                  uint32_t* __restrict__ bh) {
+    __shared__ uint32_t h[G12];
+    const int t = threadIdx.x;
+    if (*overflow) return;
+    const uint64_t count = min(*n_items, bound);
+    const uint64_t base = (uint64_t)blockIdx.x * TILE_ITEMS;
+    if (base >= count) return;  // rows past the data are never read
+    for (int i = t; i < G12; i += BLK) h[i] = 0;
+    __syncthreads();
+    // a contiguous run of IPT keys per thread; equal neighbours (pairs of one Gaussian in one
+    // row of tiles) merged into one LDS atomic
+    const uint64_t b0 = base + (uint64_t)t * IPT, b1 = min(b0 + IPT, count);
+    if (b0 < b1) {
+        uint32_t prev = keys[b0] & (G12 - 1), cnt = 1;
+        for (uint64_t i = b0 + 1; i < b1; ++i) {
+            const uint32_t k = keys[i] & (G12 - 1);
+            if (k == prev) {
+                ++cnt;
+            } else {
+                atomicAdd(&h[prev], cnt);
+                prev = k;
+                cnt = 1;
+            }
+        }
+        atomicAdd(&h[prev], cnt);
+    }
+    __syncthreads();
+    uint32_t* row = bh + (uint64_t)blockIdx.x * G12;
+    for (int i = t; i < G12; i += BLK) row[i] = h[i];
+}
+
+// Exclusive prefix over the blocks of every tile's count (in place) and the tile totals.
+// Workgroup g takes the 16 tiles [16 g, 16 g + 16): their counts of every block are read into
+// LDS, each of 16 chunks of blocks summed, the chunk sums scanned, then the prefixes written.
+__global__ __launch_bounds__(BLK) void k_g12_colscan(uint32_t* __restrict__ bh, const uint64_t* n_items,
+                                                     uint64_t bound, const uint32_t* overflow,
+                                                     uint32_t* __restrict__ tot) {
+    __shared__ uint32_t sub[G12_MAX_ROWS * 16];
+    __shared__ uint32_t csum[16][17];
+    if (*overflow) return;
+    const int t = threadIdx.x;
+    const uint64_t count = min(*n_items, bound);
+    const int nrows = (int)((count + TILE_ITEMS - 1) / TILE_ITEMS);  // <= G12_MAX_ROWS (host check)
+    const int c0 = blockIdx.x * 16;
+    for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)];
+    __syncthreads();
+    const int col = t & 15, chunk = t >> 4;
+    const int per = (nrows + 15) / 16, r0 = min(nrows, chunk * per), r1 = min(nrows, r0 + per);
+    uint32_t s = 0;
+    for (int r = r0; r < r1; ++r) s += sub[r * 16 + col];
+    csum[col][chunk] = s;
+    __syncthreads();
+    if (t < 16) {
+        uint32_t run = 0;
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t v = csum[t][k];
+            csum[t][k] = run;
+            run += v;
+        }
+        tot[c0 + t] = run;
+    }
+    __syncthreads();
+    uint32_t run = csum[col][chunk];
+    for (int r = r0; r < r1; ++r) {
+        const uint32_t v = sub[r * 16 + col];
+        sub[r * 16 + col] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int i = t; i < nrows * 16; i += BLK) bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)] = sub[i];
+}
+
+// block-wide exclusive scan of the 4096 counts c[] in place (16 consecutive per thread)
+__device__ __forceinline__ void block_excl_scan_4096(uint32_t* c, uint32_t* wsum) {
+    const int t = threadIdx.x;
+    uint32_t v[16], s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = c[t * 16 + k];
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, tot, wsum);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        c[t * 16 + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+}
+
+struct G12Args {
+    const uint32_t* kin;  // tile of each pair (emission order)
+    const uint64_t* vin;  // FP32 depth bits << 32 | Gaussian index
+    uint64_t* vout;       // the same values grouped by tile
+    const uint64_t* n_items;
+    uint64_t bound;
+    const uint32_t* overflow;
+    const uint32_t* bh;   // [blocks][4096] exclusive prefixes over blocks
+    const uint32_t* tot;  // [4096] pairs per tile
+    uint32_t* ranges;     // [n_tiles][2], written by block 0
+    int n_tiles;
+};
+
+__global__ __launch_bounds__(BLK) void k_g12_scatter(G12Args a) {
+    __shared__ uint32_t gbase[G12];           // tile start + earlier blocks' count - local start
+    __shared__ uint32_t wcnt[BLK / 64][G12];  // per-wave tile counters, then wave offsets
+    __shared__ uint32_t ds[G12];              // block-local tile starts
+    __shared__ uint32_t wsum[BLK / 64];
+    __shared__ uint64_t lv[TILE_ITEMS];
+    __shared__ uint16_t ld[TILE_ITEMS];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (*a.overflow) return;
+    const uint64_t count = min(*a.n_items, a.bound);
+    const uint64_t base = (uint64_t)blockIdx.x * TILE_ITEMS;
+    if (base >= count) return;
+    // tile starts: exclusive scan of the totals (every block forms them; block 0 writes the ranges)
+    for (int i = t; i < G12; i += BLK) gbase[i] = a.tot[i];
+    for (int k = 0; k < G12 / 64; ++k) wcnt[w][k * 64 + l] = 0;
+    __syncthreads();
+    block_excl_scan_4096(gbase, wsum);
+    if (blockIdx.x == 0)
+        for (int i = t; i < a.n_tiles; i += BLK) {
+            a.ranges[2 * i] = gbase[i];
+            a.ranges[2 * i + 1] = gbase[i] + a.tot[i];
+        }
+    const uint64_t wbase = base + (uint64_t)w * (64 * IPT);
+    uint32_t key[IPT], lr[IPT];
+    uint64_t val[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint64_t i = wbase + r * 64 + l;
+        const bool valid = i < count;
+        key[r] = valid ? (a.kin[i] & (G12 - 1)) : 0u;
+        val[r] = valid ? a.vin[i] : 0ull;
+    }
+    // rank inside the wave: lanes with the same tile, in lane order, after the wave's earlier rounds
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const bool valid = wbase + r * 64 + l < count;
+        const uint32_t d = key[r];
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 12; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = mask_rank(m);
+        const uint32_t old = valid ? wcnt[w][d] : 0u;
+        lr[r] = old + rank;
+        if (valid && rank == 0) wcnt[w][d] = old + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // per tile: the waves' exclusive offsets (in place) and the block's count
+    for (int k = 0; k < G12 / BLK; ++k) {
+        const int d = k * BLK + t;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int ww = 0; ww < BLK / 64; ++ww) {
+            const uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = mine;
+            mine += c;
+        }
+        ds[d] = mine;
+    }
+    __syncthreads();
+    block_excl_scan_4096(ds, wsum);
+    const uint32_t* row = a.bh + (uint64_t)blockIdx.x * G12;
+    for (int i = t; i < G12; i += BLK) gbase[i] = gbase[i] + row[i] - ds[i];
+    // block-local sort through LDS, then runs of one tile written together
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wbase + r * 64 + l < count) {
+            const uint32_t d = key[r];
+            const uint32_t q = ds[d] + wcnt[w][d] + lr[r];
+            lv[q] = val[r];
+            ld[q] = (uint16_t)d;
+        }
+    }
+    __syncthreads();
+    const uint32_t nitems = (uint32_t)min((uint64_t)TILE_ITEMS, count - base);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t q = r * BLK + t;
+        if (q < nitems) {
+            const uint32_t pos = gbase[ld[q]] + q;  // modulo 2^32, like the offsets it is made of
+            if (pos < count) a.vout[pos] = lv[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Per-tile sort by (depth bits, index)
 // ---------------------------------------------------------------------------------------
 constexpr int SMALL_LIST = 2048;  // 16 KB of LDS per workgroup
@@ -875,9 +1079,10 @@ struct SortLayout {
     // control block, cleared at the start of every gs_bin_sort: scan chain, pass tickets,
     // digit histograms, deferred-tile count, LPT counters, pass status tables
     size_t ctrl, scan, tickets, ghist, n_deferred, lpt, status, ctrl_end;
-    size_t offs, deferred, tk0, tk1, tv0, tv1, total;
+    size_t offs, deferred, tk0, tk1, tv0, tv1, g12_bh, g12_tot, total;
     int64_t nb_scan, nb_sort;
     int passes;
+    bool g12;  // grouping in one 12-bit counting pass (at most 4096 tiles)
 };
 
 SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
@@ -887,6 +1092,7 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.nb_scan = scan_blocks(vn);
     L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
     L.passes = std::max(1, (tile_bits(std::max(n_tiles, 1)) + 7) / 8);
+    L.g12 = n_tiles <= G12 && L.nb_sort <= G12_MAX_ROWS;
     size_t p = 0;
     L.ctrl = p;
     L.scan = p;
@@ -900,7 +1106,7 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.lpt = p;
     p = align256(p + sizeof(uint32_t) * 2 * LPT_B);
     L.status = p;
-    p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
+    if (!L.g12) p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
     L.ctrl_end = p;
     L.offs = p;  // pair offsets of the 256-entry emission blocks of every view
     p = align256(p + sizeof(uint32_t) * (size_t)((n + 255) / 256) * (size_t)std::max(n_views, 0));
@@ -915,6 +1121,10 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     p = align256(p + v8);
     L.tv1 = p;
     p = align256(p + v8);
+    L.g12_bh = p;
+    if (L.g12) p = align256(p + sizeof(uint32_t) * G12 * (size_t)L.nb_sort);
+    L.g12_tot = p;
+    if (L.g12) p = align256(p + sizeof(uint32_t) * G12);
     L.total = p;
     return L;
 }
@@ -986,36 +1196,56 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     e.tval = U64(L.tv0);
     e.eoff = bins->entry_offset;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
-    // 3. grouped by tile
-    const int np = L.passes;
-    uint32_t* ghist = U32(L.ghist);
-    const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort, 1024);
-    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np, ghist);
+    // 3. grouped by tile, 4. tile ranges
     uint32_t* kin = U32(L.tk0);
     uint64_t* vin = U64(L.tv0);
     uint32_t* kalt = U32(L.tk1);
     uint64_t* valt = U64(L.tv1);
-    for (int pass = 0; pass < np; ++pass) {
-        PassArgs pa;
-        pa.kin = kin;
-        pa.vin = vin;
-        pa.kout = kalt;
-        pa.vout = valt;
-        pa.n_items = bins->n_pairs;
-        pa.bound = bins->capacity;
-        pa.shift = 8 * pass;
-        pa.ghist = ghist + 256 * pass;
-        pa.status = U64(L.status) + (size_t)256 * L.nb_sort * pass;
-        pa.ticket = U32(L.tickets) + pass;
-        pa.err = bins->overflow;
-        hipLaunchKernelGGL(k_os_pass<uint64_t>, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
-        std::swap(kin, kalt);
+    if (L.g12) {
+        hipLaunchKernelGGL(k_g12_hist, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, kin, bins->n_pairs,
+                           bins->capacity, bins->overflow, U32(L.g12_bh));
+        hipLaunchKernelGGL(k_g12_colscan, dim3(G12 / 16), dim3(BLK), 0, stream, U32(L.g12_bh), bins->n_pairs,
+                           bins->capacity, bins->overflow, U32(L.g12_tot));
+        G12Args ga;
+        ga.kin = kin;
+        ga.vin = vin;
+        ga.vout = valt;
+        ga.n_items = bins->n_pairs;
+        ga.bound = bins->capacity;
+        ga.overflow = bins->overflow;
+        ga.bh = U32(L.g12_bh);
+        ga.tot = U32(L.g12_tot);
+        ga.ranges = bins->ranges;
+        ga.n_tiles = views->n_tiles;
+        hipLaunchKernelGGL(k_g12_scatter, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, ga);
         std::swap(vin, valt);
+    } else {
+        const int np = L.passes;
+        uint32_t* ghist = U32(L.ghist);
+        const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort, 1024);
+        hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np,
+                           ghist);
+        for (int pass = 0; pass < np; ++pass) {
+            PassArgs pa;
+            pa.kin = kin;
+            pa.vin = vin;
+            pa.kout = kalt;
+            pa.vout = valt;
+            pa.n_items = bins->n_pairs;
+            pa.bound = bins->capacity;
+            pa.shift = 8 * pass;
+            pa.ghist = ghist + 256 * pass;
+            pa.status = U64(L.status) + (size_t)256 * L.nb_sort * pass;
+            pa.ticket = U32(L.tickets) + pass;
+            pa.err = bins->overflow;
+            hipLaunchKernelGGL(k_os_pass<uint64_t>, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
+            std::swap(kin, kalt);
+            std::swap(vin, valt);
+        }
+        const unsigned rg = (unsigned)((bins->capacity + 255) / 256);
+        hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, stream, kin, bins->n_pairs, bins->capacity,
+                           bins->overflow, bins->ranges, views->n_tiles);
     }
-    // 4. tile ranges
-    const unsigned rg = (unsigned)((bins->capacity + 255) / 256);
-    hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, stream, kin, bins->n_pairs, bins->capacity, bins->overflow,
-                       bins->ranges, views->n_tiles);
     // 5. each tile's list by (depth, index); keys and values
     TileSortArgs ta;
     ta.pairs = vin;
