@@ -736,9 +736,13 @@ class VisibilityFilter:
     rendered with the list of the cluster centre nearest to its camera centre.
 
     extra_per_cluster random cameras are added to every cluster's views, as the method does
-    for robustness to test views: each sits at a random member camera's position moved by a
-    uniform offset in a ball of radius `jitter`, looks in a random direction (yaw uniform,
-    pitch uniform in +-max_pitch) and copies that member's intrinsics.
+    for robustness to test views. With extra_placement="jitter" each sits at a random member
+    camera's position moved by a uniform offset in a ball of radius `jitter`; with "cell" it is
+    drawn uniformly from the part of the cluster centre's Voronoi cell (the positions whose
+    nearest centre is this one, so the test views that will use this list) inside the box of
+    the member cameras widened by `cell_margin` in x and z, at a member's height. Either way it
+    looks in a random direction (yaw uniform, pitch uniform in +-max_pitch) and copies a
+    member's intrinsics.
 
     The Lloyd iterations run on the GPU from DEVICE_KMEANS_CAMERAS cameras on (device_kmeans=None),
     or as asked; the host and device clusterings follow the same steps."""
@@ -748,7 +752,10 @@ class VisibilityFilter:
     def __init__(self, g: Gaussians, train_cams: Sequence, k: int = 64, t_cluster: float = 0.001, params=None,
                  chunk: int = 8, tile: Tuple[int, int] = DEFAULT_TILE, seed: int = 3, device=None,
                  extra_per_cluster: int = 0, jitter: float = 1.0, max_pitch: float = np.deg2rad(30.0),
-                 materialize: bool = False, device_kmeans: Optional[bool] = None):
+                 materialize: bool = False, device_kmeans: Optional[bool] = None, extra_placement: str = "jitter",
+                 cell_margin: float = 6.0):
+        if extra_placement not in ("jitter", "cell"):
+            raise ValueError('extra_placement must be "jitter" or "cell"')
         dev = _dev(device)
         self.g, self.k, self.t_cluster, self.params, self.tile, self.device = g, k, t_cluster, params, tile, dev
         pos = np.stack([c.position for c in train_cams])
@@ -762,12 +769,17 @@ class VisibilityFilter:
                 members = np.nonzero(self.assign == c)[0]
                 if members.size == 0:
                     continue
-                for _ in range(extra_per_cluster):
+                if extra_placement == "cell":
+                    spots = self._cell_positions(pos, members, c, extra_per_cluster, cell_margin, rng)
+                for e in range(extra_per_cluster):
                     m = train_cams[int(rng.choice(members))]
-                    off = rng.standard_normal(3)
-                    off *= jitter * rng.uniform() ** (1.0 / 3.0) / max(np.linalg.norm(off), 1e-12)
-                    views.append(_camera_at(m.position + off, rng.uniform(0, 2 * np.pi),
-                                            rng.uniform(-max_pitch, max_pitch), m))
+                    if extra_placement == "cell":
+                        where = spots[e]
+                    else:
+                        off = rng.standard_normal(3)
+                        off *= jitter * rng.uniform() ** (1.0 / 3.0) / max(np.linalg.norm(off), 1e-12)
+                        where = m.position + off
+                    views.append(_camera_at(where, rng.uniform(0, 2 * np.pi), rng.uniform(-max_pitch, max_pitch), m))
                     owner.append(c)
         self.views_used = len(views)
         self.cluster_views, self.view_owner = views, np.asarray(owner, np.int32)  # every view and its cluster
@@ -781,6 +793,24 @@ class VisibilityFilter:
         # materialised lists: each cluster's Gaussians copied into compact planes (memory for
         # coalesced loads: a filtered render then reads rows instead of gathering by index)
         self.copies = [gather_gaussians(g, lst)[0] for lst in self.lists] if materialize else None
+
+    def _cell_positions(self, pos, members, c, count, margin, rng, tries=64):
+        """count positions drawn uniformly from the Voronoi cell of centre c inside the box of
+        the member cameras widened by margin in x and z, at member heights (rejection sampling;
+        members' own positions fill in if the cell is too thin to hit)."""
+        lo, hi = pos[members].min(0), pos[members].max(0)
+        lo = lo - np.array([margin, 0.0, margin])
+        hi = hi + np.array([margin, 0.0, margin])
+        out = []
+        for _ in range(tries):
+            cand = rng.uniform(lo, hi, (4 * count, 3))
+            cand[:, 1] = pos[rng.choice(members, 4 * count), 1]
+            d = ((cand[:, None, :] - self.centres[None, :, :]) ** 2).sum(-1)
+            out.extend(cand[np.argmin(d, 1) == c])
+            if len(out) >= count:
+                return np.asarray(out[:count])
+        out.extend(pos[rng.choice(members, count)])
+        return np.asarray(out[:count])
 
     def materialize(self):
         if self.copies is None:

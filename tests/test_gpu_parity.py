@@ -792,16 +792,22 @@ def test_render_batch_and_render_filtered():
         assert torch.equal(got, one.image(gs.render(g, one, P, subset=vf.lists[c])["rgb"], 0))
 
 
-def test_visibility_filter_extra_cameras_only_add():
+@pytest.mark.parametrize("placement", ["jitter", "cell"])
+def test_visibility_filter_extra_cameras_only_add(placement):
     """Extra random cameras per cluster (Sec. 3.4) only add views to a cluster, so each
     cluster's list can only grow (the per-cluster max is monotone in the view set)."""
     sc = scenes.house_scene(8000, seed=5, sh_degree=0)
     train = scenes.house_training_views(10, width=80, height=45)
     g = gs.Gaussians.from_scene(sc, DEV)
-    _say("visibility filter with extra cameras")
+    _say(f"visibility filter with extra cameras ({placement})")
     a = gs.VisibilityFilter(g, train, k=2, t_cluster=0.01, params=P, device=DEV)
-    b = gs.VisibilityFilter(g, train, k=2, t_cluster=0.01, params=P, device=DEV, extra_per_cluster=3)
+    b = gs.VisibilityFilter(g, train, k=2, t_cluster=0.01, params=P, device=DEV, extra_per_cluster=3,
+                            extra_placement=placement)
     assert b.views_used == len(train) + 6
+    assert np.array_equal(a.assign, b.assign)
+    if placement == "cell":  # each extra camera's nearest centre is its cluster's
+        for v in range(len(train), b.views_used):
+            assert b.cluster_of(b.cluster_views[v]) == b.view_owner[v]
     for c in range(2):
         sa = set(a.lists[c].cpu().numpy().tolist())
         sb = set(b.lists[c].cpu().numpy().tolist())

@@ -342,3 +342,22 @@ def test_cluster_ids_are_checked_on_the_host():
     short = torch.zeros(4 * 2 - 1, dtype=torch.int32)
     with pytest.raises(ValueError):
         gs.cluster_visibility(g, views, [0, 3], 4, 0.01, bits=short)
+
+
+def test_extra_cameras_in_the_voronoi_cell():
+    # the "cell" placement draws each cluster's extra cameras where that cluster's centre is the
+    # nearest one (ties to the lowest index), inside the members' box widened in x and z
+    rng = np.random.default_rng(3)
+    pos = np.concatenate([rng.normal([0, -1.5, 0], 0.5, (40, 3)), rng.normal([6, -1.5, 1], 0.5, (40, 3)),
+                          rng.normal([3, -4.5, 8], 0.5, (40, 3))])
+    vf = gs.VisibilityFilter.__new__(gs.VisibilityFilter)
+    vf.centres, assign = gs.kmeans(pos, 3, seed=3)
+    for c in range(3):
+        members = np.nonzero(assign == c)[0]
+        spots = vf._cell_positions(pos, members, c, 50, 2.0, np.random.default_rng(c))
+        assert spots.shape == (50, 3)
+        d = ((spots[:, None, :] - vf.centres[None]) ** 2).sum(-1)
+        assert np.all(np.argmin(d, 1) == c)
+        lo, hi = pos[members].min(0), pos[members].max(0)
+        assert np.all(spots[:, [0, 2]] >= lo[[0, 2]] - 2.0) and np.all(spots[:, [0, 2]] <= hi[[0, 2]] + 2.0)
+        assert np.all(np.isin(spots[:, 1], pos[members, 1]))  # member heights
