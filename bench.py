@@ -556,7 +556,7 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W, tune=True):
     torch.cuda.synchronize()
     out["fwd_bwd_1M_8uneven_batched_graph_views_per_s"] = 8 * kk / (time.perf_counter() - t0)
     out["fwd_bwd_1M_8uneven_batched_graph_config"] = {"tile": list(cfg.tile), "batch_depth": cfg.batch_depth,
-                                                      "lpt": cfg.lpt}
+                                                      "lpt": cfg.lpt, "pixels_per_lane": cfg.pixels_per_lane}
     log(f"  batched, {cfg}, hipGraph: {out['fwd_bwd_1M_8uneven_batched_graph_views_per_s']:.1f} views/s")
     assert step.ok()
     del step

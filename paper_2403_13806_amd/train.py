@@ -3,8 +3,8 @@ one captured hipGraph, and the autotuner that picks its launch configuration. Th
 L1 (loss="l1") or the Sec. 3.2 training loss 0.8 L2 + 0.2 D-SSIM (loss="l2_dssim", one
 gs_ssim_loss_grad call per view with the batch's element count, sharing one workspace).
 
-  StepConfig      tile size, batch depth (records staged per lane) and tile order (longest
-                  list first, or tile order)
+  StepConfig      tile size, batch depth (records staged per lane), tile order (longest
+                  list first, or tile order) and pixels per lane of the traversals
   FwdBwdStep      preallocated buffers, an eager step, capture into a hipGraph, replay
   autotune        times every candidate configuration on the actual scene and views and
                   keeps the fastest; results are cached as JSON keyed by device, scene size
@@ -36,14 +36,18 @@ class StepConfig:
     tile_h: int = 16
     batch_depth: int = 1
     lpt: bool = False
+    pixels_per_lane: int = 0  # 0: the library's default for the tile size
 
     @property
     def tile(self):
         return (self.tile_w, self.tile_h)
 
 
-CANDIDATES = ([StepConfig(tw, th, d, p) for (tw, th) in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16)]
-               for d in (1, 2) for p in (False, True)] + [StepConfig(32, 32, 1, False)])
+CANDIDATES = ([StepConfig(tw, th, 1, lpt) for (tw, th) in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16), (16, 32)]
+               for lpt in (False, True)]
+              + [StepConfig(tw, th, 2, True) for (tw, th) in [(16, 16), (32, 16), (16, 32)]]
+              + [StepConfig(tw, th, 1, True, ppl) for (tw, th) in [(16, 16), (32, 16), (16, 32)] for ppl in (1, 2, 4)]
+              + [StepConfig(32, 32, 1, False)])
 
 
 def zero_grads(g: Gaussians) -> Gaussians:
@@ -64,7 +68,7 @@ class FwdBwdStep:
         dev = torch.device(device if device is not None else "cuda")
         self.cfg = cfg
         self.loss_kind = loss
-        self.views = ViewBatch(cams, cfg.tile, dev, cfg.batch_depth, cfg.lpt)
+        self.views = ViewBatch(cams, cfg.tile, dev, cfg.batch_depth, cfg.lpt, cfg.pixels_per_lane)
         self.r = Renderer(g, self.views, params, capacity)
         self.target = self.views.pack_images(targets)
         self.grad = zero_grads(g)

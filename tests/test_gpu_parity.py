@@ -627,23 +627,33 @@ def test_full_size_house_filtering():
         assert torch.equal(a, b), f
 
 
-@pytest.mark.parametrize("tile,depth,lpt", [((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 2, False),
-                                            ((16, 8), 1, True), ((32, 16), 2, True), ((32, 32), 1, True)])
-def test_launch_forms_bitwise(tile, depth, lpt):
-    """Batch depth and the longest-first tile order change when a tile is composited and how
-    its list is staged, never the arithmetic: images, T and importance are bitwise equal."""
+@pytest.mark.parametrize("tile,depth,lpt,ppl", [((16, 16), 2, True, 1), ((8, 8), 1, True, 1), ((32, 8), 2, False, 1),
+                                                ((16, 8), 1, True, 1), ((32, 16), 2, True, 1), ((32, 32), 1, True, 1),
+                                                ((16, 32), 1, False, 2), ((16, 16), 2, True, 2),
+                                                ((32, 8), 1, True, 2), ((32, 32), 1, False, 2), ((16, 8), 2, True, 2),
+                                                ((32, 16), 1, True, 4)])
+def test_launch_forms_bitwise(tile, depth, lpt, ppl):
+    """Batch depth, the longest-first tile order and two pixels per lane change when a tile is
+    composited, how its list is staged and which lane holds a pixel, never the arithmetic:
+    images, T, the composited counts, importance and cluster bits are bitwise equal."""
     sc = scenes.mixture_scene(6000, seed=7, sh_degree=3)
     cams = scenes.uneven_views([(64, 48), (126, 83), (160, 106), (192, 108)])
     g = gs.Gaussians.from_scene(sc, DEV)
-    _say(f"launch form tile={tile} depth={depth} lpt={lpt}")
-    ref_v = gs.ViewBatch(cams, (16, 16), DEV)
+    _say(f"launch form tile={tile} depth={depth} lpt={lpt} pixels per lane={ppl}")
+    ref_v = gs.ViewBatch(cams, (16, 16), DEV, pixels_per_lane=1)
     ref = gs.render(g, ref_v, P)
     h_ref = gs.importance(g, ref_v, P)
-    vb = gs.ViewBatch(cams, tile, DEV, batch_depth=depth, lpt=lpt)
+    b_ref = gs.cluster_visibility(g, ref_v, [0, 1, 1, 0], 2, 0.01, P)
+    vb = gs.ViewBatch(cams, tile, DEV, batch_depth=depth, lpt=lpt, pixels_per_lane=ppl)
     out = gs.render(g, vb, P)
     h = gs.importance(g, vb, P)
+    b = gs.cluster_visibility(g, vb, [0, 1, 1, 0], 2, 0.01, P)
     assert torch.equal(out["rgb"], ref["rgb"]) and torch.equal(out["t_final"], ref["t_final"])
-    assert torch.equal(h, h_ref)
+    assert torch.equal(h, h_ref) and torch.equal(b, b_ref)
+    for views, o in ((ref_v, ref), (vb, out)):
+        o["nc"] = torch.zeros(views.n_pixels, dtype=torch.int32, device=DEV)
+        gs.render_fwd(o["proj"], views, o["bins"], P, n_contrib=o["nc"])
+    assert torch.equal(out["nc"], ref["nc"])
     if lpt:
         q = out["bins"].queue[:vb.n_tiles].cpu().numpy()
         assert np.array_equal(np.sort(q), np.arange(vb.n_tiles))  # every tile exactly once
