@@ -36,6 +36,8 @@ OPS_PER_COMPOSITE = 23
 OPS_PER_IMPORTANCE = 20
 OPS_PER_BACKWARD = 47
 TILE = (16, 32)  # tile of the headline frames (fastest measured: fewer pairs to sort than 16x16)
+PX = 2 if TILE[0] >= 16 and TILE[0] * TILE[1] >= 512 else 1  # pixels per lane the library picks for it
+RENDER_KERNEL = f"k_render<{TILE[0]},{TILE[1]},1,0,{PX}>"
 SPLAT = 64
 
 
@@ -201,12 +203,20 @@ def main():
     npx = rs[0].views.n_pixels
     n = g.n
     mp, mc, mt, mv = (float(np.mean(x)) for x in (pairs, composites, tested, visible))
-    passes = max(1, (int(np.ceil(np.log2(rs[0].views.n_tiles))) + 7) // 8)  # tile-grouping radix passes
+    n_tiles = rs[0].views.n_tiles
+    one_pass = n_tiles <= 4096  # grouping in one 12-bit counting pass, else onesweep radix passes
+    passes = 1 if one_pass else max(1, (int(np.ceil(np.log2(n_tiles))) + 7) // 8)
     bytes_pre = 4 * n * (3 + 3 + 4 + 1 + 48) + 4 * n + mv * (SPLAT + 4 + 8)
-    # scan (count in, offset out), emit (count + offset per entry, rect + depth per visible entry,
-    # 12 B per pair out), digit histogram (4 B per pair), grouping passes (12 B in + 12 B out per
-    # pair each), ranges (4 B per pair), per-tile sort (8 B in, 12 B out per pair)
-    bytes_sort = (4 + 4 + 8) * n + 12 * mv + mp * (12 + 4 + passes * 24 + 4 + 20) + rs[0].views.n_tiles * 8
+    # block sums (count in), emit (count per entry, rect + depth per visible entry, 12 B per pair
+    # out); one pass: block tile histograms (4 B per pair in, 16 KB per 4096 pairs out, scanned in
+    # place, read once more), scatter (12 B in, 8 B out per pair); onesweep: digit histogram
+    # (4 B per pair), passes (12 B in + 12 B out per pair each), ranges (4 B per pair); then the
+    # per-tile sort (8 B in, 12 B out per pair) and the ranges
+    if one_pass:
+        grouping = mp * (4 + 20) + 4 * 16384 * np.ceil(mp / 4096)
+    else:
+        grouping = mp * (4 + passes * 24 + 4)
+    bytes_sort = (4 + 8) * n + 12 * mv + mp * (12 + 20) + grouping + n_tiles * 8
     bytes_render = mp * (4 + SPLAT) + npx * (12 + 4 + 4) + rs[0].views.n_tiles * 8
     ops_render = OPS_PER_COMPOSITE * mc
     ops_imp, ops_bwd = OPS_PER_IMPORTANCE * mc, OPS_PER_BACKWARD * mc
@@ -214,7 +224,8 @@ def main():
         "preprocess": {"ms": avg["preprocess"], "alg_GBps": bytes_pre / avg["preprocess"] / 1e6,
                        "hbm_frac": bytes_pre / avg["preprocess"] / 1e-3 / PEAK_HBM},
         "bin_sort": {"ms": avg["bin_sort"], "alg_GBps": bytes_sort / avg["bin_sort"] / 1e6,
-                     "hbm_frac": bytes_sort / avg["bin_sort"] / 1e-3 / PEAK_HBM, "radix_passes": passes},
+                     "hbm_frac": bytes_sort / avg["bin_sort"] / 1e-3 / PEAK_HBM,
+                     "grouping": "one 12-bit counting pass" if one_pass else f"{passes} onesweep radix passes"},
         "render_fwd": {"ms": avg["render_fwd"], "alg_Tops": ops_render / avg["render_fwd"] / 1e9,
                        "alu_frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS,
                        "alg_GBps": bytes_render / avg["render_fwd"] / 1e6,
@@ -231,9 +242,9 @@ def main():
     work = {"visible_per_view": mv, "pairs_per_view": mp, "composited_per_view": mc,
             "tested_per_view": mt, "composited_per_pixel": mc / npx, "tested_per_composited": mt / max(mc, 1)}
     log(f"stages (ms): {json.dumps({k: round(v, 4) for k, v in avg.items()})}; work {json.dumps(work)}")
-    roofline = {"bound": "alu", "kernel": f"k_render<{TILE[0]},{TILE[1]},1,0>", "achieved": ops_render / avg["render_fwd"] / 1e9,
+    roofline = {"bound": "alu", "kernel": RENDER_KERNEL, "achieved": ops_render / avg["render_fwd"] / 1e9,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-ops/s",
-                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": recorded_traffic(f"k_render<{TILE[0]},{TILE[1]},1,0>"),
+                "frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS, "traffic": recorded_traffic(RENDER_KERNEL),
                 "traffic_unit": "bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
                 "alg_bytes_per_launch": bytes_render,
                 "hbm_frac": bytes_render / avg["render_fwd"] / 1e-3 / PEAK_HBM,
