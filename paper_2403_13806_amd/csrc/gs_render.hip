@@ -703,10 +703,22 @@ void k_render(RenderArgs a) {
     fwd_tile<TW, TH, DEPTH, MODE, PXW>(sm, a, tile_of_block(a));
 }
 
+// Tile order of the reverse traversal: workgroups go to the 8 XCDs round-robin, so workgroup b
+// runs on XCD b mod 8; here each XCD takes pairs of neighbouring tiles (2m, 2m + 1) in
+// consecutive slots, so that the slots of a Gaussian's pairs in two neighbouring tiles (adjacent
+// in emission order) are written through one L2. The last n mod 16 tiles keep their place.
+__device__ __forceinline__ int bwd_tile_of_block(const RenderArgs& a) {
+    if (a.queue) return (int)a.queue[blockIdx.x];
+    const int b = (int)blockIdx.x, n16 = (int)gridDim.x & ~15;
+    if (b >= n16) return b;
+    const int x = b & 7, s = b >> 3;
+    return 2 * (8 * (s >> 1) + x) + (s & 1);
+}
+
 template <int TW, int TH, int PXW, int PXH>
 __global__ __launch_bounds__(TW* TH / (PXW * PXH)) void k_render_bwd(RenderArgs a) {
     __shared__ SmemBwd<TW, TH, PXW, PXH> sm;
-    bwd_tile<TW, TH, PXW, PXH>(sm, a, tile_of_block(a));
+    bwd_tile<TW, TH, PXW, PXH>(sm, a, bwd_tile_of_block(a));
 }
 
 // L1 loss and its gradient: grid-stride over the elements, one atomic per workgroup for
