@@ -150,8 +150,9 @@ def main():
     one_cluster = torch.zeros(1, dtype=torch.int32, device=dev)
     from paper_2403_13806_amd.train import zero_grads
     gbuf = zero_grads(g)
+    # the reverse call as a training step makes it: every gradient written (no clearing before it)
     gg = L.gs_gaussians_grad(_ptr(gbuf.mean), _ptr(gbuf.scale), _ptr(gbuf.quat), _ptr(gbuf.opacity), _ptr(gbuf.sh),
-                             g.n, g.sh_degree)
+                             g.n, g.sh_degree, 1)
     dl_buf = torch.full((3 * rs[0].views.n_pixels,), 1e-6, dtype=torch.float32, device=dev)
     reps = max(3, K // 8)
     for r, cam0 in zip(rs, cams):
@@ -505,7 +506,7 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W, tune=True):
     def step():
         rgb = r.forward()
         gs.l1_loss_grad(rgb[:tgt.numel()], tgt, dl, loss)
-        r.backward(dl, grad)
+        r.backward(dl, grad, overwrite=True)
 
     for _ in range(W):
         step()
@@ -532,10 +533,11 @@ def fwd_bwd_and_batched(torch, gs, scenes, P, dev, g1m, sc1m, K, W, tune=True):
         singles.append((rv, tv, torch.empty_like(tv)))
 
     def plain():
-        for rv, tv, dv in singles:
+        # the first view writes the gradients, the others add into them
+        for v, (rv, tv, dv) in enumerate(singles):
             rgb = rv.forward()
             gs.l1_loss_grad(rgb[:tv.numel()], tv, dv, lb)
-            rv.backward(dv, gradb)
+            rv.backward(dv, gradb, overwrite=v == 0)
 
     kk = max(3, K // 8)
     for _ in range(2):

@@ -108,7 +108,10 @@ typedef struct gs_gaussians {
     int32_t sh_degree; /* 0..3 */
 } gs_gaussians;
 
-/* Gradient buffers, same layout as gs_gaussians; the library adds into them. */
+/* Gradient buffers, same layout as gs_gaussians.
+ *   overwrite  0: gs_render_bwd adds into the buffers (+=), touching only the Gaussians a
+ *              pair contributes to; 1: it writes every entry of every buffer (=), zeros where
+ *              nothing contributes, so the buffers need no clearing and are not read. */
 typedef struct gs_gaussians_grad {
     float* mean;
     float* scale;
@@ -117,6 +120,7 @@ typedef struct gs_gaussians_grad {
     float* sh;
     int64_t n;
     int32_t sh_degree;
+    int32_t overwrite;
 } gs_gaussians_grad;
 
 /* Projected Gaussian, 64 bytes, one per (view, Gaussian): everything a compositing
@@ -282,13 +286,15 @@ gs_status gs_ssim_loss_grad(const float* img, const float* target, int32_t n_pla
 /* Reverse mode of the render (the optimisation of the point representation phi, Sec. 3.2:
  * the Gaussians' positions, scales, rotations, opacities and SH coefficients are fitted by
  * gradient descent through the compositing of eq. render-gs). Given dL/d(rgb) (layout of rgb)
- * it adds dL/d(parameters) into grad (+=). Reverse traversal per pixel from n_last, the
- * transmittance before each entry recovered from t_final by division; every pair's nine 2D
- * partial sums (u, v, conic, opacity, colour) go to the pair's own slot (no atomics), and each
- * Gaussian's slots are summed in a fixed order, so the gradients repeat bit for bit from run
- * to run. proj must come from gs_preprocess with want_color = 1 and no subset; bins from
- * gs_bin_sort with entry_offset set; ws as for gs_bin_sort (gs_workspace_bytes with the
- * bins' capacity). After a pair overflow (bins->overflow != 0) nothing is added. */
+ * it adds dL/d(parameters) into grad, or writes them (grad->overwrite). Reverse traversal per
+ * pixel from n_last, the transmittance before each entry recovered from t_final by division;
+ * every pair's nine 2D partial sums (u, v, conic, opacity, colour) go to the pair's own slot
+ * (no atomics), and each Gaussian's slots are summed in a fixed order, so the gradients
+ * repeat bit for bit from run to run. proj must come from gs_preprocess with want_color = 1
+ * and no subset; bins from gs_bin_sort with entry_offset set; ws as for gs_bin_sort
+ * (gs_workspace_bytes with the bins' capacity). With grad->overwrite = 0 it adds (+=) and
+ * nothing is added after a pair overflow (bins->overflow != 0); with grad->overwrite = 1 it
+ * writes (=) every gradient, all zeros after a pair overflow. */
 gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_projected* proj,
                         const gs_bins* bins, const gs_params* p, const float* t_final, const uint32_t* n_last,
                         const float* dl_drgb, gs_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream);

@@ -43,7 +43,7 @@ class gs_gaussians(ctypes.Structure):
 
 class gs_gaussians_grad(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("scale", c_void_p), ("quat", c_void_p), ("opacity", c_void_p),
-                ("sh", c_void_p), ("n", i64), ("sh_degree", i32)]
+                ("sh", c_void_p), ("n", i64), ("sh_degree", i32), ("overwrite", i32)]
 
 
 class gs_views(ctypes.Structure):

@@ -299,6 +299,8 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_p
         return st;
     if (!grad || grad->n != g->n || grad->sh_degree != g->sh_degree)
         return set_error(GS_ERR_INVALID_ARG, "grad buffers missing or shaped unlike the Gaussians");
+    if (grad->overwrite != 0 && grad->overwrite != 1)
+        return set_error(GS_ERR_INVALID_ARG, "grad->overwrite must be 0 or 1 (got %d)", grad->overwrite);
     if (g->n > 0 && (!grad->mean || !grad->scale || !grad->quat || !grad->opacity || !grad->sh || !g->sh))
         return set_error(GS_ERR_INVALID_ARG, "gradient or SH pointer is NULL");
     if (proj->n != g->n)

@@ -38,7 +38,7 @@ __device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // inclusive prefix sum over the wave (u32)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {

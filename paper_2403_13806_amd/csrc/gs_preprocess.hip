@@ -342,7 +342,10 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 // in a fixed order by the reverse traversal's last step). One thread per Gaussian, looping
 // over the views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
 // This kernel covers position (through u, v and J), scale, rotation and opacity; the
-// colour part follows in k_preprocess_bwd_sh.
+// colour part follows in k_preprocess_bwd_sh. Adding reads and writes only the gradients of
+// Gaussians some pair contributes to; overwriting writes every one and reads none, which halves
+// the gradient traffic where (as in random storage order) the visible Gaussians are spread over
+// every cache line anyway.
 // ---------------------------------------------------------------------------------------
 struct PreBwdArgs {
     const float* mean;
@@ -357,7 +360,8 @@ struct PreBwdArgs {
     gs_params p;
     const uint32_t* count;   // [V][n]
     const float* g2;         // [9][V*n], read where count > 0
-    const uint32_t* overflow;  // nothing is added after a pair overflow
+    const uint32_t* overflow;  // nothing is added after a pair overflow (zeros written when overwriting)
+    int overwrite;             // 1: write every gradient (=) instead of adding (+=)
     float* gmean;
     float* gscale;
     float* gquat;
@@ -365,40 +369,91 @@ struct PreBwdArgs {
     float* gsh;
 };
 
+// A wave-uniform row pointer held in scalar registers, in the global address space, and the
+// element at byte offset lb (a 32-bit lane offset) of it: each access is a scalar base plus a
+// vector offset, with no 64-bit address arithmetic per lane.
+#define GS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GS_GLOBAL T* uniform_ptr(T* p) {
+    const uint64_t x = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return reinterpret_cast<GS_GLOBAL T*>(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ GS_GLOBAL T& lane(GS_GLOBAL T* row, uint32_t lb) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    return *(GS_GLOBAL T*)((GS_GLOBAL const char*)row + lb);
+}
+
+// the eleven parameters of the lane's Gaussian from rows at scalar addresses (i0: the wave's
+// first Gaussian, lb: the lane's byte offset)
+__device__ __forceinline__ Geom load_geom_rows(const PreBwdArgs& a, int64_t i0, uint32_t lb) {
+    Geom g;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        g.p[k] = lane(uniform_ptr(a.mean + k * a.n + i0), lb);
+        g.s[k] = lane(uniform_ptr(a.scale + k * a.n + i0), lb);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g.q[k] = lane(uniform_ptr(a.quat + k * a.n + i0), lb);
+    g.o = lane(uniform_ptr(a.opac + i0), lb);
+    return g;
+}
+
 __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
-    if (i >= a.n || *a.overflow) return;
-    const int64_t VN = (int64_t)a.n_views * a.n;
+    // rows of the wave's 64 Gaussians at scalar addresses, the lane's element by its offset
+    const int64_t i0 = (int64_t)blockIdx.x * 128 + 64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lb = (threadIdx.x & 63u) * 4u;
+    const int64_t n = a.n;
+    if (i0 + (lb >> 2) >= n) return;
+    auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
+    const bool acc = !a.overwrite;
+    float old[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) old[k] = 0.f;
+    if (*a.overflow) {
+        if (acc) return;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) grow(a.gmean, k) = 0.f, grow(a.gscale, k) = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) grow(a.gquat, k) = 0.f;
+        grow(a.gopac, 0) = 0.f;
+        return;
+    }
+    const int64_t VN = (int64_t)a.n_views * n;
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
     bool any = false;
     // where the first view composited this Gaussian, its 2D gradients, its parameters and the
     // gradients accumulated so far are requested together, in one round of loads
-    const uint32_t cnt0 = a.count[i];
+    const uint32_t cnt0 = lane(uniform_ptr(a.count + i0), lb);
     const bool pre = cnt0 != 0;
-    float g20[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, old[11];
+    float g20[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     Geom gm{};
     if (pre) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g20[k] = a.g2[k * VN + i];
-        gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n, i);
+        for (int k = 0; k < 6; ++k) g20[k] = lane(uniform_ptr(a.g2 + k * VN + i0), lb);
+        gm = load_geom_rows(a, i0, lb);
+        if (acc) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) old[k] = a.gmean[k * a.n + i], old[3 + k] = a.gscale[k * a.n + i];
+            for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) old[6 + k] = a.gquat[k * a.n + i];
-        old[10] = a.gopac[i];
+            for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
+            old[10] = grow(a.gopac, 0);
+        }
     }
     bool have_geom = pre;
     for (int v = 0; v < a.n_views; ++v) {
-        const int64_t o = (int64_t)v * a.n + i;
-        if ((v == 0 ? cnt0 : a.count[o]) == 0) continue;
+        const int64_t o = (int64_t)v * n + i0;
+        if ((v == 0 ? cnt0 : lane(uniform_ptr(a.count + o), lb)) == 0) continue;
         float g6[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g6[k] = v == 0 ? g20[k] : a.g2[k * VN + o];
+        for (int k = 0; k < 6; ++k) g6[k] = v == 0 ? g20[k] : lane(uniform_ptr(a.g2 + k * VN + o), lb);
         const float gu = g6[0], gv = g6[1], gA = g6[2], gB = g6[3], gC = g6[4], gO = g6[5];
         if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) continue;
         any = true;
         if (!have_geom) {
-            gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n, i);
+            gm = load_geom_rows(a, i0, lb);
             have_geom = true;
         }
         const gs_camera cam = a.cams[v];
@@ -481,68 +536,88 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         gq[2] += (gy - y * dot) * iqn;
         gq[3] += (gz - zq * dot) * iqn;
     }
-    if (!any) return;
-    if (!pre) {
+    if (!any && acc) return;
+    if (!pre && acc) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) old[k] = a.gmean[k * a.n + i], old[3 + k] = a.gscale[k * a.n + i];
+        for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) old[6 + k] = a.gquat[k * a.n + i];
-        old[10] = a.gopac[i];
+        for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
+        old[10] = grow(a.gopac, 0);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        a.gmean[k * a.n + i] = old[k] + (float)gp[k];
-        a.gscale[k * a.n + i] = old[3 + k] + (float)gs[k];
+        grow(a.gmean, k) = old[k] + (float)gp[k];
+        grow(a.gscale, k) = old[3 + k] + (float)gs[k];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.gquat[k * a.n + i] = old[6 + k] + (float)gq[k];
-    a.gopac[i] = old[10] + (float)go;
+    for (int k = 0; k < 4; ++k) grow(a.gquat, k) = old[6 + k] + (float)gq[k];
+    grow(a.gopac, 0) = old[10] + (float)go;
 }
 
 // Colour part of the reverse mode: SH coefficient gradients and the mean gradient through
 // the view direction. Split from the geometric part so that neither kernel carries the
-// other's registers. Three waves per workgroup, one per colour channel, each holding that
-// channel's coefficients of the same 64 Gaussians (16 values at SH-3 instead of 48); the
-// channels' mean-gradient parts are added through LDS at the end.
-template <int DEG>
-__global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
+// other's registers. A workgroup takes 64 G Gaussians with 3 G waves: wave (c, s) holds colour
+// channel c's coefficients of Gaussians [64 s, 64 s + 64) of them (16 values at SH-3 instead of
+// 48), so the G waves of a channel read and write 256 G contiguous bytes of each coefficient
+// plane together (G = 4 measured fastest for one view, G = 1 for several, where each lane
+// walks every view). The channels' mean-gradient parts are added through LDS at the end, onto
+// what the geometric part left (written or added).
+template <int DEG, int G>
+__global__ __launch_bounds__(192 * G) void k_preprocess_bwd_sh(PreBwdArgs a) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
-    __shared__ float s_gp[3][3][64];
-    __shared__ uint32_t s_any[3][64];
-    const int c = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 64 + l;
-    if (*a.overflow) return;  // the same for the whole workgroup
-    const bool valid = i < a.n;
-    const int64_t VN = (int64_t)a.n_views * a.n;
+    __shared__ float s_gp[3][3][64 * G];
+    __shared__ uint32_t s_any[3][64 * G];
+    // channel and sub-block are wave-uniform, so every plane's row of a wave's 64 Gaussians is a
+    // scalar address and the lanes index it with their lane number
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int c = wv / G, sub = wv % G;
+    const uint32_t l = threadIdx.x & 63u;
+    const int64_t i0 = (int64_t)blockIdx.x * (64 * G) + sub * 64, i = i0 + l;
+    const int ls = sub * 64 + (int)l;  // the Gaussian within the workgroup
+    const bool acc = !a.overwrite;
+    const int64_t n = a.n;
+    auto row = [&](float* base, int k) { return uniform_ptr(base + (int64_t)(k * 3 + c) * n + i0); };
+    auto crow = [&](const float* base, int k) { return uniform_ptr(base + (int64_t)(k * 3 + c) * n + i0); };
+    const uint32_t lb = l * 4u;  // the lane's byte offset in a row
+    if (*a.overflow) {  // the same for the whole workgroup
+        if (!acc && i < n) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) lane(row(a.gsh, k), lb) = 0.f;
+        }
+        return;
+    }
+    const bool valid = i < n;
+    const int64_t VN = (int64_t)a.n_views * n;
     float shv[NB], gsh[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        shv[k] = valid ? a.sh[(int64_t)(k * 3 + c) * a.n + i] : 0.f;
+        shv[k] = valid ? lane(crow(a.sh, k), lb) : 0.f;
         gsh[k] = 0.f;
     }
     float px = 0.f, py = 0.f, pz = 0.f;
     // the first view's count and colour gradient are requested together with the parameters
     uint32_t cnt0 = 0;
     float gc0 = 0.f;
+    const int64_t g2o = (6 + c) * VN + i0;  // colour gradient of channel c, view 0
     if (valid) {
-        px = a.mean[i];
-        py = a.mean[a.n + i];
-        pz = a.mean[2 * a.n + i];
-        cnt0 = a.count[i];
-        gc0 = a.g2[(6 + c) * VN + i];
+        px = lane(uniform_ptr(a.mean + i0), lb);
+        py = lane(uniform_ptr(a.mean + n + i0), lb);
+        pz = lane(uniform_ptr(a.mean + 2 * n + i0), lb);
+        cnt0 = lane(uniform_ptr(a.count + i0), lb);
+        gc0 = lane(uniform_ptr(a.g2 + g2o), lb);
     }
     // the accumulated SH gradient is read early where the first view composited this Gaussian
     float old[NB];
-    const bool pre = valid && cnt0 != 0 && gc0 != 0.f;
+    const bool pre = acc && valid && cnt0 != 0 && gc0 != 0.f;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) old[k] = pre ? a.gsh[(int64_t)(k * 3 + c) * a.n + i] : 0.f;
+    for (int k = 0; k < NB; ++k) old[k] = pre ? lane(row(a.gsh, k), lb) : 0.f;
     double gp[3] = {0, 0, 0};
     bool any = false;
     for (int v = 0; valid && v < a.n_views; ++v) {
-        const int64_t o = (int64_t)v * a.n + i;
-        const uint32_t cnt = v == 0 ? cnt0 : a.count[o];
+        const int64_t o = (int64_t)v * n;
+        const uint32_t cnt = v == 0 ? cnt0 : lane(uniform_ptr(a.count + o + i0), lb);
         if (cnt == 0) continue;
-        const float gc = v == 0 ? gc0 : a.g2[(6 + c) * VN + o];
+        const float gc = v == 0 ? gc0 : lane(uniform_ptr(a.g2 + g2o + o), lb);
         if (gc == 0.f) continue;
         any = true;
         const gs_camera cam = a.cams[v];
@@ -551,32 +626,35 @@ __global__ __launch_bounds__(192) void k_preprocess_bwd_sh(PreBwdArgs a) {
         view_dir(cam, px, py, pz, d, len);
         float Y[16];
         sh_basis(DEG, d[0], d[1], d[2], Y);
-        float acc = 0.f;
+        float accv = 0.f;
 #pragma unroll
-        for (int k = 0; k < NB; ++k) acc += shv[k] * Y[k];
-        if (!(acc + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
+        for (int k = 0; k < NB; ++k) accv += shv[k] * Y[k];
+        if (!(accv + 0.5f > 0.f)) continue;  // colour clamped at 0: no gradient
 #pragma unroll
         for (int k = 0; k < NB; ++k) gsh[k] += gc * Y[k];
         float gd[3];
         sh_wgrad(DEG, d[0], d[1], d[2], shv, gc, gd);
+        // d(d)/d(mean) = (I - d d^T) / len
         const double dd = (double)d[0] * gd[0] + (double)d[1] * gd[1] + (double)d[2] * gd[2];
+        const double il = 1.0 / len;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gp[k] += ((double)gd[k] - (double)d[k] * dd) / len;
+        for (int k = 0; k < 3; ++k) gp[k] += ((double)gd[k] - (double)d[k] * dd) * il;
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s_gp[c][k][l] = (float)gp[k];
-    s_any[c][l] = any ? 1u : 0u;
-    if (any) {
+    for (int k = 0; k < 3; ++k) s_gp[c][k][ls] = (float)gp[k];
+    s_any[c][ls] = any ? 1u : 0u;
+    if (valid && (any || !acc)) {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            const int64_t q = (int64_t)(k * 3 + c) * a.n + i;
-            a.gsh[q] = (pre ? old[k] : a.gsh[q]) + gsh[k];
+            GS_GLOBAL float& q = lane(row(a.gsh, k), lb);
+            q = (pre || !acc ? old[k] : q) + gsh[k];
         }
     }
     __syncthreads();
-    if (c == 0 && valid && (s_any[0][l] | s_any[1][l] | s_any[2][l])) {
+    if (c == 0 && valid && (s_any[0][ls] | s_any[1][ls] | s_any[2][ls])) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a.gmean[k * a.n + i] += s_gp[0][k][l] + s_gp[1][k][l] + s_gp[2][k][l];
+        for (int k = 0; k < 3; ++k)
+            lane(uniform_ptr(a.gmean + k * n + i0), lb) += s_gp[0][k][ls] + s_gp[1][k][ls] + s_gp[2][k][ls];
     }
 }
 
@@ -620,6 +698,14 @@ gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const 
     return check_launch("preprocess");
 }
 
+template <int DEG>
+static void launch_bwd_sh(bool one_view, int64_t n, hipStream_t stream, const PreBwdArgs& a) {
+    if (one_view)
+        hipLaunchKernelGGL((k_preprocess_bwd_sh<DEG, 4>), dim3((unsigned)((n + 255) / 256)), dim3(768), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_preprocess_bwd_sh<DEG, 1>), dim3((unsigned)((n + 63) / 64)), dim3(192), 0, stream, a);
+}
+
 gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, const gs_params* p,
                                 const gs_projected* proj, const gs_bins* bins, const float* g2,
                                 gs_gaussians_grad* grad, hipStream_t stream) {
@@ -638,6 +724,7 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.count = proj->count;
     a.g2 = g2;
     a.overflow = bins->overflow;
+    a.overwrite = grad->overwrite;
     a.gmean = grad->mean;
     a.gscale = grad->scale;
     a.gquat = grad->quat;
@@ -645,13 +732,12 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gsh = grad->sh;
     const dim3 grid((unsigned)((g->n + 127) / 128));
     hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(128), 0, stream, a);
-    // colour part: 64 Gaussians x 3 channels per workgroup
-    const dim3 gsh((unsigned)((g->n + 63) / 64));
+    // colour part: 64 G Gaussians x 3 channels per workgroup
     switch (g->sh_degree) {
-        case 0: hipLaunchKernelGGL((k_preprocess_bwd_sh<0>), gsh, dim3(192), 0, stream, a); break;
-        case 1: hipLaunchKernelGGL((k_preprocess_bwd_sh<1>), gsh, dim3(192), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL((k_preprocess_bwd_sh<2>), gsh, dim3(192), 0, stream, a); break;
-        default: hipLaunchKernelGGL((k_preprocess_bwd_sh<3>), gsh, dim3(192), 0, stream, a); break;
+        case 0: launch_bwd_sh<0>(views->n_views == 1, g->n, stream, a); break;
+        case 1: launch_bwd_sh<1>(views->n_views == 1, g->n, stream, a); break;
+        case 2: launch_bwd_sh<2>(views->n_views == 1, g->n, stream, a); break;
+        default: launch_bwd_sh<3>(views->n_views == 1, g->n, stream, a); break;
     }
     return check_launch("preprocess_bwd");
 }

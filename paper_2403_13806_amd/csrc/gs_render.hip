@@ -485,13 +485,15 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
     if (lmax > start) atomicMax(&sm.top, lmax);
     __syncthreads();
     const uint32_t top = sm.top;
-    // the quarter's last composited entry (max over its pixels): entries behind it are skipped
+    // each quarter's last composited entry (max over its pixels): entries behind it are skipped
     int ql = (int)lmax;
     ql = max(ql, dpp<0xB1>(ql));
     ql = max(ql, dpp<0x4E>(ql));
     ql = max(ql, dpp<0x141>(ql));
     ql = max(ql, dpp<0x140>(ql));
-    const uint32_t qlast = (uint32_t)ql;
+    int64_t qlast[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qlast[k] = (int64_t)(uint32_t)__builtin_amdgcn_readlane(ql, 16 * k);
     const int64_t vbase = (int64_t)view * a.n;
     const double ox = (double)(tx * TW) + 0.5, oy = (double)(ty * TH) + 0.5;
     float* accw = sm.acc + w * (BB * 9);
@@ -505,16 +507,27 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
 #pragma unroll 1
         for (int c = BB / 64 - 1; c >= 0; --c) {
             // each quarter (one row of 16 lanes) walks the entries that meet its pixels
+            // the four quarters' masks are wave-uniform: their bit walks run on the scalar unit
             const uint32_t hq = (uint32_t)(sm.hitq[c * 64 + l] >> (4 * w));
-            const uint64_t m0 = ballot(hq & 1u), m1 = ballot((hq >> 1) & 1u), m2 = ballot((hq >> 2) & 1u),
-                           m3 = ballot((hq >> 3) & 1u);
-            uint64_t m = qd == 0 ? m0 : qd == 1 ? m1 : qd == 2 ? m2 : m3;  // the same in a quarter
-            const int64_t lim = (int64_t)qlast - (int64_t)(lo + c * 64);
-            m = lim <= 0 ? 0ull : (lim >= 64 ? m : m & ((1ull << lim) - 1ull));
-            while (ballot(m != 0)) {
-                const bool act = m != 0;
-                const int b = act ? 63 - (int)__builtin_clzll(m) : 0;
-                m = act ? m & ~(1ull << b) : 0ull;
+            uint64_t mq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t m = ballot((hq >> k) & 1u);
+                const int64_t lim = qlast[k] - (int64_t)(lo + c * 64);
+                mq[k] = lim <= 0 ? 0ull : (lim >= 64 ? m : m & ((1ull << lim) - 1ull));
+            }
+            while (mq[0] | mq[1] | mq[2] | mq[3]) {
+                // byte k of pk: quarter k's record (highest set bit), or 128 when it has none
+                uint32_t pk = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bk = mq[k] ? 63u - (uint32_t)__builtin_clzll(mq[k]) : 128u;
+                    mq[k] &= ~(1ull << (bk & 63u));  // (no change when empty)
+                    pk |= bk << (8 * k);
+                }
+                const uint32_t braw = (pk >> (8 * qd)) & 255u;
+                const bool act = braw < 64u;
+                const int b = (int)(braw & 63u);
                 const int j = c * 64 + b;
                 const uint32_t pos = lo + j;
                 // whole record up front; branch-free body apart from the wave-uniform skip
@@ -537,6 +550,8 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                 for (int p = 0; p < P; ++p) {
                     const float G = falloff(q[p]);
                     const float og = s.opacity * G;
+                    // where p does not contribute al = 0 and wt = 0: S and the colour sums stay as
+                    // they are without a select (inputs are finite)
                     const float al = con[p] ? clamp_alpha(og, amax) : 0.f;
                     const float r = __builtin_amdgcn_rcpf(1.f - al);
                     T[p] = con[p] ? T[p] * r : T[p];
@@ -549,19 +564,21 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                         Sc[p][cc] = fmaf(wt, s.rgb[cc], Sc[p][cc]);  // wt = 0 where p does not contribute
                     // dq dx, dq dy (turned into the u, v gradients with the conic once per record
                     // in the flush), a b c o r g b; the geometric terms vanish where alpha is clamped
+                    // (the constant factors of dq/dalpha, -1/2, and of the b term, 2, are applied
+                    // to the sums in the flush: scaling by powers of two is exact)
                     const bool free_a = con[p] & (og < amax);
                     const float dx = (float)(xc[p % PXW] - s.u), dy = (float)(yc[p / PXW] - s.v);
-                    const float dq = free_a ? -0.5f * al * dA : 0.f;
+                    const float dq = free_a ? al * dA : 0.f;
                     const float a0 = dq * dx, a1 = dq * dy;
                     v[0] += a0;
                     v[1] += a1;
                     v[2] += a0 * dx;
-                    v[3] += 2.f * a0 * dy;
+                    v[3] += a0 * dy;
                     v[4] += a1 * dy;
                     v[5] += free_a ? dA * G : 0.f;
-                    v[6] += con[p] ? dC[p][0] * wt : 0.f;
-                    v[7] += con[p] ? dC[p][1] * wt : 0.f;
-                    v[8] += con[p] ? dC[p][2] * wt : 0.f;
+                    v[6] += dC[p][0] * wt;
+                    v[7] += dC[p][1] * wt;
+                    v[8] += dC[p][2] * wt;
                 }
                 // per-quarter sums, one field per lane, added into this wave's sums of that
                 // entry (lanes of one instruction that meet at one address are applied in a
@@ -594,9 +611,15 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
             }
             const uint32_t id = sm.gid[t];
             if ((uint32_t)t < cnt && id != 0xffffffffu) {
+                // the sums are of al dA times (dx, dy, dx^2, dx dy, dy^2); with dq = -al dA / 2,
+                // dL/du = -2 (a Sx + b Sy) and dL/d(a, b, c) = (Sxx, 2 Sxy, Syy) over sums of dq
+                // are a sx + b sy and (-sxx / 2, -sxy, -syy / 2) over these
                 const float sx = f9[0], sy = f9[1];
-                f9[0] = -2.f * ((float)sm.rec[t].ca * sx + (float)sm.rec[t].cb * sy);
-                f9[1] = -2.f * ((float)sm.rec[t].cb * sx + (float)sm.rec[t].cc * sy);
+                f9[0] = (float)sm.rec[t].ca * sx + (float)sm.rec[t].cb * sy;
+                f9[1] = (float)sm.rec[t].cb * sx + (float)sm.rec[t].cc * sy;
+                f9[2] = -0.5f * f9[2];
+                f9[3] = -f9[3];
+                f9[4] = -0.5f * f9[4];
                 const uint64_t slot = pair_slot(a, vbase + id, tx, ty);
                 if (slot < a.capacity) {
                     float* dst = a.slots + slot * 9;

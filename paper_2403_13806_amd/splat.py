@@ -515,20 +515,24 @@ def bits_to_list(bits_row: torch.Tensor, n: int) -> torch.Tensor:
 
 
 def render_bwd(g: Gaussians, views: ViewBatch, proj: Projected, bins: Bins, t_final, n_last, dl_drgb, params=None,
-               grad: Optional[Gaussians] = None, ws: Optional[torch.Tensor] = None) -> Gaussians:
-    """Add dL/dparams (given dL/drgb in the global image layout) into grad (zeros if None)."""
+               grad: Optional[Gaussians] = None, ws: Optional[torch.Tensor] = None,
+               overwrite: Optional[bool] = None) -> Gaussians:
+    """dL/dparams (given dL/drgb in the global image layout): added into grad, or written into it
+    with overwrite=True (every entry, no clearing needed). With grad None, new buffers are
+    written (overwrite is then always on)."""
     lib = L.load()
     dev = views.device
     if grad is None:
-        grad = Gaussians(torch.zeros_like(g.mean), torch.zeros_like(g.scale), torch.zeros_like(g.quat),
-                         torch.zeros_like(g.opacity), torch.zeros_like(g.sh), g.sh_degree)
+        grad = Gaussians(torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
+                         torch.empty_like(g.opacity), torch.empty_like(g.sh), g.sh_degree)
+        overwrite = True
     if bins.entry_offset is None:
         raise ValueError("render_bwd needs bins made with backward=True (the pairs' emission slots)")
     need = workspace_bytes(g.n, views.n_views, bins.capacity, views.n_tiles)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity), _ptr(grad.sh),
-                             g.n, g.sh_degree)
+                             g.n, g.sh_degree, int(bool(overwrite)))
     p = make_params(params)
     dl = dl_drgb.contiguous()
     L.check(lib.gs_render_bwd(ctypes.byref(g.struct()), ctypes.byref(views.struct()), ctypes.byref(proj.struct()),
@@ -678,12 +682,14 @@ class Renderer:
                                        ctypes.byref(self.p), _ptr(h), s))
         return h
 
-    def backward(self, dl_drgb: torch.Tensor, grad: Gaussians):
+    def backward(self, dl_drgb: torch.Tensor, grad: Gaussians, overwrite: bool = False):
+        """dL/dparams of the last forward(): added into grad, or written into every entry of it
+        with overwrite=True (then grad needs no clearing)."""
         if not self.backward_ok:
             raise ValueError("this Renderer was built without the backward (a subset, or backward=False)")
         s = _stream(self.views.device)
         gg = L.gs_gaussians_grad(_ptr(grad.mean), _ptr(grad.scale), _ptr(grad.quat), _ptr(grad.opacity),
-                                 _ptr(grad.sh), self.g.n, self.g.sh_degree)
+                                 _ptr(grad.sh), self.g.n, self.g.sh_degree, int(bool(overwrite)))
         L.check(L.load().gs_render_bwd(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self._sp),
                                        ctypes.byref(self._sb), ctypes.byref(self.p), _ptr(self.t_final),
                                        _ptr(self.n_last), _ptr(dl_drgb), ctypes.byref(gg), _ptr(self.ws),

@@ -87,9 +87,9 @@ class FwdBwdStep:
             self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
     def enqueue(self):
-        """Enqueue one step on the current stream (no allocation, no host synchronisation)."""
-        for t in (self.grad.mean, self.grad.scale, self.grad.quat, self.grad.opacity, self.grad.sh, self.loss):
-            t.zero_()
+        """Enqueue one step on the current stream (no allocation, no host synchronisation). The
+        reverse call writes every gradient, so the gradient buffers are not cleared."""
+        self.loss.zero_()
         rgb = self.r.forward()
         if self.loss_kind == "l1":
             l1_loss_grad(rgb[:self._npx3], self.target, self.dl, self.loss)
@@ -97,7 +97,7 @@ class FwdBwdStep:
             for a, b, shape in self._planes:
                 ssim_loss_grad(rgb[a:b].view(shape), self.target[a:b].view(shape), self.dl[a:b].view(shape),
                                self.loss, SSIM_LAMBDA, self._npx3, self.ws)
-        self.r.backward(self.dl, self.grad)
+        self.r.backward(self.dl, self.grad, overwrite=True)
 
     def capture(self, warmup: int = 2):
         s = torch.cuda.Stream(device=self.views.device)
@@ -309,9 +309,9 @@ class Trainer:
         shape = self.dl.shape
         ssim_loss_grad(rgb[:self.dl.numel()].view(shape), self.targets[i], self.dl, self.loss, self.cfg.lam, None,
                        self.ws_loss)
-        self.r.backward(self.dl.view(-1), self.grad)
+        self.r.backward(self.dl.view(-1), self.grad, overwrite=True)
         self.it += 1
-        adam_step(self.groups(), self.it, self.cfg.betas, self.cfg.eps, zero_grad=True)
+        adam_step(self.groups(), self.it, self.cfg.betas, self.cfg.eps, zero_grad=False)
         if self.it in self.cfg.prune_steps:
             self.prune()
         elif self.cfg.check_every > 0 and self.it % self.cfg.check_every == 0:

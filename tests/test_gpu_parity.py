@@ -370,8 +370,23 @@ def test_degenerate_inputs():
     torch.cuda.synchronize()
     assert int(bins.overflow.item()) == 1 and int(bins.n_pairs.item()) > 16
     assert torch.all(bins.keys[16:] == 7) and torch.all(bins.vals[16:] == 7)
-    rgb, t, _ = gs.render_fwd(proj, views, bins, P)
+    rgb, t, last = gs.render_fwd(proj, views, bins, P)
     assert torch.all(t == 1)  # ranges stay empty after an overflow
+    # the reverse call after an overflow: adding leaves the buffers alone, writing leaves zeros
+    from paper_2403_13806_amd.train import zero_grads
+    bb = gs.Bins(4096, views.n_tiles, DEV, entries=proj.n)
+    bb.capacity = 16
+    gs.bin_sort(proj, views, bins=bb, grow=False)
+    dl = torch.ones(3 * views.n_pixels, dtype=torch.float32, device=DEV)
+    for overwrite in (False, True):
+        gr = zero_grads(g2)
+        for x in (gr.mean, gr.scale, gr.quat, gr.opacity, gr.sh):
+            x.fill_(3.0)
+        gs.render_bwd(g2, views, proj, bb, t, last, dl, P, grad=gr, overwrite=overwrite)
+        torch.cuda.synchronize()
+        assert int(bb.overflow.item()) == 1
+        for x in (gr.mean, gr.scale, gr.quat, gr.opacity, gr.sh):
+            assert torch.all(x == (0.0 if overwrite else 3.0)), overwrite
     # the overflow word is cleared by the next frame, the sticky word keeps it
     assert int(bins.overflow_sticky.item()) == 1
     proj0 = gs.preprocess(gs.Gaussians.from_scene(sc2.subset(np.arange(1)), DEV), views, P)
@@ -443,6 +458,21 @@ def test_backward_bitwise_repeatable():
         for other in grads[1:]:
             for a, b in zip(grads[0], other):
                 assert torch.equal(a, b)
+        # writing (overwrite) into buffers of NaN gives what adding into zeros gives, bit for bit
+        gw = zero_grads(g)
+        for t in (gw.mean, gw.scale, gw.quat, gw.opacity, gw.sh):
+            t.fill_(float("nan"))
+        r.backward(w, gw, overwrite=True)
+        torch.cuda.synchronize()
+        for a, b in zip(grads[0], (gw.mean, gw.scale, gw.quat, gw.opacity, gw.sh)):
+            assert torch.equal(a, b)
+        # adding a second time doubles the single-sum groups exactly (x + x)
+        gr = zero_grads(g)
+        r.backward(w, gr)
+        r.backward(w, gr)
+        torch.cuda.synchronize()
+        for a, b in zip(grads[0][1:], (gr.scale, gr.quat, gr.opacity, gr.sh)):
+            assert torch.equal(2 * a, b)
 
 
 @pytest.mark.slow

@@ -35,6 +35,7 @@ def test_struct_layout_sizes():
     assert ctypes.sizeof(L.gs_params) == 36
     assert ctypes.sizeof(L.gs_views) == 64
     assert ctypes.sizeof(L.gs_bins) == 72
+    assert ctypes.sizeof(L.gs_gaussians_grad) == 56
 
 
 def test_view_layout():
@@ -116,8 +117,14 @@ def test_argument_errors_are_reported_before_launch():
                              ctypes.c_void_p(16), 11, 3)
     assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
-    # ... and the pairs' emission slots, and a workspace of 36 bytes per pair slot
+    # ... a write mode of 0 (add) or 1 (write)
     gg.n = 10
+    gg.overwrite = 2
+    assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
+    assert b"overwrite" in lib.gs_last_error()
+    gg.overwrite = 1
+    # ... and the pairs' emission slots, and a workspace of 36 bytes per pair slot
     assert lib.gs_render_bwd(R(g), R(v), R(out), R(b), R(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), R(gg), ctypes.c_void_p(16), 1 << 30, None) == L.GS_ERR_INVALID_ARG
     assert b"entry_offset" in lib.gs_last_error()
