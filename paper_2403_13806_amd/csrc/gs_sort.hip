@@ -3,22 +3,26 @@
 //   offsets  exclusive prefix sum of the per-(view, Gaussian) tile counts in two levels:
 //            sums of 256-entry blocks, one workgroup scanning those (it writes the pair
 //            total and the capacity check), and the scan inside each block during emission
-//   emit     load-balanced: the pairs of a wave's 64 Gaussians are contiguous in the
-//            output, so lanes walk that range 64 pairs at a time and find their Gaussian
-//            by a 6-step binary search over the wave's offsets in LDS; each pair is the
-//            global tile id (key) and FP32 depth bits << 32 | Gaussian index (value)
-//   group    onesweep LSD radix sort on the tile id (ceil(tile bits / 8) passes of 8 bits):
-//            one kernel builds the digit histograms of all passes, then one kernel per pass
-//            ranks its 4096 items (8 ballots per wave), resolves the digit offsets of earlier
-//            blocks by decoupled look-back, and scatters through LDS so that global writes
-//            are coalesced runs
+//   walk     load-balanced: the pairs of a wave's 64 Gaussians are numbered in entry order,
+//            lanes take them 64 at a time and find their Gaussian by a 6-step binary search
+//            over the wave's offsets in LDS; each pair is a global tile id and FP32 depth
+//            bits << 32 | Gaussian index
+//   group    at most 4096 tiles: every row of 4096 entries counts its pairs per tile in LDS,
+//            column scans give each row's start inside every tile's range, and a second walk
+//            writes each pair straight into its tile's range (slots from LDS counters).
+//            Beyond: the pairs are written in entry order and grouped by onesweep LSD radix
+//            passes on the tile id (ceil(tile bits / 8) passes of 8 bits: one kernel builds the
+//            digit histograms of all passes, then one kernel per pass ranks its 4096 items
+//            with 8 ballots per wave, resolves the digit offsets of earlier blocks by
+//            decoupled look-back, and scatters through LDS into coalesced runs)
 //   ranges   [start, end) of every tile in the grouped list
-//   sort     one workgroup per tile sorts the tile's list by its unique 64-bit (depth bits,
-//            index) values in LDS with a bitonic network (the result does not depend on the
-//            order the grouping left) and writes the keys (tile << 32 | depth bits) and the
-//            Gaussian indices; lists longer than the small buffer go to a second kernel with a
-//            larger one, which sorts lists longer than that in chunks and merges the chunks
-//            (merge path) through a scratch buffer
+//   sort     one workgroup per tile orders the tile's list by its unique 64-bit (depth bits,
+//            index) values in LDS (radix passes on the depth bits, or a bitonic network when
+//            depths repeat, so the result does not depend on the order the grouping left) and
+//            writes the keys (tile << 32 | depth bits) and the Gaussian indices; lists longer
+//            than the small buffer go to a second kernel with a larger one, which sorts lists
+//            longer than that in chunks and merges the chunks (merge path) through a scratch
+//            buffer
 // Every wait on another block is bounded: a wait that exceeds its spin budget sets bit 1
 // of the overflow word (results invalid) instead of hanging.
 #include <algorithm>
@@ -131,6 +135,7 @@ __device__ uint64_t lookback(const uint64_t* chain, int64_t stride, uint32_t bid
 }
 
 // block-wide exclusive scan of one u32 per thread (256 threads); returns the block total
+template <int NT = BLK>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, uint32_t* wsum) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const uint32_t incl = wave_incl_scan(x);
@@ -138,7 +143,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
     __syncthreads();
     uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < BLK / 64; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
         const uint32_t s = wsum[k];
         pre += (k < w) ? s : 0u;
         tot += s;
@@ -561,60 +566,141 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* n_p
 }
 
 // ---------------------------------------------------------------------------------------
-// Grouping by tile in one stable counting pass, for batches of at most 4096 tiles: the tile
-// histogram of every block of TILE_ITEMS pairs, the exclusive prefix of each tile's counts over
-// the blocks (column scans, which also give every tile's total and so its range), then one
-// scatter pass that ranks each block's pairs by tile (12 ballots per pair, index order kept)
-// and writes them at tile start + earlier blocks' count + rank. No block waits on another.
+// Emission straight into tile buckets, for batches of at most 4096 tiles: the pairs are never
+// written in entry order. Each row of 4096 entries (16 emission blocks of one view) builds its
+// tile histogram in LDS by walking its entries' pairs (k_bucket_count, which also writes the
+// emission blocks' pair sums); column scans give, per tile, the pairs of earlier rows and the
+// tile's total (k_bucket_colscan); then each row walks its pairs again and writes each one at
+// tile start + earlier rows' pairs + a slot taken from an LDS counter of the tile
+// (k_bucket_emit). The order inside a tile's list is then whatever the LDS counters gave; the
+// tile sort orders it by the unique (depth bits, index) values, so the result is deterministic.
 // ---------------------------------------------------------------------------------------
-constexpr int G12 = 4096;           // tiles (digit values)
-constexpr int G12_MAX_ROWS = 2048;  // blocks: the column scan holds 16 columns of every block in LDS
+constexpr int G12 = 4096;           // tiles
+constexpr int G12_MAX_ROWS = 2048;  // rows: the column scan holds 16 columns of every row in LDS
+constexpr int EB_ROW = 4096;        // entries per bucket row (16 emission blocks of 256)
 
-__global__ __launch_bounds__(BLK) void k_g12_hist(const uint32_t* __restrict__ keys, const uint64_t* n_items,
-                                                  uint64_t bound, const uint32_t* overflow,
-                                                  uint32_t* __restrict__ bh) {
-    __shared__ uint32_t h[G12];
-    const int t = threadIdx.x;
-    if (*overflow) return;
-    const uint64_t count = min(*n_items, bound);
-    const uint64_t base = (uint64_t)blockIdx.x * TILE_ITEMS;
-    if (base >= count) return;  // rows past the data are never read
-    for (int i = t; i < G12; i += BLK) h[i] = 0;
-    __syncthreads();
-    // a contiguous run of IPT keys per thread; equal neighbours (pairs of one Gaussian in one
-    // row of tiles) merged into one LDS atomic
-    const uint64_t b0 = base + (uint64_t)t * IPT, b1 = min(b0 + IPT, count);
-    if (b0 < b1) {
-        uint32_t prev = keys[b0] & (G12 - 1), cnt = 1;
-        for (uint64_t i = b0 + 1; i < b1; ++i) {
-            const uint32_t k = keys[i] & (G12 - 1);
-            if (k == prev) {
-                ++cnt;
-            } else {
-                atomicAdd(&h[prev], cnt);
-                prev = k;
-                cnt = 1;
-            }
+// The pairs of a wave's 64 consecutive entries [j0, j0 + 64) of one view: lane e holds entry
+// e's tile count c and rectangle r. Stages the entries' pair offsets (within the 64), rectangles
+// and 1 / width in the wave's LDS slots, then the lanes take the pairs 64 at a time and call
+// f(pair offset g, entry lane L, tile) for each. Returns the 64 entries' pair total.
+struct WaveStage {
+    uint32_t off[64];
+    uint64_t rect[64];
+    double inv[64];
+};
+
+template <class F>
+__device__ __forceinline__ uint32_t walk_pairs(WaveStage& st, uint32_t c, uint64_t r, int last, uint32_t tiles_x,
+                                               uint32_t tbase, F&& f) {
+    const int l = threadIdx.x & 63;
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t total = wave_read(incl, 63);
+    st.off[l] = incl - c;
+    st.rect[l] = r;
+    st.inv[l] = 1.0 / (double)((uint32_t)(r >> 32 & 0xffff) - (uint32_t)(r & 0xffff) + 1u);
+    wave_sync();
+    for (uint32_t g = l; g < total; g += 64) {
+        // largest lane L with off[L] <= g (lanes with no pairs share the next lane's offset)
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (L + step <= last && st.off[L + step] <= g) L += step;
+        const uint64_t rr = st.rect[L];
+        const uint32_t x0 = rr & 0xffff, y0 = (rr >> 16) & 0xffff, x1 = (rr >> 32) & 0xffff;
+        const uint32_t wd = x1 - x0 + 1;
+        const uint32_t k = g - st.off[L];
+        // k / wd through FP64 (exact to within one for k < 2^32), then corrected
+        uint32_t ky = (uint32_t)((double)k * st.inv[L]);
+        uint32_t kx = k - ky * wd;
+        if ((int32_t)kx < 0) {
+            --ky;
+            kx += wd;
+        } else if (kx >= wd) {
+            ++ky;
+            kx -= wd;
         }
-        atomicAdd(&h[prev], cnt);
+        f(g, L, tbase + (y0 + ky) * tiles_x + x0 + kx);
     }
-    __syncthreads();
-    uint32_t* row = bh + (uint64_t)blockIdx.x * G12;
-    for (int i = t; i < G12; i += BLK) row[i] = h[i];
+    wave_sync();  // the slots are rewritten by the next call
+    return total;
 }
 
-// Exclusive prefix over the blocks of every tile's count (in place) and the tile totals.
-// Workgroup g takes the 16 tiles [16 g, 16 g + 16): their counts of every block are read into
-// LDS, each of 16 chunks of blocks summed, the chunk sums scanned, then the prefixes written.
-__global__ __launch_bounds__(BLK) void k_g12_colscan(uint32_t* __restrict__ bh, const uint64_t* n_items,
-                                                     uint64_t bound, const uint32_t* overflow,
-                                                     uint32_t* __restrict__ tot) {
+struct BucketArgs {
+    const uint32_t* count;
+    const uint64_t* rect;
+    const float* depth;
+    const gs_camera* cams;
+    const int32_t* tile_offset;
+    int64_t n;           // entries per view
+    int64_t nbv;         // emission blocks (256 entries) per view
+    int64_t nbr;         // bucket rows (4096 entries) per view
+    int tile_w;
+    int n_tiles;
+    int ncols;           // columns kept per row: n_tiles rounded up to 16
+    uint32_t* bsum;      // [n_views][nbv] pair sums, then (scanned) exclusive pair offsets
+    uint32_t* bh;        // [rows][G12] tile histograms, then exclusive prefixes over rows
+    const uint32_t* tot; // [G12] pairs per tile
+    const uint32_t* overflow;
+    uint64_t* vout;      // FP32 depth bits << 32 | Gaussian index, grouped by tile
+    uint64_t capacity;
+    uint32_t* ranges;    // [n_tiles][2], written by the first row
+    uint32_t* eoff;      // [n_views * n] first pair of each entry, or NULL
+};
+
+constexpr int BK_T = 1024;  // threads of the bucket kernels: one wave per emission block of the row
+
+// It also clears the frame's state first (the job of k_zero4 when there is no pair to bin):
+// no later kernel of the frame runs before it ends.
+__global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear) {
+    __shared__ uint32_t hist[G12];
+    __shared__ WaveStage st[BK_T / 64];
+    {
+        const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+        const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            for (int64_t i = tid; i < clear.n[b]; i += nth) clear.p[b][i] = 0u;
+    }
+    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int i = t; i < a.ncols; i += BK_T) hist[i] = 0u;
+    __syncthreads();
+    const uint32_t* cv = a.count + (int64_t)v * a.n;
+    const uint64_t* rv = a.rect + (int64_t)v * a.n;
+    const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
+    const uint32_t tbase = (uint32_t)a.tile_offset[v];
+    // wave w takes the row's emission block w, 64 entries at a time
+    {
+        const int64_t eb = (int64_t)blockIdx.x * 16 + w;
+        uint32_t bsum = 0;
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j0 = eb * 256 + k * 64;
+            if (j0 >= a.n) break;  // the same for the whole wave
+            const int64_t j = j0 + l;
+            const uint32_t c = j < a.n ? cv[j] : 0u;
+            const uint64_t r = c ? rv[j] : 0ull;
+            const int last = (int)min((int64_t)63, a.n - 1 - j0);
+            bsum += walk_pairs(st[w], c, r, last, tiles_x, tbase,
+                               [&](uint32_t, int, uint32_t tile) {
+                                   if (tile < (uint32_t)a.n_tiles) atomicAdd(&hist[tile], 1u);
+                               });
+        }
+        if (l == 0 && eb * 256 < a.n) a.bsum[(int64_t)v * a.nbv + eb] = bsum;
+    }
+    __syncthreads();
+    uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * G12;
+    for (int i = t; i < a.ncols; i += BK_T) row[i] = hist[i];
+}
+
+// Exclusive prefix over the rows of every tile's count (in place) and the tile totals.
+// Workgroup g takes the 16 tiles [16 g, 16 g + 16): their counts of every row are read into
+// LDS, each of 16 chunks of rows summed, the chunk sums scanned, then the prefixes written.
+__global__ __launch_bounds__(BLK) void k_bucket_colscan(uint32_t* __restrict__ bh, int nrows,
+                                                        const uint32_t* overflow, uint32_t* __restrict__ tot) {
     __shared__ uint32_t sub[G12_MAX_ROWS * 16];
     __shared__ uint32_t csum[16][17];
     if (*overflow) return;
     const int t = threadIdx.x;
-    const uint64_t count = min(*n_items, bound);
-    const int nrows = (int)((count + TILE_ITEMS - 1) / TILE_ITEMS);  // <= G12_MAX_ROWS (host check)
     const int c0 = blockIdx.x * 16;
     for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)];
     __syncthreads();
@@ -644,122 +730,78 @@ __global__ __launch_bounds__(BLK) void k_g12_colscan(uint32_t* __restrict__ bh, 
     for (int i = t; i < nrows * 16; i += BLK) bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)] = sub[i];
 }
 
-// block-wide exclusive scan of the 4096 counts c[] in place (16 consecutive per thread)
+// block-wide exclusive scan of the 4096 counts c[] in place (4096 / NT consecutive per thread)
+template <int NT>
 __device__ __forceinline__ void block_excl_scan_4096(uint32_t* c, uint32_t* wsum) {
+    constexpr int PER = G12 / NT;
     const int t = threadIdx.x;
-    uint32_t v[16], s = 0;
+    uint32_t v[PER], s = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        v[k] = c[t * 16 + k];
+    for (int k = 0; k < PER; ++k) {
+        v[k] = c[t * PER + k];
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan(s, tot, wsum);
+    uint32_t run = block_excl_scan<NT>(s, tot, wsum);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        c[t * 16 + k] = run;
+    for (int k = 0; k < PER; ++k) {
+        c[t * PER + k] = run;
         run += v[k];
     }
     __syncthreads();
 }
 
-struct G12Args {
-    const uint32_t* kin;  // tile of each pair (emission order)
-    const uint64_t* vin;  // FP32 depth bits << 32 | Gaussian index
-    uint64_t* vout;       // the same values grouped by tile
-    const uint64_t* n_items;
-    uint64_t bound;
-    const uint32_t* overflow;
-    const uint32_t* bh;   // [blocks][4096] exclusive prefixes over blocks
-    const uint32_t* tot;  // [4096] pairs per tile
-    uint32_t* ranges;     // [n_tiles][2], written by block 0
-    int n_tiles;
-};
-
-__global__ __launch_bounds__(BLK) void k_g12_scatter(G12Args a) {
-    __shared__ uint32_t gbase[G12];           // tile start + earlier blocks' count - local start
-    __shared__ uint32_t wcnt[BLK / 64][G12];  // per-wave tile counters, then wave offsets
-    __shared__ uint32_t ds[G12];              // block-local tile starts
-    __shared__ uint32_t wsum[BLK / 64];
-    __shared__ uint64_t lv[TILE_ITEMS];
-    __shared__ uint16_t ld[TILE_ITEMS];
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    if (*a.overflow) return;
-    const uint64_t count = min(*a.n_items, a.bound);
-    const uint64_t base = (uint64_t)blockIdx.x * TILE_ITEMS;
-    if (base >= count) return;
-    // tile starts: exclusive scan of the totals (every block forms them; block 0 writes the ranges)
-    for (int i = t; i < G12; i += BLK) gbase[i] = a.tot[i];
-    for (int k = 0; k < G12 / 64; ++k) wcnt[w][k * 64 + l] = 0;
+__global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
+    __shared__ uint32_t cur[G12];  // next slot of every tile in this row's part of the bucket
+    __shared__ uint32_t wsum[BK_T / 64];
+    __shared__ WaveStage st[BK_T / 64];
+    __shared__ uint32_t s_db[BK_T / 64][64];
+    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (*a.overflow) return;  // the same for every thread
+    // tile starts: exclusive scan of the totals (every row forms them; the first writes ranges)
+    for (int i = t; i < G12; i += BK_T) cur[i] = i < a.n_tiles ? a.tot[i] : 0u;
     __syncthreads();
-    block_excl_scan_4096(gbase, wsum);
-    if (blockIdx.x == 0)
-        for (int i = t; i < a.n_tiles; i += BLK) {
-            a.ranges[2 * i] = gbase[i];
-            a.ranges[2 * i + 1] = gbase[i] + a.tot[i];
+    block_excl_scan_4096<BK_T>(cur, wsum);
+    const uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * G12;
+    const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+    for (int i = t; i < a.n_tiles; i += BK_T) {
+        const uint32_t s0 = cur[i];
+        if (first) {
+            a.ranges[2 * i] = s0;
+            a.ranges[2 * i + 1] = s0 + a.tot[i];
         }
-    const uint64_t wbase = base + (uint64_t)w * (64 * IPT);
-    uint32_t key[IPT], lr[IPT];
-    uint64_t val[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint64_t i = wbase + r * 64 + l;
-        const bool valid = i < count;
-        key[r] = valid ? (a.kin[i] & (G12 - 1)) : 0u;
-        val[r] = valid ? a.vin[i] : 0ull;
-    }
-    // rank inside the wave: lanes with the same tile, in lane order, after the wave's earlier rounds
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const bool valid = wbase + r * 64 + l < count;
-        const uint32_t d = key[r];
-        uint64_t m = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 12; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        const uint32_t rank = mask_rank(m);
-        const uint32_t old = valid ? wcnt[w][d] : 0u;
-        lr[r] = old + rank;
-        if (valid && rank == 0) wcnt[w][d] = old + (uint32_t)__popcll(m);
+        cur[i] = s0 + row[i];
     }
     __syncthreads();
-    // per tile: the waves' exclusive offsets (in place) and the block's count
-    for (int k = 0; k < G12 / BLK; ++k) {
-        const int d = k * BLK + t;
-        uint32_t mine = 0;
-#pragma unroll
-        for (int ww = 0; ww < BLK / 64; ++ww) {
-            const uint32_t c = wcnt[ww][d];
-            wcnt[ww][d] = mine;
-            mine += c;
-        }
-        ds[d] = mine;
-    }
-    __syncthreads();
-    block_excl_scan_4096(ds, wsum);
-    const uint32_t* row = a.bh + (uint64_t)blockIdx.x * G12;
-    for (int i = t; i < G12; i += BLK) gbase[i] = gbase[i] + row[i] - ds[i];
-    // block-local sort through LDS, then runs of one tile written together
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        if (wbase + r * 64 + l < count) {
-            const uint32_t d = key[r];
-            const uint32_t q = ds[d] + wcnt[w][d] + lr[r];
-            lv[q] = val[r];
-            ld[q] = (uint16_t)d;
-        }
-    }
-    __syncthreads();
-    const uint32_t nitems = (uint32_t)min((uint64_t)TILE_ITEMS, count - base);
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t q = r * BLK + t;
-        if (q < nitems) {
-            const uint32_t pos = gbase[ld[q]] + q;  // modulo 2^32, like the offsets it is made of
-            if (pos < count) a.vout[pos] = lv[q];
+    const uint32_t* cv = a.count + (int64_t)v * a.n;
+    const uint64_t* rv = a.rect + (int64_t)v * a.n;
+    const float* dv = a.depth + (int64_t)v * a.n;
+    const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
+    const uint32_t tbase = (uint32_t)a.tile_offset[v];
+    {
+        const int64_t eb = (int64_t)blockIdx.x * 16 + w;  // the wave's emission block
+        if (eb * 256 >= a.n) return;  // the whole wave (no workgroup barrier below)
+        uint32_t run = a.bsum[(int64_t)v * a.nbv + eb];  // first pair of the emission block
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j0 = eb * 256 + k * 64;
+            if (j0 >= a.n) break;
+            const int64_t j = j0 + l;
+            const uint32_t c = j < a.n ? cv[j] : 0u;
+            uint64_t r = 0;
+            uint32_t db = 0;
+            if (c) {
+                r = rv[j];
+                db = __float_as_uint(dv[j]);
+            }
+            if (a.eoff && j < a.n) a.eoff[(int64_t)v * a.n + j] = run + wave_incl_scan(c) - c;
+            s_db[w][l] = db;
+            const int last = (int)min((int64_t)63, a.n - 1 - j0);
+            run += walk_pairs(st[w], c, r, last, tiles_x, tbase, [&](uint32_t, int L, uint32_t tile) {
+                if (tile >= (uint32_t)a.n_tiles) return;
+                const uint32_t pos = atomicAdd(&cur[tile], 1u);
+                if (pos < a.capacity) a.vout[pos] = ((uint64_t)s_db[w][L] << 32) | (uint32_t)(j0 + L);
+            });
         }
     }
 }
@@ -847,19 +889,28 @@ __device__ __forceinline__ int merge_split(const uint64_t* A, int na, const uint
 }
 
 // Stable LSD radix sort of one tile's list (len <= SMALL_LIST) by its FP32 depth bits,
-// 8-bit digits, in LDS. The grouping passes keep emission order inside a tile, which is
-// increasing Gaussian index, so equal depths end in index order: the (depth, index) order.
-// Wave w owns the contiguous items [w C, (w + 1) C) (C a multiple of 64) and ranks them
-// with wave-private digit counters, as the grouping passes do; passes whose digit is the
-// same for every item of the tile are skipped.
+// 8-bit digits, in LDS. Wave w owns the contiguous items [w C, (w + 1) C) (C a multiple of 64)
+// and ranks them with wave-private digit counters; passes whose digit is the same for every
+// item of the tile are skipped. Equal depths keep the order the grouping left, which is not
+// index order (the bucket emission takes slots from LDS counters): runs of equal depth bits in
+// the sorted list (rare, and short) are then put in index order, or, for a run longer than 64,
+// the whole list is sorted again by its unique 64-bit (depth bits, index) values with a
+// bitonic network, so the result is the (depth, index) order whatever order the list came in.
 constexpr int RS_ROUNDS = SMALL_LIST / BLK;  // items per thread
 
 __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
-    __shared__ uint32_t sk[SMALL_LIST], sv[SMALL_LIST];
+    __shared__ union {
+        struct {
+            uint32_t k[SMALL_LIST], v[SMALL_LIST];
+        } kv;
+        uint64_t kv64[SMALL_LIST];
+    } lds;
+    uint32_t* sk = lds.kv.k;
+    uint32_t* sv = lds.kv.v;
     __shared__ uint32_t wcnt[BLK / 64][256];
     __shared__ uint32_t ds[256];
     __shared__ uint32_t wsum[BLK / 64];
-    __shared__ uint32_t diff;
+    __shared__ uint32_t diff, ties;
     const int tile = blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
     if (*a.overflow) return;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -873,7 +924,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
     const int C = (((len + 3) >> 2) + 63) & ~63;
     const int R = C >> 6;
     const int wb = w * C;
-    if (t == 0) diff = 0;
+    if (t == 0) diff = 0, ties = 0;
     const uint32_t k0 = (uint32_t)(src[0] >> 32);
     uint32_t key[RS_ROUNDS], val[RS_ROUNDS], lr[RS_ROUNDS];
     uint32_t dx = 0;
@@ -941,6 +992,68 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
                 key[r] = sk[i];
                 val[r] = sv[i];
             }
+        }
+    }
+    // equal depth bits next to each other in the sorted list? (sk holds the last pass's
+    // order; with no pass at all every depth is the same)
+    bool tie = dmask == 0u && len > 1;
+    if (dmask != 0u) {
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            const int i = wb + 64 * r + l;
+            tie |= i + 1 < len && key[r] == sk[i + 1];
+        }
+    }
+    if (tie) atomicOr(&ties, 1u);
+    __syncthreads();
+    if (ties) {  // the same for the whole workgroup
+        if (dmask == 0u) {  // no pass ran: the list is not in LDS yet
+#pragma unroll
+            for (int r = 0; r < RS_ROUNDS; ++r) {
+                if (r >= R) break;
+                const int i = wb + 64 * r + l;
+                if (i < len) sk[i] = key[r], sv[i] = val[r];
+            }
+            __syncthreads();
+        }
+        // the thread holding the first item of a run of equal depths puts the run's indices in
+        // increasing order (runs are short: two items, as a rule); a run longer than 64 sends
+        // the whole list to the bitonic sort of its (depth bits, index) values
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            const int i = wb + 64 * r + l;
+            if (i >= len) continue;
+            const uint32_t kk = sk[i];
+            if ((i > 0 && sk[i - 1] == kk) || i + 1 >= len || sk[i + 1] != kk) continue;
+            int j = i + 1;
+            while (j < len && j - i <= 64 && sk[j] == kk) ++j;
+            if (j - i > 64) {
+                atomicOr(&ties, 2u);
+                continue;
+            }
+            for (int x = i + 1; x < j; ++x) {  // insertion sort of sv[i, j)
+                const uint32_t y = sv[x];
+                int z = x - 1;
+                while (z >= i && sv[z] > y) {
+                    sv[z + 1] = sv[z];
+                    --z;
+                }
+                sv[z + 1] = y;
+            }
+        }
+        __syncthreads();
+        if (ties & 2u) {
+            sort_in_lds(lds.kv64, src, len);
+            write_tile(a, tile, start, lds.kv64, len);
+            return;
+        }
+#pragma unroll
+        for (int r = 0; r < RS_ROUNDS; ++r) {
+            if (r >= R) break;
+            const int i = wb + 64 * r + l;
+            if (i < len) val[r] = sv[i];
         }
     }
 #pragma unroll
@@ -1080,9 +1193,9 @@ struct SortLayout {
     // digit histograms, deferred-tile count, LPT counters, pass status tables
     size_t ctrl, scan, tickets, ghist, n_deferred, lpt, status, ctrl_end;
     size_t offs, deferred, tk0, tk1, tv0, tv1, g12_bh, g12_tot, total;
-    int64_t nb_scan, nb_sort;
+    int64_t nb_scan, nb_sort, nbr;
     int passes;
-    bool g12;  // grouping in one 12-bit counting pass (at most 4096 tiles)
+    bool g12;  // emission into tile buckets (at most 4096 tiles)
 };
 
 SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
@@ -1092,7 +1205,8 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.nb_scan = scan_blocks(vn);
     L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
     L.passes = std::max(1, (tile_bits(std::max(n_tiles, 1)) + 7) / 8);
-    L.g12 = n_tiles <= G12 && L.nb_sort <= G12_MAX_ROWS;
+    L.nbr = (n + EB_ROW - 1) / EB_ROW;
+    L.g12 = n_tiles <= G12 && L.nbr * (int64_t)std::max(n_views, 1) <= G12_MAX_ROWS;
     size_t p = 0;
     L.ctrl = p;
     L.scan = p;
@@ -1122,7 +1236,7 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.tv1 = p;
     p = align256(p + v8);
     L.g12_bh = p;
-    if (L.g12) p = align256(p + sizeof(uint32_t) * G12 * (size_t)L.nb_sort);
+    if (L.g12) p = align256(p + sizeof(uint32_t) * G12 * (size_t)L.nbr * (size_t)std::max(n_views, 1));
     L.g12_tot = p;
     if (L.g12) p = align256(p + sizeof(uint32_t) * G12);
     L.total = p;
@@ -1146,6 +1260,60 @@ static gs_status launch_lpt(const gs_views* views, gs_bins* bins, uint32_t* lpt,
     hipLaunchKernelGGL(k_lpt_scatter, dim3(g), dim3(256), 0, stream, bins->ranges, views->n_tiles, lpt, lpt + LPT_B,
                        bins->queue);
     return check_launch("bin_sort");
+}
+
+// Beyond 4096 tiles: the pairs are written in entry order (tile; depth bits, index), grouped by
+// the onesweep passes on the tile id, and the tile ranges read off the grouped keys. Sets vin
+// to the grouped values and valt to the other value buffer.
+static void launch_entry_order_grouping(const gs_projected* proj, const gs_views* views, gs_bins* bins,
+                                        const SortLayout& L, char* w, hipStream_t stream, uint64_t*& vin,
+                                        uint64_t*& valt) {
+    auto U32 = [&](size_t off) { return (uint32_t*)(w + off); };
+    auto U64 = [&](size_t off) { return (uint64_t*)(w + off); };
+    const int64_t n = proj->n;
+    EmitArgs e;
+    e.count = proj->count;
+    e.bpre = U32(L.offs);
+    e.rect = proj->rect;
+    e.depth = proj->depth;
+    e.cams = views->cams;
+    e.tile_offset = views->tile_offset;
+    e.n = n;
+    e.tile_w = views->tile_w;
+    e.overflow = bins->overflow;
+    e.tkey = U32(L.tk0);
+    e.tval = U64(L.tv0);
+    e.eoff = bins->entry_offset;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
+    uint32_t* kin = U32(L.tk0);
+    uint32_t* kalt = U32(L.tk1);
+    vin = U64(L.tv0);
+    valt = U64(L.tv1);
+    const int np = L.passes;
+    uint32_t* ghist = U32(L.ghist);
+    const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort, 1024);
+    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np,
+                       ghist);
+    for (int pass = 0; pass < np; ++pass) {
+        PassArgs pa;
+        pa.kin = kin;
+        pa.vin = vin;
+        pa.kout = kalt;
+        pa.vout = valt;
+        pa.n_items = bins->n_pairs;
+        pa.bound = bins->capacity;
+        pa.shift = 8 * pass;
+        pa.ghist = ghist + 256 * pass;
+        pa.status = U64(L.status) + (size_t)256 * L.nb_sort * pass;
+        pa.ticket = U32(L.tickets) + pass;
+        pa.err = bins->overflow;
+        hipLaunchKernelGGL(k_os_pass<uint64_t>, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
+        std::swap(kin, kalt);
+        std::swap(vin, valt);
+    }
+    const unsigned rg = (unsigned)((bins->capacity + 255) / 256);
+    hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, stream, kin, bins->n_pairs, bins->capacity, bins->overflow,
+                       bins->ranges, views->n_tiles);
 }
 
 gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* ws,
@@ -1174,77 +1342,47 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     }
 
     // 1. pair offsets of the emission blocks (clearing the state above first), pair total,
-    // capacity check
+    // capacity check; with tile buckets also every row's tile histogram
     const int64_t nbv = (n + 255) / 256;
-    hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0, stream,
-                       proj->count, n, nbv, U32(L.offs), f);
+    BucketArgs ba;
+    ba.count = proj->count;
+    ba.rect = proj->rect;
+    ba.depth = proj->depth;
+    ba.cams = views->cams;
+    ba.tile_offset = views->tile_offset;
+    ba.n = n;
+    ba.nbv = nbv;
+    ba.nbr = L.nbr;
+    ba.tile_w = views->tile_w;
+    ba.n_tiles = views->n_tiles;
+    ba.ncols = (views->n_tiles + 15) / 16 * 16;
+    ba.bsum = U32(L.offs);
+    ba.bh = U32(L.g12_bh);
+    ba.tot = U32(L.g12_tot);
+    ba.overflow = bins->overflow;
+    ba.vout = U64(L.tv1);
+    ba.capacity = bins->capacity;
+    ba.ranges = bins->ranges;
+    ba.eoff = bins->entry_offset;
+    if (L.g12)
+        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba, f);
+    else
+        hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0,
+                           stream, proj->count, n, nbv, U32(L.offs), f);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views, bins->n_pairs,
                        bins->overflow, bins->capacity, bins->overflow_sticky);
     if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
-    // 2. pairs (tile; depth bits, index)
-    EmitArgs e;
-    e.count = proj->count;
-    e.bpre = U32(L.offs);
-    e.rect = proj->rect;
-    e.depth = proj->depth;
-    e.cams = views->cams;
-    e.tile_offset = views->tile_offset;
-    e.n = n;
-    e.tile_w = views->tile_w;
-    e.overflow = bins->overflow;
-    e.tkey = U32(L.tk0);
-    e.tval = U64(L.tv0);
-    e.eoff = bins->entry_offset;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)views->n_views), dim3(256), 0, stream, e);
-    // 3. grouped by tile, 4. tile ranges
-    uint32_t* kin = U32(L.tk0);
-    uint64_t* vin = U64(L.tv0);
-    uint32_t* kalt = U32(L.tk1);
-    uint64_t* valt = U64(L.tv1);
+    uint64_t* vin;
+    uint64_t* valt;
     if (L.g12) {
-        hipLaunchKernelGGL(k_g12_hist, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, kin, bins->n_pairs,
-                           bins->capacity, bins->overflow, U32(L.g12_bh));
-        hipLaunchKernelGGL(k_g12_colscan, dim3(G12 / 16), dim3(BLK), 0, stream, U32(L.g12_bh), bins->n_pairs,
-                           bins->capacity, bins->overflow, U32(L.g12_tot));
-        G12Args ga;
-        ga.kin = kin;
-        ga.vin = vin;
-        ga.vout = valt;
-        ga.n_items = bins->n_pairs;
-        ga.bound = bins->capacity;
-        ga.overflow = bins->overflow;
-        ga.bh = U32(L.g12_bh);
-        ga.tot = U32(L.g12_tot);
-        ga.ranges = bins->ranges;
-        ga.n_tiles = views->n_tiles;
-        hipLaunchKernelGGL(k_g12_scatter, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, ga);
-        std::swap(vin, valt);
+        // 2. per-tile prefixes over the rows and tile totals, 3. pairs written into their tiles
+        hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.ncols / 16)), dim3(BLK), 0, stream, U32(L.g12_bh),
+                           (int)(L.nbr * views->n_views), bins->overflow, U32(L.g12_tot));
+        hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba);
+        vin = U64(L.tv1);
+        valt = U64(L.tv0);
     } else {
-        const int np = L.passes;
-        uint32_t* ghist = U32(L.ghist);
-        const unsigned hb = (unsigned)std::min<int64_t>(L.nb_sort, 1024);
-        hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(BLK), 0, stream, U32(L.tk0), bins->n_pairs, bins->capacity, np,
-                           ghist);
-        for (int pass = 0; pass < np; ++pass) {
-            PassArgs pa;
-            pa.kin = kin;
-            pa.vin = vin;
-            pa.kout = kalt;
-            pa.vout = valt;
-            pa.n_items = bins->n_pairs;
-            pa.bound = bins->capacity;
-            pa.shift = 8 * pass;
-            pa.ghist = ghist + 256 * pass;
-            pa.status = U64(L.status) + (size_t)256 * L.nb_sort * pass;
-            pa.ticket = U32(L.tickets) + pass;
-            pa.err = bins->overflow;
-            hipLaunchKernelGGL(k_os_pass<uint64_t>, dim3((unsigned)L.nb_sort), dim3(BLK), 0, stream, pa);
-            std::swap(kin, kalt);
-            std::swap(vin, valt);
-        }
-        const unsigned rg = (unsigned)((bins->capacity + 255) / 256);
-        hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(256), 0, stream, kin, bins->n_pairs, bins->capacity,
-                           bins->overflow, bins->ranges, views->n_tiles);
+        launch_entry_order_grouping(proj, views, bins, L, w, stream, vin, valt);
     }
     // 5. each tile's list by (depth, index); keys and values
     TileSortArgs ta;

@@ -100,6 +100,44 @@ def test_keys_bit_exact(case, tile):
             assert ranges[tid, 0] == ranges[tid, 1]
 
 
+@pytest.mark.parametrize("spread", [1.0, 0.03, 0.0])
+def test_keys_bit_exact_with_depth_ties(spread):
+    """Groups of Gaussians sharing one position (equal FP32 depths, so the order inside a tile
+    rests on the index tie-break alone): keys, values and ranges bit-exact against the
+    oracle's (key, value) order, with short runs in short lists, lists beyond the small
+    per-tile buffer (spread 0.03) and one run of 300 equal depths (spread 0: every Gaussian at
+    one point). The tile grouping leaves any order inside a tile; the tile sort must restore
+    index order among equal depths."""
+    sc = scenes.uniform_cube_scene(3000 if spread > 0 else 300, seed=11)
+    rng = np.random.default_rng(4)
+    sc.mean = (sc.mean[:, rng.integers(0, min(500, sc.n), sc.n)] * np.float32(spread)).astype(np.float32)
+    cam = scenes.plain_view()
+    _say(f"keys with depth ties, spread {spread}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch([cam], (16, 16), DEV)
+    proj = gs.preprocess(g, views, P)
+    bins = gs.bin_sort(proj, views)
+    torch.cuda.synchronize()
+    npairs = int(bins.n_pairs.item())
+    assert int(bins.overflow.item()) == 0
+    keys = bins.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = bins.vals[:npairs].cpu().numpy().view(np.uint32)
+    t = splat_table(proj)
+    rect = np.where((t["count"] > 0)[:, None], t["rect"], np.array([0, 0, -1, -1]))
+    k1, v1 = oracle.pairs([t["depth"]], [rect], [(cam.width, cam.height)], (16, 16))
+    assert np.array_equal(keys, k1) and np.array_equal(vals, v1)
+    ties = int(np.sum(k1[1:] == k1[:-1]))
+    lens = np.bincount((k1 >> np.uint64(32)).astype(np.int64), minlength=views.n_tiles)
+    _say(f"  {ties} equal neighbouring keys, longest list {lens.max()}")
+    assert ties > 100
+    if 0 < spread < 1.0:
+        assert lens.max() > 2048
+    ranges = bins.ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    assert np.array_equal(ranges[:, 1] - ranges[:, 0], lens)
+    assert np.array_equal(ranges[lens > 0, 0], starts[lens > 0])
+
+
 @pytest.mark.parametrize("n", [3000, 20000])
 def test_long_tile_lists(n):
     """Thousands of Gaussians packed around the image centre (a corner of four 16x16
