@@ -640,7 +640,9 @@ struct BucketArgs {
     uint32_t* bsum;      // [n_views][nbv] pair sums, then (scanned) exclusive pair offsets
     uint32_t* bh;        // [rows][G12] tile histograms, then exclusive prefixes over rows
     const uint32_t* tot; // [G12] pairs per tile
-    const uint32_t* overflow;
+    uint32_t* overflow;  // set (with the sticky word) when the pairs exceed the capacity
+    uint32_t* sticky;    // or NULL
+    const uint64_t* n_pairs;  // pair total (the column scans add it up)
     uint64_t* vout;      // FP32 depth bits << 32 | Gaussian index, grouped by tile
     uint64_t capacity;
     uint32_t* ranges;    // [n_tiles][2], written by the first row
@@ -695,11 +697,11 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
 // Exclusive prefix over the rows of every tile's count (in place) and the tile totals.
 // Workgroup g takes the 16 tiles [16 g, 16 g + 16): their counts of every row are read into
 // LDS, each of 16 chunks of rows summed, the chunk sums scanned, then the prefixes written.
+// Each workgroup also adds its 16 totals to the pair total (zero on entry).
 __global__ __launch_bounds__(BLK) void k_bucket_colscan(uint32_t* __restrict__ bh, int nrows,
-                                                        const uint32_t* overflow, uint32_t* __restrict__ tot) {
+                                                        uint32_t* __restrict__ tot, uint64_t* n_pairs) {
     __shared__ uint32_t sub[G12_MAX_ROWS * 16];
     __shared__ uint32_t csum[16][17];
-    if (*overflow) return;
     const int t = threadIdx.x;
     const int c0 = blockIdx.x * 16;
     for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)];
@@ -718,8 +720,14 @@ __global__ __launch_bounds__(BLK) void k_bucket_colscan(uint32_t* __restrict__ b
             run += v;
         }
         tot[c0 + t] = run;
+        csum[t][16] = run;
     }
     __syncthreads();
+    if (t == 0) {
+        uint64_t all = 0;
+        for (int k = 0; k < 16; ++k) all += csum[k][16];
+        if (all) atomicAdd((unsigned long long*)n_pairs, (unsigned long long)all);
+    }
     uint32_t run = csum[col][chunk];
     for (int r = r0; r < r1; ++r) {
         const uint32_t v = sub[r * 16 + col];
@@ -757,13 +765,20 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
     __shared__ WaveStage st[BK_T / 64];
     __shared__ uint32_t s_db[BK_T / 64][64];
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
-    if (*a.overflow) return;  // the same for every thread
+    const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+    // the capacity check (every workgroup reads the complete total; the first sets the flags)
+    if (*a.n_pairs > a.capacity) {
+        if (first && t == 0) {
+            atomicOr(a.overflow, 1u);
+            if (a.sticky) atomicOr(a.sticky, 1u);
+        }
+        return;
+    }
     // tile starts: exclusive scan of the totals (every row forms them; the first writes ranges)
     for (int i = t; i < G12; i += BK_T) cur[i] = i < a.n_tiles ? a.tot[i] : 0u;
     __syncthreads();
     block_excl_scan_4096<BK_T>(cur, wsum);
     const uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * G12;
-    const bool first = blockIdx.x == 0 && blockIdx.y == 0;
     for (int i = t; i < a.n_tiles; i += BK_T) {
         const uint32_t s0 = cur[i];
         if (first) {
@@ -1341,8 +1356,8 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
         return launch_lpt(views, bins, nullptr, stream);
     }
 
-    // 1. pair offsets of the emission blocks (clearing the state above first), pair total,
-    // capacity check; with tile buckets also every row's tile histogram
+    // 1. pair sums of the emission blocks (clearing the state above first); with tile buckets
+    // also every row's tile histogram
     const int64_t nbv = (n + 255) / 256;
     BucketArgs ba;
     ba.count = proj->count;
@@ -1360,28 +1375,34 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ba.bh = U32(L.g12_bh);
     ba.tot = U32(L.g12_tot);
     ba.overflow = bins->overflow;
+    ba.sticky = bins->overflow_sticky;
+    ba.n_pairs = bins->n_pairs;
     ba.vout = U64(L.tv1);
     ba.capacity = bins->capacity;
     ba.ranges = bins->ranges;
     ba.eoff = bins->entry_offset;
-    if (L.g12)
-        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba, f);
-    else
-        hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0,
-                           stream, proj->count, n, nbv, U32(L.offs), f);
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views, bins->n_pairs,
-                       bins->overflow, bins->capacity, bins->overflow_sticky);
-    if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
     uint64_t* vin;
     uint64_t* valt;
     if (L.g12) {
-        // 2. per-tile prefixes over the rows and tile totals, 3. pairs written into their tiles
+        // (the emission blocks' pair offsets are only scanned when the entries' first pairs
+        // are asked for; the column scans give the pair total and the emission its check)
+        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba, f);
+        if (bins->entry_offset)
+            hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views,
+                               (uint64_t*)nullptr, (uint32_t*)nullptr, bins->capacity, (uint32_t*)nullptr);
+        // 2. per-tile prefixes over the rows, tile totals and the pair total, 3. pairs written
+        // into their tiles
         hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.ncols / 16)), dim3(BLK), 0, stream, U32(L.g12_bh),
-                           (int)(L.nbr * views->n_views), bins->overflow, U32(L.g12_tot));
+                           (int)(L.nbr * views->n_views), U32(L.g12_tot), bins->n_pairs);
         hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba);
         vin = U64(L.tv1);
         valt = U64(L.tv0);
     } else {
+        hipLaunchKernelGGL(k_count_bsums, dim3((unsigned)((nbv + 15) / 16), (unsigned)views->n_views), dim3(256), 0,
+                           stream, proj->count, n, nbv, U32(L.offs), f);
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(SB_T), 0, stream, U32(L.offs), nbv * views->n_views,
+                           bins->n_pairs, bins->overflow, bins->capacity, bins->overflow_sticky);
+        if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
         launch_entry_order_grouping(proj, views, bins, L, w, stream, vin, valt);
     }
     // 5. each tile's list by (depth, index); keys and values
