@@ -420,6 +420,8 @@ __device__ __forceinline__ float row_sum9(const float (&v)[9], int lane) {
 // after entry j and S the colour composited behind it (S starts at T_final * bg):
 //   T_j = T / (1 - alpha_j), w_j = alpha_j T_j,
 //   dL/dc_j = dL/dC * w_j,  dL/dalpha_j = sum_c dL/dC_c (T_j c_jc - S_c / (1 - alpha_j)),
+// kept per pixel as U = dL/dC . S (U += w_j Q_j with Q_j = dL/dC . c_j, so that
+// dL/dalpha_j = T_j Q_j - U / (1 - alpha_j)),
 // then alpha = o G (unless clamped), G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2,
 // dx = xc - u. Each row of 16 lanes holds a 4x4 quarter of the wave's block and walks only
 // the entries that meet its quarter, so one iteration serves up to four entries; the nine
@@ -453,7 +455,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
     for (int i = 0; i < PXW; ++i) xc[i] = (double)(px0 + i) + 0.5;
 #pragma unroll
     for (int j = 0; j < PXH; ++j) yc[j] = (double)(py0 + j) + 0.5;
-    float T[P], dC[P][3], Sc[P][3];
+    float T[P], dC[P][3], U[P];
     uint32_t last[P];
     bool inside[P];
     uint32_t lmax = start;
@@ -464,17 +466,16 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
         T[p] = 1.f;
         last[p] = start;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dC[p][c] = Sc[p][c] = 0.f;
+        for (int c = 0; c < 3; ++c) dC[p][c] = 0.f;
+        U[p] = 0.f;
         if (inside[p]) {
             const int64_t pix = poff + (int64_t)py * W + px;
             T[p] = a.t_in[pix];
             last[p] = a.last_in[pix];
             const float* d = a.dl_drgb + 3 * poff + (int64_t)py * W + px;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                dC[p][c] = d[c * plane];
-                Sc[p][c] = T[p] * a.p.bg[c];
-            }
+            for (int c = 0; c < 3; ++c) dC[p][c] = d[c * plane];
+            U[p] = T[p] * (dC[p][0] * a.p.bg[0] + dC[p][1] * a.p.bg[1] + dC[p][2] * a.p.bg[2]);
         }
         // never read outside the tile's list, whatever n_last holds
         last[p] = min(max(last[p], start), end);
@@ -496,7 +497,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
     for (int k = 0; k < 4; ++k) qlast[k] = (int64_t)(uint32_t)__builtin_amdgcn_readlane(ql, 16 * k);
     const int64_t vbase = (int64_t)view * a.n;
     const double ox = (double)(tx * TW) + 0.5, oy = (double)(ty * TH) + 0.5;
-    float* accw = sm.acc + w * (BB * 9);
+    const int accw = w * (BB * 9);  // this wave's accumulators in sm.acc
     for (int q = t; q < NW * BB * 9; q += NT) sm.acc[q] = 0.f;
     for (uint32_t hi = top; hi > start;) {
         const uint32_t lo = (hi - start > (uint32_t)BB) ? hi - BB : start;
@@ -550,18 +551,15 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                 for (int p = 0; p < P; ++p) {
                     const float G = falloff(q[p]);
                     const float og = s.opacity * G;
-                    // where p does not contribute al = 0 and wt = 0: S and the colour sums stay as
+                    // where p does not contribute al = 0 and wt = 0: U and the colour sums stay as
                     // they are without a select (inputs are finite)
                     const float al = con[p] ? clamp_alpha(og, amax) : 0.f;
                     const float r = __builtin_amdgcn_rcpf(1.f - al);
                     T[p] = con[p] ? T[p] * r : T[p];
                     const float wt = al * T[p];
-                    const float dA = dC[p][0] * (T[p] * s.rgb[0] - Sc[p][0] * r) +
-                                     dC[p][1] * (T[p] * s.rgb[1] - Sc[p][1] * r) +
-                                     dC[p][2] * (T[p] * s.rgb[2] - Sc[p][2] * r);
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc)
-                        Sc[p][cc] = fmaf(wt, s.rgb[cc], Sc[p][cc]);  // wt = 0 where p does not contribute
+                    const float Q = dC[p][0] * s.rgb[0] + dC[p][1] * s.rgb[1] + dC[p][2] * s.rgb[2];
+                    const float dA = T[p] * Q - U[p] * r;
+                    U[p] = fmaf(wt, Q, U[p]);  // wt = 0 where p does not contribute
                     // dq dx, dq dy (turned into the u, v gradients with the conic once per record
                     // in the flush), a b c o r g b; the geometric terms vanish where alpha is clamped
                     // (the constant factors of dq/dalpha, -1/2, and of the b term, 2, are applied
@@ -584,7 +582,7 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                 // entry (lanes of one instruction that meet at one address are applied in a
                 // fixed order, so the result does not depend on timing)
                 const float z = row_sum9(v, l);
-                if (act & (fld < 9)) atomicAdd(&accw[j * 9 + fld], z);
+                if (act & (fld < 9)) atomicAdd(&sm.acc[accw + j * 9 + fld], z);
             }
         }
         __syncthreads();
