@@ -54,6 +54,8 @@
  *     are then left empty and the caller must retry with a larger capacity. Bit 1
  *     is set if a cross-block wait inside the sort ran out of its spin budget
  *     (results invalid, nothing written out of bounds); the kernels never hang.
+ *     Bit 2 is set when a view has more tiles than views->max_view_tiles declares
+ *     (results invalid, nothing written out of bounds).
  *   - Accumulating outputs (importance h, visibility bits, gradients) are
  *     combined into what the buffer holds (max, OR, +=), so results over view
  *     chunks compose; the caller initialises them.
@@ -159,7 +161,9 @@ typedef struct gs_views {
                                     tile_w >= 16, 4 also tile_h >= 16; 0 picks the default for
                                     the tile size. Results do not depend on it, except for the
                                     order of the reverse traversal's FP32 sums */
-    int32_t reserved;            /* set to 0 */
+    int32_t max_view_tiles;      /* tiles of the view with the most (gs_view_layout's table gives
+                                    them), or 0: taken as n_tiles. gs_bin_sort writes the pairs
+                                    straight into their tiles' ranges when it is at most 8192 */
 } gs_views;
 
 /* Per-(view, Gaussian) outputs of gs_preprocess, [n_views][n] each:

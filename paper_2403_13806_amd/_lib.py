@@ -49,7 +49,7 @@ class gs_gaussians_grad(ctypes.Structure):
 class gs_views(ctypes.Structure):
     _fields_ = [("cams", c_void_p), ("tile_offset", c_void_p), ("pixel_offset", c_void_p), ("n_views", i32),
                 ("tile_w", i32), ("tile_h", i32), ("n_tiles", i32), ("n_pixels", i64), ("batch_depth", i32),
-                ("lpt", i32), ("pixels_per_lane", i32), ("reserved", i32)]
+                ("lpt", i32), ("pixels_per_lane", i32), ("max_view_tiles", i32)]
 
 
 class gs_projected(ctypes.Structure):

@@ -97,6 +97,8 @@ static gs_status check_views(const gs_views* v) {
     if ((ppl >= 2 && v->tile_w < 16) || (ppl == 4 && v->tile_h < 16))
         return set_error(GS_ERR_UNSUPPORTED, "pixels_per_lane %d needs a tile of at least %dx%d", ppl, 16,
                          ppl == 4 ? 16 : 8);
+    if (v->max_view_tiles < 0 || v->max_view_tiles > v->n_tiles)
+        return set_error(GS_ERR_INVALID_ARG, "max_view_tiles must be in [0, n_tiles] (got %d)", v->max_view_tiles);
     return GS_OK;
 }
 

@@ -566,23 +566,24 @@ __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* n_p
 }
 
 // ---------------------------------------------------------------------------------------
-// Emission straight into tile buckets, for batches of at most 4096 tiles: the pairs are never
-// written in entry order. Each row of 4096 entries (16 emission blocks of one view) builds its
-// tile histogram in LDS by walking its entries' pairs (k_bucket_count, which also writes the
-// emission blocks' pair sums); column scans give, per tile, the pairs of earlier rows and the
-// tile's total (k_bucket_colscan); then each row walks its pairs again and writes each one at
-// tile start + earlier rows' pairs + a slot taken from an LDS counter of the tile
-// (k_bucket_emit). The order inside a tile's list is then whatever the LDS counters gave; the
-// tile sort orders it by the unique (depth bits, index) values, so the result is deterministic.
+// Emission straight into tile buckets, for batches whose views have at most 8192 tiles each:
+// the pairs are never written in entry order. Each row of 4096 entries (16 emission blocks of
+// one view) builds its view's tile histogram in LDS by walking its entries' pairs
+// (k_bucket_count, which also writes the emission blocks' pair sums); column scans over each
+// view's rows give, per tile, the pairs of earlier rows, the tile's total, and each view's
+// total (k_bucket_colscan); then each row walks its pairs again and writes each one at tile
+// start + earlier rows' pairs + a slot taken from an LDS counter of the tile (k_bucket_emit).
+// The order inside a tile's list is then whatever the LDS counters gave; the tile sort orders
+// it by the unique (depth bits, index) values, so the result is deterministic.
 // ---------------------------------------------------------------------------------------
-constexpr int G12 = 4096;           // tiles
-constexpr int G12_MAX_ROWS = 2048;  // rows: the column scan holds 16 columns of every row in LDS
-constexpr int EB_ROW = 4096;        // entries per bucket row (16 emission blocks of 256)
+constexpr int BUCKET_TILES = 8192;     // tiles of one view (LDS counters)
+constexpr int BUCKET_MAX_ROWS = 2048;  // rows of one view: the column scan holds 16 columns of each in LDS
+constexpr int EB_ROW = 4096;           // entries per bucket row (16 emission blocks of 256)
 
 // The pairs of a wave's 64 consecutive entries [j0, j0 + 64) of one view: lane e holds entry
 // e's tile count c and rectangle r. Stages the entries' pair offsets (within the 64), rectangles
 // and 1 / width in the wave's LDS slots, then the lanes take the pairs 64 at a time and call
-// f(pair offset g, entry lane L, tile) for each. Returns the 64 entries' pair total.
+// f(pair offset g, entry lane L, tile of the view) for each. Returns the 64 entries' pair total.
 struct WaveStage {
     uint32_t off[64];
     uint64_t rect[64];
@@ -591,7 +592,7 @@ struct WaveStage {
 
 template <class F>
 __device__ __forceinline__ uint32_t walk_pairs(WaveStage& st, uint32_t c, uint64_t r, int last, uint32_t tiles_x,
-                                               uint32_t tbase, F&& f) {
+                                               F&& f) {
     const int l = threadIdx.x & 63;
     const uint32_t incl = wave_incl_scan(c);
     const uint32_t total = wave_read(incl, 63);
@@ -619,7 +620,7 @@ __device__ __forceinline__ uint32_t walk_pairs(WaveStage& st, uint32_t c, uint64
             ++ky;
             kx -= wd;
         }
-        f(g, L, tbase + (y0 + ky) * tiles_x + x0 + kx);
+        f(g, L, (y0 + ky) * tiles_x + x0 + kx);
     }
     wave_sync();  // the slots are rewritten by the next call
     return total;
@@ -635,26 +636,33 @@ struct BucketArgs {
     int64_t nbv;         // emission blocks (256 entries) per view
     int64_t nbr;         // bucket rows (4096 entries) per view
     int tile_w;
-    int n_tiles;
-    int ncols;           // columns kept per row: n_tiles rounded up to 16
+    int n_views;
+    int stride;          // columns per row: the largest view's tile count (declared), rounded up to 16
     uint32_t* bsum;      // [n_views][nbv] pair sums, then (scanned) exclusive pair offsets
-    uint32_t* bh;        // [rows][G12] tile histograms, then exclusive prefixes over rows
-    const uint32_t* tot; // [G12] pairs per tile
-    uint32_t* overflow;  // set (with the sticky word) when the pairs exceed the capacity
+    uint32_t* bh;        // [n_views][nbr][stride] tile histograms, then exclusive prefixes over rows
+    uint32_t* tot;       // [n_tiles] pairs per tile
+    uint64_t* view_tot;  // [n_views] pairs per view (zero on entry)
+    uint32_t* overflow;  // bit 0: the pairs exceed the capacity; bit 2: a view exceeds stride
     uint32_t* sticky;    // or NULL
-    const uint64_t* n_pairs;  // pair total (the column scans add it up)
+    uint64_t* n_pairs;   // pair total (zero on entry; the column scans add it up)
     uint64_t* vout;      // FP32 depth bits << 32 | Gaussian index, grouped by tile
     uint64_t capacity;
-    uint32_t* ranges;    // [n_tiles][2], written by the first row
+    uint32_t* ranges;    // [n_tiles][2], written by each view's first row
     uint32_t* eoff;      // [n_views * n] first pair of each entry, or NULL
 };
 
 constexpr int BK_T = 1024;  // threads of the bucket kernels: one wave per emission block of the row
 
+// tiles of view v, and whether they fit the rows' columns (a view larger than declared is
+// reported by the column scans and nothing is binned)
+__device__ __forceinline__ int view_tiles(const BucketArgs& a, int v) {
+    return a.tile_offset[v + 1] - a.tile_offset[v];
+}
+
 // It also clears the frame's state first (the job of k_zero4 when there is no pair to bin):
 // no later kernel of the frame runs before it ends.
 __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear) {
-    __shared__ uint32_t hist[G12];
+    __shared__ uint32_t hist[BUCKET_TILES];
     __shared__ WaveStage st[BK_T / 64];
     {
         const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
@@ -664,12 +672,14 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
             for (int64_t i = tid; i < clear.n[b]; i += nth) clear.p[b][i] = 0u;
     }
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
-    for (int i = t; i < a.ncols; i += BK_T) hist[i] = 0u;
+    const int nt = view_tiles(a, v);
+    const bool fits = nt <= a.stride;  // the same for the whole workgroup
+    const int ncols = (nt + 15) & ~15;
+    for (int i = t; i < ncols && fits; i += BK_T) hist[i] = 0u;
     __syncthreads();
     const uint32_t* cv = a.count + (int64_t)v * a.n;
     const uint64_t* rv = a.rect + (int64_t)v * a.n;
     const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
-    const uint32_t tbase = (uint32_t)a.tile_offset[v];
     // wave w takes the row's emission block w, 64 entries at a time
     {
         const int64_t eb = (int64_t)blockIdx.x * 16 + w;
@@ -682,29 +692,39 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
             const uint32_t c = j < a.n ? cv[j] : 0u;
             const uint64_t r = c ? rv[j] : 0ull;
             const int last = (int)min((int64_t)63, a.n - 1 - j0);
-            bsum += walk_pairs(st[w], c, r, last, tiles_x, tbase,
-                               [&](uint32_t, int, uint32_t tile) {
-                                   if (tile < (uint32_t)a.n_tiles) atomicAdd(&hist[tile], 1u);
-                               });
+            bsum += walk_pairs(st[w], c, r, last, tiles_x, [&](uint32_t, int, uint32_t tile) {
+                if (fits && tile < (uint32_t)nt) atomicAdd(&hist[tile], 1u);
+            });
         }
         if (l == 0 && eb * 256 < a.n) a.bsum[(int64_t)v * a.nbv + eb] = bsum;
     }
     __syncthreads();
-    uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * G12;
-    for (int i = t; i < a.ncols; i += BK_T) row[i] = hist[i];
+    uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * a.stride;
+    for (int i = t; i < ncols && fits; i += BK_T) row[i] = hist[i];
 }
 
-// Exclusive prefix over the rows of every tile's count (in place) and the tile totals.
-// Workgroup g takes the 16 tiles [16 g, 16 g + 16): their counts of every row are read into
-// LDS, each of 16 chunks of rows summed, the chunk sums scanned, then the prefixes written.
-// Each workgroup also adds its 16 totals to the pair total (zero on entry).
-__global__ __launch_bounds__(BLK) void k_bucket_colscan(uint32_t* __restrict__ bh, int nrows,
-                                                        uint32_t* __restrict__ tot, uint64_t* n_pairs) {
-    __shared__ uint32_t sub[G12_MAX_ROWS * 16];
+// Exclusive prefix over a view's rows of every tile's count (in place) and the tile totals.
+// Workgroup (g, v) takes tiles [16 g, 16 g + 16) of view v: their counts of every row are read
+// into LDS, each of 16 chunks of rows summed, the chunk sums scanned, then the prefixes
+// written. Each workgroup also adds its totals to the view's and to the pair total. The first
+// workgroup of a view too large for the rows' columns sets bit 2 of the overflow word.
+__global__ __launch_bounds__(BLK) void k_bucket_colscan(BucketArgs a) {
+    __shared__ uint32_t sub[BUCKET_MAX_ROWS * 16];
     __shared__ uint32_t csum[16][17];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, v = blockIdx.y;
+    const int nt = view_tiles(a, v);
+    if (nt > a.stride) {
+        if (blockIdx.x == 0 && t == 0) {
+            atomicOr(a.overflow, 4u);
+            if (a.sticky) atomicOr(a.sticky, 4u);
+        }
+        return;
+    }
     const int c0 = blockIdx.x * 16;
-    for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)];
+    if (c0 >= nt) return;  // the whole workgroup
+    const int nrows = (int)a.nbr;
+    uint32_t* bh = a.bh + (int64_t)v * a.nbr * a.stride;
+    for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * a.stride + c0 + (i & 15)];
     __syncthreads();
     const int col = t & 15, chunk = t >> 4;
     const int per = (nrows + 15) / 16, r0 = min(nrows, chunk * per), r1 = min(nrows, r0 + per);
@@ -715,55 +735,59 @@ __global__ __launch_bounds__(BLK) void k_bucket_colscan(uint32_t* __restrict__ b
     if (t < 16) {
         uint32_t run = 0;
         for (int k = 0; k < 16; ++k) {
-            const uint32_t v = csum[t][k];
+            const uint32_t x = csum[t][k];
             csum[t][k] = run;
-            run += v;
+            run += x;
         }
-        tot[c0 + t] = run;
-        csum[t][16] = run;
+        if (c0 + t < nt) a.tot[a.tile_offset[v] + c0 + t] = run;
+        csum[t][16] = run;  // (zero for the padding columns)
     }
     __syncthreads();
     if (t == 0) {
         uint64_t all = 0;
         for (int k = 0; k < 16; ++k) all += csum[k][16];
-        if (all) atomicAdd((unsigned long long*)n_pairs, (unsigned long long)all);
+        if (all) {
+            atomicAdd((unsigned long long*)a.n_pairs, (unsigned long long)all);
+            atomicAdd((unsigned long long*)(a.view_tot + v), (unsigned long long)all);
+        }
     }
     uint32_t run = csum[col][chunk];
     for (int r = r0; r < r1; ++r) {
-        const uint32_t v = sub[r * 16 + col];
+        const uint32_t x = sub[r * 16 + col];
         sub[r * 16 + col] = run;
-        run += v;
+        run += x;
     }
     __syncthreads();
-    for (int i = t; i < nrows * 16; i += BLK) bh[(uint64_t)(i >> 4) * G12 + c0 + (i & 15)] = sub[i];
+    for (int i = t; i < nrows * 16; i += BLK) bh[(uint64_t)(i >> 4) * a.stride + c0 + (i & 15)] = sub[i];
 }
 
-// block-wide exclusive scan of the 4096 counts c[] in place (4096 / NT consecutive per thread)
-template <int NT>
-__device__ __forceinline__ void block_excl_scan_4096(uint32_t* c, uint32_t* wsum) {
-    constexpr int PER = G12 / NT;
+// block-wide exclusive scan of the N counts c[] in place (N / NT consecutive per thread)
+template <int NT, int N>
+__device__ __forceinline__ void block_excl_scan_lds(uint32_t* c, uint32_t* wsum) {
+    constexpr int PER = N / NT;
     const int t = threadIdx.x;
-    uint32_t v[PER], s = 0;
+    uint32_t x[PER], s = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = c[t * PER + k];
-        s += v[k];
+        x[k] = c[t * PER + k];
+        s += x[k];
     }
     uint32_t tot;
     uint32_t run = block_excl_scan<NT>(s, tot, wsum);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         c[t * PER + k] = run;
-        run += v[k];
+        run += x[k];
     }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
-    __shared__ uint32_t cur[G12];  // next slot of every tile in this row's part of the bucket
+    __shared__ uint32_t cur[BUCKET_TILES];  // next slot of every tile in this row's part of the bucket
     __shared__ uint32_t wsum[BK_T / 64];
     __shared__ WaveStage st[BK_T / 64];
     __shared__ uint32_t s_db[BK_T / 64][64];
+    __shared__ uint64_t s_vstart;
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
     const bool first = blockIdx.x == 0 && blockIdx.y == 0;
     // the capacity check (every workgroup reads the complete total; the first sets the flags)
@@ -774,16 +798,33 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
         }
         return;
     }
-    // tile starts: exclusive scan of the totals (every row forms them; the first writes ranges)
-    for (int i = t; i < G12; i += BK_T) cur[i] = i < a.n_tiles ? a.tot[i] : 0u;
+    if (*a.overflow) return;  // a view too large for the rows (set by the column scans)
+    const int nt = view_tiles(a, v);
+    const int tbase = a.tile_offset[v];
+    // the view's first pair: the totals of the earlier views
+    if (t < 64) {
+        uint64_t s = 0;
+        for (int k = t; k < v; k += 64) s += a.view_tot[k];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (t == 0) s_vstart = s;
+    }
+    // tile starts within the view: exclusive scan of its totals (each view's first row writes
+    // the ranges)
+    for (int i = t; i < BUCKET_TILES; i += BK_T) cur[i] = i < nt ? a.tot[tbase + i] : 0u;
     __syncthreads();
-    block_excl_scan_4096<BK_T>(cur, wsum);
-    const uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * G12;
-    for (int i = t; i < a.n_tiles; i += BK_T) {
-        const uint32_t s0 = cur[i];
-        if (first) {
-            a.ranges[2 * i] = s0;
-            a.ranges[2 * i + 1] = s0 + a.tot[i];
+    block_excl_scan_lds<BK_T, BUCKET_TILES>(cur, wsum);
+    const uint32_t vstart = (uint32_t)s_vstart;  // (below 2^32 when the capacity check passed)
+    const uint32_t* row = a.bh + ((int64_t)v * a.nbr + blockIdx.x) * a.stride;
+    for (int i = t; i < nt; i += BK_T) {
+        const uint32_t s0 = vstart + cur[i];
+        if (blockIdx.x == 0) {
+            a.ranges[2 * (tbase + i)] = s0;
+            a.ranges[2 * (tbase + i) + 1] = s0 + a.tot[tbase + i];
         }
         cur[i] = s0 + row[i];
     }
@@ -792,7 +833,6 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
     const uint64_t* rv = a.rect + (int64_t)v * a.n;
     const float* dv = a.depth + (int64_t)v * a.n;
     const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
-    const uint32_t tbase = (uint32_t)a.tile_offset[v];
     {
         const int64_t eb = (int64_t)blockIdx.x * 16 + w;  // the wave's emission block
         if (eb * 256 >= a.n) return;  // the whole wave (no workgroup barrier below)
@@ -812,8 +852,8 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
             if (a.eoff && j < a.n) a.eoff[(int64_t)v * a.n + j] = run + wave_incl_scan(c) - c;
             s_db[w][l] = db;
             const int last = (int)min((int64_t)63, a.n - 1 - j0);
-            run += walk_pairs(st[w], c, r, last, tiles_x, tbase, [&](uint32_t, int L, uint32_t tile) {
-                if (tile >= (uint32_t)a.n_tiles) return;
+            run += walk_pairs(st[w], c, r, last, tiles_x, [&](uint32_t, int L, uint32_t tile) {
+                if (tile >= (uint32_t)nt) return;
                 const uint32_t pos = atomicAdd(&cur[tile], 1u);
                 if (pos < a.capacity) a.vout[pos] = ((uint64_t)s_db[w][L] << 32) | (uint32_t)(j0 + L);
             });
@@ -1206,11 +1246,14 @@ static int tile_bits(int n_tiles) {
 struct SortLayout {
     // control block, cleared at the start of every gs_bin_sort: scan chain, pass tickets,
     // digit histograms, deferred-tile count, LPT counters, pass status tables
-    size_t ctrl, scan, tickets, ghist, n_deferred, lpt, status, ctrl_end;
-    size_t offs, deferred, tk0, tk1, tv0, tv1, g12_bh, g12_tot, total;
+    size_t ctrl, scan, tickets, ghist, n_deferred, lpt, view_tot, status, ctrl_end;
+    size_t offs, deferred, tk0, tk1, tv0, tv1, bk_bh, bk_tot, total;
     int64_t nb_scan, nb_sort, nbr;
     int passes;
-    bool g12;  // emission into tile buckets (at most 4096 tiles)
+    // emission into tile buckets is possible: rows of a view and the histogram space (sized for
+    // views of up to min(n_tiles, BUCKET_TILES) tiles) within bounds; it is used when the
+    // largest view also has at most BUCKET_TILES tiles
+    bool bucket;
 };
 
 SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles) {
@@ -1221,7 +1264,11 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
     L.passes = std::max(1, (tile_bits(std::max(n_tiles, 1)) + 7) / 8);
     L.nbr = (n + EB_ROW - 1) / EB_ROW;
-    L.g12 = n_tiles <= G12 && L.nbr * (int64_t)std::max(n_views, 1) <= G12_MAX_ROWS;
+    // histogram rows of the widest view the bucket emission takes; kept within one value
+    // buffer's bytes (8 per pair of capacity), or 4 MB
+    const size_t bk_stride = (size_t)((std::min(std::max(n_tiles, 1), BUCKET_TILES) + 15) / 16 * 16);
+    const size_t bk_bytes = sizeof(uint32_t) * bk_stride * (size_t)L.nbr * (size_t)std::max(n_views, 1);
+    L.bucket = L.nbr <= BUCKET_MAX_ROWS && bk_bytes <= std::max<size_t>(8 * (size_t)capacity, (size_t)4 << 20);
     size_t p = 0;
     L.ctrl = p;
     L.scan = p;
@@ -1234,8 +1281,10 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     p = align256(p + sizeof(uint32_t));
     L.lpt = p;
     p = align256(p + sizeof(uint32_t) * 2 * LPT_B);
+    L.view_tot = p;
+    p = align256(p + sizeof(uint64_t) * (size_t)std::max(n_views, 1));
     L.status = p;
-    if (!L.g12) p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
+    p = align256(p + sizeof(uint64_t) * 256 * (size_t)L.nb_sort * (size_t)L.passes);
     L.ctrl_end = p;
     L.offs = p;  // pair offsets of the 256-entry emission blocks of every view
     p = align256(p + sizeof(uint32_t) * (size_t)((n + 255) / 256) * (size_t)std::max(n_views, 0));
@@ -1250,10 +1299,10 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     p = align256(p + v8);
     L.tv1 = p;
     p = align256(p + v8);
-    L.g12_bh = p;
-    if (L.g12) p = align256(p + sizeof(uint32_t) * G12 * (size_t)L.nbr * (size_t)std::max(n_views, 1));
-    L.g12_tot = p;
-    if (L.g12) p = align256(p + sizeof(uint32_t) * G12);
+    L.bk_bh = p;
+    if (L.bucket) p = align256(p + bk_bytes);
+    L.bk_tot = p;
+    if (L.bucket) p = align256(p + sizeof(uint32_t) * nt);
     L.total = p;
     return L;
 }
@@ -1356,6 +1405,11 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
         return launch_lpt(views, bins, nullptr, stream);
     }
 
+    // the largest view's tiles decide between the bucket emission and the entry-order grouping
+    const int mvt = views->max_view_tiles > 0 ? views->max_view_tiles : views->n_tiles;
+    const bool bucket = L.bucket && mvt <= BUCKET_TILES;
+    if (bucket) f.n[3] = (int64_t)((L.status - L.ctrl) / 4);  // (no onesweep status tables)
+
     // 1. pair sums of the emission blocks (clearing the state above first); with tile buckets
     // also every row's tile histogram
     const int64_t nbv = (n + 255) / 256;
@@ -1369,11 +1423,12 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ba.nbv = nbv;
     ba.nbr = L.nbr;
     ba.tile_w = views->tile_w;
-    ba.n_tiles = views->n_tiles;
-    ba.ncols = (views->n_tiles + 15) / 16 * 16;
+    ba.n_views = views->n_views;
+    ba.stride = (std::min(mvt, views->n_tiles) + 15) / 16 * 16;
     ba.bsum = U32(L.offs);
-    ba.bh = U32(L.g12_bh);
-    ba.tot = U32(L.g12_tot);
+    ba.bh = U32(L.bk_bh);
+    ba.tot = U32(L.bk_tot);
+    ba.view_tot = U64(L.view_tot);
     ba.overflow = bins->overflow;
     ba.sticky = bins->overflow_sticky;
     ba.n_pairs = bins->n_pairs;
@@ -1383,7 +1438,7 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ba.eoff = bins->entry_offset;
     uint64_t* vin;
     uint64_t* valt;
-    if (L.g12) {
+    if (bucket) {
         // (the emission blocks' pair offsets are only scanned when the entries' first pairs
         // are asked for; the column scans give the pair total and the emission its check)
         hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba, f);
@@ -1392,8 +1447,8 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
                                (uint64_t*)nullptr, (uint32_t*)nullptr, bins->capacity, (uint32_t*)nullptr);
         // 2. per-tile prefixes over the rows, tile totals and the pair total, 3. pairs written
         // into their tiles
-        hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.ncols / 16)), dim3(BLK), 0, stream, U32(L.g12_bh),
-                           (int)(L.nbr * views->n_views), U32(L.g12_tot), bins->n_pairs);
+        hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.stride / 16), (unsigned)views->n_views), dim3(BLK), 0,
+                           stream, ba);
         hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba);
         vin = U64(L.tv1);
         valt = U64(L.tv0);

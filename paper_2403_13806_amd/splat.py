@@ -120,6 +120,7 @@ class ViewBatch:
         self.tile_offset_host = np.array(toff[:], np.int64)
         self.pixel_offset_host = np.array(poff[:], np.int64)
         self.n_tiles = int(self.tile_offset_host[-1])
+        self.max_view_tiles = int(np.diff(self.tile_offset_host).max()) if self.n_views else 0
         self.n_pixels = int(self.pixel_offset_host[-1])
         raw = bytes(arr)
         self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
@@ -130,7 +131,7 @@ class ViewBatch:
     def struct(self) -> L.gs_views:
         return L.gs_views(_ptr(self.cams_dev), _ptr(self.tile_offset), _ptr(self.pixel_offset), self.n_views,
                           self.tile[0], self.tile[1], self.n_tiles, self.n_pixels, self.batch_depth,
-                          int(self.lpt), self.pixels_per_lane, 0)
+                          int(self.lpt), self.pixels_per_lane, self.max_view_tiles)
 
     def image(self, rgb: torch.Tensor, v: int) -> torch.Tensor:
         """View v's planar [3][H][W] image inside a global rgb buffer."""

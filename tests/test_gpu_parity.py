@@ -100,6 +100,69 @@ def test_keys_bit_exact(case, tile):
             assert ranges[tid, 0] == ranges[tid, 1]
 
 
+@pytest.mark.parametrize("path", ["buckets", "entry_order"])
+def test_keys_bit_exact_multi_view(path):
+    """A batch of views of uneven size binned in one call: keys, values, ranges and the
+    entries' first pairs bit-exact against the oracle's (key, value) order over the views. The
+    views' tiles go straight into per-view tile buckets ("buckets"); with a 2048x1152 view added
+    (9216 tiles at 16x16, more than the buckets hold) the pairs are written in entry order and
+    grouped by radix passes instead ("entry_order")."""
+    sc = scenes.mixture_scene(12000, seed=12, sh_degree=1)
+    sizes = [(197, 141), (320, 180), (64, 48)] + ([(2048, 1152)] if path == "entry_order" else [])
+    cams = scenes.uneven_views(sizes)
+    _say(f"multi-view keys ({path})")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch(cams, (16, 16), DEV)
+    assert (views.max_view_tiles > 8192) == (path == "entry_order")
+    proj = gs.preprocess(g, views, P)
+    bins = gs.bin_sort(proj, views, backward=True)
+    torch.cuda.synchronize()
+    npairs = int(bins.n_pairs.item())
+    assert int(bins.overflow.item()) == 0
+    keys = bins.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = bins.vals[:npairs].cpu().numpy().view(np.uint32)
+    depths, rects, counts = [], [], []
+    for v in range(len(cams)):
+        t = splat_table(proj, v)
+        depths.append(t["depth"])
+        rects.append(np.where((t["count"] > 0)[:, None], t["rect"], np.array([0, 0, -1, -1])))
+        counts.append(t["count"].astype(np.int64))
+    k1, v1 = oracle.pairs(depths, rects, [(c.width, c.height) for c in cams], (16, 16))
+    assert np.array_equal(keys, k1) and np.array_equal(vals, v1)
+    lens = np.bincount((k1 >> np.uint64(32)).astype(np.int64), minlength=views.n_tiles)
+    ranges = bins.ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    assert np.array_equal(ranges[:, 1] - ranges[:, 0], lens)
+    assert np.array_equal(ranges[lens > 0, 0], starts[lens > 0])
+    eoff = bins.entry_offset.cpu().numpy().view(np.uint32).astype(np.int64)
+    c = np.concatenate(counts)
+    assert np.array_equal(eoff, np.concatenate([[0], np.cumsum(c)[:-1]]))
+
+
+def test_bucket_view_larger_than_declared():
+    """A batch whose largest view has more tiles than max_view_tiles declares: the bins report
+    bit 2 of the overflow word (and the sticky word), the tile ranges stay empty, and the next
+    frame with a correct declaration bins normally."""
+    sc = scenes.mixture_scene(4000, seed=13, sh_degree=1)
+    cams = scenes.uneven_views([(197, 141), (320, 180)])
+    _say("bucket emission with an understated max_view_tiles")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    views = gs.ViewBatch(cams, (16, 16), DEV)
+    true_max = views.max_view_tiles
+    proj = gs.preprocess(g, views, P)
+    bins = gs.Bins(1 << 20, views.n_tiles, DEV)
+    views.max_view_tiles = 120  # the 320x180 view has 20 x 12 = 240 tiles
+    gs.bin_sort(proj, views, bins=bins, grow=False)
+    torch.cuda.synchronize()
+    assert int(bins.overflow.item()) & 4
+    assert int(bins.overflow_sticky.item()) & 4
+    assert torch.all(bins.ranges == 0)
+    views.max_view_tiles = true_max
+    gs.bin_sort(proj, views, bins=bins, grow=False)
+    torch.cuda.synchronize()
+    assert int(bins.overflow.item()) == 0 and int(bins.n_pairs.item()) > 0
+
+
 @pytest.mark.parametrize("spread", [1.0, 0.03, 0.0])
 def test_keys_bit_exact_with_depth_ties(spread):
     """Groups of Gaussians sharing one position (equal FP32 depths, so the order inside a tile

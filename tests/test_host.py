@@ -145,6 +145,12 @@ def test_argument_errors_are_reported_before_launch():
     v4.lpt = 1  # bins has no queue
     assert lib.gs_importance(R(out), R(v4), R(b), R(p), ctypes.c_void_p(16), None) == L.GS_ERR_INVALID_ARG
     assert b"queue" in lib.gs_last_error()
+    # the largest view's tile count lies in [0, n_tiles]
+    v6 = _dummy_views()
+    for bad in (-1, v6.n_tiles + 1):
+        v6.max_view_tiles = bad
+        assert lib.gs_preprocess(R(g), R(v6), R(p), None, 0, 1, R(out), None) == L.GS_ERR_INVALID_ARG
+        assert b"max_view_tiles" in lib.gs_last_error()
 
 
 def test_prune_argument_errors():
