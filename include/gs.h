@@ -242,8 +242,9 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* 
  * arguments and results as gs_bin_sort; the scratch is a static device array of
  * GS_BIN_SORT_NOALLOC_BYTES (64 MiB) that each GPU the library runs on holds until the
  * process ends (its address is looked up once per device, on the first call). The call
- * allocates nothing. A frame whose scratch need (the gs_bin_sort workspace, about 25 bytes per
- * pair of capacity plus 2 KB per 256 entries) exceeds it returns GS_ERR_UNSUPPORTED before
+ * allocates nothing. A frame whose scratch need (the gs_bin_sort workspace: about 25 bytes per
+ * pair of capacity, plus 4 bytes per 4096 entries and tile of the largest view, at most 8192)
+ * exceeds it returns GS_ERR_UNSUPPORTED before
  * anything is enqueued. Every call on one GPU shares that GPU's scratch, which keeps the last
  * call's contents (each call clears what it needs itself): calls that overlap on one GPU
  * (other streams, other threads) race, so serialise them. */
