@@ -205,19 +205,21 @@ def main():
     n = g.n
     mp, mc, mt, mv = (float(np.mean(x)) for x in (pairs, composites, tested, visible))
     n_tiles = rs[0].views.n_tiles
-    one_pass = n_tiles <= 4096  # grouping in one 12-bit counting pass, else onesweep radix passes
-    passes = 1 if one_pass else max(1, (int(np.ceil(np.log2(n_tiles))) + 7) // 8)
+    buckets = n_tiles <= 8192  # pairs emitted straight into per-view tile buckets, else onesweep radix passes
+    passes = 1 if buckets else max(1, (int(np.ceil(np.log2(n_tiles))) + 7) // 8)
     bytes_pre = 4 * n * (3 + 3 + 4 + 1 + 48) + 4 * n + mv * (SPLAT + 4 + 8)
-    # block sums (count in), emit (count per entry, rect + depth per visible entry, 12 B per pair
-    # out); one pass: block tile histograms (4 B per pair in, 16 KB per 4096 pairs out, scanned in
-    # place, read once more), scatter (12 B in, 8 B out per pair); onesweep: digit histogram
-    # (4 B per pair), passes (12 B in + 12 B out per pair each), ranges (4 B per pair); then the
-    # per-tile sort (8 B in, 12 B out per pair) and the ranges
-    if one_pass:
-        grouping = mp * (4 + 20) + 4 * 16384 * np.ceil(mp / 4096)
+    # buckets: two walks over the entries (count per entry, rectangle per visible entry, and in
+    # the second the depth too), one row of tile counts per 4096 entries (written, scanned in
+    # place, read by the emission: 4 passes of 4 B per tile), 8 B per pair into its tile's range.
+    # Entry order: block sums (count in), emission (count per entry, rect + depth per visible
+    # entry, 12 B per pair out), digit histogram (4 B per pair), passes (12 B in + 12 B out per
+    # pair each), ranges (4 B per pair). Then the per-tile sort (8 B in, 12 B out per pair) and
+    # the ranges
+    if buckets:
+        stride = (n_tiles + 15) // 16 * 16
+        bytes_sort = 8 * n + 24 * mv + 16 * stride * np.ceil(n / 4096) + mp * (8 + 20) + n_tiles * 12
     else:
-        grouping = mp * (4 + passes * 24 + 4)
-    bytes_sort = (4 + 8) * n + 12 * mv + mp * (12 + 20) + grouping + n_tiles * 8
+        bytes_sort = (4 + 8) * n + 12 * mv + mp * (12 + 20) + mp * (4 + passes * 24 + 4) + n_tiles * 8
     bytes_render = mp * (4 + SPLAT) + npx * (12 + 4 + 4) + rs[0].views.n_tiles * 8
     ops_render = OPS_PER_COMPOSITE * mc
     ops_imp, ops_bwd = OPS_PER_IMPORTANCE * mc, OPS_PER_BACKWARD * mc
@@ -226,7 +228,8 @@ def main():
                        "hbm_frac": bytes_pre / avg["preprocess"] / 1e-3 / PEAK_HBM},
         "bin_sort": {"ms": avg["bin_sort"], "alg_GBps": bytes_sort / avg["bin_sort"] / 1e6,
                      "hbm_frac": bytes_sort / avg["bin_sort"] / 1e-3 / PEAK_HBM,
-                     "grouping": "one 12-bit counting pass" if one_pass else f"{passes} onesweep radix passes"},
+                     "grouping": "tile buckets (per-view LDS histograms, no grouping pass)" if buckets
+                     else f"{passes} onesweep radix passes"},
         "render_fwd": {"ms": avg["render_fwd"], "alg_Tops": ops_render / avg["render_fwd"] / 1e9,
                        "alu_frac": ops_render / avg["render_fwd"] / 1e-3 / PEAK_LANE_OPS,
                        "alg_GBps": bytes_render / avg["render_fwd"] / 1e6,
