@@ -36,6 +36,7 @@ OPS_PER_COMPOSITE = 23
 OPS_PER_IMPORTANCE = 20
 OPS_PER_BACKWARD = 47
 TILE = (16, 32)  # tile of the headline frames (fastest measured: fewer pairs to sort than 16x16)
+LPT = True  # longest list first: the compositing tiles' order (its queue is built inside the binning)
 PX = 2 if TILE[0] >= 16 and TILE[0] * TILE[1] >= 512 else 1  # pixels per lane the library picks for it
 RENDER_KERNEL = f"k_render<{TILE[0]},{TILE[1]},1,0,{PX}>"
 SPLAT = 64
@@ -116,7 +117,7 @@ def main():
     cams = scenes.orbit_views(8)
     g = gs.Gaussians.from_scene(sc, dev)
     # forward-only frames: the pairs' emission slots (the backward's input) are not kept
-    rs = [gs.Renderer(g, gs.ViewBatch([c], TILE, dev), P, backward=False) for c in cams]
+    rs = [gs.Renderer(g, gs.ViewBatch([c], TILE, dev, lpt=LPT), P, backward=False) for c in cams]
     torch.cuda.synchronize()
 
     # ---------------- headline: plain forward frames/s ----------------
@@ -158,7 +159,7 @@ def main():
     for r, cam0 in zip(rs, cams):
         s = _stream(dev)
         # the reverse call runs on a renderer that keeps the emission slots, after its forward
-        rb = gs.Renderer(g, gs.ViewBatch([cam0], TILE, dev), P, capacity=r.bins.capacity)
+        rb = gs.Renderer(g, gs.ViewBatch([cam0], TILE, dev, lpt=LPT), P, capacity=r.bins.capacity)
         rb.forward()
         for _ in range(reps):
             with Timer(torch) as a:
@@ -288,7 +289,8 @@ def main():
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "1M Gaussians (mixture of 32 clusters, SH degree 3), 1256x828, 8 orbit views, "
                                "plain forward per frame", "gaussians": n, "width": 1256, "height": 828,
-                   "views": 8, "tile": f"{TILE[0]}x{TILE[1]}", "parallelism": "single GPU"},
+                   "views": 8, "tile": f"{TILE[0]}x{TILE[1]}",
+                   "tile_order": "longest-first" if LPT else "tile index", "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
@@ -353,7 +355,7 @@ def prune_pass(torch, gs, g, h, dev, t_prune=0.01, reps=5):
 def pipelined_frames(torch, gs, P, dev, g, cams, K, W):
     """The headline frames rendered by PathRenderer(pipeline=2)."""
     from paper_2403_13806_amd.splat import PathRenderer
-    pipe = PathRenderer(g, cams, P, device=dev, pipeline=2)
+    pipe = PathRenderer(g, cams, P, tile=TILE, device=dev, lpt=LPT, pipeline=2)
     for k in range(W):
         pipe.frame(k % len(cams))
     pipe.sync()

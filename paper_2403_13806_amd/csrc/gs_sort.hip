@@ -1232,6 +1232,32 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint32_t* __restrict_
     }
 }
 
+// The same order from one workgroup, for at most LPT_ONE_TILES tiles: bucket counts in LDS,
+// their descending scan, then every tile placed by an LDS counter of its bucket (one launch).
+constexpr int LPT_ONE_T = 1024, LPT_ONE_TILES = 65536;
+
+__global__ __launch_bounds__(LPT_ONE_T) void k_lpt_one(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                       uint32_t* __restrict__ queue) {
+    __shared__ uint32_t lh[LPT_B], base[LPT_B];
+    const int t = threadIdx.x;
+    if (t < LPT_B) lh[t] = 0;
+    __syncthreads();
+    for (int i = t; i < n_tiles; i += LPT_ONE_T) atomicAdd(&lh[lpt_bucket(ranges, i)], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int b = LPT_B - 1; b >= 0; --b) {
+            base[b] = acc;
+            acc += lh[b];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n_tiles; i += LPT_ONE_T) {
+        const uint32_t pos = atomicAdd(&base[lpt_bucket(ranges, i)], 1u);
+        if (pos < (uint32_t)n_tiles) queue[pos] = (uint32_t)i;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------------------
@@ -1318,6 +1344,10 @@ static gs_status launch_lpt(const gs_views* views, gs_bins* bins, uint32_t* lpt,
     const unsigned g = (unsigned)((views->n_tiles + 255) / 256);
     if (!lpt) {
         hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, stream, bins->queue, views->n_tiles);
+        return check_launch("bin_sort");
+    }
+    if (views->n_tiles <= LPT_ONE_TILES) {
+        hipLaunchKernelGGL(k_lpt_one, dim3(1), dim3(LPT_ONE_T), 0, stream, bins->ranges, views->n_tiles, bins->queue);
         return check_launch("bin_sort");
     }
     hipLaunchKernelGGL(k_lpt_hist, dim3(std::min(g, 1024u)), dim3(256), 0, stream, bins->ranges, views->n_tiles, lpt);
