@@ -879,6 +879,7 @@ struct TileSortArgs {
     uint32_t* n_deferred;  // number of deferred tiles (zero on entry)
     uint32_t* deferred;    // [n_tiles] their ids
     uint32_t* sticky;      // OR-ed with the overflow word, or NULL
+    const uint32_t* order; // tiles longest list first (workgroup b sorts order[b]), or NULL
 };
 
 // Ascending bitonic sort of s[0, N) by a 256-thread workgroup (N a power of two >= 2).
@@ -966,8 +967,8 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
     __shared__ uint32_t ds[256];
     __shared__ uint32_t wsum[BLK / 64];
     __shared__ uint32_t diff, ties;
-    const int tile = blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
-    if (*a.overflow) return;
+    const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (*a.overflow || tile >= a.n_tiles) return;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     if (end <= start || (uint64_t)end > a.capacity) return;
     const int len = (int)(end - start);
@@ -1490,7 +1491,9 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
         if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
         launch_entry_order_grouping(proj, views, bins, L, w, stream, vin, valt);
     }
-    // 5. each tile's list by (depth, index); keys and values
+    // 5. the longest-first order when asked for (from the ranges; the tile sort takes the longest
+    // lists first too), 6. each tile's list by (depth, index); keys and values
+    if ((st = launch_lpt(views, bins, U32(L.lpt), stream))) return st;
     TileSortArgs ta;
     ta.pairs = vin;
     ta.scratch = valt;
@@ -1503,9 +1506,10 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ta.n_deferred = U32(L.n_deferred);
     ta.deferred = U32(L.deferred);
     ta.sticky = bins->overflow_sticky;
+    ta.order = bins->queue;
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)views->n_tiles), dim3(256), 0, stream, ta);
     hipLaunchKernelGGL(k_tile_sort_large, dim3((unsigned)std::min(views->n_tiles, 512)), dim3(256), 0, stream, ta);
-    return launch_lpt(views, bins, U32(L.lpt), stream);
+    return check_launch("bin_sort");
 }
 
 // ---------------------------------------------------------------------------------------
