@@ -215,6 +215,7 @@ class TrainConfig:
     seed: int = 0
     headroom: float = 2.0
     check_every: int = 1000
+    lpt: bool = True  # the traversals take the step view's tiles longest list first
 
     @classmethod
     def light(cls, **kw) -> "TrainConfig":
@@ -269,7 +270,7 @@ class Trainer:
     def _set_gaussians(self, g: Gaussians, m: Gaussians, v: Gaussians):
         self.g, self.m, self.v = g, m, v
         self.grad = zero_grads(g)
-        self.view = ViewBatch([self.cams[0]], self.tile, self.device)
+        self.view = ViewBatch([self.cams[0]], self.tile, self.device, lpt=self.cfg.lpt)
         self.r = Renderer(g, self.view, self.params, capacity=self._capacity(g))
 
     def _capacity(self, g: Gaussians) -> int:
