@@ -339,8 +339,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 // ---------------------------------------------------------------------------------------
 // Reverse mode: chain per-(view, Gaussian) gradients of the 2D quantities (u, v, conic
 // a, b, c, opacity, rgb) to the parameters (the per-entry sums over the entry's pairs, formed
-// in a fixed order by the reverse traversal's last step). One thread per Gaussian, looping
-// over the views of the batch, so each Gaussian's gradient is owned by one thread (no atomics).
+// in a fixed order by the reverse traversal's last step). One lane per Gaussian, looping
+// over the views of the batch, so each Gaussian's gradient is owned by one lane (no atomics).
 // This kernel covers position (through u, v and J), scale, rotation and opacity; the
 // colour part follows in k_preprocess_bwd_sh. Adding reads and writes only the gradients of
 // Gaussians some pair contributes to; overwriting writes every one and reads none, which halves
@@ -401,48 +401,31 @@ __device__ __forceinline__ Geom load_geom_rows(const PreBwdArgs& a, int64_t i0, 
     return g;
 }
 
-__global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
-    // rows of the wave's 64 Gaussians at scalar addresses, the lane's element by its offset
-    const int64_t i0 = (int64_t)blockIdx.x * 128 + 64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t lb = (threadIdx.x & 63u) * 4u;
+// The parameter chain of one Gaussian that some view composited (byte offset lb from the row
+// base i0): every view's 2D gradients chained back in view order, then written (or added).
+__device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint32_t lb, bool acc) {
     const int64_t n = a.n;
-    if (i0 + (lb >> 2) >= n) return;
     auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
-    const bool acc = !a.overwrite;
-    float old[11];
-#pragma unroll
-    for (int k = 0; k < 11; ++k) old[k] = 0.f;
-    if (*a.overflow) {
-        if (acc) return;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) grow(a.gmean, k) = 0.f, grow(a.gscale, k) = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) grow(a.gquat, k) = 0.f;
-        grow(a.gopac, 0) = 0.f;
-        return;
-    }
     const int64_t VN = (int64_t)a.n_views * n;
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
     bool any = false;
-    // where the first view composited this Gaussian, its 2D gradients, its parameters and the
-    // gradients accumulated so far are requested together, in one round of loads
+    // parameters, the first view's count and 2D gradients and the gradients accumulated so far
+    // are requested together, in one round of loads
+    const Geom gm = load_geom_rows(a, i0, lb);
     const uint32_t cnt0 = lane(uniform_ptr(a.count + i0), lb);
-    const bool pre = cnt0 != 0;
-    float g20[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    Geom gm{};
-    if (pre) {
+    float g20[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g20[k] = lane(uniform_ptr(a.g2 + k * VN + i0), lb);
-        gm = load_geom_rows(a, i0, lb);
-        if (acc) {
+    for (int k = 0; k < 6; ++k) g20[k] = lane(uniform_ptr(a.g2 + k * VN + i0), lb);
+    float old[11];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
+    for (int k = 0; k < 11; ++k) old[k] = 0.f;
+    if (acc) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
-            old[10] = grow(a.gopac, 0);
-        }
+        for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
+        old[10] = grow(a.gopac, 0);
     }
-    bool have_geom = pre;
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t o = (int64_t)v * n + i0;
         if ((v == 0 ? cnt0 : lane(uniform_ptr(a.count + o), lb)) == 0) continue;
@@ -452,10 +435,6 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         const float gu = g6[0], gv = g6[1], gA = g6[2], gB = g6[3], gC = g6[4], gO = g6[5];
         if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) continue;
         any = true;
-        if (!have_geom) {
-            gm = load_geom_rows(a, i0, lb);
-            have_geom = true;
-        }
         const gs_camera cam = a.cams[v];
         Proj P;
         double op;
@@ -535,15 +514,8 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         gq[1] += (gx - x * dot) * iqn;
         gq[2] += (gy - y * dot) * iqn;
         gq[3] += (gz - zq * dot) * iqn;
-    }
+        }
     if (!any && acc) return;
-    if (!pre && acc) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
-        old[10] = grow(a.gopac, 0);
-    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         grow(a.gmean, k) = old[k] + (float)gp[k];
@@ -554,6 +526,69 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
     grow(a.gopac, 0) = old[10] + (float)go;
 }
 
+// One wave per workgroup takes BWD_CHUNK consecutive Gaussians. It lists in LDS those that some
+// view composited and runs the parameter chain on them 64 at a time, so the long FP64 chain
+// runs on nearly full waves even where few Gaussians are visible (about one in five for one
+// view of a large scene, spread over every wave in random storage order); the others get
+// zeros when overwriting and nothing when adding.
+constexpr int BWD_CHUNK = 256;
+
+__global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
+    __shared__ uint16_t s_list[BWD_CHUNK];
+    const int64_t i0 = (int64_t)blockIdx.x * BWD_CHUNK;
+    const uint32_t l = threadIdx.x;
+    const int64_t n = a.n;
+    const bool acc = !a.overwrite;
+    auto zero = [&](uint32_t lb) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lane(uniform_ptr(a.gmean + k * n + i0), lb) = 0.f;
+            lane(uniform_ptr(a.gscale + k * n + i0), lb) = 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lane(uniform_ptr(a.gquat + k * n + i0), lb) = 0.f;
+        lane(uniform_ptr(a.gopac + i0), lb) = 0.f;
+    };
+    if (*a.overflow) {  // nothing is added after a pair overflow; zeros are written when overwriting
+        if (acc) return;
+        for (uint32_t li = l; li < BWD_CHUNK; li += 64)
+            if (i0 + li < n) zero(li * 4u);
+        return;
+    }
+    // the chunk's counts in the first view are requested together; later views are read only
+    // for Gaussians not yet found composited
+    constexpr int NS = BWD_CHUNK / 64;
+    uint32_t cnt[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const uint32_t li = 64 * j + l;
+        cnt[j] = i0 + li < n ? lane(uniform_ptr(a.count + i0), li * 4u) : 0u;
+    }
+    uint64_t act_mask[NS];
+    uint32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const uint32_t li = 64 * j + l;
+        bool act = cnt[j] != 0;
+        for (int v = 1; i0 + li < n && !act && v < a.n_views; ++v)
+            act = lane(uniform_ptr(a.count + (int64_t)v * n + i0), li * 4u) != 0;
+        act_mask[j] = ballot(act);
+        if (act) s_list[total + mask_rank(act_mask[j])] = (uint16_t)li;
+        total += (uint32_t)__builtin_popcountll(act_mask[j]);
+    }
+    __syncthreads();
+    for (uint32_t b = 0; b < total; b += 64)
+        if (b + l < total) geom_chain(a, i0, (uint32_t)s_list[b + l] * 4u, acc);
+    // zeros for the rest, after the chain's loads so they do not wait behind these stores
+    if (!acc) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const uint32_t li = 64 * j + l;
+            if (i0 + li < n && !((act_mask[j] >> l) & 1)) zero(li * 4u);
+        }
+    }
+}
+
 // Colour part of the reverse mode: SH coefficient gradients and the mean gradient through
 // the view direction. Split from the geometric part so that neither kernel carries the
 // other's registers. A workgroup takes 64 G Gaussians with 3 G waves: wave (c, s) holds colour
@@ -561,9 +596,12 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
 // 48), so the G waves of a channel read and write 256 G contiguous bytes of each coefficient
 // plane together (G = 4 measured fastest for one view, G = 1 for several, where each lane
 // walks every view). The channels' mean-gradient parts are added through LDS at the end, onto
-// what the geometric part left (written or added).
+// what the geometric part left (written or added). The kernel streams the coefficient planes
+// (read once, written once), so what bounds it is the memory requests in flight: the register
+// budget is held to six waves per SIMD, two workgroups per CU at G = 4, and the gradient rows
+// are stored past the caches.
 template <int DEG, int G>
-__global__ __launch_bounds__(192 * G) void k_preprocess_bwd_sh(PreBwdArgs a) {
+__global__ __launch_bounds__(192 * G) __attribute__((amdgpu_waves_per_eu(6))) void k_preprocess_bwd_sh(PreBwdArgs a) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     __shared__ float s_gp[3][3][64 * G];
     __shared__ uint32_t s_any[3][64 * G];
@@ -606,11 +644,6 @@ __global__ __launch_bounds__(192 * G) void k_preprocess_bwd_sh(PreBwdArgs a) {
         cnt0 = lane(uniform_ptr(a.count + i0), lb);
         gc0 = lane(uniform_ptr(a.g2 + g2o), lb);
     }
-    // the accumulated SH gradient is read early where the first view composited this Gaussian
-    float old[NB];
-    const bool pre = acc && valid && cnt0 != 0 && gc0 != 0.f;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) old[k] = pre ? lane(row(a.gsh, k), lb) : 0.f;
     double gp[3] = {0, 0, 0};
     bool any = false;
     for (int v = 0; valid && v < a.n_views; ++v) {
@@ -643,12 +676,17 @@ __global__ __launch_bounds__(192 * G) void k_preprocess_bwd_sh(PreBwdArgs a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) s_gp[c][k][ls] = (float)gp[k];
     s_any[c][ls] = any ? 1u : 0u;
-    if (valid && (any || !acc)) {
+    // written rows are not read again here: streamed past the caches. (Two branches, so that
+    // no read of the old gradient is speculated into the writing one.)
+    if (valid && acc && any) {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             GS_GLOBAL float& q = lane(row(a.gsh, k), lb);
-            q = (pre || !acc ? old[k] : q) + gsh[k];
+            q = q + gsh[k];
         }
+    } else if (valid && !acc) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) __builtin_nontemporal_store(0.f + gsh[k], &lane(row(a.gsh, k), lb));
     }
     __syncthreads();
     if (c == 0 && valid && (s_any[0][ls] | s_any[1][ls] | s_any[2][ls])) {
@@ -730,8 +768,8 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gquat = grad->quat;
     a.gopac = grad->opacity;
     a.gsh = grad->sh;
-    const dim3 grid((unsigned)((g->n + 127) / 128));
-    hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(128), 0, stream, a);
+    const dim3 grid((unsigned)((g->n + BWD_CHUNK - 1) / BWD_CHUNK));
+    hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(64), 0, stream, a);
     // colour part: 64 G Gaussians x 3 channels per workgroup
     switch (g->sh_degree) {
         case 0: launch_bwd_sh<0>(views->n_views == 1, g->n, stream, a); break;
