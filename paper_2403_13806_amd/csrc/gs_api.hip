@@ -33,7 +33,8 @@ gs_status check_launch(const char* what) {
 gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_params*, const int32_t*, int64_t, int,
                             gs_projected*, hipStream_t);
 gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
-                                const gs_bins*, const float*, gs_gaussians_grad*, hipStream_t);
+                                const gs_bins*, const float*, float*, gs_gaussians_grad*, hipStream_t);
+bool bwd_sums_in_chain(const gs_views*);
 gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t);
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
@@ -64,7 +65,7 @@ gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*
 gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
                             int32_t, float, uint32_t*, hipStream_t);
 gs_status launch_render_bwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const float*,
-                            const uint32_t*, const float*, float*, float*, hipStream_t);
+                            const uint32_t*, const float*, float*, float*, bool, hipStream_t);
 
 // nine FP32 partial gradients per pair slot, then their nine sums per (view, entry)
 static size_t bwd_slots_bytes(uint64_t capacity) { return (sizeof(float) * 9 * (size_t)capacity + 255) & ~(size_t)255; }
@@ -318,8 +319,10 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_p
     hipStream_t s = (hipStream_t)stream;
     float* slots = (float*)ws;
     float* g2 = (float*)((char*)ws + bwd_slots_bytes(bins->capacity));
-    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, slots, g2, s))) return st;
-    return launch_preprocess_bwd(g, views, p, proj, bins, g2, grad, s);
+    const bool pair_sums = !bwd_sums_in_chain(views);
+    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, slots, g2, pair_sums, s)))
+        return st;
+    return launch_preprocess_bwd(g, views, p, proj, bins, slots, g2, grad, s);
 }
 
 gs_status gs_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,

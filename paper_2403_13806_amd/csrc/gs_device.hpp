@@ -88,6 +88,34 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// one step of a segmented scan of nine fields keyed by the owner lane L
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_step(int L, float (&x)[9]) {
+    const int Ld = __builtin_amdgcn_update_dpp(-1, L, CTRL, ROW_MASK, 0xf, false);
+    const bool merge = Ld == L;
+#pragma unroll
+    for (int f = 0; f < 9; ++f) {
+        const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[f]), CTRL, ROW_MASK, 0xf, true));
+        x[f] = merge ? x[f] + y : x[f];
+    }
+}
+
+// Segmented inclusive scan of nine fields over the wave's lanes, runs keyed by the owner L
+// (non-decreasing over the lanes; a lane with a unique key is a run of its own), with the
+// steps of a wave scan: shifts by 1, 2, 4, 8 inside each row of 16, then the last lane of a
+// row added into the next rows. A lane adds what arrives only from a lane of its own run (a
+// source with the same owner means every lane in between has it too); lanes that receive
+// nothing get zeros. The last lane of each run ends with the run's sum, formed in the same
+// order on every call. Must be called with all 64 lanes active.
+__device__ __forceinline__ void seg_scan9(int L, float (&x)[9]) {
+    seg_step<0x111, 0xf>(L, x);
+    seg_step<0x112, 0xf>(L, x);
+    seg_step<0x114, 0xf>(L, x);
+    seg_step<0x118, 0xf>(L, x);
+    seg_step<0x142, 0xa>(L, x);
+    seg_step<0x143, 0xc>(L, x);
+}
+
 // ---------------------------------------------------------------------------------------
 // View lookup for a global tile id: largest v with tile_offset[v] <= tile.
 // ---------------------------------------------------------------------------------------

@@ -360,6 +360,12 @@ struct PreBwdArgs {
     gs_params p;
     const uint32_t* count;   // [V][n]
     const float* g2;         // [9][V*n], read where count > 0
+    // one view: the pair slots are summed here instead (entry o owns the nine-float slots
+    // [eoff[o], eoff[o] + count[o])), and only the colour fields 6..8 are written to g2w
+    const uint32_t* eoff;
+    const float* slots;
+    uint64_t capacity;
+    float* g2w;
     const uint32_t* overflow;  // nothing is added after a pair overflow (zeros written when overwriting)
     int overwrite;             // 1: write every gradient (=) instead of adding (+=)
     float* gmean;
@@ -403,7 +409,10 @@ __device__ __forceinline__ Geom load_geom_rows(const PreBwdArgs& a, int64_t i0, 
 
 // The parameter chain of one Gaussian that some view composited (byte offset lb from the row
 // base i0): every view's 2D gradients chained back in view order, then written (or added).
-__device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint32_t lb, bool acc) {
+// With SUMS the first (only) view's 2D gradients come from the workgroup's sums sg in LDS.
+template <bool SUMS>
+__device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint32_t lb, bool acc,
+                                           const float (*sg)[9]) {
     const int64_t n = a.n;
     auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
     const int64_t VN = (int64_t)a.n_views * n;
@@ -415,7 +424,7 @@ __device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint
     const uint32_t cnt0 = lane(uniform_ptr(a.count + i0), lb);
     float g20[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) g20[k] = lane(uniform_ptr(a.g2 + k * VN + i0), lb);
+    for (int k = 0; k < 6; ++k) g20[k] = SUMS ? sg[lb >> 2][k] : lane(uniform_ptr(a.g2 + k * VN + i0), lb);
     float old[11];
 #pragma unroll
     for (int k = 0; k < 11; ++k) old[k] = 0.f;
@@ -531,10 +540,18 @@ __device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint
 // runs on nearly full waves even where few Gaussians are visible (about one in five for one
 // view of a large scene, spread over every wave in random storage order); the others get
 // zeros when overwriting and nothing when adding.
+// With SUMS (one view) the wave first sums its Gaussians' pair slots itself: their slots form
+// one range, read 64 at a time (coalesced) and reduced by a segmented scan whose run ends add
+// into the owner's sums in LDS, round after round (the same additions, in the same order, as
+// k_pair_sums makes); the colour fields go to g2 for the SH kernel.
 constexpr int BWD_CHUNK = 256;
 
+template <bool SUMS>
 __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
     __shared__ uint16_t s_list[BWD_CHUNK];
+    __shared__ uint32_t s_beg[SUMS ? BWD_CHUNK : 1];
+    __shared__ float s_g[SUMS ? BWD_CHUNK : 1][9];
+    __shared__ uint32_t s_end;
     const int64_t i0 = (int64_t)blockIdx.x * BWD_CHUNK;
     const uint32_t l = threadIdx.x;
     const int64_t n = a.n;
@@ -558,11 +575,14 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
     // the chunk's counts in the first view are requested together; later views are read only
     // for Gaussians not yet found composited
     constexpr int NS = BWD_CHUNK / 64;
-    uint32_t cnt[NS];
+    const int last = (int)min((int64_t)BWD_CHUNK - 1, n - 1 - i0);  // the chunk's last Gaussian
+    uint32_t cnt[NS], eo[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         const uint32_t li = 64 * j + l;
-        cnt[j] = i0 + li < n ? lane(uniform_ptr(a.count + i0), li * 4u) : 0u;
+        const bool valid = i0 + li < n;
+        cnt[j] = valid ? lane(uniform_ptr(a.count + i0), li * 4u) : 0u;
+        if (SUMS) eo[j] = valid ? lane(uniform_ptr(a.eoff + i0), li * 4u) : 0u;
     }
     uint64_t act_mask[NS];
     uint32_t total = 0;
@@ -575,10 +595,49 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
         act_mask[j] = ballot(act);
         if (act) s_list[total + mask_rank(act_mask[j])] = (uint16_t)li;
         total += (uint32_t)__builtin_popcountll(act_mask[j]);
+        if (SUMS) {
+            if ((int)li <= last) s_beg[li] = eo[j];
+            if ((int)li == last) s_end = eo[j] + cnt[j];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) s_g[li][f] = 0.f;
+        }
     }
     __syncthreads();
+    if (SUMS) {
+        const uint32_t S0 = s_beg[0], S1 = s_end;
+        for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
+            const uint32_t sl = base + l;
+            const bool in = sl < S1 && (uint64_t)sl < a.capacity;
+            // owner: the largest Gaussian of the chunk whose run starts at or before sl (those
+            // with no pairs share the next one's start, so the largest is the one with pairs)
+            int L = 0;
+#pragma unroll
+            for (int step = BWD_CHUNK / 2; step > 0; step >>= 1)
+                if (L + step <= last && s_beg[L + step] <= sl) L += step;
+            if (!in) L = -1 - (int)l;  // unique: never merged with another lane
+            float x[9];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) x[f] = in ? a.slots[(uint64_t)sl * 9 + f] : 0.f;
+            seg_scan9(L, x);
+            const int Ln = __shfl_down(L, 1);
+            if (in && (l == 63 || Ln != L)) {
+#pragma unroll
+                for (int f = 0; f < 9; ++f) s_g[L][f] += x[f];
+            }
+        }
+        __syncthreads();
+        // colour fields of the composited entries, for the SH kernel
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const uint32_t li = 64 * j + l;
+            if (cnt[j] != 0) {
+#pragma unroll
+                for (int f = 6; f < 9; ++f) lane(uniform_ptr(a.g2w + f * n + i0), li * 4u) = s_g[li][f];
+            }
+        }
+    }
     for (uint32_t b = 0; b < total; b += 64)
-        if (b + l < total) geom_chain(a, i0, (uint32_t)s_list[b + l] * 4u, acc);
+        if (b + l < total) geom_chain<SUMS>(a, i0, (uint32_t)s_list[b + l] * 4u, acc, s_g);
     // zeros for the rest, after the chain's loads so they do not wait behind these stores
     if (!acc) {
 #pragma unroll
@@ -744,8 +803,12 @@ static void launch_bwd_sh(bool one_view, int64_t n, hipStream_t stream, const Pr
         hipLaunchKernelGGL((k_preprocess_bwd_sh<DEG, 1>), dim3((unsigned)((n + 63) / 64)), dim3(192), 0, stream, a);
 }
 
+// With one view the pair slots are summed by the geometric kernel (no k_pair_sums launch
+// before it): that saves a launch and the round trip of the six geometric fields through g2.
+bool bwd_sums_in_chain(const gs_views* views) { return views->n_views == 1; }
+
 gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, const gs_params* p,
-                                const gs_projected* proj, const gs_bins* bins, const float* g2,
+                                const gs_projected* proj, const gs_bins* bins, const float* slots, float* g2,
                                 gs_gaussians_grad* grad, hipStream_t stream) {
     if (g->n == 0) return GS_OK;
     PreBwdArgs a;
@@ -761,6 +824,10 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.p = *p;
     a.count = proj->count;
     a.g2 = g2;
+    a.eoff = bins->entry_offset;
+    a.slots = slots;
+    a.capacity = bins->capacity;
+    a.g2w = g2;
     a.overflow = bins->overflow;
     a.overwrite = grad->overwrite;
     a.gmean = grad->mean;
@@ -769,7 +836,10 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gopac = grad->opacity;
     a.gsh = grad->sh;
     const dim3 grid((unsigned)((g->n + BWD_CHUNK - 1) / BWD_CHUNK));
-    hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(64), 0, stream, a);
+    if (bwd_sums_in_chain(views))
+        hipLaunchKernelGGL(k_preprocess_bwd<true>, grid, dim3(64), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_preprocess_bwd<false>, grid, dim3(64), 0, stream, a);
     // colour part: 64 G Gaussians x 3 channels per workgroup
     switch (g->sh_degree) {
         case 0: launch_bwd_sh<0>(views->n_views == 1, g->n, stream, a); break;

@@ -641,18 +641,6 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
     }
 }
 
-// one step of a segmented scan of nine fields keyed by the owner lane L (see k_pair_sums)
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void seg_step(int L, float (&x)[9]) {
-    const int Ld = __builtin_amdgcn_update_dpp(-1, L, CTRL, ROW_MASK, 0xf, false);
-    const bool merge = Ld == L;
-#pragma unroll
-    for (int f = 0; f < 9; ++f) {
-        const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[f]), CTRL, ROW_MASK, 0xf, true));
-        x[f] = merge ? x[f] + y : x[f];
-    }
-}
-
 // Per-entry sums of the pair slots: entry o owns the slots [entry_offset[o], entry_offset[o] +
 // count[o]) and consecutive entries own consecutive runs, so the runs of a wave's 64 entries
 // form one range, read 64 slots at a time (coalesced). In each chunk a segmented inclusive
@@ -694,17 +682,7 @@ __global__ __launch_bounds__(256) void k_pair_sums(const uint32_t* __restrict__ 
         float x[9];
 #pragma unroll
         for (int f = 0; f < 9; ++f) x[f] = in ? slots[(uint64_t)sl * 9 + f] : 0.f;
-        // segmented inclusive scan over the lanes with the steps of a wave scan: shifts by 1, 2,
-        // 4, 8 inside each row of 16, then the last lane of a row added into the next rows. A
-        // lane adds what arrives only from a lane of its own run (owners are non-decreasing over
-        // the lanes, so a source with the same owner means every lane in between has it too);
-        // lanes that receive nothing get zeros.
-        seg_step<0x111, 0xf>(L, x);
-        seg_step<0x112, 0xf>(L, x);
-        seg_step<0x114, 0xf>(L, x);
-        seg_step<0x118, 0xf>(L, x);
-        seg_step<0x142, 0xa>(L, x);
-        seg_step<0x143, 0xc>(L, x);
+        seg_scan9(L, x);
         const int Ln = __shfl_down(L, 1);
         if (in && (l == 63 || Ln != L)) {
 #pragma unroll
@@ -936,7 +914,7 @@ gs_status launch_visibility(const gs_projected* proj, const gs_views* views, con
 
 gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
                             const float* t_final, const uint32_t* n_last, const float* dl_drgb, float* slots,
-                            float* g2, hipStream_t s) {
+                            float* g2, bool pair_sums, hipStream_t s) {
     if (views->n_tiles == 0) return GS_OK;
     const int64_t vn = proj->n * (int64_t)views->n_views;
     RenderArgs a = base_args(proj, views, bins, p);
@@ -949,7 +927,7 @@ gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, con
     a.slots = slots;
     if (!launch_bwd(a, views->tile_w, views->tile_h, bwd_pixels_per_lane(views), views->n_tiles, s))
         return finish(false, "render_bwd");
-    if (vn > 0)
+    if (vn > 0 && pair_sums)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj->count,
                            bins->entry_offset, vn, slots, bins->capacity, bins->overflow, g2);
     return check_launch("render_bwd");
