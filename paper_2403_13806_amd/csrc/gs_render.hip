@@ -169,6 +169,7 @@ struct BwdShape {
     static constexpr int BW = 8 * PXW, BH = 8 * PXH;  // wave block
     static constexpr int WPR = TW / BW;           // waves per row of blocks
     static constexpr int BB = NT < 128 ? NT : 128;  // records per batch
+    static constexpr int SH = NT / BB;              // threads staging one record (each tests every SH-th block)
     static_assert(TW % BW == 0 && TH % BH == 0 && NW >= 1, "tile not a whole number of wave blocks");
     static_assert(NW * 4 <= 64, "quarter masks hold 64 bits");
 };
@@ -177,7 +178,7 @@ template <int TW, int TH, int PXW, int PXH>
 struct SmemBwd {
     using S = BwdShape<TW, TH, PXW, PXH>;
     gs_splat rec[S::BB];
-    uint64_t hitq[S::BB];  // quarter masks, bit 4 w + quarter
+    uint64_t hitq[S::SH][S::BB];  // quarter masks, bit 4 w + quarter, in SH parts (OR-ed when read)
     uint32_t gid[S::BB];
     float acc[S::NW * S::BB * 9];  // [wave][record][field]
     uint32_t top;
@@ -208,25 +209,27 @@ template <int TW, int TH, int PXW, int PXH>
 __device__ __forceinline__ void stage_q(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, const gs_splat* sp,
                                         uint32_t base, uint32_t cnt, double ox, double oy) {
     using S = BwdShape<TW, TH, PXW, PXH>;
-    const uint32_t q = threadIdx.x;
-    if (q >= (uint32_t)S::BB) return;
+    // SH threads per record (all of the workgroup's threads when it has more than BB): thread
+    // part h tests the quarters 4 w + qd = h, h + SH, ...; the FP64 tests are the staging's
+    // critical path, so splitting them shortens every batch's wait at the barrier
+    const uint32_t q = threadIdx.x % S::BB, h = threadIdx.x / S::BB;
     uint64_t hm = 0;
     const uint32_t id = q < cnt ? a.vals[base + q] : 0xffffffffu;
     if ((int64_t)id < a.n) {  // (out of range only in the output of a timed-out sort)
         const gs_splat s = sp[id];
-        sm.rec[q] = s;
+        if (h == 0) sm.rec[q] = s;
         const double kx = -s.cb / s.cc, ky = -s.cb / s.ca;
         const double lim = s.qmax * (1.0 + 1e-9) + 1e-12;
 #pragma unroll 1
-        for (int bit = 0; bit < 4 * S::NW; ++bit) {
+        for (int bit = (int)h; bit < 4 * S::NW; bit += S::SH) {
             const int w = bit >> 2, qd = bit & 3;
             const double x0 = ox + (double)((w % S::WPR) * S::BW + (qd & 1) * 4 * PXW) - s.u;
             const double y0 = oy + (double)((w / S::WPR) * S::BH + (qd >> 1) * 4 * PXH) - s.v;
             if (rect_hit(s, x0, x0 + (4 * PXW - 1), y0, y0 + (4 * PXH - 1), kx, ky, lim)) hm |= 1ull << bit;
         }
     }
-    sm.gid[q] = (int64_t)id < a.n ? id : 0xffffffffu;
-    sm.hitq[q] = hm;
+    if (h == 0) sm.gid[q] = (int64_t)id < a.n ? id : 0xffffffffu;
+    sm.hitq[h][q] = hm;
 }
 
 // emission slot of the pair (tile (tx, ty) of its view, entry o): entry o's pairs are
@@ -509,7 +512,10 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
         for (int c = BB / 64 - 1; c >= 0; --c) {
             // each quarter (one row of 16 lanes) walks the entries that meet its pixels
             // the four quarters' masks are wave-uniform: their bit walks run on the scalar unit
-            const uint32_t hq = (uint32_t)(sm.hitq[c * 64 + l] >> (4 * w));
+            uint64_t hm = sm.hitq[0][c * 64 + l];
+#pragma unroll
+            for (int h = 1; h < S::SH; ++h) hm |= sm.hitq[h][c * 64 + l];
+            const uint32_t hq = (uint32_t)(hm >> (4 * w));
             uint64_t mq[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
