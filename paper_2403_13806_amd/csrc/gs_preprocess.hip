@@ -251,7 +251,8 @@ struct PreArgs {
 
 // DEG and COLOR are compile-time so the SH coefficients of the lane's Gaussian are loaded
 // into registers together with the geometry, before the projection math: every load of the
-// lane is in flight at once instead of the SH loads waiting behind the FP64 chain.
+// lane is in flight at once instead of the SH loads waiting behind the FP64 chain. The
+// coefficient planes are read once per frame: streamed past the caches.
 template <int DEG, bool COLOR>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     const int v = blockIdx.y;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     float shv[COLOR ? NB * 3 : 1];
     if (COLOR) {
 #pragma unroll
-        for (int k = 0; k < NB * 3; ++k) shv[k] = a.sh[(int64_t)k * a.n_all + i];
+        for (int k = 0; k < NB * 3; ++k) shv[k] = __builtin_nontemporal_load(&a.sh[(int64_t)k * a.n_all + i]);
 #pragma unroll
         for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
     }
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(192 * G) __attribute__((amdgpu_waves_per_eu(6))) vo
     float shv[NB], gsh[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        shv[k] = valid ? lane(crow(a.sh, k), lb) : 0.f;
+        shv[k] = valid ? __builtin_nontemporal_load(&lane(crow(a.sh, k), lb)) : 0.f;
         gsh[k] = 0.f;
     }
     float px = 0.f, py = 0.f, pz = 0.f;
