@@ -550,9 +550,8 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                     any |= con[p];
                 }
                 if (ballot(any) == 0) continue;
+                // the first pixel's terms start the sums (no adds onto zeros)
                 float v[9];
-#pragma unroll
-                for (int f = 0; f < 9; ++f) v[f] = 0.f;
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     const float G = falloff(q[p]);
@@ -574,15 +573,10 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
                     const float dx = (float)(xc[p % PXW] - s.u), dy = (float)(yc[p / PXW] - s.v);
                     const float dq = free_a ? al * dA : 0.f;
                     const float a0 = dq * dx, a1 = dq * dy;
-                    v[0] += a0;
-                    v[1] += a1;
-                    v[2] += a0 * dx;
-                    v[3] += a0 * dy;
-                    v[4] += a1 * dy;
-                    v[5] += free_a ? dA * G : 0.f;
-                    v[6] += dC[p][0] * wt;
-                    v[7] += dC[p][1] * wt;
-                    v[8] += dC[p][2] * wt;
+                    const float t9[9] = {a0,          a1,          a0 * dx, a0 * dy, a1 * dy, free_a ? dA * G : 0.f,
+                                         dC[p][0] * wt, dC[p][1] * wt, dC[p][2] * wt};
+#pragma unroll
+                    for (int f = 0; f < 9; ++f) v[f] = p == 0 ? t9[f] : v[f] + t9[f];
                 }
                 // per-quarter sums, one field per lane, added into this wave's sums of that
                 // entry (lanes of one instruction that meet at one address are applied in a
