@@ -626,6 +626,36 @@ __device__ __forceinline__ uint32_t walk_pairs(WaveStage& st, uint32_t c, uint64
     return total;
 }
 
+// Longest-first tile order from one workgroup of NT threads: tiles are bucketed by the bit
+// length of their list size len(i) (LPT_B buckets) in LDS, the buckets laid out from the longest
+// down, then every tile placed by an LDS counter of its bucket. (The order inside a bucket is
+// whatever the counters give: it only decides which tile a workgroup takes, never a result.)
+constexpr int LPT_B = 33;
+
+__device__ __forceinline__ int lpt_bits(uint32_t c) { return c ? 32 - __clz(c) : 0; }
+
+template <int NT, class Len>
+__device__ void lpt_order_block(Len len, int n_tiles, uint32_t* __restrict__ queue) {
+    __shared__ uint32_t lh[LPT_B], base[LPT_B];
+    const int t = threadIdx.x;
+    if (t < LPT_B) lh[t] = 0;
+    __syncthreads();
+    for (int i = t; i < n_tiles; i += NT) atomicAdd(&lh[lpt_bits(len(i))], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int b = LPT_B - 1; b >= 0; --b) {
+            base[b] = acc;
+            acc += lh[b];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n_tiles; i += NT) {
+        const uint32_t pos = atomicAdd(&base[lpt_bits(len(i))], 1u);
+        if (pos < (uint32_t)n_tiles) queue[pos] = (uint32_t)i;
+    }
+}
+
 struct BucketArgs {
     const uint32_t* count;
     const uint64_t* rect;
@@ -649,6 +679,8 @@ struct BucketArgs {
     uint64_t capacity;
     uint32_t* ranges;    // [n_tiles][2], written by each view's first row
     uint32_t* eoff;      // [n_views * n] first pair of each entry, or NULL
+    uint32_t* queue;     // longest-first tile order, built by an extra workgroup of the emission, or NULL
+    int n_tiles;         // all views' tiles
 };
 
 constexpr int BK_T = 1024;  // threads of the bucket kernels: one wave per emission block of the row
@@ -664,6 +696,21 @@ __device__ __forceinline__ int view_tiles(const BucketArgs& a, int v) {
 __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear) {
     __shared__ uint32_t hist[BUCKET_TILES];
     __shared__ WaveStage st[BK_T / 64];
+    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint32_t* cv = a.count + (int64_t)v * a.n;
+    const uint64_t* rv = a.rect + (int64_t)v * a.n;
+    // wave w takes the row's emission block w, 64 entries at a time; the block's counts and
+    // rectangles are requested first, together (rectangles of culled entries too: in random
+    // storage order their cache lines are read for the visible ones anyway)
+    const int64_t eb = (int64_t)blockIdx.x * 16 + w;
+    uint32_t c4[4];
+    uint64_t r4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = eb * 256 + k * 64 + l;
+        c4[k] = j < a.n ? cv[j] : 0u;
+        r4[k] = j < a.n ? rv[j] : 0ull;
+    }
     {
         const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
         const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
@@ -671,28 +718,20 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
         for (int b = 0; b < 4; ++b)
             for (int64_t i = tid; i < clear.n[b]; i += nth) clear.p[b][i] = 0u;
     }
-    const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
     const int nt = view_tiles(a, v);
     const bool fits = nt <= a.stride;  // the same for the whole workgroup
     const int ncols = (nt + 15) & ~15;
     for (int i = t; i < ncols && fits; i += BK_T) hist[i] = 0u;
     __syncthreads();
-    const uint32_t* cv = a.count + (int64_t)v * a.n;
-    const uint64_t* rv = a.rect + (int64_t)v * a.n;
     const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
-    // wave w takes the row's emission block w, 64 entries at a time
     {
-        const int64_t eb = (int64_t)blockIdx.x * 16 + w;
         uint32_t bsum = 0;
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t j0 = eb * 256 + k * 64;
             if (j0 >= a.n) break;  // the same for the whole wave
-            const int64_t j = j0 + l;
-            const uint32_t c = j < a.n ? cv[j] : 0u;
-            const uint64_t r = c ? rv[j] : 0ull;
             const int last = (int)min((int64_t)63, a.n - 1 - j0);
-            bsum += walk_pairs(st[w], c, r, last, tiles_x, [&](uint32_t, int, uint32_t tile) {
+            bsum += walk_pairs(st[w], c4[k], c4[k] ? r4[k] : 0ull, last, tiles_x, [&](uint32_t, int, uint32_t tile) {
                 if (fits && tile < (uint32_t)nt) atomicAdd(&hist[tile], 1u);
             });
         }
@@ -789,7 +828,27 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
     __shared__ uint32_t s_db[BK_T / 64][64];
     __shared__ uint64_t s_vstart;
     const int v = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (blockIdx.x == a.nbr) {  // the extra column: view 0's builds the longest-first order
+        if (v == 0) lpt_order_block<BK_T>([&](int i) { return a.tot[i]; }, a.n_tiles, a.queue);
+        return;
+    }
     const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+    const uint32_t* cv = a.count + (int64_t)v * a.n;
+    const uint64_t* rv = a.rect + (int64_t)v * a.n;
+    const float* dv = a.depth + (int64_t)v * a.n;
+    // the wave's emission block: its counts, rectangles and depths and its first pair are
+    // requested first, together, so they arrive while the tile starts are scanned
+    const int64_t eb = (int64_t)blockIdx.x * 16 + w;
+    uint32_t c4[4], d4[4];
+    uint64_t r4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = eb * 256 + k * 64 + l;
+        c4[k] = j < a.n ? cv[j] : 0u;
+        r4[k] = j < a.n ? rv[j] : 0ull;
+        d4[k] = j < a.n ? __float_as_uint(dv[j]) : 0u;
+    }
+    const uint32_t run0 = eb * 256 < a.n ? a.bsum[(int64_t)v * a.nbv + eb] : 0u;
     // the capacity check (every workgroup reads the complete total; the first sets the flags)
     if (*a.n_pairs > a.capacity) {
         if (first && t == 0) {
@@ -829,26 +888,18 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
         cur[i] = s0 + row[i];
     }
     __syncthreads();
-    const uint32_t* cv = a.count + (int64_t)v * a.n;
-    const uint64_t* rv = a.rect + (int64_t)v * a.n;
-    const float* dv = a.depth + (int64_t)v * a.n;
     const uint32_t tiles_x = (uint32_t)div_up(a.cams[v].width, a.tile_w);
     {
-        const int64_t eb = (int64_t)blockIdx.x * 16 + w;  // the wave's emission block
         if (eb * 256 >= a.n) return;  // the whole wave (no workgroup barrier below)
-        uint32_t run = a.bsum[(int64_t)v * a.nbv + eb];  // first pair of the emission block
-#pragma unroll 1
+        uint32_t run = run0;  // first pair of the emission block
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t j0 = eb * 256 + k * 64;
             if (j0 >= a.n) break;
             const int64_t j = j0 + l;
-            const uint32_t c = j < a.n ? cv[j] : 0u;
-            uint64_t r = 0;
-            uint32_t db = 0;
-            if (c) {
-                r = rv[j];
-                db = __float_as_uint(dv[j]);
-            }
+            const uint32_t c = c4[k];
+            const uint64_t r = c ? r4[k] : 0ull;
+            const uint32_t db = c ? d4[k] : 0u;
             if (a.eoff && j < a.n) a.eoff[(int64_t)v * a.n + j] = run + wave_incl_scan(c) - c;
             s_db[w][l] = db;
             const int last = (int)min((int64_t)63, a.n - 1 - j0);
@@ -1185,11 +1236,8 @@ __global__ void k_iota(uint32_t* __restrict__ p, int n) {
 // Longest-first tile order of the traversals (views->lpt): tiles are bucketed by
 // bit length of their list size (33 buckets) and laid out from the longest bucket down.
 // ---------------------------------------------------------------------------------------
-constexpr int LPT_B = 33;
-
 __device__ __forceinline__ int lpt_bucket(const uint32_t* ranges, int tile) {
-    const uint32_t c = ranges[2 * tile + 1] - ranges[2 * tile];
-    return c ? 32 - __clz(c) : 0;
+    return lpt_bits(ranges[2 * tile + 1] - ranges[2 * tile]);
 }
 
 __global__ __launch_bounds__(256) void k_lpt_hist(const uint32_t* __restrict__ ranges, int n_tiles,
@@ -1239,24 +1287,7 @@ constexpr int LPT_ONE_T = 1024, LPT_ONE_TILES = 65536;
 
 __global__ __launch_bounds__(LPT_ONE_T) void k_lpt_one(const uint32_t* __restrict__ ranges, int n_tiles,
                                                        uint32_t* __restrict__ queue) {
-    __shared__ uint32_t lh[LPT_B], base[LPT_B];
-    const int t = threadIdx.x;
-    if (t < LPT_B) lh[t] = 0;
-    __syncthreads();
-    for (int i = t; i < n_tiles; i += LPT_ONE_T) atomicAdd(&lh[lpt_bucket(ranges, i)], 1u);
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int b = LPT_B - 1; b >= 0; --b) {
-            base[b] = acc;
-            acc += lh[b];
-        }
-    }
-    __syncthreads();
-    for (int i = t; i < n_tiles; i += LPT_ONE_T) {
-        const uint32_t pos = atomicAdd(&base[lpt_bucket(ranges, i)], 1u);
-        if (pos < (uint32_t)n_tiles) queue[pos] = (uint32_t)i;
-    }
+    lpt_order_block<LPT_ONE_T>([&](int i) { return ranges[2 * i + 1] - ranges[2 * i]; }, n_tiles, queue);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1467,6 +1498,10 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ba.capacity = bins->capacity;
     ba.ranges = bins->ranges;
     ba.eoff = bins->entry_offset;
+    ba.n_tiles = views->n_tiles;
+    // with the tile buckets the longest-first order comes from an extra workgroup of the
+    // emission (from the tile totals), beside the emission instead of a launch after it
+    ba.queue = bucket && bins->queue && views->n_tiles <= LPT_ONE_TILES ? bins->queue : nullptr;
     uint64_t* vin;
     uint64_t* valt;
     if (bucket) {
@@ -1480,7 +1515,8 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
         // into their tiles
         hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.stride / 16), (unsigned)views->n_views), dim3(BLK), 0,
                            stream, ba);
-        hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr, (unsigned)views->n_views), dim3(BK_T), 0, stream, ba);
+        hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr + (ba.queue ? 1u : 0u), (unsigned)views->n_views),
+                           dim3(BK_T), 0, stream, ba);
         vin = U64(L.tv1);
         valt = U64(L.tv0);
     } else {
@@ -1491,9 +1527,10 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
         if (L.nb_sort == 0) return launch_lpt(views, bins, U32(L.lpt), stream);
         launch_entry_order_grouping(proj, views, bins, L, w, stream, vin, valt);
     }
-    // 5. the longest-first order when asked for (from the ranges; the tile sort takes the longest
-    // lists first too), 6. each tile's list by (depth, index); keys and values
-    if ((st = launch_lpt(views, bins, U32(L.lpt), stream))) return st;
+    // 5. the longest-first order when asked for (from the ranges, unless the emission built it;
+    // the tile sort takes the longest lists first too), 6. each tile's list by (depth, index);
+    // keys and values
+    if (!ba.queue && (st = launch_lpt(views, bins, U32(L.lpt), stream))) return st;
     TileSortArgs ta;
     ta.pairs = vin;
     ta.scratch = valt;
