@@ -19,10 +19,9 @@
 //   sort     one workgroup per tile orders the tile's list by its unique 64-bit (depth bits,
 //            index) values in LDS (radix passes on the depth bits, or a bitonic network when
 //            depths repeat, so the result does not depend on the order the grouping left) and
-//            writes the keys (tile << 32 | depth bits) and the Gaussian indices; lists longer
-//            than the small buffer go to a second kernel with a larger one, which sorts lists
-//            longer than that in chunks and merges the chunks (merge path) through a scratch
-//            buffer
+//            writes the keys (tile << 32 | depth bits) and the Gaussian indices; a list longer
+//            than the LDS buffer is sorted by the same workgroup in chunks of that size, merged
+//            (merge path) back and forth through a scratch buffer
 // Every wait on another block is bounded: a wait that exceeds its spin budget sets bit 1
 // of the overflow word (results invalid) instead of hanging.
 #include <algorithm>
@@ -916,7 +915,6 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
 // Per-tile sort by (depth bits, index)
 // ---------------------------------------------------------------------------------------
 constexpr int SMALL_LIST = 2048;  // 16 KB of LDS per workgroup
-constexpr int LARGE_LIST = 8192;  // 64 KB
 
 struct TileSortArgs {
     uint64_t* pairs;    // values grouped by tile; also the merge buffer of very long lists
@@ -927,8 +925,6 @@ struct TileSortArgs {
     const uint32_t* overflow;
     uint64_t* keys;
     uint32_t* vals;
-    uint32_t* n_deferred;  // number of deferred tiles (zero on entry)
-    uint32_t* deferred;    // [n_tiles] their ids
     uint32_t* sticky;      // OR-ed with the overflow word, or NULL
     const uint32_t* order; // tiles longest list first (workgroup b sorts order[b]), or NULL
 };
@@ -995,6 +991,41 @@ __device__ __forceinline__ int merge_split(const uint64_t* A, int na, const uint
     return lo;
 }
 
+// A list longer than SMALL_LIST, sorted by the workgroup that owns its tile: chunks of
+// SMALL_LIST by the bitonic sort in LDS into the scratch area of the list, then pairwise merges
+// (merge path: thread i takes the i-th 1/256 of the merged output) back and forth between the
+// scratch and the list's own area, then the keys and values written.
+__device__ void sort_long(const TileSortArgs& a, int tile, uint32_t start, int len, uint64_t* s) {
+    uint64_t* src = a.scratch + start;
+    uint64_t* dst = a.pairs + start;
+    for (int c0 = 0; c0 < len; c0 += SMALL_LIST) {
+        const int cl = min(SMALL_LIST, len - c0);
+        sort_in_lds(s, a.pairs + start + c0, cl);
+        for (int i = threadIdx.x; i < cl; i += blockDim.x) src[c0 + i] = s[i];
+        __syncthreads();
+    }
+    for (int wd = SMALL_LIST; wd < len; wd <<= 1) {
+        for (int m0 = 0; m0 < len; m0 += 2 * wd) {
+            const int na = min(wd, len - m0), nb = max(0, min(wd, len - m0 - wd));
+            const uint64_t* A = src + m0;
+            const uint64_t* B = A + na;
+            const int M = na + nb;
+            const int d0 = (int)((int64_t)M * threadIdx.x / blockDim.x);
+            const int d1 = (int)((int64_t)M * (threadIdx.x + 1) / blockDim.x);
+            int i = merge_split(A, na, B, nb, d0), j = d0 - i;
+            for (int d = d0; d < d1; ++d) {
+                const bool takeA = j >= nb || (i < na && A[i] < B[j]);
+                dst[m0 + d] = takeA ? A[i++] : B[j++];
+            }
+        }
+        __syncthreads();
+        uint64_t* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    write_tile(a, tile, start, src, len);
+}
+
 // Stable LSD radix sort of one tile's list (len <= SMALL_LIST) by its FP32 depth bits,
 // 8-bit digits, in LDS. Wave w owns the contiguous items [w C, (w + 1) C) (C a multiple of 64)
 // and ranks them with wave-private digit counters; passes whose digit is the same for every
@@ -1019,12 +1050,17 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
     __shared__ uint32_t wsum[BLK / 64];
     __shared__ uint32_t diff, ties;
     const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
+    // the last launch of the binning: every flag of this frame is set by now
+    if (a.sticky && blockIdx.x == 0 && t == 0) {
+        const uint32_t o = *a.overflow;
+        if (o) atomicOr(a.sticky, o);
+    }
     if (*a.overflow || tile >= a.n_tiles) return;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     if (end <= start || (uint64_t)end > a.capacity) return;
     const int len = (int)(end - start);
-    if (len > SMALL_LIST) {
-        if (t == 0) a.deferred[atomicAdd(a.n_deferred, 1u)] = (uint32_t)tile;
+    if (len > SMALL_LIST) {  // (the same for the whole workgroup)
+        sort_long(a, tile, start, len, lds.kv64);
         return;
     }
     const uint64_t* src = a.pairs + start;
@@ -1174,59 +1210,6 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(TileSortArgs a) {
     }
 }
 
-// deferred (long) lists; a grid-stride loop over them
-__global__ __launch_bounds__(256) void k_tile_sort_large(TileSortArgs a) {
-    __shared__ uint64_t s[LARGE_LIST];
-    // the last launch of the binning: every flag of this frame is set by now
-    if (a.sticky && blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t o = *a.overflow;
-        if (o) atomicOr(a.sticky, o);
-    }
-    if (*a.overflow) return;
-    const uint32_t nd = min(*a.n_deferred, (uint32_t)a.n_tiles);
-    for (uint32_t it = blockIdx.x; it < nd; it += gridDim.x) {
-        const int tile = (int)a.deferred[it];
-        const uint32_t start = a.ranges[2 * tile];
-        const int len = (int)(a.ranges[2 * tile + 1] - start);
-        if (len <= LARGE_LIST) {
-            sort_in_lds(s, a.pairs + start, len);
-            write_tile(a, tile, start, s, len);
-            __syncthreads();
-            continue;
-        }
-        // sorted chunks of LARGE_LIST into scratch, then pairwise merges back and forth
-        uint64_t* src = a.scratch + start;
-        uint64_t* dst = a.pairs + start;
-        for (int c0 = 0; c0 < len; c0 += LARGE_LIST) {
-            const int cl = min(LARGE_LIST, len - c0);
-            sort_in_lds(s, a.pairs + start + c0, cl);
-            for (int i = threadIdx.x; i < cl; i += blockDim.x) src[c0 + i] = s[i];
-            __syncthreads();
-        }
-        for (int wd = LARGE_LIST; wd < len; wd <<= 1) {
-            for (int m0 = 0; m0 < len; m0 += 2 * wd) {
-                const int na = min(wd, len - m0), nb = max(0, min(wd, len - m0 - wd));
-                const uint64_t* A = src + m0;
-                const uint64_t* B = A + na;
-                const int M = na + nb;
-                const int d0 = (int)((int64_t)M * threadIdx.x / blockDim.x);
-                const int d1 = (int)((int64_t)M * (threadIdx.x + 1) / blockDim.x);
-                int i = merge_split(A, na, B, nb, d0), j = d0 - i;
-                for (int d = d0; d < d1; ++d) {
-                    const bool takeA = j >= nb || (i < na && A[i] < B[j]);
-                    dst[m0 + d] = takeA ? A[i++] : B[j++];
-                }
-            }
-            __syncthreads();
-            uint64_t* tmp = src;
-            src = dst;
-            dst = tmp;
-        }
-        write_tile(a, tile, start, src, len);
-        __syncthreads();
-    }
-}
-
 __global__ void k_iota(uint32_t* __restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (uint32_t)i;
@@ -1303,9 +1286,9 @@ static int tile_bits(int n_tiles) {
 
 struct SortLayout {
     // control block, cleared at the start of every gs_bin_sort: scan chain, pass tickets,
-    // digit histograms, deferred-tile count, LPT counters, pass status tables
-    size_t ctrl, scan, tickets, ghist, n_deferred, lpt, view_tot, status, ctrl_end;
-    size_t offs, deferred, tk0, tk1, tv0, tv1, bk_bh, bk_tot, total;
+    // digit histograms, LPT counters, pass status tables
+    size_t ctrl, scan, tickets, ghist, lpt, view_tot, status, ctrl_end;
+    size_t offs, tk0, tk1, tv0, tv1, bk_bh, bk_tot, total;
     int64_t nb_scan, nb_sort, nbr;
     int passes;
     // emission into tile buckets is possible: rows of a view and the histogram space (sized for
@@ -1335,8 +1318,6 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     p = align256(p + sizeof(uint32_t) * KEY_PASSES);
     L.ghist = p;
     p = align256(p + sizeof(uint32_t) * 256 * KEY_PASSES);
-    L.n_deferred = p;
-    p = align256(p + sizeof(uint32_t));
     L.lpt = p;
     p = align256(p + sizeof(uint32_t) * 2 * LPT_B);
     L.view_tot = p;
@@ -1346,8 +1327,6 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.ctrl_end = p;
     L.offs = p;  // pair offsets of the 256-entry emission blocks of every view
     p = align256(p + sizeof(uint32_t) * (size_t)((n + 255) / 256) * (size_t)std::max(n_views, 0));
-    L.deferred = p;
-    p = align256(p + sizeof(uint32_t) * nt);
     const size_t k4 = sizeof(uint32_t) * (size_t)capacity, v8 = sizeof(uint64_t) * (size_t)capacity;
     L.tk0 = p;
     p = align256(p + k4);
@@ -1540,12 +1519,9 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
     ta.overflow = bins->overflow;
     ta.keys = bins->keys;
     ta.vals = bins->vals;
-    ta.n_deferred = U32(L.n_deferred);
-    ta.deferred = U32(L.deferred);
     ta.sticky = bins->overflow_sticky;
     ta.order = bins->queue;
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)views->n_tiles), dim3(256), 0, stream, ta);
-    hipLaunchKernelGGL(k_tile_sort_large, dim3((unsigned)std::min(views->n_tiles, 512)), dim3(256), 0, stream, ta);
     return check_launch("bin_sort");
 }
 
