@@ -742,13 +742,18 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
 }
 
 // Exclusive prefix over a view's rows of every tile's count (in place) and the tile totals.
-// Workgroup (g, v) takes tiles [16 g, 16 g + 16) of view v: their counts of every row are read
-// into LDS, each of 16 chunks of rows summed, the chunk sums scanned, then the prefixes
+// Workgroup (g, v) takes tiles [CS g, CS g + CS) of view v: their counts of every row are read
+// into LDS, each of BLK / CS chunks of rows summed, the chunk sums scanned, then the prefixes
 // written. Each workgroup also adds its totals to the view's and to the pair total. The first
-// workgroup of a view too large for the rows' columns sets bit 2 of the overflow word.
+// workgroup of a view too large for the rows' columns sets bit 2 of the overflow word. (Narrow
+// column groups give more workgroups than CUs for a view of a few thousand tiles.)
+constexpr int COLSCAN_CS = 8;
+
+template <int CS>
 __global__ __launch_bounds__(BLK) void k_bucket_colscan(BucketArgs a) {
-    __shared__ uint32_t sub[BUCKET_MAX_ROWS * 16];
-    __shared__ uint32_t csum[16][17];
+    constexpr int NCH = BLK / CS;
+    __shared__ uint32_t sub[BUCKET_MAX_ROWS * CS];
+    __shared__ uint32_t csum[CS][NCH + 1];
     const int t = threadIdx.x, v = blockIdx.y;
     const int nt = view_tiles(a, v);
     if (nt > a.stride) {
@@ -758,32 +763,32 @@ __global__ __launch_bounds__(BLK) void k_bucket_colscan(BucketArgs a) {
         }
         return;
     }
-    const int c0 = blockIdx.x * 16;
+    const int c0 = blockIdx.x * CS;
     if (c0 >= nt) return;  // the whole workgroup
     const int nrows = (int)a.nbr;
     uint32_t* bh = a.bh + (int64_t)v * a.nbr * a.stride;
-    for (int i = t; i < nrows * 16; i += BLK) sub[i] = bh[(uint64_t)(i >> 4) * a.stride + c0 + (i & 15)];
+    for (int i = t; i < nrows * CS; i += BLK) sub[i] = bh[(uint64_t)(i / CS) * a.stride + c0 + (i % CS)];
     __syncthreads();
-    const int col = t & 15, chunk = t >> 4;
-    const int per = (nrows + 15) / 16, r0 = min(nrows, chunk * per), r1 = min(nrows, r0 + per);
+    const int col = t % CS, chunk = t / CS;
+    const int per = (nrows + NCH - 1) / NCH, r0 = min(nrows, chunk * per), r1 = min(nrows, r0 + per);
     uint32_t s = 0;
-    for (int r = r0; r < r1; ++r) s += sub[r * 16 + col];
+    for (int r = r0; r < r1; ++r) s += sub[r * CS + col];
     csum[col][chunk] = s;
     __syncthreads();
-    if (t < 16) {
+    if (t < CS) {
         uint32_t run = 0;
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < NCH; ++k) {
             const uint32_t x = csum[t][k];
             csum[t][k] = run;
             run += x;
         }
         if (c0 + t < nt) a.tot[a.tile_offset[v] + c0 + t] = run;
-        csum[t][16] = run;  // (zero for the padding columns)
+        csum[t][NCH] = run;  // (zero for the padding columns)
     }
     __syncthreads();
     if (t == 0) {
         uint64_t all = 0;
-        for (int k = 0; k < 16; ++k) all += csum[k][16];
+        for (int k = 0; k < CS; ++k) all += csum[k][NCH];
         if (all) {
             atomicAdd((unsigned long long*)a.n_pairs, (unsigned long long)all);
             atomicAdd((unsigned long long*)(a.view_tot + v), (unsigned long long)all);
@@ -791,12 +796,12 @@ __global__ __launch_bounds__(BLK) void k_bucket_colscan(BucketArgs a) {
     }
     uint32_t run = csum[col][chunk];
     for (int r = r0; r < r1; ++r) {
-        const uint32_t x = sub[r * 16 + col];
-        sub[r * 16 + col] = run;
+        const uint32_t x = sub[r * CS + col];
+        sub[r * CS + col] = run;
         run += x;
     }
     __syncthreads();
-    for (int i = t; i < nrows * 16; i += BLK) bh[(uint64_t)(i >> 4) * a.stride + c0 + (i & 15)] = sub[i];
+    for (int i = t; i < nrows * CS; i += BLK) bh[(uint64_t)(i / CS) * a.stride + c0 + (i % CS)] = sub[i];
 }
 
 // block-wide exclusive scan of the N counts c[] in place (N / NT consecutive per thread)
@@ -1492,8 +1497,8 @@ gs_status launch_bin_sort(const gs_projected* proj, const gs_views* views, gs_bi
                                (uint64_t*)nullptr, (uint32_t*)nullptr, bins->capacity, (uint32_t*)nullptr);
         // 2. per-tile prefixes over the rows, tile totals and the pair total, 3. pairs written
         // into their tiles
-        hipLaunchKernelGGL(k_bucket_colscan, dim3((unsigned)(ba.stride / 16), (unsigned)views->n_views), dim3(BLK), 0,
-                           stream, ba);
+        hipLaunchKernelGGL(k_bucket_colscan<COLSCAN_CS>, dim3((unsigned)(ba.stride / COLSCAN_CS), (unsigned)views->n_views),
+                           dim3(BLK), 0, stream, ba);
         hipLaunchKernelGGL(k_bucket_emit, dim3((unsigned)L.nbr + (ba.queue ? 1u : 0u), (unsigned)views->n_views),
                            dim3(BK_T), 0, stream, ba);
         vin = U64(L.tv1);
