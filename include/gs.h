@@ -260,6 +260,17 @@ gs_status gs_bin_sort_noalloc(const gs_projected* proj, const gs_views* views, g
 gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
                         float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, void* stream);
 
+/* gs_bin_sort followed by gs_render_fwd, in fewer launches: each tile's sort by (depth, index)
+ * (eq. render-gs) is done by the compositing workgroup of that tile right before it composites
+ * the tile, so the tiles sorted first start compositing while others are still being sorted.
+ * Arguments as in the two calls (ws as for gs_bin_sort); the same results: keys, vals, ranges,
+ * counts and flags of bins as gs_bin_sort leaves them, and the same image, t_final, n_last and
+ * n_contrib, bit for bit. Tile shapes whose compositing workgroup does not have 256 threads
+ * (the sort's) run the two steps as two launches. */
+gs_status gs_bin_sort_render_fwd(const gs_projected* proj, const gs_views* views, gs_bins* bins, const gs_params* p,
+                                 float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, void* ws,
+                                 size_t ws_bytes, void* stream);
+
 /* L1 photometric loss of a rendered batch against a target (the per-view training loss
  * whose gradient drives gs_render_bwd): dl_drgb[i] = sign(rgb[i] - target[i]) * scale
  * (sign(0) = 0) for i < n, and *loss_accum += scale * sum |rgb - target| (device scalar).

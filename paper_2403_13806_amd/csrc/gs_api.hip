@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gs_device.hpp"
+#include "gs_tile_sort.hpp"
 
 namespace gs {
 
@@ -35,7 +36,9 @@ gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_param
 gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
                                 const gs_bins*, const float*, float*, gs_gaussians_grad*, hipStream_t);
 bool bwd_sums_in_chain(const gs_views*);
-gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t);
+gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t, TileSortArgs*);
+gs_status launch_render_fwd_sorted(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
+                                   float*, uint32_t*, uint32_t*, const TileSortArgs&, hipStream_t);
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
 gs_status launch_bits_to_list(const uint32_t*, int64_t, int32_t*, int64_t*, void*, hipStream_t);
@@ -231,7 +234,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, gs_bins* 
     const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
     if (ws_bytes < need || (need > 0 && !ws))
         return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
-    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);
+    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream, nullptr);
 }
 
 gs_status gs_bin_sort_noalloc(const gs_projected* proj, const gs_views* views, gs_bins* bins, void* stream) {
@@ -244,7 +247,7 @@ gs_status gs_bin_sort_noalloc(const gs_projected* proj, const gs_views* views, g
                          "(use gs_bin_sort with a workspace)", need, (size_t)GS_BIN_SORT_NOALLOC_BYTES);
     void* ws = nullptr;
     if ((st = noalloc_scratch(&ws))) return st;
-    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream);
+    return launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream, nullptr);
 }
 
 gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
@@ -257,6 +260,24 @@ gs_status gs_render_fwd(const gs_projected* proj, const gs_views* views, const g
     if (views->n_pixels > 0 && (!rgb || !t_final || !n_last))
         return set_error(GS_ERR_INVALID_ARG, "output image pointer is NULL");
     return launch_render_fwd(proj, views, bins, p, rgb, t_final, n_last, n_contrib, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort_render_fwd(const gs_projected* proj, const gs_views* views, gs_bins* bins, const gs_params* p,
+                                 float* rgb, float* t_final, uint32_t* n_last, uint32_t* n_contrib, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if ((st = check_queue(views, bins))) return st;
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    if (views->n_pixels > 0 && (!rgb || !t_final || !n_last))
+        return set_error(GS_ERR_INVALID_ARG, "output image pointer is NULL");
+    TileSortArgs ta;
+    if ((st = launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream, &ta))) return st;
+    return launch_render_fwd_sorted(proj, views, bins, p, rgb, t_final, n_last, n_contrib, ta, (hipStream_t)stream);
 }
 
 gs_status gs_l1_loss_grad(const float* rgb, const float* target, int64_t n, float scale, float* dl_drgb,

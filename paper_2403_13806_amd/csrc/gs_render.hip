@@ -22,6 +22,7 @@
 #include <mutex>
 
 #include "gs_device.hpp"
+#include "gs_tile_sort.hpp"
 
 namespace gs {
 
@@ -715,6 +716,28 @@ void k_render(RenderArgs a) {
     fwd_tile<TW, TH, DEPTH, MODE, PXW>(sm, a, tile_of_block(a));
 }
 
+// Sorting and compositing in one launch: each workgroup first sorts its tile's list (as the
+// binning's sort launch would, writing the keys and values) and then composites it, reusing the
+// same LDS. Tiles whose lists are sorted early start compositing while others still sort, and
+// the launch between the two is gone. For the tile shapes whose workgroup has the sort's TS_T
+// threads.
+template <int TW, int TH, int DEPTH, int MODE, int PXW>
+__global__ __launch_bounds__(TW* TH / PXW) void k_sort_render(RenderArgs a, TileSortArgs ta) {
+    static_assert(TW * TH / PXW == TS_T, "one thread of the sort per compositing thread");
+    __shared__ union {
+        TileSortLds s;
+        Smem<TW, TH, DEPTH, PXW> r;
+    } u;
+    const int tile = tile_of_block(a);
+    if (ta.sticky && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t o = *ta.overflow;
+        if (o) atomicOr(ta.sticky, o);
+    }
+    sort_tile(u.s, ta, tile);
+    __syncthreads();  // the LDS changes hands; the tile's sorted values are read back below
+    fwd_tile<TW, TH, DEPTH, MODE, PXW>(u.r, a, tile);
+}
+
 // Tile order of the reverse traversal: workgroups go to the 8 XCDs round-robin, so workgroup b
 // runs on XCD b mod 8; here each XCD takes pairs of neighbouring tiles (2m, 2m + 1) in
 // consecutive slots, so that the slots of a Gaussian's pairs in two neighbouring tiles (adjacent
@@ -884,6 +907,46 @@ gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, con
                               : launch_mode<MODE_FWD>(a, views->tile_w, views->tile_h, views->batch_depth, px,
                                                       views->n_tiles, s);
     return finish(ok, "render_fwd");
+}
+
+void launch_tile_sort(const TileSortArgs& ta, hipStream_t stream);
+
+template <int MODE>
+static bool launch_sort_mode(const RenderArgs& a, const TileSortArgs& ta, int tw, int th, int depth, int px,
+                             int n_tiles, hipStream_t s) {
+#define GS_CASE(W_, H_, D_, P_)                                                                          \
+    if (tw == W_ && th == H_ && depth == D_ && px == P_) {                                               \
+        hipLaunchKernelGGL((k_sort_render<W_, H_, D_, MODE, P_>), dim3(n_tiles), dim3(W_ * H_ / P_), 0, s, a, ta); \
+        return true;                                                                                     \
+    }
+    GS_CASE(16, 16, 1, 1) GS_CASE(16, 16, 2, 1)
+    GS_CASE(32, 8, 1, 1) GS_CASE(32, 8, 2, 1)
+    GS_CASE(8, 32, 1, 1) GS_CASE(8, 32, 2, 1)
+    GS_CASE(32, 16, 1, 2) GS_CASE(16, 32, 1, 2) GS_CASE(32, 16, 2, 2) GS_CASE(16, 32, 2, 2)
+#undef GS_CASE
+    return false;
+}
+
+// compositing of lists whose per-tile sort is still to be done (ta, from the binning): in the
+// compositing launch where the tile shape allows, else the sort launch and then compositing
+gs_status launch_render_fwd_sorted(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                                   const gs_params* p, float* rgb, float* t_final, uint32_t* n_last,
+                                   uint32_t* n_contrib, const TileSortArgs& ta, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.rgb = rgb;
+    a.t_final = t_final;
+    a.n_last = n_last;
+    a.n_contrib = n_contrib;
+    const int px = fwd_pixels_per_lane(views);
+    const bool fused =
+        n_contrib ? launch_sort_mode<MODE_FWD_COUNT>(a, ta, views->tile_w, views->tile_h, views->batch_depth, px,
+                                                     views->n_tiles, s)
+                  : launch_sort_mode<MODE_FWD>(a, ta, views->tile_w, views->tile_h, views->batch_depth, px,
+                                               views->n_tiles, s);
+    if (fused) return check_launch("bin_sort_render_fwd");
+    launch_tile_sort(ta, s);
+    return launch_render_fwd(proj, views, bins, p, rgb, t_final, n_last, n_contrib, s);
 }
 
 gs_status launch_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,

@@ -665,8 +665,13 @@ class Renderer:
 
     def forward(self):
         s = _stream(self.views.device)
-        self._pre(s)
-        self.render_only(s)
+        lib = L.load()
+        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self.p),
+                                  _ptr(self.subset), self.n_entries, int(self.want_color), ctypes.byref(self._sp), s))
+        # binning, and each tile's sort inside the compositing launch
+        L.check(lib.gs_bin_sort_render_fwd(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
+                                           ctypes.byref(self.p), _ptr(self.rgb), _ptr(self.t_final),
+                                           _ptr(self.n_last), None, _ptr(self.ws), self.ws.numel(), s))
         return self.rgb
 
     def render_only(self, s=None, n_contrib: Optional[torch.Tensor] = None):
@@ -925,9 +930,8 @@ class PathRenderer:
             s = _stream(self.device)
         L.check(lib.gs_preprocess(ctypes.byref(src), ctypes.byref(sv), ctypes.byref(self.p), _ptr(subset), n, 1,
                                   ctypes.byref(sp), s))
-        L.check(lib.gs_bin_sort(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(sb), _ptr(ws), ws.numel(), s))
-        L.check(lib.gs_render_fwd(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(sb), ctypes.byref(self.p),
-                                  _ptr(rgb), _ptr(t_final), _ptr(n_last), None, s))
+        L.check(lib.gs_bin_sort_render_fwd(ctypes.byref(sp), ctypes.byref(sv), ctypes.byref(sb), ctypes.byref(self.p),
+                                           _ptr(rgb), _ptr(t_final), _ptr(n_last), None, _ptr(ws), ws.numel(), s))
         return rgb
 
     def ok(self) -> bool:

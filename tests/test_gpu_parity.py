@@ -794,6 +794,63 @@ def test_launch_forms_bitwise(tile, depth, lpt, ppl):
         assert np.all(np.diff(bl) <= 0)  # longest first, by powers of two
 
 
+@pytest.mark.parametrize("tile,ppl,lpt,scene", [((16, 32), 0, True, "mixture"), ((16, 16), 1, False, "mixture"),
+                                               ((32, 16), 2, True, "mixture"), ((16, 32), 2, False, "mixture"),
+                                               ((8, 8), 1, True, "mixture"), ((16, 16), 1, True, "long"),
+                                               ((16, 32), 0, False, "long"), ((16, 32), 0, True, "overflow")])
+def test_bin_sort_render_fused_bitwise(tile, ppl, lpt, scene):
+    """gs_bin_sort_render_fwd (each tile sorted by the workgroup that composites it; two launches
+    for tile shapes whose compositing workgroup is not the sort's 256 threads) leaves the bins
+    exactly as gs_bin_sort does and renders exactly what gs_render_fwd renders after it: keys,
+    values, ranges, flags, image, T, last entries and composited counts, long lists (chunked
+    sort and merges) and a pair overflow included."""
+    import ctypes
+    from paper_2403_13806_amd import _lib as L
+    from paper_2403_13806_amd.splat import _ptr, _stream
+    if scene == "mixture":
+        sc = scenes.mixture_scene(6000, seed=7, sh_degree=3)
+        cams = scenes.uneven_views([(64, 48), (126, 83), (160, 106), (192, 108)])
+    else:
+        sc = scenes.uniform_cube_scene(12000, seed=7)
+        sc.mean = (sc.mean * np.float32(0.03)).astype(np.float32)
+        cams = [scenes.plain_view()]
+    _say(f"fused sort and compositing tile={tile} ppl={ppl} lpt={lpt} scene={scene}")
+    g = gs.Gaussians.from_scene(sc, DEV)
+    vb = gs.ViewBatch(cams, tile, DEV, lpt=lpt, pixels_per_lane=ppl)
+    r = gs.Renderer(g, vb, P, capacity=2000 if scene == "overflow" else None)
+    lib = L.load()
+    s = _stream(DEV)
+    res = []
+    for fused in (False, True):
+        for t in (r.bins.keys, r.bins.vals, r.rgb, r.t_final, r.n_last):
+            t.fill_(7)  # whatever the other run left
+        nc = torch.full((vb.n_pixels,), -1, dtype=torch.int32, device=DEV)
+        if fused:
+            L.check(lib.gs_preprocess(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r.p), None, r.n_entries,
+                                      1, ctypes.byref(r._sp), s))
+            L.check(lib.gs_bin_sort_render_fwd(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                               ctypes.byref(r.p), _ptr(r.rgb), _ptr(r.t_final), _ptr(r.n_last),
+                                               _ptr(nc), _ptr(r.ws), r.ws.numel(), s))
+        else:
+            r._pre(s)
+            r.render_only(s, nc)
+        torch.cuda.synchronize()
+        n = min(int(r.bins.n_pairs.item()), r.bins.capacity)
+        res.append(dict(keys=r.bins.keys[:n].clone(), vals=r.bins.vals[:n].clone(), ranges=r.bins.ranges.clone(),
+                        overflow=int(r.bins.overflow.item()), rgb=r.rgb.clone(), t=r.t_final.clone(),
+                        last=r.n_last.clone(), nc=nc.clone()))
+    a, b = res
+    assert a["overflow"] == b["overflow"] and (a["overflow"] != 0) == (scene == "overflow")
+    for k in ("ranges", "rgb", "t", "last", "nc"):
+        assert torch.equal(a[k], b[k]), k
+    if scene != "overflow":  # (after an overflow the pair buffers hold nothing defined)
+        assert torch.equal(a["keys"], b["keys"]) and torch.equal(a["vals"], b["vals"])
+    # the frames of Renderer.forward() are the fused ones, without the counts
+    r.forward()
+    torch.cuda.synchronize()
+    assert torch.equal(r.rgb, a["rgb"])
+
+
 def test_graph_replay_matches_eager():
     """A captured fwd + L1 + bwd step replayed several times, with eager work in between,
     reproduces the eager step bit for bit: images, gradients and the loss (the loss word is a
