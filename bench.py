@@ -139,6 +139,8 @@ def main():
     log(f"forward: {fps:.1f} frames/s (wall), {K / ev_ms * 1e3:.1f} frames/s (events)")
 
     # ---------------- per-stage kernel times (events around each call) ----------------
+    # (the stages are timed as separate calls: binning with its own tile sort, then compositing
+    # alone; the headline frames above sort each tile inside the compositing launch instead)
     import ctypes
     from paper_2403_13806_amd import _lib as L
     from paper_2403_13806_amd.splat import _ptr, _stream
@@ -290,7 +292,8 @@ def main():
         "config": {"workload": "1M Gaussians (mixture of 32 clusters, SH degree 3), 1256x828, 8 orbit views, "
                                "plain forward per frame", "gaussians": n, "width": 1256, "height": 828,
                    "views": 8, "tile": f"{TILE[0]}x{TILE[1]}",
-                   "tile_order": "longest-first" if LPT else "tile index", "parallelism": "single GPU"},
+                   "tile_order": "longest-first" if LPT else "tile index",
+                   "tile_sort": "in the compositing launch (gs_bin_sort_render_fwd)", "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
