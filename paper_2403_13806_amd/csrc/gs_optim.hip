@@ -9,6 +9,7 @@
 //   logit   u = log(x/(1-x))  (x in (0, 1); opacities), x clamped to [1e-6, 1 - 1e-6] first
 // with du = dx * x (log) or dx * x (1 - x) (logit); Adam runs on u and x is mapped back.
 #include <cmath>
+#include <cstdint>
 
 #include "gs_device.hpp"
 
@@ -18,8 +19,9 @@ namespace {
 
 constexpr int GROUPS_PER_LAUNCH = 16;
 constexpr int NT = 256;
-constexpr int PER_THREAD = 4;
+constexpr int PER_THREAD = 16;
 constexpr int CHUNK = NT * PER_THREAD;  // elements per workgroup, all of one group
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 struct AdamTable {
     float* p[GROUPS_PER_LAUNCH];
@@ -30,18 +32,45 @@ struct AdamTable {
     int64_t blk[GROUPS_PER_LAUNCH + 1];  // first workgroup of each group
     float lr[GROUPS_PER_LAUNCH];
     int32_t mode[GROUPS_PER_LAUNCH];
+    int32_t vec[GROUPS_PER_LAUNCH];  // all four planes 16-byte aligned: 4-element loads and stores
     int32_t count_groups;
     int32_t zero_grad;
     float b1, b2, omb1, omb2, eps, inv_bc1, inv_sqrt_bc2;  // omb = 1 - b, formed in FP64
 };
 
-// one workgroup = CHUNK consecutive elements of one group (group, pointers and mode are
-// uniform); each lane loads its PER_THREAD elements (NT apart, coalesced) before computing
+// one element: parameter x, gradient dx and moments m, v in; new x, m, v out
+__device__ __forceinline__ void adam1(const AdamTable& t, int mode, float lr, float& x, float dx, float& m, float& v) {
+    float xv = x, uu = xv, du = dx;
+    if (mode == GS_ADAM_LOG) {
+        uu = logf(xv);
+        du = dx * xv;
+    } else if (mode == GS_ADAM_LOGIT) {
+        xv = fminf(fmaxf(xv, 1e-6f), 1.f - 1e-6f);
+        uu = logf(xv / (1.f - xv));
+        du = dx * xv * (1.f - xv);
+    }
+    m = t.b1 * m + t.omb1 * du;
+    v = t.b2 * v + t.omb2 * du * du;
+    uu -= lr * (m * t.inv_bc1) / (sqrtf(v) * t.inv_sqrt_bc2 + t.eps);
+    if (mode == GS_ADAM_LOG)
+        xv = expf(uu);
+    else if (mode == GS_ADAM_LOGIT)
+        xv = 1.f / (1.f + expf(-uu));
+    else
+        xv = uu;
+    x = xv;
+}
+
+// One workgroup = CHUNK consecutive elements of one group (group, pointers and mode are
+// uniform). Aligned groups: each lane takes PER_THREAD / 4 runs of 4 consecutive elements
+// (NT runs apart: each wave instruction moves 1 KB), all loads of the lane issued before any
+// arithmetic, every plane read and written once with streaming (nontemporal) accesses; the
+// tail of a group shorter than 4 goes element by element. Otherwise PER_THREAD single
+// elements NT apart. The arithmetic per element is the same in both.
 __global__ __launch_bounds__(NT) void k_adam(AdamTable t) {
     const int64_t b = blockIdx.x;
     int k = 0;
     while (b >= t.blk[k + 1]) ++k;
-    const int64_t base = (b - t.blk[k]) * CHUNK + threadIdx.x;
     const int64_t n = t.count[k];
     float* __restrict__ P = t.p[k];
     float* __restrict__ G = t.g[k];
@@ -49,6 +78,46 @@ __global__ __launch_bounds__(NT) void k_adam(AdamTable t) {
     float* __restrict__ V = t.v[k];
     const int mode = t.mode[k];
     const float lr = t.lr[k];
+    if (t.vec[k]) {
+        constexpr int R = PER_THREAD / 4;
+        const int64_t q0 = (b - t.blk[k]) * (CHUNK / 4) + threadIdx.x;  // first run of the lane
+        f4 x[R], dx[R], m[R], v[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int64_t e = 4 * (q0 + u * NT);
+            if (e + 3 < n) {
+                x[u] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(P + e));
+                dx[u] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(G + e));
+                m[u] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(M + e));
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(V + e));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int64_t e = 4 * (q0 + u * NT);
+            if (e + 3 < n) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float xc = x[u][c], mc = m[u][c], vc = v[u][c];
+                    adam1(t, mode, lr, xc, dx[u][c], mc, vc);
+                    x[u][c] = xc, m[u][c] = mc, v[u][c] = vc;
+                }
+                __builtin_nontemporal_store(x[u], reinterpret_cast<f4*>(P + e));
+                __builtin_nontemporal_store(m[u], reinterpret_cast<f4*>(M + e));
+                __builtin_nontemporal_store(v[u], reinterpret_cast<f4*>(V + e));
+                if (t.zero_grad) __builtin_nontemporal_store(f4(0.f), reinterpret_cast<f4*>(G + e));
+            } else {
+                for (int64_t j = e; j < n && j < e + 4; ++j) {
+                    float xj = P[j], mj = M[j], vj = V[j];
+                    adam1(t, mode, lr, xj, G[j], mj, vj);
+                    P[j] = xj, M[j] = mj, V[j] = vj;
+                    if (t.zero_grad) G[j] = 0.f;
+                }
+            }
+        }
+        return;
+    }
+    const int64_t base = (b - t.blk[k]) * CHUNK + threadIdx.x;
     float x[PER_THREAD], dx[PER_THREAD], m0[PER_THREAD], v0[PER_THREAD];
 #pragma unroll
     for (int u = 0; u < PER_THREAD; ++u) {
@@ -60,27 +129,10 @@ __global__ __launch_bounds__(NT) void k_adam(AdamTable t) {
     for (int u = 0; u < PER_THREAD; ++u) {
         const int64_t j = base + u * NT;
         if (j >= n) continue;
-        float xv = x[u], uu = xv, du = dx[u];
-        if (mode == GS_ADAM_LOG) {
-            uu = logf(xv);
-            du = dx[u] * xv;
-        } else if (mode == GS_ADAM_LOGIT) {
-            xv = fminf(fmaxf(xv, 1e-6f), 1.f - 1e-6f);
-            uu = logf(xv / (1.f - xv));
-            du = dx[u] * xv * (1.f - xv);
-        }
-        const float m = t.b1 * m0[u] + t.omb1 * du;
-        const float v = t.b2 * v0[u] + t.omb2 * du * du;
-        uu -= lr * (m * t.inv_bc1) / (sqrtf(v) * t.inv_sqrt_bc2 + t.eps);
-        if (mode == GS_ADAM_LOG)
-            xv = expf(uu);
-        else if (mode == GS_ADAM_LOGIT)
-            xv = 1.f / (1.f + expf(-uu));
-        else
-            xv = uu;
-        P[j] = xv;
-        M[j] = m;
-        V[j] = v;
+        adam1(t, mode, lr, x[u], dx[u], m0[u], v0[u]);
+        P[j] = x[u];
+        M[j] = m0[u];
+        V[j] = v0[u];
         if (t.zero_grad) G[j] = 0.f;
     }
 }
@@ -112,6 +164,8 @@ gs_status launch_adam(const gs_adam_group* groups, int32_t n_groups, double b1, 
         t.blk[c + 1] = t.blk[c] + (groups[k].count + CHUNK - 1) / CHUNK;
         t.lr[c] = groups[k].lr;
         t.mode[c] = groups[k].mode;
+        t.vec[c] = ((reinterpret_cast<uintptr_t>(t.p[c]) | reinterpret_cast<uintptr_t>(t.g[c]) |
+                     reinterpret_cast<uintptr_t>(t.m[c]) | reinterpret_cast<uintptr_t>(t.v[c])) & 15u) == 0;
         if (t.count_groups == GROUPS_PER_LAUNCH) {
             gs_status st = flush();
             if (st != GS_OK) return st;
