@@ -35,7 +35,6 @@ gs_status launch_preprocess(const gs_gaussians*, const gs_views*, const gs_param
                             gs_projected*, hipStream_t);
 gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_params*, const gs_projected*,
                                 const gs_bins*, const float*, float*, gs_gaussians_grad*, hipStream_t);
-bool bwd_sums_in_chain(const gs_views*);
 gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t, TileSortArgs*);
 gs_status launch_render_fwd_sorted(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
                                    float*, uint32_t*, uint32_t*, const TileSortArgs&, hipStream_t);
@@ -68,7 +67,7 @@ gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*
 gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
                             int32_t, float, uint32_t*, hipStream_t);
 gs_status launch_render_bwd(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const float*,
-                            const uint32_t*, const float*, float*, float*, bool, hipStream_t);
+                            const uint32_t*, const float*, float*, hipStream_t);
 
 // nine FP32 partial gradients per pair slot, then their nine sums per (view, entry)
 static size_t bwd_slots_bytes(uint64_t capacity) { return (sizeof(float) * 9 * (size_t)capacity + 255) & ~(size_t)255; }
@@ -340,9 +339,7 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_views* views, const gs_p
     hipStream_t s = (hipStream_t)stream;
     float* slots = (float*)ws;
     float* g2 = (float*)((char*)ws + bwd_slots_bytes(bins->capacity));
-    const bool pair_sums = !bwd_sums_in_chain(views);
-    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, slots, g2, pair_sums, s)))
-        return st;
+    if ((st = launch_render_bwd(proj, views, bins, p, t_final, n_last, dl_drgb, slots, s))) return st;
     return launch_preprocess_bwd(g, views, p, proj, bins, slots, g2, grad, s);
 }
 

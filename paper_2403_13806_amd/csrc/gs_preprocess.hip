@@ -339,11 +339,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 
 // ---------------------------------------------------------------------------------------
 // Reverse mode: chain per-(view, Gaussian) gradients of the 2D quantities (u, v, conic
-// a, b, c, opacity, rgb) to the parameters (the per-entry sums over the entry's pairs, formed
-// in a fixed order by the reverse traversal's last step). One lane per Gaussian, looping
-// over the views of the batch, so each Gaussian's gradient is owned by one lane (no atomics).
-// This kernel covers position (through u, v and J), scale, rotation and opacity; the
-// colour part follows in k_preprocess_bwd_sh. Adding reads and writes only the gradients of
+// a, b, c, opacity, rgb) to the parameters. The per-entry 2D gradients are the sums of the
+// entry's pair slots (the reverse traversal's per-(tile, entry) partial sums), formed here in a
+// fixed order. One lane per Gaussian, looping over the views of the batch, so each Gaussian's
+// gradient is owned by one lane (no atomics). The geometric kernels cover position (through u,
+// v and J), scale, rotation and opacity; the colour part follows in k_preprocess_bwd_sh. Adding reads and writes only the gradients of
 // Gaussians some pair contributes to; overwriting writes every one and reads none, which halves
 // the gradient traffic where (as in random storage order) the visible Gaussians are spread over
 // every cache line anyway.
@@ -360,9 +360,9 @@ struct PreBwdArgs {
     int n_views;
     gs_params p;
     const uint32_t* count;   // [V][n]
-    const float* g2;         // [9][V*n], read where count > 0
-    // one view: the pair slots are summed here instead (entry o owns the nine-float slots
-    // [eoff[o], eoff[o] + count[o])), and only the colour fields 6..8 are written to g2w
+    const float* g2;         // [9][V*n]: the colour fields 6..8, read by the SH kernel where count > 0
+    // the pair slots, summed by the geometric kernels (entry o owns the nine-float slots
+    // [eoff[o], eoff[o] + count[o])), which write the colour fields 6..8 of g2 (g2w)
     const uint32_t* eoff;
     const float* slots;
     uint64_t capacity;
@@ -408,24 +408,127 @@ __device__ __forceinline__ Geom load_geom_rows(const PreBwdArgs& a, int64_t i0, 
     return g;
 }
 
-// The parameter chain of one Gaussian that some view composited (byte offset lb from the row
-// base i0): every view's 2D gradients chained back in view order, then written (or added).
-// With SUMS the first (only) view's 2D gradients come from the workgroup's sums sg in LDS.
-template <bool SUMS>
+// The parameter chain's running sums of one Gaussian (FP64, over the views in order)
+struct GeomAcc {
+    double gp[3], gs[3], gq[4], go;
+    bool any;  // some view's 2D gradients were not all zero
+};
+
+// One view's 2D gradients g6 = (u, v, conic a, b, c, opacity) of the Gaussian with parameters gm,
+// seen by camera cam, chained to its parameters and added into A.
+__device__ __forceinline__ void chain_step(const PreBwdArgs& a, const Geom& gm, const gs_camera& cam,
+                                           const float (&g6)[6], GeomAcc& A) {
+    const float gu = g6[0], gv = g6[1], gA = g6[2], gB = g6[3], gC = g6[4], gO = g6[5];
+    if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) return;
+    A.any = true;
+    Proj P;
+    double op;
+    if (!project_vals(cam, a.p, gm, P, op)) return;
+    A.go += gO;
+    const double idet = 1.0 / P.det;
+    const double ca = P.syy * idet, cb = -P.sxy * idet, cc = P.sxx * idet;
+    // conic Q = Sigma'^-1; for a symmetric perturbation dSigma', dQ = -Q dSigma' Q.
+    // With G = [[gA, gB/2], [gB/2, gC]] the gradient w.r.t. Sigma' is -Q G Q.
+    const double g00 = gA, g01 = 0.5 * gB, g11 = gC;
+    const double QG00 = ca * g00 + cb * g01, QG01 = ca * g01 + cb * g11;
+    const double QG10 = cb * g00 + cc * g01, QG11 = cb * g01 + cc * g11;
+    const double H00 = -(QG00 * ca + QG01 * cb);
+    const double H01 = -(QG00 * cb + QG01 * cc);
+    const double H11 = -(QG10 * cb + QG11 * cc);
+    const double H[2][2] = {{H00, H01}, {H01, H11}};
+    // Sigma' = T Sigma T^T: dL/dSigma = T^T H T, dL/dT = 2 H T Sigma
+    double GS[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            GS[r][c] = P.T[0][r] * (H[0][0] * P.T[0][c] + H[0][1] * P.T[1][c]) +
+                       P.T[1][r] * (H[1][0] * P.T[0][c] + H[1][1] * P.T[1][c]);
+    double HT[2][3], GT[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) HT[r][c] = H[r][0] * P.T[0][c] + H[r][1] * P.T[1][c];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            GT[r][c] = 2.0 * (HT[r][0] * P.Sg[0][c] + HT[r][1] * P.Sg[1][c] + HT[r][2] * P.Sg[2][c]);
+    // T = J R with J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]: dL/dJ = GT R^T
+    const float* Rc = cam.R;
+    double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        GJ00 += GT[0][k] * Rc[0 * 3 + k];
+        GJ02 += GT[0][k] * Rc[2 * 3 + k];
+        GJ11 += GT[1][k] * Rc[1 * 3 + k];
+        GJ12 += GT[1][k] * Rc[2 * 3 + k];
+    }
+    const double fx = cam.fx, fy = cam.fy, z = P.z, iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+    double gc[3];
+    gc[0] = -fx * iz2 * GJ02 + fx * iz * gu;
+    gc[1] = -fy * iz2 * GJ12 + fy * iz * gv;
+    gc[2] = -fx * iz2 * GJ00 + 2.0 * fx * P.x * iz3 * GJ02 - fy * iz2 * GJ11 + 2.0 * fy * P.y * iz3 * GJ12 -
+            fx * P.x * iz2 * gu - fy * P.y * iz2 * gv;
+    // world mean: p_c = R p + t
+#pragma unroll
+    for (int k = 0; k < 3; ++k) A.gp[k] += Rc[k] * gc[0] + Rc[3 + k] * gc[1] + Rc[6 + k] * gc[2];
+    // Sigma = M M^T with M = Rq diag(s): dL/dM = 2 GS M
+    const double s[3] = {gm.s[0], gm.s[1], gm.s[2]};
+    double GR[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double gm =
+                2.0 * (GS[r][0] * P.Rq[0][c] * s[c] + GS[r][1] * P.Rq[1][c] * s[c] + GS[r][2] * P.Rq[2][c] * s[c]);
+            A.gs[c] += gm * P.Rq[r][c];
+            GR[r][c] = gm * s[c];
+        }
+    const double w = P.qh[0], x = P.qh[1], y = P.qh[2], zq = P.qh[3];
+    double gw = 2.0 * (-zq * GR[0][1] + y * GR[0][2] + zq * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+    double gx = 2.0 * (y * GR[0][1] + zq * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] +
+                       zq * GR[2][0] + w * GR[2][1] - 2.0 * x * GR[2][2]);
+    double gy = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + zq * GR[1][2] -
+                       w * GR[2][0] + zq * GR[2][1] - 2.0 * y * GR[2][2]);
+    double gz = 2.0 * (-2.0 * zq * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * zq * GR[1][1] +
+                       y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+    const double dot = w * gw + x * gx + y * gy + zq * gz;
+    const double iqn = 1.0 / P.qn;
+    A.gq[0] += (gw - w * dot) * iqn;
+    A.gq[1] += (gx - x * dot) * iqn;
+    A.gq[2] += (gy - y * dot) * iqn;
+    A.gq[3] += (gz - zq * dot) * iqn;
+    
+}
+
+// the chain's results: written (old = 0) or added onto the gradients held (old)
+__device__ __forceinline__ void write_geom(const PreBwdArgs& a, int64_t i0, uint32_t lb, const float (&old)[11],
+                                           const GeomAcc& A) {
+    const int64_t n = a.n;
+    auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        grow(a.gmean, k) = old[k] + (float)A.gp[k];
+        grow(a.gscale, k) = old[3 + k] + (float)A.gs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) grow(a.gquat, k) = old[6 + k] + (float)A.gq[k];
+    grow(a.gopac, 0) = old[10] + (float)A.go;
+}
+
+// The parameter chain of one Gaussian composited in the one view (byte offset lb from the row
+// base i0), from the view's 2D gradients summed in LDS (sg), written (or added).
 __device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint32_t lb, bool acc,
                                            const float (*sg)[9]) {
     const int64_t n = a.n;
     auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
-    const int64_t VN = (int64_t)a.n_views * n;
-    double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-    bool any = false;
-    // parameters, the first view's count and 2D gradients and the gradients accumulated so far
-    // are requested together, in one round of loads
+    GeomAcc A = {};
+    // parameters and the gradients accumulated so far are requested together
     const Geom gm = load_geom_rows(a, i0, lb);
-    const uint32_t cnt0 = lane(uniform_ptr(a.count + i0), lb);
-    float g20[6];
+    float g6[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) g20[k] = SUMS ? sg[lb >> 2][k] : lane(uniform_ptr(a.g2 + k * VN + i0), lb);
+    for (int k = 0; k < 6; ++k) g6[k] = sg[lb >> 2][k];
     float old[11];
 #pragma unroll
     for (int k = 0; k < 11; ++k) old[k] = 0.f;
@@ -436,122 +539,26 @@ __device__ __forceinline__ void geom_chain(const PreBwdArgs& a, int64_t i0, uint
         for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
         old[10] = grow(a.gopac, 0);
     }
-    for (int v = 0; v < a.n_views; ++v) {
-        const int64_t o = (int64_t)v * n + i0;
-        if ((v == 0 ? cnt0 : lane(uniform_ptr(a.count + o), lb)) == 0) continue;
-        float g6[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) g6[k] = v == 0 ? g20[k] : lane(uniform_ptr(a.g2 + k * VN + o), lb);
-        const float gu = g6[0], gv = g6[1], gA = g6[2], gB = g6[3], gC = g6[4], gO = g6[5];
-        if (gu == 0.f && gv == 0.f && gA == 0.f && gB == 0.f && gC == 0.f && gO == 0.f) continue;
-        any = true;
-        const gs_camera cam = a.cams[v];
-        Proj P;
-        double op;
-        if (!project_vals(cam, a.p, gm, P, op)) continue;
-        go += gO;
-        const double idet = 1.0 / P.det;
-        const double ca = P.syy * idet, cb = -P.sxy * idet, cc = P.sxx * idet;
-        // conic Q = Sigma'^-1; for a symmetric perturbation dSigma', dQ = -Q dSigma' Q.
-        // With G = [[gA, gB/2], [gB/2, gC]] the gradient w.r.t. Sigma' is -Q G Q.
-        const double g00 = gA, g01 = 0.5 * gB, g11 = gC;
-        const double QG00 = ca * g00 + cb * g01, QG01 = ca * g01 + cb * g11;
-        const double QG10 = cb * g00 + cc * g01, QG11 = cb * g01 + cc * g11;
-        const double H00 = -(QG00 * ca + QG01 * cb);
-        const double H01 = -(QG00 * cb + QG01 * cc);
-        const double H11 = -(QG10 * cb + QG11 * cc);
-        const double H[2][2] = {{H00, H01}, {H01, H11}};
-        // Sigma' = T Sigma T^T: dL/dSigma = T^T H T, dL/dT = 2 H T Sigma
-        double GS[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                GS[r][c] = P.T[0][r] * (H[0][0] * P.T[0][c] + H[0][1] * P.T[1][c]) +
-                           P.T[1][r] * (H[1][0] * P.T[0][c] + H[1][1] * P.T[1][c]);
-        double HT[2][3], GT[2][3];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) HT[r][c] = H[r][0] * P.T[0][c] + H[r][1] * P.T[1][c];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                GT[r][c] = 2.0 * (HT[r][0] * P.Sg[0][c] + HT[r][1] * P.Sg[1][c] + HT[r][2] * P.Sg[2][c]);
-        // T = J R with J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]: dL/dJ = GT R^T
-        const float* Rc = cam.R;
-        double GJ00 = 0, GJ02 = 0, GJ11 = 0, GJ12 = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            GJ00 += GT[0][k] * Rc[0 * 3 + k];
-            GJ02 += GT[0][k] * Rc[2 * 3 + k];
-            GJ11 += GT[1][k] * Rc[1 * 3 + k];
-            GJ12 += GT[1][k] * Rc[2 * 3 + k];
-        }
-        const double fx = cam.fx, fy = cam.fy, z = P.z, iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
-        double gc[3];
-        gc[0] = -fx * iz2 * GJ02 + fx * iz * gu;
-        gc[1] = -fy * iz2 * GJ12 + fy * iz * gv;
-        gc[2] = -fx * iz2 * GJ00 + 2.0 * fx * P.x * iz3 * GJ02 - fy * iz2 * GJ11 + 2.0 * fy * P.y * iz3 * GJ12 -
-                fx * P.x * iz2 * gu - fy * P.y * iz2 * gv;
-        // world mean: p_c = R p + t
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gp[k] += Rc[k] * gc[0] + Rc[3 + k] * gc[1] + Rc[6 + k] * gc[2];
-        // Sigma = M M^T with M = Rq diag(s): dL/dM = 2 GS M
-        const double s[3] = {gm.s[0], gm.s[1], gm.s[2]};
-        double GR[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double gm =
-                    2.0 * (GS[r][0] * P.Rq[0][c] * s[c] + GS[r][1] * P.Rq[1][c] * s[c] + GS[r][2] * P.Rq[2][c] * s[c]);
-                gs[c] += gm * P.Rq[r][c];
-                GR[r][c] = gm * s[c];
-            }
-        const double w = P.qh[0], x = P.qh[1], y = P.qh[2], zq = P.qh[3];
-        double gw = 2.0 * (-zq * GR[0][1] + y * GR[0][2] + zq * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
-        double gx = 2.0 * (y * GR[0][1] + zq * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] +
-                           zq * GR[2][0] + w * GR[2][1] - 2.0 * x * GR[2][2]);
-        double gy = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + zq * GR[1][2] -
-                           w * GR[2][0] + zq * GR[2][1] - 2.0 * y * GR[2][2]);
-        double gz = 2.0 * (-2.0 * zq * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * zq * GR[1][1] +
-                           y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
-        const double dot = w * gw + x * gx + y * gy + zq * gz;
-        const double iqn = 1.0 / P.qn;
-        gq[0] += (gw - w * dot) * iqn;
-        gq[1] += (gx - x * dot) * iqn;
-        gq[2] += (gy - y * dot) * iqn;
-        gq[3] += (gz - zq * dot) * iqn;
-        }
-    if (!any && acc) return;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        grow(a.gmean, k) = old[k] + (float)gp[k];
-        grow(a.gscale, k) = old[3 + k] + (float)gs[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) grow(a.gquat, k) = old[6 + k] + (float)gq[k];
-    grow(a.gopac, 0) = old[10] + (float)go;
+    chain_step(a, gm, a.cams[0], g6, A);
+    if (!A.any && acc) return;
+    write_geom(a, i0, lb, old, A);
 }
 
-// One wave per workgroup takes BWD_CHUNK consecutive Gaussians. It lists in LDS those that some
-// view composited and runs the parameter chain on them 64 at a time, so the long FP64 chain
-// runs on nearly full waves even where few Gaussians are visible (about one in five for one
-// view of a large scene, spread over every wave in random storage order); the others get
-// zeros when overwriting and nothing when adding.
-// With SUMS (one view) the wave first sums its Gaussians' pair slots itself: their slots form
-// one range, read 64 at a time (coalesced) and reduced by a segmented scan whose run ends add
-// into the owner's sums in LDS, round after round (the same additions, in the same order, as
-// k_pair_sums makes); the colour fields go to g2 for the SH kernel.
+// One view. One wave per workgroup takes BWD_CHUNK consecutive Gaussians. It first sums their
+// pair slots: entry o owns the slots [eoff[o], eoff[o] + count[o]) and consecutive entries own
+// consecutive runs, so the chunk's slots form one range, read 64 at a time (coalesced) and
+// reduced by a segmented scan whose run ends add into the owner's sums in LDS, round after
+// round (every sum formed in the same order on every call); the colour fields go to g2 for
+// the SH kernel. It lists in LDS the Gaussians the view composited and runs the parameter chain
+// on them 64 at a time, so the long FP64 chain runs on nearly full waves even where few
+// Gaussians are visible (about one in five for a view of a large scene, spread over every
+// wave in random storage order); the others get zeros when overwriting and nothing when adding.
 constexpr int BWD_CHUNK = 256;
 
-template <bool SUMS>
 __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
     __shared__ uint16_t s_list[BWD_CHUNK];
-    __shared__ uint32_t s_beg[SUMS ? BWD_CHUNK : 1];
-    __shared__ float s_g[SUMS ? BWD_CHUNK : 1][9];
+    __shared__ uint32_t s_beg[BWD_CHUNK];
+    __shared__ float s_g[BWD_CHUNK][9];
     __shared__ uint32_t s_end;
     const int64_t i0 = (int64_t)blockIdx.x * BWD_CHUNK;
     const uint32_t l = threadIdx.x;
@@ -573,8 +580,7 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
             if (i0 + li < n) zero(li * 4u);
         return;
     }
-    // the chunk's counts in the first view are requested together; later views are read only
-    // for Gaussians not yet found composited
+    // the chunk's counts and first slots are requested together
     constexpr int NS = BWD_CHUNK / 64;
     const int last = (int)min((int64_t)BWD_CHUNK - 1, n - 1 - i0);  // the chunk's last Gaussian
     uint32_t cnt[NS], eo[NS];
@@ -583,28 +589,24 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
         const uint32_t li = 64 * j + l;
         const bool valid = i0 + li < n;
         cnt[j] = valid ? lane(uniform_ptr(a.count + i0), li * 4u) : 0u;
-        if (SUMS) eo[j] = valid ? lane(uniform_ptr(a.eoff + i0), li * 4u) : 0u;
+        eo[j] = valid ? lane(uniform_ptr(a.eoff + i0), li * 4u) : 0u;
     }
     uint64_t act_mask[NS];
     uint32_t total = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         const uint32_t li = 64 * j + l;
-        bool act = cnt[j] != 0;
-        for (int v = 1; i0 + li < n && !act && v < a.n_views; ++v)
-            act = lane(uniform_ptr(a.count + (int64_t)v * n + i0), li * 4u) != 0;
+        const bool act = cnt[j] != 0;
         act_mask[j] = ballot(act);
         if (act) s_list[total + mask_rank(act_mask[j])] = (uint16_t)li;
         total += (uint32_t)__builtin_popcountll(act_mask[j]);
-        if (SUMS) {
-            if ((int)li <= last) s_beg[li] = eo[j];
-            if ((int)li == last) s_end = eo[j] + cnt[j];
+        if ((int)li <= last) s_beg[li] = eo[j];
+        if ((int)li == last) s_end = eo[j] + cnt[j];
 #pragma unroll
-            for (int f = 0; f < 9; ++f) s_g[li][f] = 0.f;
-        }
+        for (int f = 0; f < 9; ++f) s_g[li][f] = 0.f;
     }
     __syncthreads();
-    if (SUMS) {
+    {
         const uint32_t S0 = s_beg[0], S1 = s_end;
         for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
             const uint32_t sl = base + l;
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
         }
     }
     for (uint32_t b = 0; b < total; b += 64)
-        if (b + l < total) geom_chain<SUMS>(a, i0, (uint32_t)s_list[b + l] * 4u, acc, s_g);
+        if (b + l < total) geom_chain(a, i0, (uint32_t)s_list[b + l] * 4u, acc, s_g);
     // zeros for the rest, after the chain's loads so they do not wait behind these stores
     if (!acc) {
 #pragma unroll
@@ -646,6 +648,94 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
             const uint32_t li = 64 * j + l;
             if (i0 + li < n && !((act_mask[j] >> l) & 1)) zero(li * 4u);
         }
+    }
+}
+
+// Several views: one wave per 64 Gaussians. For each view in turn the wave sums its Gaussians'
+// pair slots of that view (one coalesced range, segmented scan, run ends added into LDS sums,
+// as the one-view kernel does for its chunk), writes the colour sums for the SH kernel, and each lane
+// whose Gaussian that view composited adds the view's chain step. A lane's chain runs over the
+// views in order, as in the one-lane chain above.
+__global__ __launch_bounds__(64) void k_preprocess_bwd_mv(PreBwdArgs a) {
+    __shared__ uint32_t s_beg[64];
+    __shared__ float s_g[64][9];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const uint32_t l = threadIdx.x, lb = l * 4u;
+    const int64_t n = a.n, VN = (int64_t)a.n_views * n;
+    const bool acc = !a.overwrite, valid = i0 + l < n;
+    const int last = (int)min((int64_t)63, n - 1 - i0);  // the chunk's last Gaussian
+    auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
+    auto zero = [&]() {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) grow(a.gmean, k) = 0.f, grow(a.gscale, k) = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) grow(a.gquat, k) = 0.f;
+        grow(a.gopac, 0) = 0.f;
+    };
+    if (*a.overflow) {  // nothing is added after a pair overflow; zeros are written when overwriting
+        if (!acc && valid) zero();
+        return;
+    }
+    bool act = false;
+    for (int v = 0; valid && !act && v < a.n_views; ++v)
+        act = lane(uniform_ptr(a.count + (int64_t)v * n + i0), lb) != 0;
+    GeomAcc A = {};
+    Geom gm{};
+    float old[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) old[k] = 0.f;
+    if (act) {
+        gm = load_geom_rows(a, i0, lb);
+        if (acc) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
+            old[10] = grow(a.gopac, 0);
+        }
+    }
+    for (int v = 0; v < a.n_views; ++v) {
+        const int64_t o0 = (int64_t)v * n + i0;
+        const uint32_t c = valid ? lane(uniform_ptr(a.count + o0), lb) : 0u;
+        const uint32_t e = valid ? lane(uniform_ptr(a.eoff + o0), lb) : 0u;
+        if ((int)l <= last) s_beg[l] = e;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) s_g[l][f] = 0.f;
+        const uint32_t S0 = wave_read(e, 0), S1 = wave_read(e + c, last);
+        wave_sync();
+        for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
+            const uint32_t sl = base + l;
+            const bool in = sl < S1 && (uint64_t)sl < a.capacity;
+            int L = 0;  // owner: the largest entry whose run starts at or before sl
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (L + step <= last && s_beg[L + step] <= sl) L += step;
+            if (!in) L = -1 - (int)l;  // unique: never merged with another lane
+            float x[9];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) x[f] = in ? a.slots[(uint64_t)sl * 9 + f] : 0.f;
+            seg_scan9(L, x);
+            const int Ln = __shfl_down(L, 1);
+            if (in && (l == 63 || Ln != L)) {
+#pragma unroll
+                for (int f = 0; f < 9; ++f) s_g[L][f] += x[f];
+            }
+        }
+        wave_sync();
+        if (c != 0) {
+#pragma unroll
+            for (int f = 6; f < 9; ++f) lane(uniform_ptr(a.g2w + f * VN + o0), lb) = s_g[l][f];
+            float g6[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) g6[k] = s_g[l][k];
+            chain_step(a, gm, a.cams[v], g6, A);
+        }
+        wave_sync();  // the sums are rewritten for the next view
+    }
+    if (act) {
+        if (A.any || !acc) write_geom(a, i0, lb, old, A);
+    } else if (valid && !acc) {
+        zero();
     }
 }
 
@@ -804,10 +894,6 @@ static void launch_bwd_sh(bool one_view, int64_t n, hipStream_t stream, const Pr
         hipLaunchKernelGGL((k_preprocess_bwd_sh<DEG, 1>), dim3((unsigned)((n + 63) / 64)), dim3(192), 0, stream, a);
 }
 
-// With one view the pair slots are summed by the geometric kernel (no k_pair_sums launch
-// before it): that saves a launch and the round trip of the six geometric fields through g2.
-bool bwd_sums_in_chain(const gs_views* views) { return views->n_views == 1; }
-
 gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, const gs_params* p,
                                 const gs_projected* proj, const gs_bins* bins, const float* slots, float* g2,
                                 gs_gaussians_grad* grad, hipStream_t stream) {
@@ -837,10 +923,10 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     a.gopac = grad->opacity;
     a.gsh = grad->sh;
     const dim3 grid((unsigned)((g->n + BWD_CHUNK - 1) / BWD_CHUNK));
-    if (bwd_sums_in_chain(views))
-        hipLaunchKernelGGL(k_preprocess_bwd<true>, grid, dim3(64), 0, stream, a);
+    if (views->n_views == 1)
+        hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(64), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_preprocess_bwd<false>, grid, dim3(64), 0, stream, a);
+        hipLaunchKernelGGL(k_preprocess_bwd_mv, dim3((unsigned)((g->n + 63) / 64)), dim3(64), 0, stream, a);
     // colour part: 64 G Gaussians x 3 channels per workgroup
     switch (g->sh_degree) {
         case 0: launch_bwd_sh<0>(views->n_views == 1, g->n, stream, a); break;

@@ -642,66 +642,6 @@ __device__ void bwd_tile(SmemBwd<TW, TH, PXW, PXH>& sm, const RenderArgs& a, int
     }
 }
 
-// Per-entry sums of the pair slots: entry o owns the slots [entry_offset[o], entry_offset[o] +
-// count[o]) and consecutive entries own consecutive runs, so the runs of a wave's 64 entries
-// form one range, read 64 slots at a time (coalesced). In each chunk a segmented inclusive
-// scan over the lanes (lanes of one entry are contiguous) sums every entry's slots in the
-// chunk, and the last lane of each run hands the sum to the entry's own lane through LDS; the
-// entry's lane adds the chunks in order. Every sum is formed in the same order on every run.
-// Writes g2[f][o] (f < 9) for the entries with count > 0.
-__global__ __launch_bounds__(256) void k_pair_sums(const uint32_t* __restrict__ count,
-                                                   const uint32_t* __restrict__ eoff, int64_t vn,
-                                                   const float* __restrict__ slots, uint64_t capacity,
-                                                   const uint32_t* overflow, float* __restrict__ g2) {
-    __shared__ uint32_t s_beg[4][64];
-    __shared__ float s_part[4][64 * 9];
-    if (*overflow) return;  // the slots are incomplete; nothing is added downstream either
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t o0 = ((int64_t)blockIdx.x * 4 + w) * 64;
-    if (o0 >= vn) return;  // the whole wave (no workgroup barrier below)
-    const int64_t o = o0 + l;
-    const bool valid = o < vn;
-    const uint32_t c = valid ? count[o] : 0u;
-    const uint32_t e = valid ? eoff[o] : 0u;
-    const int last = (int)min((int64_t)63, vn - 1 - o0);
-    const uint32_t S0 = wave_read(e, 0), S1 = wave_read(e + c, last);
-    s_beg[w][l] = e;
-    wave_sync();
-    float acc[9];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) acc[f] = 0.f;
-    for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
-        const uint32_t sl = base + l;
-        const bool in = sl < S1 && (uint64_t)sl < capacity;
-        // owner: the largest lane whose run starts at or before sl (lanes with no pairs share
-        // the next lane's start, so the largest such lane is the one with pairs)
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (L + step <= last && s_beg[w][L + step] <= sl) L += step;
-        if (!in) L = -1 - l;  // unique: never merged with another lane
-        float x[9];
-#pragma unroll
-        for (int f = 0; f < 9; ++f) x[f] = in ? slots[(uint64_t)sl * 9 + f] : 0.f;
-        seg_scan9(L, x);
-        const int Ln = __shfl_down(L, 1);
-        if (in && (l == 63 || Ln != L)) {
-#pragma unroll
-            for (int f = 0; f < 9; ++f) s_part[w][L * 9 + f] = x[f];
-        }
-        wave_sync();
-        if (c > 0 && e < base + 64 && e + c > base) {
-#pragma unroll
-            for (int f = 0; f < 9; ++f) acc[f] += s_part[w][l * 9 + f];
-        }
-        wave_sync();
-    }
-    if (c > 0) {
-#pragma unroll
-        for (int f = 0; f < 9; ++f) g2[f * vn + o] = acc[f];
-    }
-}
-
 // tile of this workgroup: its own, or the entry of the longest-first list at its position
 __device__ __forceinline__ int tile_of_block(const RenderArgs& a) {
     return a.queue ? (int)a.queue[blockIdx.x] : (int)blockIdx.x;
@@ -977,9 +917,8 @@ gs_status launch_visibility(const gs_projected* proj, const gs_views* views, con
 
 gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,
                             const float* t_final, const uint32_t* n_last, const float* dl_drgb, float* slots,
-                            float* g2, bool pair_sums, hipStream_t s) {
+                            hipStream_t s) {
     if (views->n_tiles == 0) return GS_OK;
-    const int64_t vn = proj->n * (int64_t)views->n_views;
     RenderArgs a = base_args(proj, views, bins, p);
     a.t_in = t_final;
     a.last_in = n_last;
@@ -990,9 +929,6 @@ gs_status launch_render_bwd(const gs_projected* proj, const gs_views* views, con
     a.slots = slots;
     if (!launch_bwd(a, views->tile_w, views->tile_h, bwd_pixels_per_lane(views), views->n_tiles, s))
         return finish(false, "render_bwd");
-    if (vn > 0 && pair_sums)
-        hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj->count,
-                           bins->entry_offset, vn, slots, bins->capacity, bins->overflow, g2);
     return check_launch("render_bwd");
 }
 
