@@ -651,64 +651,76 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd(PreBwdArgs a) {
     }
 }
 
-// Several views: one wave per 64 Gaussians. For each view in turn the wave sums its Gaussians'
-// pair slots of that view (one coalesced range, segmented scan, run ends added into LDS sums,
-// as the one-view kernel does for its chunk), writes the colour sums for the SH kernel, and each lane
-// whose Gaussian that view composited adds the view's chain step. A lane's chain runs over the
-// views in order, as in the one-lane chain above.
+// Several views: one wave per workgroup takes MV_CHUNK consecutive Gaussians and goes through
+// the views in order. For each view it sums the chunk's pair slots of that view (one coalesced
+// range, as the one-view kernel does), writes the colour sums for the SH kernel, lists the
+// Gaussians that view composited and runs that view's chain step on them 64 at a time, the
+// running FP64 sums of every Gaussian of the chunk held in LDS between views. So the FP64 step
+// runs on nearly full waves although each view composites only some of the Gaussians, and each
+// Gaussian's sums still run over the views in order.
+constexpr int MV_CHUNK = 128;
+
 __global__ __launch_bounds__(64) void k_preprocess_bwd_mv(PreBwdArgs a) {
-    __shared__ uint32_t s_beg[64];
-    __shared__ float s_g[64][9];
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const uint32_t l = threadIdx.x, lb = l * 4u;
+    constexpr int NS = MV_CHUNK / 64;
+    __shared__ uint32_t s_beg[MV_CHUNK];
+    __shared__ float s_g[MV_CHUNK][9];
+    __shared__ uint16_t s_list[MV_CHUNK];
+    __shared__ double s_acc[11][MV_CHUNK];  // gp[3], gs[3], gq[4], go of each Gaussian
+    __shared__ uint32_t s_any[MV_CHUNK];
+    __shared__ uint32_t s_end;
+    const int64_t i0 = (int64_t)blockIdx.x * MV_CHUNK;
+    const uint32_t l = threadIdx.x;
     const int64_t n = a.n, VN = (int64_t)a.n_views * n;
-    const bool acc = !a.overwrite, valid = i0 + l < n;
-    const int last = (int)min((int64_t)63, n - 1 - i0);  // the chunk's last Gaussian
-    auto grow = [&](float* base, int k) -> GS_GLOBAL float& { return lane(uniform_ptr(base + k * n + i0), lb); };
-    auto zero = [&]() {
+    const bool acc = !a.overwrite;
+    const int last = (int)min((int64_t)MV_CHUNK - 1, n - 1 - i0);  // the chunk's last Gaussian
+    auto grow = [&](float* base, int k, uint32_t lb) -> GS_GLOBAL float& {
+        return lane(uniform_ptr(base + k * n + i0), lb);
+    };
+    auto zero = [&](uint32_t lb) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) grow(a.gmean, k) = 0.f, grow(a.gscale, k) = 0.f;
+        for (int k = 0; k < 3; ++k) grow(a.gmean, k, lb) = 0.f, grow(a.gscale, k, lb) = 0.f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) grow(a.gquat, k) = 0.f;
-        grow(a.gopac, 0) = 0.f;
+        for (int k = 0; k < 4; ++k) grow(a.gquat, k, lb) = 0.f;
+        grow(a.gopac, 0, lb) = 0.f;
     };
     if (*a.overflow) {  // nothing is added after a pair overflow; zeros are written when overwriting
-        if (!acc && valid) zero();
+        if (acc) return;
+        for (uint32_t li = l; li < MV_CHUNK; li += 64)
+            if (i0 + li < n) zero(li * 4u);
         return;
     }
-    bool act = false;
-    for (int v = 0; valid && !act && v < a.n_views; ++v)
-        act = lane(uniform_ptr(a.count + (int64_t)v * n + i0), lb) != 0;
-    GeomAcc A = {};
-    Geom gm{};
-    float old[11];
 #pragma unroll
-    for (int k = 0; k < 11; ++k) old[k] = 0.f;
-    if (act) {
-        gm = load_geom_rows(a, i0, lb);
-        if (acc) {
+    for (int j = 0; j < NS; ++j) {
+        const uint32_t li = 64 * j + l;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k), old[3 + k] = grow(a.gscale, k);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k);
-            old[10] = grow(a.gopac, 0);
-        }
+        for (int k = 0; k < 11; ++k) s_acc[k][li] = 0.0;
+        s_any[li] = 0u;
     }
+    uint64_t seen[NS];  // composited in some view so far
+#pragma unroll
+    for (int j = 0; j < NS; ++j) seen[j] = 0;
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t o0 = (int64_t)v * n + i0;
-        const uint32_t c = valid ? lane(uniform_ptr(a.count + o0), lb) : 0u;
-        const uint32_t e = valid ? lane(uniform_ptr(a.eoff + o0), lb) : 0u;
-        if ((int)l <= last) s_beg[l] = e;
+        uint32_t cnt[NS];
 #pragma unroll
-        for (int f = 0; f < 9; ++f) s_g[l][f] = 0.f;
-        const uint32_t S0 = wave_read(e, 0), S1 = wave_read(e + c, last);
-        wave_sync();
+        for (int j = 0; j < NS; ++j) {
+            const uint32_t li = 64 * j + l;
+            const bool valid = i0 + li < n;
+            cnt[j] = valid ? lane(uniform_ptr(a.count + o0), li * 4u) : 0u;
+            const uint32_t e = valid ? lane(uniform_ptr(a.eoff + o0), li * 4u) : 0u;
+            if ((int)li <= last) s_beg[li] = e;
+            if ((int)li == last) s_end = e + cnt[j];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) s_g[li][f] = 0.f;
+        }
+        __syncthreads();
+        const uint32_t S0 = s_beg[0], S1 = s_end;
         for (uint32_t base = S0; base < S1; base += 64) {  // the same for the whole wave
             const uint32_t sl = base + l;
             const bool in = sl < S1 && (uint64_t)sl < a.capacity;
-            int L = 0;  // owner: the largest entry whose run starts at or before sl
+            int L = 0;  // owner: the largest Gaussian of the chunk whose run starts at or before sl
 #pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
+            for (int step = MV_CHUNK / 2; step > 0; step >>= 1)
                 if (L + step <= last && s_beg[L + step] <= sl) L += step;
             if (!in) L = -1 - (int)l;  // unique: never merged with another lane
             float x[9];
@@ -721,21 +733,77 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd_mv(PreBwdArgs a) {
                 for (int f = 0; f < 9; ++f) s_g[L][f] += x[f];
             }
         }
-        wave_sync();
-        if (c != 0) {
+        __syncthreads();
+        // colour sums of this view's composited entries; the list of them
+        uint32_t total = 0;
 #pragma unroll
-            for (int f = 6; f < 9; ++f) lane(uniform_ptr(a.g2w + f * VN + o0), lb) = s_g[l][f];
-            float g6[6];
+        for (int j = 0; j < NS; ++j) {
+            const uint32_t li = 64 * j + l;
+            const bool c = cnt[j] != 0;
+            if (c) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) g6[k] = s_g[l][k];
-            chain_step(a, gm, a.cams[v], g6, A);
+                for (int f = 6; f < 9; ++f) lane(uniform_ptr(a.g2w + f * VN + o0), li * 4u) = s_g[li][f];
+            }
+            const uint64_t m = ballot(c);
+            if (c) s_list[total + mask_rank(m)] = (uint16_t)li;
+            total += (uint32_t)__builtin_popcountll(m);
+            seen[j] |= m;
         }
-        wave_sync();  // the sums are rewritten for the next view
+        __syncthreads();
+        const gs_camera cam = a.cams[v];
+        for (uint32_t b = 0; b < total; b += 64) {
+            if (b + l < total) {
+                const uint32_t li = s_list[b + l];
+                const Geom gm = load_geom_rows(a, i0, li * 4u);
+                GeomAcc A;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) A.gp[k] = s_acc[k][li], A.gs[k] = s_acc[3 + k][li];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A.gq[k] = s_acc[6 + k][li];
+                A.go = s_acc[10][li];
+                A.any = s_any[li] != 0u;
+                float g6[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) g6[k] = s_g[li][k];
+                chain_step(a, gm, cam, g6, A);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s_acc[k][li] = A.gp[k], s_acc[3 + k][li] = A.gs[k];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_acc[6 + k][li] = A.gq[k];
+                s_acc[10][li] = A.go;
+                s_any[li] = A.any ? 1u : 0u;
+            }
+        }
+        __syncthreads();  // the sums and lists are rewritten for the next view
     }
-    if (act) {
-        if (A.any || !acc) write_geom(a, i0, lb, old, A);
-    } else if (valid && !acc) {
-        zero();
+    // the results, written (or added) for the Gaussians some view composited; zeros for the rest
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const uint32_t li = 64 * j + l, lb = li * 4u;
+        if (i0 + li >= n) continue;
+        if ((seen[j] >> l) & 1) {
+            GeomAcc A;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) A.gp[k] = s_acc[k][li], A.gs[k] = s_acc[3 + k][li];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) A.gq[k] = s_acc[6 + k][li];
+            A.go = s_acc[10][li];
+            A.any = s_any[li] != 0u;
+            if (!A.any && acc) continue;
+            float old[11];
+#pragma unroll
+            for (int k = 0; k < 11; ++k) old[k] = 0.f;
+            if (acc) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) old[k] = grow(a.gmean, k, lb), old[3 + k] = grow(a.gscale, k, lb);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) old[6 + k] = grow(a.gquat, k, lb);
+                old[10] = grow(a.gopac, 0, lb);
+            }
+            write_geom(a, i0, lb, old, A);
+        } else if (!acc) {
+            zero(lb);
+        }
     }
 }
 
@@ -926,7 +994,8 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, const gs_views* views, co
     if (views->n_views == 1)
         hipLaunchKernelGGL(k_preprocess_bwd, grid, dim3(64), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_preprocess_bwd_mv, dim3((unsigned)((g->n + 63) / 64)), dim3(64), 0, stream, a);
+        hipLaunchKernelGGL(k_preprocess_bwd_mv, dim3((unsigned)((g->n + MV_CHUNK - 1) / MV_CHUNK)), dim3(64), 0, stream,
+                           a);
     // colour part: 64 G Gaussians x 3 channels per workgroup
     switch (g->sh_degree) {
         case 0: launch_bwd_sh<0>(views->n_views == 1, g->n, stream, a); break;
