@@ -204,8 +204,8 @@ def test_keys_bit_exact_with_depth_ties(spread):
 @pytest.mark.parametrize("n", [3000, 20000])
 def test_long_tile_lists(n):
     """Thousands of Gaussians packed around the image centre (a corner of four 16x16
-    tiles): tile lists longer than the small per-tile sort buffer (> 2048 entries) and, at
-    n = 20000, longer than the large one (> 8192: chunked sort and merges). Keys, values
+    tiles): tile lists longer than the per-tile LDS sort buffer (> 2048 entries: chunks and one
+    merge) and, at n = 20000, longer than 8192 (several merge passes). Keys, values
     and ranges bit-exact; image within the tolerance."""
     sc = scenes.uniform_cube_scene(n, seed=7)
     sc.mean = (sc.mean * np.float32(0.03)).astype(np.float32)
