@@ -664,7 +664,7 @@ struct BucketArgs {
     int n_tiles;         // all views' tiles
 };
 
-constexpr int BK_T = 1024;  // threads of the bucket kernels: one wave per emission block of the row
+constexpr int BK_T = EB_ROW / 4;  // threads of the bucket kernels: one wave per emission block of the row
 
 // tiles of view v, and whether they fit the rows' columns (a view larger than declared is
 // reported by the column scans and nothing is binned)
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs a, Fill4 clear
     // wave w takes the row's emission block w, 64 entries at a time; the block's counts and
     // rectangles are requested first, together (rectangles of culled entries too: in random
     // storage order their cache lines are read for the visible ones anyway)
-    const int64_t eb = (int64_t)blockIdx.x * 16 + w;
+    const int64_t eb = (int64_t)blockIdx.x * (BK_T / 64) + w;
     uint32_t c4[4];
     uint64_t r4[4];
 #pragma unroll
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_emit(BucketArgs a) {
     const float* dv = a.depth + (int64_t)v * a.n;
     // the wave's emission block: its counts, rectangles and depths and its first pair are
     // requested first, together, so they arrive while the tile starts are scanned
-    const int64_t eb = (int64_t)blockIdx.x * 16 + w;
+    const int64_t eb = (int64_t)blockIdx.x * (BK_T / 64) + w;
     uint32_t c4[4], d4[4];
     uint64_t r4[4];
 #pragma unroll
