@@ -332,6 +332,17 @@ gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views,
                                 const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
                                 uint32_t* bits_accum, void* stream);
 
+/* gs_bin_sort followed by gs_importance, and gs_bin_sort followed by gs_cluster_visibility,
+ * with each tile's (depth, index) sort done by the traversal workgroup of that tile right
+ * before it walks the tile (as gs_bin_sort_render_fwd does for compositing). Arguments as in
+ * the two calls (ws as for gs_bin_sort); the same results bit for bit: the bins as gs_bin_sort
+ * leaves them, and the same h_accum or bits_accum. */
+gs_status gs_bin_sort_importance(const gs_projected* proj, const gs_views* views, gs_bins* bins, const gs_params* p,
+                                 float* h_accum, void* ws, size_t ws_bytes, void* stream);
+gs_status gs_bin_sort_cluster_visibility(const gs_projected* proj, const gs_views* views, gs_bins* bins,
+                                         const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
+                                         uint32_t* bits_accum, void* ws, size_t ws_bytes, void* stream);
+
 /* Visibility-list compaction (Sec. 3.4, list-based rendering): write the indices of the
  * set bits of bits_row (device [ceil(n/32)]) in increasing order to list (device [n]) and
  * their number to *count (device int64). ws: at least gs_workspace_bytes(n, 1, 0, 0). */

@@ -74,7 +74,8 @@ SPLAT_BYTES = 64
 
 EXPORTS = ["gs_view_layout", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_bin_sort_noalloc",
            "gs_render_fwd", "gs_bin_sort_render_fwd", "gs_render_bwd",
-           "gs_importance", "gs_cluster_visibility", "gs_bits_to_list", "gs_kmeans", "gs_kmeans_seed",
+           "gs_importance", "gs_cluster_visibility", "gs_bin_sort_importance", "gs_bin_sort_cluster_visibility",
+           "gs_bits_to_list", "gs_kmeans", "gs_kmeans_seed",
            "gs_kmeans_workspace_bytes", "gs_kmeans_lloyd", "gs_nearest_centre",
            "gs_l1_loss_grad", "gs_ssim_workspace_bytes", "gs_ssim_loss_grad", "gs_prune_mask", "gs_prune",
            "gs_gather", "gs_nn_workspace_bytes", "gs_nn_distance", "gs_init_gaussians",
@@ -114,6 +115,12 @@ def load(path: str = LIB_PATH):
     L.gs_bin_sort_render_fwd.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), P(gs_params), c_void_p,
                                          c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]
     L.gs_bin_sort_render_fwd.restype = i32
+    L.gs_bin_sort_importance.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), P(gs_params), c_void_p,
+                                         c_void_p, ctypes.c_size_t, c_void_p]
+    L.gs_bin_sort_importance.restype = i32
+    L.gs_bin_sort_cluster_visibility.argtypes = [P(gs_projected), P(gs_views), P(gs_bins), P(gs_params), c_void_p,
+                                                 i32, f32, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]
+    L.gs_bin_sort_cluster_visibility.restype = i32
     L.gs_l1_loss_grad.argtypes = [c_void_p, c_void_p, i64, f32, c_void_p, c_void_p, c_void_p]
     L.gs_l1_loss_grad.restype = i32
     L.gs_ssim_workspace_bytes.argtypes = [i32, i32, i32]

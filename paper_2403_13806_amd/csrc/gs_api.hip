@@ -38,6 +38,10 @@ gs_status launch_preprocess_bwd(const gs_gaussians*, const gs_views*, const gs_p
 gs_status launch_bin_sort(const gs_projected*, const gs_views*, gs_bins*, void*, hipStream_t, TileSortArgs*);
 gs_status launch_render_fwd_sorted(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
                                    float*, uint32_t*, uint32_t*, const TileSortArgs&, hipStream_t);
+gs_status launch_importance_sorted(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
+                                   const TileSortArgs&, hipStream_t);
+gs_status launch_visibility_sorted(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*,
+                                   const int32_t*, int32_t, float, uint32_t*, const TileSortArgs&, hipStream_t);
 size_t sort_workspace_bytes(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_tiles);
 size_t list_workspace_bytes(int64_t n);
 gs_status launch_bits_to_list(const uint32_t*, int64_t, int32_t*, int64_t*, void*, hipStream_t);
@@ -367,6 +371,43 @@ gs_status gs_cluster_visibility(const gs_projected* proj, const gs_views* views,
     if (!(t_cluster >= 0.f)) return set_error(GS_ERR_INVALID_ARG, "t_cluster must be >= 0");
     if ((st = check_queue(views, bins))) return st;
     return launch_visibility(proj, views, bins, p, view_cluster, k, t_cluster, bits_accum, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort_importance(const gs_projected* proj, const gs_views* views, gs_bins* bins, const gs_params* p,
+                                 float* h_accum, void* ws, size_t ws_bytes, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if (proj->n > 0 && !h_accum) return set_error(GS_ERR_INVALID_ARG, "h_accum is NULL");
+    if ((st = check_queue(views, bins))) return st;
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    TileSortArgs ta;
+    if ((st = launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream, &ta))) return st;
+    return launch_importance_sorted(proj, views, bins, p, h_accum, ta, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort_cluster_visibility(const gs_projected* proj, const gs_views* views, gs_bins* bins,
+                                         const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
+                                         uint32_t* bits_accum, void* ws, size_t ws_bytes, void* stream) {
+    gs_status st;
+    if ((st = check_projected(proj, true)) || (st = check_views(views)) || (st = check_bins(bins)) ||
+        (st = check_params(p)))
+        return st;
+    if (k < 1) return set_error(GS_ERR_INVALID_ARG, "k must be >= 1 (got %d)", k);
+    if (!view_cluster || (proj->n > 0 && !bits_accum))
+        return set_error(GS_ERR_INVALID_ARG, "view_cluster or bits_accum is NULL");
+    if (!(t_cluster >= 0.f)) return set_error(GS_ERR_INVALID_ARG, "t_cluster must be >= 0");
+    if ((st = check_queue(views, bins))) return st;
+    const size_t need = sort_workspace_bytes(proj->n, views->n_views, bins->capacity, views->n_tiles);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+    TileSortArgs ta;
+    if ((st = launch_bin_sort(proj, views, bins, ws, (hipStream_t)stream, &ta))) return st;
+    return launch_visibility_sorted(proj, views, bins, p, view_cluster, k, t_cluster, bits_accum, ta,
+                                    (hipStream_t)stream);
 }
 
 gs_status gs_bits_to_list(const uint32_t* bits_row, int64_t n, int32_t* list, int64_t* count, void* ws,

@@ -850,6 +850,10 @@ gs_status launch_render_fwd(const gs_projected* proj, const gs_views* views, con
 }
 
 void launch_tile_sort(const TileSortArgs& ta, hipStream_t stream);
+gs_status launch_importance(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, float*,
+                            hipStream_t);
+gs_status launch_visibility(const gs_projected*, const gs_views*, const gs_bins*, const gs_params*, const int32_t*,
+                            int32_t, float, uint32_t*, hipStream_t);
 
 template <int MODE>
 static bool launch_sort_mode(const RenderArgs& a, const TileSortArgs& ta, int tw, int th, int depth, int px,
@@ -887,6 +891,37 @@ gs_status launch_render_fwd_sorted(const gs_projected* proj, const gs_views* vie
     if (fused) return check_launch("bin_sort_render_fwd");
     launch_tile_sort(ta, s);
     return launch_render_fwd(proj, views, bins, p, rgb, t_final, n_last, n_contrib, s);
+}
+
+// the importance and cluster-visibility traversals over lists whose per-tile sort is still to
+// be done (ta), as launch_render_fwd_sorted does for compositing
+gs_status launch_importance_sorted(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                                   const gs_params* p, float* h, const TileSortArgs& ta, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.h = h;
+    if (launch_sort_mode<MODE_IMPORTANCE>(a, ta, views->tile_w, views->tile_h, views->batch_depth,
+                                          fwd_pixels_per_lane(views), views->n_tiles, s))
+        return check_launch("bin_sort_importance");
+    launch_tile_sort(ta, s);
+    return launch_importance(proj, views, bins, p, h, s);
+}
+
+gs_status launch_visibility_sorted(const gs_projected* proj, const gs_views* views, const gs_bins* bins,
+                                   const gs_params* p, const int32_t* view_cluster, int32_t k, float t_cluster,
+                                   uint32_t* bits, const TileSortArgs& ta, hipStream_t s) {
+    if (views->n_tiles == 0) return GS_OK;
+    RenderArgs a = base_args(proj, views, bins, p);
+    a.bits = bits;
+    a.view_cluster = view_cluster;
+    a.k_clusters = k;
+    a.words = (proj->n + 31) / 32;
+    a.t_cluster = t_cluster;
+    if (launch_sort_mode<MODE_VISIBILITY>(a, ta, views->tile_w, views->tile_h, views->batch_depth,
+                                          fwd_pixels_per_lane(views), views->n_tiles, s))
+        return check_launch("bin_sort_cluster_visibility");
+    launch_tile_sort(ta, s);
+    return launch_visibility(proj, views, bins, p, view_cluster, k, t_cluster, bits, s);
 }
 
 gs_status launch_importance(const gs_projected* proj, const gs_views* views, const gs_bins* bins, const gs_params* p,

@@ -683,6 +683,17 @@ class Renderer:
 
     def importance(self, h: torch.Tensor):
         s = _stream(self.views.device)
+        lib = L.load()
+        L.check(lib.gs_preprocess(ctypes.byref(self._sg), ctypes.byref(self._sv), ctypes.byref(self.p),
+                                  _ptr(self.subset), self.n_entries, int(self.want_color), ctypes.byref(self._sp), s))
+        # binning, and each tile's sort inside the importance launch
+        L.check(lib.gs_bin_sort_importance(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
+                                           ctypes.byref(self.p), _ptr(h), _ptr(self.ws), self.ws.numel(), s))
+        return h
+
+    def importance_split(self, h: torch.Tensor):
+        """importance() with the binning's own sort launch, then the importance pass."""
+        s = _stream(self.views.device)
         self._pre(s)
         L.check(L.load().gs_importance(ctypes.byref(self._sp), ctypes.byref(self._sv), ctypes.byref(self._sb),
                                        ctypes.byref(self.p), _ptr(h), s))

@@ -803,7 +803,9 @@ def test_bin_sort_render_fused_bitwise(tile, ppl, lpt, scene):
     for tile shapes whose compositing workgroup is not the sort's 256 threads) leaves the bins
     exactly as gs_bin_sort does and renders exactly what gs_render_fwd renders after it: keys,
     values, ranges, flags, image, T, last entries and composited counts, long lists (chunked
-    sort and merges) and a pair overflow included."""
+    sort and merges) and a pair overflow included; the same for the importance and cluster
+    visibility passes with the sort in their launch (gs_bin_sort_importance,
+    gs_bin_sort_cluster_visibility)."""
     import ctypes
     from paper_2403_13806_amd import _lib as L
     from paper_2403_13806_amd.splat import _ptr, _stream
@@ -849,6 +851,39 @@ def test_bin_sort_render_fused_bitwise(tile, ppl, lpt, scene):
     r.forward()
     torch.cuda.synchronize()
     assert torch.equal(r.rgb, a["rgb"])
+    # importance and cluster visibility with the sort in their launch against the two calls
+    vc = torch.as_tensor(np.arange(vb.n_views, dtype=np.int32) % 2, device=DEV)
+    words = (g.n + 31) // 32
+    got = []
+    for fused in (False, True):
+        h = torch.zeros(g.n, device=DEV)
+        bits = torch.zeros(2 * words, dtype=torch.int32, device=DEV)
+        L.check(lib.gs_preprocess(ctypes.byref(r._sg), ctypes.byref(r._sv), ctypes.byref(r.p), None, r.n_entries, 1,
+                                  ctypes.byref(r._sp), s))
+        if fused:
+            L.check(lib.gs_bin_sort_importance(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                               ctypes.byref(r.p), _ptr(h), _ptr(r.ws), r.ws.numel(), s))
+            L.check(lib.gs_bin_sort_cluster_visibility(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                                       ctypes.byref(r.p), _ptr(vc), 2, 0.01, _ptr(bits), _ptr(r.ws),
+                                                       r.ws.numel(), s))
+        else:
+            L.check(lib.gs_bin_sort(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb), _ptr(r.ws),
+                                    r.ws.numel(), s))
+            L.check(lib.gs_importance(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                      ctypes.byref(r.p), _ptr(h), s))
+            L.check(lib.gs_bin_sort(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb), _ptr(r.ws),
+                                    r.ws.numel(), s))
+            L.check(lib.gs_cluster_visibility(ctypes.byref(r._sp), ctypes.byref(r._sv), ctypes.byref(r._sb),
+                                              ctypes.byref(r.p), _ptr(vc), 2, 0.01, _ptr(bits), s))
+        torch.cuda.synchronize()
+        n = min(int(r.bins.n_pairs.item()), r.bins.capacity)
+        got.append((h, bits, r.bins.ranges.clone(), r.bins.keys[:n].clone(), r.bins.vals[:n].clone()))
+    for x, y in zip(got[0][:3], got[1][:3]):
+        assert torch.equal(x, y)
+    if scene != "overflow":
+        assert torch.equal(got[0][3], got[1][3]) and torch.equal(got[0][4], got[1][4])
+    if scene == "mixture":
+        assert got[0][0].any() and got[0][1].any()
 
 
 def test_graph_replay_matches_eager():
