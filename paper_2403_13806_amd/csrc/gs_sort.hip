@@ -1011,11 +1011,13 @@ SortLayout sort_layout(int64_t n, int32_t n_views, uint64_t capacity, int32_t n_
     L.nb_sort = (int64_t)((capacity + TILE_ITEMS - 1) / TILE_ITEMS);
     L.passes = std::max(1, (tile_bits(std::max(n_tiles, 1)) + 7) / 8);
     L.nbr = (n + EB_ROW - 1) / EB_ROW;
-    // histogram rows of the widest view the bucket emission takes; kept within one value
-    // buffer's bytes (8 per pair of capacity), or 4 MB
+    // histogram rows of the widest view the bucket emission takes (sized for min(n_tiles, 8192)
+    // columns, which bounds any view's); kept within one value buffer's bytes (8 per pair of
+    // capacity), or 256 MB: a batch of eight 1M-entry views takes 64 MB, against a grouping
+    // that costs hundreds of microseconds more per batch
     const size_t bk_stride = (size_t)((std::min(std::max(n_tiles, 1), BUCKET_TILES) + 15) / 16 * 16);
     const size_t bk_bytes = sizeof(uint32_t) * bk_stride * (size_t)L.nbr * (size_t)std::max(n_views, 1);
-    L.bucket = L.nbr <= BUCKET_MAX_ROWS && bk_bytes <= std::max<size_t>(8 * (size_t)capacity, (size_t)4 << 20);
+    L.bucket = L.nbr <= BUCKET_MAX_ROWS && bk_bytes <= std::max<size_t>(8 * (size_t)capacity, (size_t)256 << 20);
     size_t p = 0;
     L.ctrl = p;
     L.scan = p;
