@@ -242,6 +242,7 @@ struct PreArgs {
     int tile_w, tile_h;
     const int32_t* subset;
     int64_t n;
+    int n_views;
     int want_color;
     gs_splat* splat;
     float* depth;
@@ -249,32 +250,12 @@ struct PreArgs {
     uint32_t* count;
 };
 
-// DEG and COLOR are compile-time so the SH coefficients of the lane's Gaussian are loaded
-// into registers together with the geometry, before the projection math: every load of the
-// lane is in flight at once instead of the SH loads waiting behind the FP64 chain. The
-// coefficient planes are read once per frame: streamed past the caches.
+// One (view, entry) o of the lane's Gaussian (parameters gm, SH coefficients shv) seen by cam:
+// count, depth, tile rectangle and the 64-byte record.
 template <int DEG, bool COLOR>
-__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
-    const int v = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= a.n) return;
-    const int64_t i = a.subset ? (int64_t)a.subset[j] : j;
-    const int64_t o = (int64_t)v * a.n + j;
-    if (i < 0 || i >= a.n_all) {  // a subset index outside the scene selects nothing
-        a.count[o] = 0u;
-        return;
-    }
-    const gs_camera cam = a.cams[v];
+__device__ __forceinline__ void project_one(const PreArgs& a, const gs_camera& cam, int64_t o, const Geom& gm,
+                                            const float* shv) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
-    // every load of the lane is issued here, then waited for once
-    const Geom gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n_all, i);
-    float shv[COLOR ? NB * 3 : 1];
-    if (COLOR) {
-#pragma unroll
-        for (int k = 0; k < NB * 3; ++k) shv[k] = __builtin_nontemporal_load(&a.sh[(int64_t)k * a.n_all + i]);
-#pragma unroll
-        for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
-    }
     Proj P;
     double op;
     if (!project_vals(cam, a.p, gm, P, op)) {
@@ -335,6 +316,59 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     double4* dst = reinterpret_cast<double4*>(a.splat + o);
     dst[0] = src[0];
     dst[1] = src[1];
+}
+
+// DEG and COLOR are compile-time so the SH coefficients of the lane's Gaussian are loaded
+// into registers together with the geometry, before the projection math: every load of the
+// lane is in flight at once instead of the SH loads waiting behind the FP64 chain. The
+// coefficient planes are read once per frame: streamed past the caches.
+template <int DEG, bool COLOR>
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t i = a.subset ? (int64_t)a.subset[j] : j;
+    const int64_t o = (int64_t)v * a.n + j;
+    if (i < 0 || i >= a.n_all) {  // a subset index outside the scene selects nothing
+        a.count[o] = 0u;
+        return;
+    }
+    const gs_camera cam = a.cams[v];
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    // every load of the lane is issued here, then waited for once
+    const Geom gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n_all, i);
+    float shv[COLOR ? NB * 3 : 1];
+    if (COLOR) {
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) shv[k] = __builtin_nontemporal_load(&a.sh[(int64_t)k * a.n_all + i]);
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
+    }
+    project_one<DEG, COLOR>(a, cam, o, gm, shv);
+}
+
+// Several views: the lane reads its Gaussian's parameters and SH coefficients once and projects
+// it into every view of the batch in turn (each view re-reading 236 bytes per Gaussian would
+// move the batch's whole parameter set once per view).
+template <int DEG, bool COLOR>
+__global__ __launch_bounds__(256) void k_preprocess_views(PreArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t i = a.subset ? (int64_t)a.subset[j] : j;
+    if (i < 0 || i >= a.n_all) {  // a subset index outside the scene selects nothing
+        for (int v = 0; v < a.n_views; ++v) a.count[(int64_t)v * a.n + j] = 0u;
+        return;
+    }
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const Geom gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n_all, i);
+    float shv[COLOR ? NB * 3 : 1];
+    if (COLOR) {
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) shv[k] = __builtin_nontemporal_load(&a.sh[(int64_t)k * a.n_all + i]);
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
+    }
+    for (int v = 0; v < a.n_views; ++v) project_one<DEG, COLOR>(a, a.cams[v], (int64_t)v * a.n + j, gm, shv);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -940,15 +974,30 @@ gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const 
     a.depth = out->depth;
     a.rect = out->rect;
     a.count = out->count;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)views->n_views);
-    if (!want_color) {
-        hipLaunchKernelGGL((k_preprocess<0, false>), grid, dim3(256), 0, stream, a);
+    a.n_views = views->n_views;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (views->n_views == 1) {
+        const dim3 grid(blocks, 1);
+        if (!want_color) {
+            hipLaunchKernelGGL((k_preprocess<0, false>), grid, dim3(256), 0, stream, a);
+        } else {
+            switch (g->sh_degree) {
+                case 0: hipLaunchKernelGGL((k_preprocess<0, true>), grid, dim3(256), 0, stream, a); break;
+                case 1: hipLaunchKernelGGL((k_preprocess<1, true>), grid, dim3(256), 0, stream, a); break;
+                case 2: hipLaunchKernelGGL((k_preprocess<2, true>), grid, dim3(256), 0, stream, a); break;
+                default: hipLaunchKernelGGL((k_preprocess<3, true>), grid, dim3(256), 0, stream, a); break;
+            }
+        }
     } else {
-        switch (g->sh_degree) {
-            case 0: hipLaunchKernelGGL((k_preprocess<0, true>), grid, dim3(256), 0, stream, a); break;
-            case 1: hipLaunchKernelGGL((k_preprocess<1, true>), grid, dim3(256), 0, stream, a); break;
-            case 2: hipLaunchKernelGGL((k_preprocess<2, true>), grid, dim3(256), 0, stream, a); break;
-            default: hipLaunchKernelGGL((k_preprocess<3, true>), grid, dim3(256), 0, stream, a); break;
+        if (!want_color) {
+            hipLaunchKernelGGL((k_preprocess_views<0, false>), dim3(blocks), dim3(256), 0, stream, a);
+        } else {
+            switch (g->sh_degree) {
+                case 0: hipLaunchKernelGGL((k_preprocess_views<0, true>), dim3(blocks), dim3(256), 0, stream, a); break;
+                case 1: hipLaunchKernelGGL((k_preprocess_views<1, true>), dim3(blocks), dim3(256), 0, stream, a); break;
+                case 2: hipLaunchKernelGGL((k_preprocess_views<2, true>), dim3(blocks), dim3(256), 0, stream, a); break;
+                default: hipLaunchKernelGGL((k_preprocess_views<3, true>), dim3(blocks), dim3(256), 0, stream, a); break;
+            }
         }
     }
     return check_launch("preprocess");
