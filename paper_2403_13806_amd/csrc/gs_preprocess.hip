@@ -898,11 +898,20 @@ __global__ __launch_bounds__(192 * G) __attribute__((amdgpu_waves_per_eu(6))) vo
     }
     double gp[3] = {0, 0, 0};
     bool any = false;
+    // the next view's count and colour gradient are requested before this view's math, so
+    // their latency hides behind it (the gradient is read whatever the count; it is used
+    // only where the count is not zero)
+    uint32_t cnt_next = cnt0;
+    float gc_next = gc0;
     for (int v = 0; valid && v < a.n_views; ++v) {
-        const int64_t o = (int64_t)v * n;
-        const uint32_t cnt = v == 0 ? cnt0 : lane(uniform_ptr(a.count + o + i0), lb);
+        const uint32_t cnt = cnt_next;
+        const float gc = gc_next;
+        if (v + 1 < a.n_views) {
+            const int64_t o = (int64_t)(v + 1) * n;
+            cnt_next = lane(uniform_ptr(a.count + o + i0), lb);
+            gc_next = lane(uniform_ptr(a.g2 + g2o + o), lb);
+        }
         if (cnt == 0) continue;
-        const float gc = v == 0 ? gc0 : lane(uniform_ptr(a.g2 + g2o + o), lb);
         if (gc == 0.f) continue;
         any = true;
         const gs_camera cam = a.cams[v];
