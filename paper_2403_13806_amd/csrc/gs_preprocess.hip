@@ -733,15 +733,28 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd_mv(PreBwdArgs a) {
     uint64_t seen[NS];  // composited in some view so far
 #pragma unroll
     for (int j = 0; j < NS; ++j) seen[j] = 0;
+    // counts and entry offsets of the view after the current one, requested before the current
+    // view's chain so that their latency hides behind it
+    uint32_t cnt_nx[NS], e_nx[NS];
+    auto fetch = [&](int v) {
+        const int64_t o0 = (int64_t)v * n + i0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const uint32_t li = 64 * j + l;
+            const bool valid = i0 + li < n;
+            cnt_nx[j] = valid ? lane(uniform_ptr(a.count + o0), li * 4u) : 0u;
+            e_nx[j] = valid ? lane(uniform_ptr(a.eoff + o0), li * 4u) : 0u;
+        }
+    };
+    fetch(0);
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t o0 = (int64_t)v * n + i0;
         uint32_t cnt[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const uint32_t li = 64 * j + l;
-            const bool valid = i0 + li < n;
-            cnt[j] = valid ? lane(uniform_ptr(a.count + o0), li * 4u) : 0u;
-            const uint32_t e = valid ? lane(uniform_ptr(a.eoff + o0), li * 4u) : 0u;
+            cnt[j] = cnt_nx[j];
+            const uint32_t e = e_nx[j];
             if ((int)li <= last) s_beg[li] = e;
             if ((int)li == last) s_end = e + cnt[j];
 #pragma unroll
@@ -784,6 +797,7 @@ __global__ __launch_bounds__(64) void k_preprocess_bwd_mv(PreBwdArgs a) {
             seen[j] |= m;
         }
         __syncthreads();
+        if (v + 1 < a.n_views) fetch(v + 1);
         const gs_camera cam = a.cams[v];
         for (uint32_t b = 0; b < total; b += 64) {
             if (b + l < total) {
