@@ -286,6 +286,43 @@ def test_batched_views_equal_single_views_bitwise():
         assert torch.equal(vb.plane(out["t_final"], v), one.plane(o1["t_final"], 0))
 
 
+@pytest.mark.parametrize("deg,color", [(0, True), (1, True), (2, True), (3, True), (3, False)])
+def test_preprocess_views_equal_single_views_bitwise(deg, color):
+    """A batch's projection (one lane per Gaussian walking every view) against one view at a
+    time, entry by entry, with a subset that repeats indices and holds some outside the scene
+    (those select nothing in any view)."""
+    sc = scenes.mixture_scene(5000, seed=11 + deg, sh_degree=deg)
+    cams = scenes.uneven_views([(96, 64), (150, 110), (61, 45)])
+    g = gs.Gaussians.from_scene(sc, DEV)
+    rng = np.random.default_rng(deg)
+    sub = rng.integers(0, sc.n, 3001).astype(np.int32)
+    bad = np.array([5, 77, 1500, 3000])
+    sub[bad] = [-1, sc.n, sc.n + 12345, -7]
+    sub[10:20] = sub[0]
+    subset = torch.as_tensor(sub, device=DEV)
+    _say(f"preprocess views deg={deg} color={color}")
+    vb = gs.ViewBatch(cams, (16, 16), DEV)
+    pb = gs.preprocess(g, vb, P, subset=subset, want_color=color)
+    torch.cuda.synchronize()
+    n = len(sub)
+    seen = 0
+    for v, c in enumerate(cams):
+        p1 = gs.preprocess(g, gs.ViewBatch([c], (16, 16), DEV), P, subset=subset, want_color=color)
+        torch.cuda.synchronize()
+        cb = pb.count[v * n:(v + 1) * n].cpu().numpy()
+        c1 = p1.count.cpu().numpy()
+        assert np.array_equal(cb, c1)
+        assert not cb.view(np.uint32)[bad].any()
+        vis = torch.as_tensor(c1 != 0, device=DEV)
+        seen += int(vis.sum())
+        rb = pb.splat.view(torch.uint8).view(-1, 64)[v * n:(v + 1) * n][vis]
+        r1 = p1.splat.view(torch.uint8).view(-1, 64)[vis]
+        assert torch.equal(rb, r1)
+        assert torch.equal(pb.depth[v * n:(v + 1) * n][vis], p1.depth[vis])
+        assert torch.equal(pb.rect[v * n:(v + 1) * n][vis], p1.rect[vis])
+    assert seen > 500
+
+
 @pytest.mark.parametrize("case", ["plain", "mixture"])
 def test_importance_matches_oracle(case):
     sc, cam0 = _case(case)
