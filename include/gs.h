@@ -156,11 +156,12 @@ typedef struct gs_views {
                                     (2 only for tiles of at most 512 pixels) */
     int32_t lpt;                 /* 1: the traversals take tiles longest list first (bins->queue);
                                     0: in tile order */
-    int32_t pixels_per_lane;     /* each lane of the traversals handles 1, 2 (2 x 1) or 4 (2 x 2;
-                                    2 x 1 in the forward ones) neighbouring pixels; 2 needs
-                                    tile_w >= 16, 4 also tile_h >= 16; 0 picks the default for
-                                    the tile size. Results do not depend on it, except for the
-                                    order of the reverse traversal's FP32 sums */
+    int32_t pixels_per_lane;     /* each lane of the traversals handles 1, 2 (2 x 1) or 4 (2 x 2
+                                    in the reverse one; 4 x 1 in the forward ones where tile_w >=
+                                    32, else 2 x 1) neighbouring pixels; 2 needs tile_w >= 16, 4
+                                    also tile_h >= 16; 0 picks the default for the tile size.
+                                    Results do not depend on it, except for the order of the
+                                    reverse traversal's FP32 sums */
     int32_t max_view_tiles;      /* tiles of the view with the most (gs_view_layout's table gives
                                     them), or 0: taken as n_tiles. gs_bin_sort writes the pairs
                                     straight into their tiles' ranges when it is at most 8192 */

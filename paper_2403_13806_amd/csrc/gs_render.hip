@@ -755,7 +755,8 @@ static void launch_tiles(K kernel, const RenderArgs& a, int threads, int n_tiles
     hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(threads), 0, s, a);
 }
 
-// pixels per lane of the forward traversals: 1, or 2 (2 x 1) where the tile is at least 16 wide
+// pixels per lane of the forward traversals: 1, 2 (2 x 1) where the tile is at least 16 wide, or
+// 4 (4 x 1) where it is at least 32 wide
 template <int MODE>
 static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int px, int n_tiles, hipStream_t s) {
 #define GS_CASE(W_, H_, D_, P_)                                                                  \
@@ -775,17 +776,19 @@ static bool launch_mode(const RenderArgs& a, int tw, int th, int depth, int px, 
     GS_CASE(16, 8, 1, 2) GS_CASE(16, 16, 1, 2) GS_CASE(32, 8, 1, 2) GS_CASE(32, 16, 1, 2) GS_CASE(16, 32, 1, 2)
     GS_CASE(32, 32, 1, 2)
     GS_CASE(16, 8, 2, 2) GS_CASE(16, 16, 2, 2) GS_CASE(32, 8, 2, 2) GS_CASE(32, 16, 2, 2) GS_CASE(16, 32, 2, 2)
+    GS_CASE(32, 16, 1, 4) GS_CASE(32, 16, 2, 4) GS_CASE(32, 32, 1, 4)
 #undef GS_CASE
     return false;
 }
 
-// as asked (4, a 2 x 2 cluster, means 2 here), else 2 for tiles of at least 512 pixels: at
-// 1256 x 828 and 1M Gaussians, 16 x 32 tiles composite in 138 us at two pixels per lane against
-// 150 us at one; 16 x 16 tiles gain nothing and their importance pass loses 8%
+// as asked (4 is a row of four pixels where the tile is at least 32 wide, else two), else 2 for
+// tiles of at least 512 pixels: at 1256 x 828 and 1M Gaussians, 16 x 32 tiles composite in
+// 138 us at two pixels per lane against 150 us at one; 16 x 16 tiles gain nothing and their
+// importance pass loses 8%
 static int fwd_pixels_per_lane(const gs_views* v) {
     const int p = v->pixels_per_lane;
     if (p == 1 || p == 2) return p;
-    if (p == 4) return 2;
+    if (p == 4) return v->tile_w >= 32 ? 4 : 2;
     return v->tile_w >= 16 && v->tile_w * v->tile_h >= 512 ? 2 : 1;
 }
 
@@ -867,6 +870,7 @@ static bool launch_sort_mode(const RenderArgs& a, const TileSortArgs& ta, int tw
     GS_CASE(32, 8, 1, 1) GS_CASE(32, 8, 2, 1)
     GS_CASE(8, 32, 1, 1) GS_CASE(8, 32, 2, 1)
     GS_CASE(32, 16, 1, 2) GS_CASE(16, 32, 1, 2) GS_CASE(32, 16, 2, 2) GS_CASE(16, 32, 2, 2)
+    GS_CASE(32, 32, 1, 4)
 #undef GS_CASE
     return false;
 }

@@ -799,9 +799,9 @@ def test_full_size_house_filtering():
                                                 ((16, 8), 1, True, 1), ((32, 16), 2, True, 1), ((32, 32), 1, True, 1),
                                                 ((16, 32), 1, False, 2), ((16, 16), 2, True, 2),
                                                 ((32, 8), 1, True, 2), ((32, 32), 1, False, 2), ((16, 8), 2, True, 2),
-                                                ((32, 16), 1, True, 4)])
+                                                ((32, 16), 1, True, 4), ((32, 16), 2, False, 4), ((32, 32), 1, True, 4)])
 def test_launch_forms_bitwise(tile, depth, lpt, ppl):
-    """Batch depth, the longest-first tile order and two pixels per lane change when a tile is
+    """Batch depth, the longest-first tile order and two or four pixels per lane change when a tile is
     composited, how its list is staged and which lane holds a pixel, never the arithmetic:
     images, T, the composited counts, importance and cluster bits are bitwise equal."""
     sc = scenes.mixture_scene(6000, seed=7, sh_degree=3)
@@ -834,7 +834,8 @@ def test_launch_forms_bitwise(tile, depth, lpt, ppl):
 @pytest.mark.parametrize("tile,ppl,lpt,scene", [((16, 32), 0, True, "mixture"), ((16, 16), 1, False, "mixture"),
                                                ((32, 16), 2, True, "mixture"), ((16, 32), 2, False, "mixture"),
                                                ((8, 8), 1, True, "mixture"), ((16, 16), 1, True, "long"),
-                                               ((16, 32), 0, False, "long"), ((16, 32), 0, True, "overflow")])
+                                               ((16, 32), 0, False, "long"), ((16, 32), 0, True, "overflow"),
+                                               ((32, 32), 4, True, "mixture"), ((32, 32), 4, False, "long")])
 def test_bin_sort_render_fused_bitwise(tile, ppl, lpt, scene):
     """gs_bin_sort_render_fwd (each tile sorted by the workgroup that composites it; two launches
     for tile shapes whose compositing workgroup is not the sort's 256 threads) leaves the bins
