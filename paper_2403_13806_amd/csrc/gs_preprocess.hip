@@ -250,17 +250,13 @@ struct PreArgs {
     uint32_t* count;
 };
 
-// One (view, entry) o of the lane's Gaussian (parameters gm, SH coefficients shv) seen by cam:
-// count, depth, tile rectangle and the 64-byte record.
-template <int DEG, bool COLOR>
-__device__ __forceinline__ void project_one(const PreArgs& a, const gs_camera& cam, int64_t o, const Geom& gm,
-                                            const float* shv) {
-    constexpr int NB = (DEG + 1) * (DEG + 1);
-    Proj P;
-    double op;
+// The geometric part of entry o (view cam): writes its count and, when it meets some tile, its
+// depth and tile rectangle; returns the count.
+__device__ __forceinline__ uint32_t project_geom(const PreArgs& a, const gs_camera& cam, int64_t o, const Geom& gm,
+                                                 Proj& P, double& op) {
     if (!project_vals(cam, a.p, gm, P, op)) {
         a.count[o] = 0u;
-        return;
+        return 0u;
     }
     // tile rectangle of the support's bounding box, widened by 2^-16 px
     double rx0, rx1, ry0, ry1;
@@ -281,26 +277,36 @@ __device__ __forceinline__ void project_one(const PreArgs& a, const gs_camera& c
     uint32_t cnt = 0;
     if (rx1 >= rx0 && ry1 >= ry0) cnt = (uint32_t)((rx1 - rx0 + 1.0) * (ry1 - ry0 + 1.0));
     a.count[o] = cnt;
-    if (cnt == 0) return;
+    if (cnt == 0) return 0u;
     a.depth[o] = (float)P.z;
     a.rect[o] = (uint64_t)(uint32_t)rx0 | ((uint64_t)(uint32_t)ry0 << 16) | ((uint64_t)(uint32_t)rx1 << 32) |
                 ((uint64_t)(uint32_t)ry1 << 48);
-    float rgb[3] = {0.f, 0.f, 0.f};
-    if (COLOR) {
-        float d[3];
-        double len;
-        view_dir(cam, gm.p[0], gm.p[1], gm.p[2], d, len);
-        float Y[16];
-        sh_basis(DEG, d[0], d[1], d[2], Y);
+    return cnt;
+}
+
+// Colour of a Gaussian at position p seen by cam from its SH coefficients shv (Sec. 3.2).
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const gs_camera& cam, float p0, float p1, float p2, const float* shv,
+                                          float rgb[3]) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    float d[3];
+    double len;
+    view_dir(cam, p0, p1, p2, d, len);
+    float Y[16];
+    sh_basis(DEG, d[0], d[1], d[2], Y);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float acc = 0.f;
+    for (int c = 0; c < 3; ++c) {
+        float acc = 0.f;
 #pragma unroll
-            for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
-            // finite in FP32 (overflow saturates), so a zero weight always contributes zero
-            rgb[c] = fminf(fmaxf(acc + 0.5f, 0.f), 3.402823466e38f);
-        }
+        for (int k = 0; k < NB; ++k) acc += shv[k * 3 + c] * Y[k];
+        // finite in FP32 (overflow saturates), so a zero weight always contributes zero
+        rgb[c] = fminf(fmaxf(acc + 0.5f, 0.f), 3.402823466e38f);
     }
+}
+
+// the 64-byte record of entry o
+__device__ __forceinline__ void write_record(const PreArgs& a, int64_t o, const Proj& P, double op,
+                                             const float rgb[3]) {
     gs_splat s;
     s.u = P.u;
     s.v = P.v;
@@ -316,6 +322,19 @@ __device__ __forceinline__ void project_one(const PreArgs& a, const gs_camera& c
     double4* dst = reinterpret_cast<double4*>(a.splat + o);
     dst[0] = src[0];
     dst[1] = src[1];
+}
+
+// One (view, entry) o of the lane's Gaussian (parameters gm, SH coefficients shv) seen by cam:
+// count, depth, tile rectangle and the 64-byte record.
+template <int DEG, bool COLOR>
+__device__ __forceinline__ void project_one(const PreArgs& a, const gs_camera& cam, int64_t o, const Geom& gm,
+                                            const float* shv) {
+    Proj P;
+    double op;
+    if (project_geom(a, cam, o, gm, P, op) == 0u) return;
+    float rgb[3] = {0.f, 0.f, 0.f};
+    if (COLOR) sh_colour<DEG>(cam, gm.p[0], gm.p[1], gm.p[2], shv, rgb);
+    write_record(a, o, P, op, rgb);
 }
 
 // DEG and COLOR are compile-time so the SH coefficients of the lane's Gaussian are loaded
@@ -345,6 +364,48 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         for (int k = 0; k < NB * 3; ++k) asm volatile("" ::"v"(shv[k]));
     }
     project_one<DEG, COLOR>(a, cam, o, gm, shv);
+}
+
+// One view with colour: a workgroup takes 64 Gaussians with two waves. Wave 0 loads the geometry and
+// runs the FP64 projection (count, depth, rectangle); wave 1 loads the positions and the SH
+// coefficients and evaluates the colours into LDS; after one barrier wave 0 writes the records.
+// Each wave holds half the registers of the one-wave form, and the two waves' loads and math
+// overlap. The arithmetic of every value is that of k_preprocess.
+template <int DEG>
+__global__ __launch_bounds__(128) void k_preprocess_split(PreArgs a) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    __shared__ float s_rgb[3][64];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 64 + l;
+    const bool inr = j < a.n;
+    const int64_t i = inr ? (a.subset ? (int64_t)a.subset[j] : j) : -1;
+    const bool valid = inr && i >= 0 && i < a.n_all;  // a subset index outside the scene selects nothing
+    const gs_camera cam = a.cams[0];
+    Proj P;
+    double op = 0.0;
+    uint32_t cnt = 0u;
+    if (wv == 0) {
+        if (valid) {
+            const Geom gm = load_geom(a.mean, a.scale, a.quat, a.opac, a.n_all, i);
+            cnt = project_geom(a, cam, j, gm, P, op);
+        } else if (inr) {
+            a.count[j] = 0u;
+        }
+    } else if (valid) {
+        float shv[NB * 3];
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) shv[k] = __builtin_nontemporal_load(&a.sh[(int64_t)k * a.n_all + i]);
+        float rgb[3];
+        sh_colour<DEG>(cam, a.mean[i], a.mean[a.n_all + i], a.mean[2 * a.n_all + i], shv, rgb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_rgb[c][l] = rgb[c];
+    }
+    __syncthreads();
+    if (wv == 0 && cnt != 0u) {
+        const float rgb[3] = {s_rgb[0][l], s_rgb[1][l], s_rgb[2][l]};
+        write_record(a, j, P, op, rgb);
+    }
 }
 
 // Several views: the lane reads its Gaussian's parameters and SH coefficients once and projects
@@ -1001,14 +1062,15 @@ gs_status launch_preprocess(const gs_gaussians* g, const gs_views* views, const 
     const unsigned blocks = (unsigned)((n + 255) / 256);
     if (views->n_views == 1) {
         const dim3 grid(blocks, 1);
+        const unsigned blocks64 = (unsigned)((n + 63) / 64);
         if (!want_color) {
             hipLaunchKernelGGL((k_preprocess<0, false>), grid, dim3(256), 0, stream, a);
         } else {
             switch (g->sh_degree) {
                 case 0: hipLaunchKernelGGL((k_preprocess<0, true>), grid, dim3(256), 0, stream, a); break;
                 case 1: hipLaunchKernelGGL((k_preprocess<1, true>), grid, dim3(256), 0, stream, a); break;
-                case 2: hipLaunchKernelGGL((k_preprocess<2, true>), grid, dim3(256), 0, stream, a); break;
-                default: hipLaunchKernelGGL((k_preprocess<3, true>), grid, dim3(256), 0, stream, a); break;
+                case 2: hipLaunchKernelGGL((k_preprocess_split<2>), dim3(blocks64), dim3(128), 0, stream, a); break;
+                default: hipLaunchKernelGGL((k_preprocess_split<3>), dim3(blocks64), dim3(128), 0, stream, a); break;
             }
         }
     } else {
